@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark of the Faster Mean Shift hot path on one MI355X.
+
+A step is one whole ms_fit (Algorithm 2: seed draws, batched iterations with
+early stopping, merge, pool coverage, seed-count control, labelling) on the
+200,000-point, 3-D, 50-blob anisotropic Gaussian mixture with h = 15
+(synthetic stand-in for the paper's 200K-point simulation, Section III),
+with X already resident in HBM.
+
+Printed (one JSON line):
+  value            pair evaluations per second over the whole step
+                   (sum over iterations of active seeds x n, divided by the
+                   measured step time);
+  time_to_cluster  the step time itself;
+  roofline         the fused step kernel at its largest launch of the
+                   workload (512 seeds x 200,000 points), timed with HIP
+                   events on the stream the library launches on;
+  cpu_baseline     the FP64 oracle on the host's cores, on the same fit.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VEC_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_pair(d):
+    # distance 2D+3, weight 2 (+1 exp, not counted), accumulate 2D+1
+    return 4 * d + 6
+
+
+def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
+    """Average duration of one fused-step iteration with every seed active:
+    (t(iters) - t(0)) / iters, HIP events on the library's stream."""
+    def run(k):
+        st = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        api.step(X, seeds, h, kernel=kernel, precision=precision, tol=1e-30, n_iter=k)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    run(iters)  # warm
+    base = min(run(0) for _ in range(3))
+    full = min(run(iters) for _ in range(3))
+    return (full - base) / iters
+
+
+def cpu_baseline(w, args):
+    import oracle
+    oracle.lib()
+    th = oracle.threads()
+    t0 = time.perf_counter()
+    r = oracle.fit(w.X, w.h, kernel=w.kernel)
+    dt = time.perf_counter() - t0
+    return {"value": r.pairs / dt, "unit": "pair evals/s", "cores": th, "kind": "oracle",
+            "sample": f"one whole FP64 fit of the same workload ({len(r.round_B)} rounds, "
+                      f"{r.pairs:.3e} pairs, K={r.k}) in {dt:.2f} s",
+            "time_to_cluster_ms": dt * 1e3}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2112_13891_amd import api, workloads
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    api.lib()
+    w = workloads.aniso3d(seed=0)
+    X = torch.from_numpy(w.X).cuda()
+    n, d = w.X.shape
+    log(f"workload aniso3d n={n} d={d} h={w.h} kernel={w.kernel}")
+
+    def one(prec):
+        return api.fit(X, w.h, kernel=w.kernel, precision=prec)
+
+    results = {}
+    for prec in ([args.precision] if args.precision == "fp32" else ["fp32", "bf16"]):
+        for _ in range(args.warmup):
+            one(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(args.steps):
+            last = one(prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        results[prec] = (dt, last)
+        log(f"{prec}: {dt / args.steps * 1e3:.3f} ms/fit, K={last.k}, pairs={last.pairs}, "
+            f"iterate_ms={last.iterate_ms:.3f} merge_ms={last.merge_ms:.3f} "
+            f"assign_ms={last.assign_ms:.3f} total_ms={last.total_ms:.3f}")
+
+    dt, last = results[args.precision]
+    ms_per_step = dt / args.steps * 1e3
+    value = last.pairs * args.steps / dt
+
+    # dominant kernel: the fused step at the workload's largest launch
+    rng = np.random.default_rng(0)
+    m = int(max(last.round_B)) if last.rounds else 512
+    seeds = torch.from_numpy(w.X[rng.choice(n, m, replace=False)]).cuda()
+    t_it = time_kernel(api, torch, X, seeds, w.h, w.kernel, args.precision, args.kernel_iters)
+    pairs = m * n
+    achieved_tflops = pairs * flops_per_pair(d) / (t_it * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VEC_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VEC_PEAK_TFLOPS, "traffic": None,
+            "kernel": "fused step (step_kernel + finalize_kernel, one iteration)",
+            "launch": f"{m} seeds x {n} points", "avg_ms": t_it,
+            "pair_evals_per_s": pairs / (t_it * 1e-3)}
+    log(f"kernel: {t_it * 1e3:.1f} us/iteration at {m}x{n}: {pairs / (t_it * 1e-3):.3e} pairs/s, "
+        f"{achieved_tflops:.2f} TFLOP/s")
+
+    # throughput stress: every point a seed (Algorithm 1 shape), one iteration
+    t_all = time_kernel(api, torch, X, X, w.h, w.kernel, args.precision, 2)
+    stress = n * n / (t_all * 1e-3)
+    log(f"all-seeds iteration: {t_all:.2f} ms -> {stress:.3e} pairs/s")
+
+    out = {
+        "metric": "seed-point pair evals/s + time-to-cluster 200K pts, BF16-refined vs FP32",
+        "value": value,
+        "unit": "pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": "aniso3d: 200,000 points, D=3, 50 anisotropic Gaussian blobs "
+                               "(centres U[0,1000]^3, per-axis sigma U[3,8], Dirichlet(2) weights), "
+                               "Gaussian kernel h=15, pool seeding N0=128, L=8, tol=1e-3, "
+                               "max_iter=100, merge/cover radius h",
+                   "n": n, "d": d, "precision": args.precision, "K": last.k,
+                   "rounds": [int(b) for b in last.round_B], "pairs_per_fit": last.pairs},
+        "time_to_cluster_ms": ms_per_step,
+        "breakdown_ms": {"iterate": last.iterate_ms, "merge_and_pool": last.merge_ms,
+                         "assign": last.assign_ms, "host_total": last.total_ms},
+        "kernel_pair_evals_per_s": pairs / (t_it * 1e-3),
+        "all_seeds_iteration_pair_evals_per_s": stress,
+        "roofline": roof,
+    }
+    if "bf16" in results:
+        out["fp32_time_to_cluster_ms"] = results["fp32"][0] / args.steps * 1e3
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, args)
+        out["cpu_baseline"] = cb
+        log(f"cpu oracle: {cb['value']:.3e} pairs/s on {cb['cores']} threads")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * fms.h -- C ABI of libfms, an MI355X (gfx950) implementation of GPU Faster
+ * Mean Shift with the Euclidean metric (You et al., arXiv 2112.13891).
+ *
+ * Problem statement (Algorithms 1 and 2): given a bandwidth h and a vector set
+ * S = {x_1..x_n} in R^d, return the modes of the kernel density estimate of
+ * eq. (7) and a cluster for every point, by iterating seeds s <- m(s), where
+ * m(s) is the kernel-weighted mean of ALL n points (Section II-B, the batched
+ * update that replaces the window search of eq. (13)-(15)).
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major and contiguous.  Every array argument named as a
+ *     "device" pointer is GPU memory owned by the caller (for instance a torch
+ *     tensor); the library never frees caller memory and never keeps a pointer
+ *     after the call returns (ms_fit) or after the enqueued work finishes
+ *     (ms_step, ms_assign).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     ms_step and ms_assign are stream-ordered and asynchronous; ms_fit
+ *     returns only once K is known on the host.
+ *   - 1 <= d <= 64; 1 <= n <= 2^31 - 1.
+ *   - Return value: MS_OK (0) or a negative ms_status.  No exception crosses
+ *     the ABI.  ms_last_error() gives a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Calls on distinct streams may run concurrently from different threads.
+ *   - Same inputs, parameters and rng_seed give bitwise-identical outputs on
+ *     the same device and build (no floating-point atomics on result paths).
+ */
+#ifndef FMS_H
+#define FMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MS_OK = 0,
+    MS_E_INVALID = -1,   /* bad argument (message says which) */
+    MS_E_NONFINITE = -2, /* X holds NaN or Inf (only when check_finite != 0) */
+    MS_E_CAPACITY = -3,  /* more modes than max_modes; *k_out = required K */
+    MS_E_NO_MODES = -4,  /* no seed converged */
+    MS_E_NOMEM = -5,     /* device workspace allocation failed */
+    MS_E_HIP = -6        /* a HIP runtime call failed */
+} ms_status;
+
+typedef enum {
+    /* windowed kernel of eq. (12): weight 1 iff |s - x|^2 <= h^2 (inclusive) */
+    MS_KERNEL_FLAT = 0,
+    /* Gaussian profile: weight exp(-|s - x|^2 / (2 h^2)) */
+    MS_KERNEL_GAUSSIAN = 1
+} ms_kernel;
+
+typedef enum {
+    MS_PREC_FP32 = 0,        /* FP32 direct differences, FP32 accumulation */
+    MS_PREC_BF16_REFINE = 1  /* BF16 MFMA products, FP32 recompute within
+                                refine_radius*h, FP32 accumulation */
+} ms_precision;
+
+/* Method parameters.  Field order is part of the ABI. */
+typedef struct {
+    uint64_t rng_seed;        /* SplitMix64 state for the seed draws */
+    float h;                  /* bandwidth, > 0 (Algorithms 1-2 "Require h") */
+    int32_t kernel;           /* ms_kernel */
+    int32_t precision;        /* ms_precision */
+    float tol;                /* converged iff |s_t - s_{t-1}| < tol*h; > 0 */
+    int32_t max_iter;         /* at most this many updates per seed; >= 1 */
+    float merge_radius;       /* modes within merge_radius*h merge (x h) */
+    float cover_radius;       /* pool points within cover_radius*h of a mode
+                                 leave the seed pool (x h); >= 0 */
+    float gamma;              /* early stop once ceil(gamma*B) of a batch of B
+                                 seeds converged (Section II-C); (0, 1] */
+    int32_t n_initial;        /* initial seed count N (Section II-D: 128) */
+    int32_t L;                /* stop once N >= L*M (Section II-D: 8) */
+    float refine_radius;      /* BF16 path: exact FP32 distance for pairs
+                                 whose lower bound is within refine_radius*h */
+    int32_t all_points_as_seeds; /* 1: Algorithm 1 (every point is a seed,
+                                    one batch); 0: Algorithm 2 (pool) */
+    int32_t check_finite;     /* 1: scan X for NaN/Inf first */
+    int32_t reserved[4];      /* must be 0 */
+} ms_params;
+
+/* Fills *p with the defaults: h = 1, Gaussian, FP32, tol = 1e-3,
+ * max_iter = 100, merge_radius = cover_radius = 1, gamma = 1,
+ * n_initial = 128, L = 8, refine_radius = 2, pool mode, rng_seed = 0. */
+void ms_default_params(ms_params *p);
+
+#define MS_DIAG_MAX_ROUNDS 64
+
+/* Optional diagnostics of ms_fit (host memory).  The pointer fields are
+ * optional host arrays the caller provides (NULL to skip); "drawn" arrays
+ * need room for n entries (all drawn seeds, concatenated by round). */
+typedef struct {
+    int32_t rounds;                          /* rounds run */
+    int32_t round_N[MS_DIAG_MAX_ROUNDS];     /* requested seed count N */
+    int32_t round_B[MS_DIAG_MAX_ROUNDS];     /* seeds drawn */
+    int32_t round_M[MS_DIAG_MAX_ROUNDS];     /* modes after the round */
+    int32_t round_T[MS_DIAG_MAX_ROUNDS];     /* iterations the batch ran */
+    int32_t round_converged[MS_DIAG_MAX_ROUNDS];
+    int64_t pairs;            /* sum over iterations of active seeds x n */
+    int64_t refined_pairs;    /* BF16 path: pairs recomputed in FP32 */
+    double iterate_ms;        /* GPU time of the seed iterations (events) */
+    double merge_ms;          /* GPU+host time of merge and pool update */
+    double assign_ms;         /* GPU time of the labelling */
+    double total_ms;          /* host wall time inside ms_fit */
+    int64_t workspace_bytes;  /* peak device workspace */
+    int32_t *drawn;           /* [n] drawn point ids */
+    int32_t *drawn_iters;     /* [n] updates each drawn seed received */
+    int8_t *drawn_status;     /* [n] 1 converged, 0 discarded, 2 failed */
+    float *drawn_final;       /* [n*d] final seed positions */
+    int32_t *counts;          /* [max_modes] seeds merged into each mode */
+} ms_diag;
+
+/*
+ * ms_fit -- the whole method: Algorithm 2 (seed selection, batched
+ * iteration with early stopping, prune modes, cluster by distance to modes)
+ * with the seed-count control of Section II-D; Algorithm 1 when
+ * p->all_points_as_seeds is set.
+ *
+ *   X       device, n x d float32 points.
+ *   modes   device, max_modes x d float32; receives the K modes in creation
+ *           order (a mode is the final position of the first seed that
+ *           founded it).
+ *   k_out   host; receives K (also on MS_E_CAPACITY: the K required).
+ *   labels  device, n int32 (may be NULL); nearest mode, ties to the lowest
+ *           index.
+ *   diag    host, optional (NULL to skip).
+ * Host-synchronous: returns when K is on the host and labels are written.
+ * Errors: MS_E_INVALID, MS_E_NONFINITE, MS_E_CAPACITY, MS_E_NO_MODES,
+ * MS_E_NOMEM, MS_E_HIP.  On error the contents of modes/labels are
+ * unspecified.
+ */
+int ms_fit(const ms_params *p, const float *X, int64_t n, int32_t d,
+           float *modes, int32_t max_modes, int32_t *k_out, int32_t *labels,
+           ms_diag *diag, void *stream);
+
+/*
+ * ms_step -- up to n_iter updates s <- m(s) of caller-given seeds (the inner
+ * "while not converge" loop of Algorithms 1-2), without early stopping of
+ * the batch.  Seeds whose converged flag is nonzero on entry are left as
+ * they are.  Stream-ordered and asynchronous.
+ *
+ *   seeds      device, m x d float32, in/out.
+ *   converged  device, m uint8, in/out: 0 active, 1 converged
+ *              (|shift| < tol*h), 2 failed (sum of weights 0 or non-finite).
+ *   iters      device, m int32, out: updates applied during this call.
+ *   shift2     device, m float32, out: squared length of the last update
+ *              (unchanged for seeds that received none).
+ * Uses p->h, kernel, precision, tol, refine_radius; other fields ignored.
+ */
+int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
+            float *seeds, int32_t m, int32_t n_iter, uint8_t *converged,
+            int32_t *iters, float *shift2, void *stream);
+
+/*
+ * ms_assign -- "cluster x by the distance to modes" (Algorithm 2, last
+ * loop): labels[i] = argmin_j |x_i - mode_j|^2 by FP32 direct differences,
+ * ties to the lowest j.  margin (optional, may be NULL): distance to the
+ * second-nearest mode minus distance to the nearest (+inf when k == 1).
+ * All pointers are device memory.  Stream-ordered and asynchronous.
+ */
+int ms_assign(const float *X, int64_t n, int32_t d, const float *modes,
+              int32_t k, int32_t *labels, float *margin, void *stream);
+
+/*
+ * ms_forward_update -- one Gaussian update of every seed with no stopping,
+ * S_out = m(S_in) (Section II-B), for `nbatch` independent point sets at
+ * once: X is nbatch x n x d, S_in and S_out are nbatch x m x d, and each
+ * set's seeds see only that set's points.  The element type is float32
+ * (dtype_bytes = 4) or float64 (8).  The differentiable form of the method
+ * (Section II-B unrolled T times with S_0 = X) is built from this call and
+ * ms_step_adjoint.  Device pointers; stream-ordered and asynchronous.
+ */
+int ms_forward_update(const void *X, int32_t nbatch, int64_t n, const void *S_in,
+                      int64_t m, int32_t d, double h, void *S_out,
+                      int32_t dtype_bytes, void *stream);
+
+/*
+ * ms_step_adjoint -- reverse-mode derivative of ms_forward_update.  With
+ * w_ij = exp(-|s_j - x_i|^2/(2h^2)), W_j = sum_i w_ij, s'_j = sum_i w_ij x_i
+ * / W_j and the upstream gradient G = dL/dS' (nbatch x m x d):
+ *     beta_ij = w_ij * (g_j . (x_i - s'_j)) / (h^2 W_j)
+ *     dL/ds_j = sum_i beta_ij (x_i - s_j)
+ *     dL/dx_i = sum_j [ (w_ij / W_j) g_j + beta_ij (s_j - x_i) ]
+ * are ADDED to dS (nbatch x m x d) and dX (nbatch x n x d).  The weights
+ * are recomputed, never stored.  Same layout and dtype rules as
+ * ms_forward_update.  Device pointers; stream-ordered and asynchronous.
+ */
+int ms_step_adjoint(const void *X, int32_t nbatch, int64_t n, const void *S,
+                    int64_t m, int32_t d, double h, const void *G, void *dS,
+                    void *dX, int32_t dtype_bytes, void *stream);
+
+/*
+ * ms_seed_draw -- the library's seed selection on host memory: draws
+ * `count` ids from pool[0..len) by a partial Fisher-Yates shuffle driven by
+ * SplitMix64 with the multiply-high bound (the same draw ms_fit makes each
+ * round).  *state is the generator state (in/out); out receives the ids in
+ * slot order.  pool is not modified.  Host only; no GPU needed.
+ */
+int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
+                 int32_t count, int32_t *out);
+
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char *ms_last_error(void);
+
+/* Library version string. */
+const char *ms_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMS_H */

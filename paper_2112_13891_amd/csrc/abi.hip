@@ -1,0 +1,779 @@
+// abi.hip -- the C ABI of libfms and the host control of the method:
+// argument checking, seed selection (SplitMix64 + partial Fisher-Yates on
+// pool positions), the round loop of Algorithm 2 with the seed-count control
+// of Section II-D, merge resolution and workspace management.
+//
+// Per round the host crosses to the device twice: once after the batch has
+// iterated and the merge passes ran (status, merge state and positions come
+// back), once after the pool was updated (its new length comes back).
+// Within the batch the iterations are enqueued in chunks and the host only
+// polls a pinned copy of the device control block between chunks.
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "fms_internal.h"
+
+namespace fms {
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? MS_E_NOMEM : MS_E_HIP,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define FMS_HIP(expr)                                              \
+    do {                                                           \
+        hipError_t _e = (expr);                                    \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);          \
+    } while (0)
+
+#define FMS_CHECK(expr)              \
+    do {                             \
+        int _rc = (expr);            \
+        if (_rc != MS_OK) return _rc; \
+    } while (0)
+
+// ---- seed selection ---------------------------------------------------------
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014).
+struct SplitMix64 {
+    uint64_t state;
+    uint64_t next() {
+        state += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+};
+
+// Partial Fisher-Yates over positions 0..len-1, simulated sparsely: only the
+// touched positions are stored.  pos[t] receives the position that ends up in
+// slot t (slot t is final after its own swap, since later swaps only touch
+// slots > t).  Swap partner of slot t: t + floor(r * (len - t) / 2^64).
+void draw_positions(uint64_t* state, int32_t len, int32_t count, int32_t* pos) {
+    SplitMix64 g{*state};
+    std::unordered_map<int32_t, int32_t> moved;
+    moved.reserve((size_t)count * 2 + 1);
+    auto at = [&](int32_t p) {
+        auto it = moved.find(p);
+        return it == moved.end() ? p : it->second;
+    };
+    for (int32_t t = 0; t < count; ++t) {
+        const uint64_t r = g.next();
+        const int32_t j =
+            t + (int32_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)(len - t)) >> 64);
+        const int32_t vt = at(t), vj = at(j);
+        moved[j] = vt;
+        moved[t] = vj;
+        pos[t] = vj;
+    }
+    *state = g.state;
+}
+
+// ---- device memory ------------------------------------------------------------
+
+// Test hook: FMS_FAIL_ALLOC_AFTER=k makes the (k+1)-th allocation of a call fail.
+struct AllocBudget {
+    long long left = -1;
+    AllocBudget() {
+        const char* e = std::getenv("FMS_FAIL_ALLOC_AFTER");
+        if (e && *e) left = std::atoll(e);
+    }
+    bool take() {
+        if (left < 0) return true;
+        if (left == 0) return false;
+        --left;
+        return true;
+    }
+};
+
+// Stream-ordered device buffers owned by one call; freed on scope exit.
+class Workspace {
+   public:
+    explicit Workspace(hipStream_t s) : s_(s) {}
+    ~Workspace() {
+        for (void* p : bufs_) (void)hipFreeAsync(p, s_);
+    }
+    template <typename T>
+    int alloc(T** out, size_t count) {
+        size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+        void* p = nullptr;
+        if (!budget_.take()) return fail(MS_E_NOMEM, "device workspace allocation failed (test hook)");
+        hipError_t e = hipMallocAsync(&p, bytes, s_);
+        if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorOutOfMemory : e, "hipMallocAsync");
+        bufs_.push_back(p);
+        bytes_ += bytes;
+        peak_ = std::max(peak_, bytes_);
+        *out = (T*)p;
+        return MS_OK;
+    }
+    template <typename T>
+    void release(T* p) {
+        for (size_t i = 0; i < bufs_.size(); ++i)
+            if (bufs_[i] == (void*)p) {
+                (void)hipFreeAsync(p, s_);
+                bufs_.erase(bufs_.begin() + i);
+                return;
+            }
+    }
+    long long peak() const { return peak_; }
+
+   private:
+    hipStream_t s_;
+    std::vector<void*> bufs_;
+    AllocBudget budget_;
+    long long bytes_ = 0, peak_ = 0;
+};
+
+// Pinned host staging, per thread, grown on demand and kept for reuse.
+struct Pinned {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return MS_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(bytes, 1 << 16);
+        FMS_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+        cap = want;
+        return MS_OK;
+    }
+};
+thread_local Pinned g_pin_ctl, g_pin_pos, g_pin_rb, g_pin_modes;
+
+
+int ensure_pool_release_threshold() {
+    static bool done[64] = {};
+    int dev = 0;
+    FMS_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && !done[dev]) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        done[dev] = true;
+    }
+    return MS_OK;
+}
+
+// ---- argument checks -------------------------------------------------------------
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+int check_common(const float* X, int64_t n, int32_t d) {
+    if (!X) return fail(MS_E_INVALID, "X is NULL");
+    if (n < 1 || n > INT_MAX) return fail(MS_E_INVALID, "n must be in [1, 2^31-1]");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if ((long long)n * step_shape(d).DP > (1LL << 40))
+        return fail(MS_E_INVALID, "n*d too large");
+    return MS_OK;
+}
+
+int check_params(const ms_params* p, bool for_fit) {
+    if (!p) return fail(MS_E_INVALID, "params is NULL");
+    if (!finite_pos(p->h)) return fail(MS_E_INVALID, "h must be finite and > 0");
+    if (p->kernel != MS_KERNEL_FLAT && p->kernel != MS_KERNEL_GAUSSIAN)
+        return fail(MS_E_INVALID, "unknown kernel");
+    if (p->precision != MS_PREC_FP32 && p->precision != MS_PREC_BF16_REFINE)
+        return fail(MS_E_INVALID, "unknown precision");
+    if (!finite_pos(p->tol)) return fail(MS_E_INVALID, "tol must be finite and > 0");
+    if (!std::isfinite(p->tol * p->h) || p->tol * p->h <= 0.0f)
+        return fail(MS_E_INVALID, "tol*h must be a positive finite float");
+    if (p->precision == MS_PREC_BF16_REFINE && !(std::isfinite(p->refine_radius) && p->refine_radius >= 0.0f))
+        return fail(MS_E_INVALID, "refine_radius must be finite and >= 0");
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
+    if (!for_fit) return MS_OK;
+    if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
+        return fail(MS_E_INVALID, "max_iter must be in [1, 4096]");
+    if (!(std::isfinite(p->merge_radius) && p->merge_radius >= 0.0f))
+        return fail(MS_E_INVALID, "merge_radius must be finite and >= 0");
+    if (!(std::isfinite(p->cover_radius) && p->cover_radius >= 0.0f))
+        return fail(MS_E_INVALID, "cover_radius must be finite and >= 0");
+    if (!(p->gamma > 0.0f && p->gamma <= 1.0f)) return fail(MS_E_INVALID, "gamma must be in (0, 1]");
+    if (p->n_initial < 1) return fail(MS_E_INVALID, "n_initial must be >= 1");
+    if (p->L < 1) return fail(MS_E_INVALID, "L must be >= 1");
+    return MS_OK;
+}
+
+float packed_scale(const ms_params* p) {
+    if (p->kernel != MS_KERNEL_GAUSSIAN) return 1.0f;
+    // w = exp(-q/(2h^2)) = exp2(-|c x - c s|^2) with c^2 = log2(e)/(2h^2)
+    return (float)std::sqrt(1.4426950408889634 / (2.0 * (double)p->h * (double)p->h));
+}
+
+// ---- cached device workspace of ms_fit ----------------------------------------------
+
+// ms_fit is host-synchronous, so one thread never has two fits in flight: its
+// device buffers can be kept and reused by the next fit on the same thread
+// and device (grown on demand, never shrunk).
+enum Slot {
+    SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
+    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_COUNT
+};
+
+struct DevCache {
+    int dev = -1;
+    void* p[SL_COUNT] = {};
+    size_t cap[SL_COUNT] = {};
+    long long held = 0;
+};
+thread_local std::vector<DevCache> g_cache;
+
+DevCache& cache_for_device(int dev) {
+    for (auto& c : g_cache)
+        if (c.dev == dev) return c;
+    g_cache.emplace_back();
+    g_cache.back().dev = dev;
+    return g_cache.back();
+}
+
+template <typename T>
+int cache_get(DevCache& c, AllocBudget& budget, Slot sl, size_t count, T** out,
+              bool keep_contents = false, hipStream_t s = nullptr) {
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (c.cap[sl] < bytes) {
+        if (!budget.take()) return fail(MS_E_NOMEM, "device workspace allocation failed (test hook)");
+        const size_t want = std::max(bytes, c.cap[sl] + c.cap[sl] / 2);
+        void* np = nullptr;
+        hipError_t e = hipMalloc(&np, want);
+        if (e != hipSuccess || !np) return hip_fail(e == hipSuccess ? hipErrorOutOfMemory : e, "hipMalloc");
+        if (c.p[sl]) {
+            if (keep_contents) {
+                hipError_t e2 = hipMemcpyAsync(np, c.p[sl], c.cap[sl], hipMemcpyDeviceToDevice, s);
+                if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+                if (e2 != hipSuccess) {
+                    (void)hipFree(np);
+                    return hip_fail(e2, "workspace grow copy");
+                }
+            }
+            (void)hipFree(c.p[sl]);
+            c.held -= (long long)c.cap[sl];
+        }
+        c.p[sl] = np;
+        c.cap[sl] = want;
+        c.held += (long long)want;
+    }
+    *out = (T*)c.p[sl];
+    return MS_OK;
+}
+
+// Layout of the per-round readback buffer: the control block first, then the
+// batch arrays the host needs, sized for the current batch B so that one
+// contiguous copy brings everything back.
+struct RbLayout {
+    size_t state, ids, iters, status, S, total;
+};
+
+RbLayout rb_layout(int B, int DP) {
+    auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
+    RbLayout L;
+    size_t o = up(sizeof(Ctl), 256);
+    L.state = o; o += (size_t)B * 4;
+    L.ids = o; o += (size_t)B * 4;
+    L.iters = o; o += (size_t)B * 4;
+    L.status = o; o += (size_t)B;
+    o = up(o, 16);
+    L.S = o; o += (size_t)B * DP * 4;
+    L.total = up(o, 256);
+    return L;
+}
+
+// Enqueue up to max_iter iterations, in chunks, stopping once a snapshot of
+// the control block shows the batch finished.
+int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror, hipEvent_t ev[2]) {
+    const int kChunk = 4;
+    int t = 0, pending = -1, pending_t = 0, slot = 0;
+    while (t < max_iter) {
+        const int c = std::min(kChunk, max_iter - t);
+        for (int k = 0; k < c; ++k) FMS_HIP(launch_iteration(b, t + k, s));
+        t += c;
+        FMS_HIP(hipMemcpyAsync(&mirror[slot], b.ctl, offsetof(Ctl, conv_it) + (size_t)(t + 1) * 4,
+                               hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipEventRecord(ev[slot], s));
+        if (pending >= 0) {
+            FMS_HIP(hipEventSynchronize(ev[pending]));
+            const Ctl& cs = mirror[pending];
+            int conv = 0;
+            for (int u = 0; u < pending_t; ++u) conv += cs.conv_it[u];
+            if (conv >= cs.need || cs.count[pending_t % 3] == 0) break;
+        }
+        pending = slot;
+        pending_t = t;
+        slot ^= 1;
+    }
+    return MS_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct Events {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Events() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    int create() {
+        for (auto& x : e)
+            if (!x) FMS_HIP(hipEventCreate(&x));
+        return MS_OK;
+    }
+};
+thread_local Events g_events;
+
+bool log_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("MS_LOG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+
+// FP32 squared distance with the same operation order as the device kernels.
+float host_dist2(const float* a, const float* b, int d) {
+    float q = 0.0f;
+    for (int k = 0; k < d; ++k) {
+        float t = a[k] - b[k];
+        q = std::fmaf(t, t, q);
+    }
+    return q;
+}
+
+void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_params* p,
+                float scale, const float* Xp, Ctl* ctl) {
+    const float tolh = p->tol * p->h;
+    b.n = n;
+    b.d = d;
+    b.n_seeds = B;
+    b.sh = sh;
+    b.kernel = p->kernel;
+    b.h = p->h;
+    b.scale = scale;
+    b.inv_scale = 1.0f / scale;
+    b.thr2 = tolh * tolh;
+    b.Xp = Xp;
+    b.grid = step_grid(sh, B, n);
+    b.ctl = ctl;
+}
+
+int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int32_t max_modes,
+             int32_t* k_out, int32_t* labels, ms_diag* diag, hipStream_t s) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const bool trace = log_enabled();
+    int dev = 0;
+    FMS_HIP(hipGetDevice(&dev));
+    DevCache& C = cache_for_device(dev);
+    AllocBudget budget;
+    FMS_CHECK(g_events.create());
+    hipEvent_t* ev = g_events.e;
+
+    if (p->check_finite) {
+        int32_t* flag;
+        FMS_CHECK(cache_get(C, budget, SL_FLAG, 1, &flag));
+        FMS_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+        FMS_HIP(launch_check_finite(X, (long long)n * d, flag, s));
+        int32_t hflag = 0;
+        FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipStreamSynchronize(s));
+        if (hflag) return fail(MS_E_NONFINITE, "X contains NaN or Inf");
+    }
+
+    const StepShape base = step_shape(d);
+    const int DP = base.DP;
+    const bool all = p->all_points_as_seeds != 0;
+    const float scale = packed_scale(p);
+    const float rm = p->merge_radius * p->h, rc = p->cover_radius * p->h;
+    const float r2m = rm * rm, r2c = rc * rc;
+
+    float* Xp;
+    FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
+    FMS_HIP(launch_pack_points(X, n, d, DP, scale, Xp, s));
+
+    int32_t* pool[2] = {nullptr, nullptr};
+    uint8_t* removed = nullptr;
+    int32_t* block_tmp = nullptr;
+    int pool_len = n;
+    if (!all) {
+        FMS_CHECK(cache_get(C, budget, SL_POOL0, n, &pool[0]));
+        FMS_CHECK(cache_get(C, budget, SL_POOL1, n, &pool[1]));
+        FMS_CHECK(cache_get(C, budget, SL_REMOVED, n, &removed));
+        FMS_CHECK(cache_get(C, budget, SL_BLOCKS, pool_compact_blocks(n) + 1, &block_tmp));
+        FMS_HIP(launch_iota(pool[0], n, s));
+    }
+
+    // device mode store (DP stride), grown on demand
+    int Kcap = std::min(n, 1024);
+    float* modes_ws;
+    FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)Kcap * DP, &modes_ws));
+    std::vector<int32_t> counts;
+
+    FMS_CHECK(g_pin_ctl.ensure(2 * sizeof(Ctl)));
+    Ctl* mirror = (Ctl*)g_pin_ctl.p;
+
+    uint64_t rng = p->rng_seed;
+    long long N = p->n_initial;
+    int K = 0, rounds = 0;
+    long long pairs = 0, drawn_total = 0;
+    double iterate_ms = 0.0, merge_ms = 0.0;
+    int cur = 0;
+    if (trace) std::fprintf(stderr, "[fms] fit n=%d d=%d setup %.3f ms\n", n, d, ms_since(t_start));
+
+    for (;;) {
+        const auto t_round = std::chrono::steady_clock::now();
+        const int B = all ? n : (int)std::min<long long>(N, pool_len);
+        const StepShape sh = step_shape_for(d, B);
+        Batch b;
+        fill_batch(b, n, d, B, sh, p, scale, Xp, nullptr);
+        const long long part_floats = step_part_floats(sh, B, b.grid);
+        const RbLayout L = rb_layout(B, DP);
+        char* rbuf;
+        FMS_CHECK(cache_get(C, budget, SL_RB, L.total, &rbuf));
+        Ctl* ctl = (Ctl*)rbuf;
+        b.ctl = ctl;
+        // the pool length lives in the control block across rounds; keep it
+        int32_t* bstate = (int32_t*)(rbuf + L.state);
+        int32_t* bids = (int32_t*)(rbuf + L.ids);
+        b.iters = (int32_t*)(rbuf + L.iters);
+        b.status = (uint8_t*)(rbuf + L.status);
+        b.S = (float*)(rbuf + L.S);
+        FMS_CHECK(cache_get(C, budget, SL_ACT0, B, &b.act[0]));
+        FMS_CHECK(cache_get(C, budget, SL_ACT1, B, &b.act[1]));
+        FMS_CHECK(cache_get(C, budget, SL_SHIFT2, B, &b.shift2));
+        FMS_CHECK(cache_get(C, budget, SL_PART, (size_t)part_floats, &b.part));
+
+        if (all) {
+            FMS_HIP(launch_iota(bids, B, s));
+        } else {
+            int32_t* dpos;
+            FMS_CHECK(cache_get(C, budget, SL_POS, B, &dpos));
+            FMS_CHECK(g_pin_pos.ensure((size_t)B * sizeof(int32_t)));
+            int32_t* hpos = (int32_t*)g_pin_pos.p;
+            draw_positions(&rng, pool_len, B, hpos);
+            FMS_HIP(hipMemcpyAsync(dpos, hpos, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            FMS_HIP(launch_fill_u8(removed, pool_len, 0, s));
+            FMS_HIP(launch_gather_ids(pool[cur], dpos, B, bids, removed, s));
+        }
+        FMS_HIP(launch_seed_init_from_ids(X, d, DP, bids, B, b, s));
+        const int need = (int)std::ceil((double)p->gamma * (double)B);
+        FMS_HIP(launch_ctl_reset(ctl, B, need, p->max_iter, s));
+
+        FMS_HIP(hipEventRecord(ev[2], s));
+        FMS_CHECK(iterate_batch(b, p->max_iter, s, mirror, ev));
+        FMS_HIP(hipEventRecord(ev[3], s));
+        const auto t_merge = std::chrono::steady_clock::now();
+
+        // merge ("prune modes"): old modes first, then parallel decision passes
+        const int K_old = K;
+        FMS_HIP(launch_merge_first_old(b.S, DP, d, b.status, B, modes_ws, K_old, r2m, bstate, s));
+        const int kPasses = 3;
+        for (int q = 0; q < kPasses; ++q)
+            FMS_HIP(launch_merge_decide_pass(b.S, DP, d, B, K_old, r2m, bstate, &ctl->und[q], s));
+
+        // one copy brings back the control block and the batch
+        FMS_CHECK(g_pin_rb.ensure(L.total));
+        char* hrb = (char*)g_pin_rb.p;
+        FMS_HIP(hipMemcpyAsync(hrb, rbuf, L.total, hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipStreamSynchronize(s));
+        const Ctl& cs = *(const Ctl*)hrb;
+        const int32_t* h_state = (const int32_t*)(hrb + L.state);
+        const int32_t* h_ids = (const int32_t*)(hrb + L.ids);
+        const int32_t* h_iters = (const int32_t*)(hrb + L.iters);
+        const uint8_t* h_status = (const uint8_t*)(hrb + L.status);
+        const float* h_S = (const float*)(hrb + L.S);
+        {
+            float ms = 0.0f;
+            FMS_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+            iterate_ms += ms;
+        }
+        pairs += cs.pairs;
+
+        // resolve: number the founders in seed order; a seed the device passes
+        // left undecided gets the same rule here (all earlier seeds are decided
+        // by the time it is reached, so this is exact)
+        std::vector<int32_t> mode_of(B, -1);
+        std::vector<int32_t> founders;
+        for (int i = 0; i < B; ++i) {
+            int st = h_state[i];
+            if (st == MG_SKIP) continue;
+            if (st == MG_UNDECIDED) {
+                st = MG_FOUNDER;
+                const float* si = h_S + (size_t)i * DP;
+                for (int j : founders) {   // increasing seed order
+                    if (host_dist2(si, h_S + (size_t)j * DP, d) <= r2m) {
+                        st = K_old + j;
+                        break;
+                    }
+                }
+            }
+            if (st == MG_FOUNDER) {
+                mode_of[i] = K;
+                founders.push_back(i);
+                counts.push_back(1);
+                ++K;
+            } else if (st >= K_old) {
+                mode_of[i] = mode_of[st - K_old];
+                counts[mode_of[i]] += 1;
+            } else {
+                mode_of[i] = st;
+                counts[st] += 1;
+            }
+        }
+        if (K > Kcap) {
+            int newcap = Kcap;
+            while (newcap < K) newcap *= 2;
+            newcap = std::min(newcap, n);
+            FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)newcap * DP, &modes_ws, true, s));
+            Kcap = newcap;
+        }
+        if (K > K_old) {
+            FMS_CHECK(g_pin_modes.ensure((size_t)(K - K_old) * DP * 4));
+            float* hm = (float*)g_pin_modes.p;
+            for (int q = 0; q < K - K_old; ++q)
+                std::memcpy(hm + (size_t)q * DP, h_S + (size_t)founders[q] * DP, (size_t)DP * 4);
+            FMS_HIP(hipMemcpyAsync(modes_ws + (size_t)K_old * DP, hm, (size_t)(K - K_old) * DP * 4,
+                                   hipMemcpyHostToDevice, s));
+        }
+
+        if (diag) {
+            if (rounds < MS_DIAG_MAX_ROUNDS) {
+                diag->round_N[rounds] = all ? B : (int32_t)std::min<long long>(N, INT_MAX);
+                diag->round_B[rounds] = B;
+                diag->round_M[rounds] = K;
+                diag->round_T[rounds] = cs.iters_run;
+                int conv = 0;
+                for (int u = 0; u < cs.iters_run; ++u) conv += cs.conv_it[u];
+                diag->round_converged[rounds] = conv;
+            }
+            for (int i = 0; i < B; ++i) {
+                const long long o = drawn_total + i;
+                if (diag->drawn) diag->drawn[o] = h_ids[i];
+                if (diag->drawn_iters) diag->drawn_iters[o] = h_iters[i];
+                if (diag->drawn_status)
+                    diag->drawn_status[o] = h_status[i] == ST_CONVERGED ? 1 : (h_status[i] == ST_FAILED ? 2 : 0);
+                if (diag->drawn_final)
+                    for (int k = 0; k < d; ++k) diag->drawn_final[o * d + k] = h_S[(size_t)i * DP + k];
+            }
+        }
+        drawn_total += B;
+        rounds += 1;
+        if (all) {
+            merge_ms += ms_since(t_merge);
+            break;
+        }
+
+        // seed pool: drop the drawn seeds and the points the new modes cover,
+        // keep the rest in ascending order
+        FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, K, r2c, removed, s));
+        FMS_HIP(launch_pool_compact(pool[cur], removed, pool_len, pool[cur ^ 1], block_tmp, ctl, s));
+        FMS_HIP(hipMemcpyAsync(mirror, ctl, offsetof(Ctl, conv_it), hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipStreamSynchronize(s));
+        pool_len = mirror->pool_len;
+        cur ^= 1;
+        merge_ms += ms_since(t_merge);
+        if (trace)
+            std::fprintf(stderr, "[fms] round %d B=%d T=%d K=%d pool=%d round %.3f ms (merge+pool %.3f)\n",
+                         rounds, B, cs.iters_run, K, pool_len, ms_since(t_round), ms_since(t_merge));
+        if (pool_len == 0 || N >= (long long)p->L * K) break;
+        N *= 2;
+    }
+
+    *k_out = K;
+    if (diag) {
+        diag->rounds = rounds;
+        diag->pairs = pairs;
+        diag->refined_pairs = 0;
+        diag->iterate_ms = iterate_ms;
+        diag->merge_ms = merge_ms;
+        if (diag->counts)
+            for (int j = 0; j < std::min(K, max_modes); ++j) diag->counts[j] = counts[j];
+    }
+    if (K == 0) return fail(MS_E_NO_MODES, "no seed converged");
+    if (K > max_modes) return fail(MS_E_CAPACITY, "more modes than max_modes (k_out holds the required K)");
+
+    FMS_HIP(hipMemcpy2DAsync(modes, (size_t)d * 4, modes_ws, (size_t)DP * 4, (size_t)d * 4, K,
+                             hipMemcpyDeviceToDevice, s));
+    if (labels) {
+        FMS_HIP(hipEventRecord(ev[2], s));
+        FMS_HIP(launch_assign(X, n, d, modes, K, labels, nullptr, s));
+        FMS_HIP(hipEventRecord(ev[3], s));
+    }
+    FMS_HIP(hipStreamSynchronize(s));
+    if (diag) {
+        float ms = 0.0f;
+        if (labels) FMS_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+        diag->assign_ms = ms;
+        diag->workspace_bytes = C.held;
+        diag->total_ms = ms_since(t_start);
+    }
+    if (trace) std::fprintf(stderr, "[fms] fit done K=%d total %.3f ms\n", K, ms_since(t_start));
+    return MS_OK;
+}
+
+int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, int m, int n_iter,
+              uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
+    FMS_CHECK(ensure_pool_release_threshold());
+    Workspace ws(s);
+    const StepShape sh = step_shape_for(d, m);
+    const float scale = packed_scale(p);
+    float* Xp;
+    FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
+    FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
+    Ctl* ctl;
+    FMS_CHECK(ws.alloc(&ctl, 1));
+    Batch b;
+    fill_batch(b, n, d, m, sh, p, scale, Xp, ctl);
+    FMS_CHECK(ws.alloc(&b.S, (size_t)m * sh.DP));
+    FMS_CHECK(ws.alloc(&b.act[0], m));
+    FMS_CHECK(ws.alloc(&b.act[1], m));
+    FMS_CHECK(ws.alloc(&b.status, m));
+    FMS_CHECK(ws.alloc(&b.iters, m));
+    FMS_CHECK(ws.alloc(&b.shift2, m));
+    FMS_CHECK(ws.alloc(&b.part, (size_t)step_part_floats(sh, m, b.grid)));
+    FMS_HIP(launch_ctl_reset(ctl, 0, INT_MAX, n_iter, s));
+    FMS_HIP(launch_seed_init_from_array(seeds, converged, d, m, b, s));
+    for (int t = 0; t < n_iter; ++t) FMS_HIP(launch_iteration(b, t, s));
+    FMS_HIP(launch_seed_export(b, m, seeds, converged, iters, shift2, s));
+    return MS_OK;
+}
+
+}  // namespace
+}  // namespace fms
+
+using namespace fms;
+
+extern "C" {
+
+void ms_default_params(ms_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->rng_seed = 0;
+    p->h = 1.0f;
+    p->kernel = MS_KERNEL_GAUSSIAN;
+    p->precision = MS_PREC_FP32;
+    p->tol = 1e-3f;
+    p->max_iter = 100;
+    p->merge_radius = 1.0f;
+    p->cover_radius = 1.0f;
+    p->gamma = 1.0f;
+    p->n_initial = 128;
+    p->L = 8;
+    p->refine_radius = 2.0f;
+    p->all_points_as_seeds = 0;
+    p->check_finite = 0;
+}
+
+int ms_fit(const ms_params* p, const float* X, int64_t n, int32_t d, float* modes,
+           int32_t max_modes, int32_t* k_out, int32_t* labels, ms_diag* diag, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_params(p, true));
+    FMS_CHECK(check_common(X, n, d));
+    if (!modes) return fail(MS_E_INVALID, "modes is NULL");
+    if (!k_out) return fail(MS_E_INVALID, "k_out is NULL");
+    if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");
+    if (p->precision != MS_PREC_FP32)
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE is not available in this build");
+    *k_out = 0;
+    return fit_impl(p, X, (int)n, d, modes, max_modes, k_out, labels, diag, (hipStream_t)stream);
+}
+
+int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* seeds, int32_t m,
+            int32_t n_iter, uint8_t* converged, int32_t* iters, float* shift2, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_params(p, false));
+    FMS_CHECK(check_common(X, n, d));
+    if (m < 0) return fail(MS_E_INVALID, "m must be >= 0");
+    if (n_iter < 0 || n_iter > kMaxIterCap) return fail(MS_E_INVALID, "n_iter must be in [0, 4096]");
+    if (m == 0) return MS_OK;
+    if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
+    if (p->precision != MS_PREC_FP32)
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE is not available in this build");
+    return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
+}
+
+int ms_assign(const float* X, int64_t n, int32_t d, const float* modes, int32_t k, int32_t* labels,
+              float* margin, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_common(X, n, d));
+    if (!modes) return fail(MS_E_INVALID, "modes is NULL");
+    if (!labels) return fail(MS_E_INVALID, "labels is NULL");
+    if (k < 1) return fail(MS_E_INVALID, "k must be >= 1");
+    FMS_HIP(launch_assign(X, (int)n, d, modes, k, labels, margin, (hipStream_t)stream));
+    return MS_OK;
+}
+
+static int check_diff(const void* X, int32_t nbatch, int64_t n, const void* S, int64_t m, int32_t d,
+                      double h, int32_t bytes) {
+    if (!X || !S) return fail(MS_E_INVALID, "NULL array");
+    if (bytes != 4 && bytes != 8) return fail(MS_E_INVALID, "dtype_bytes must be 4 or 8");
+    if (nbatch < 1 || nbatch > 65535) return fail(MS_E_INVALID, "nbatch must be in [1, 65535]");
+    if (n < 1 || m < 1 || n > INT_MAX / 2 || m > INT_MAX / 2) return fail(MS_E_INVALID, "bad n or m");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (!(std::isfinite(h) && h > 0.0)) return fail(MS_E_INVALID, "h must be finite and > 0");
+    return MS_OK;
+}
+
+int ms_forward_update(const void* X, int32_t nbatch, int64_t n, const void* S_in, int64_t m, int32_t d,
+                      double h, void* S_out, int32_t dtype_bytes, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_diff(X, nbatch, n, S_in, m, d, h, dtype_bytes));
+    if (!S_out) return fail(MS_E_INVALID, "S_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    FMS_CHECK(ensure_pool_release_threshold());
+    Workspace ws(s);
+    char* w;
+    FMS_CHECK(ws.alloc(&w, adjoint_workspace_bytes(nbatch, (int)n, (int)m, d, dtype_bytes)));
+    FMS_HIP(launch_forward_update(X, nbatch, (int)n, S_in, (int)m, d, h, S_out, dtype_bytes, w, s));
+    return MS_OK;
+}
+
+int ms_step_adjoint(const void* X, int32_t nbatch, int64_t n, const void* S, int64_t m, int32_t d,
+                    double h, const void* G, void* dS, void* dX, int32_t dtype_bytes, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_diff(X, nbatch, n, S, m, d, h, dtype_bytes));
+    if (!G || !dS || !dX) return fail(MS_E_INVALID, "NULL gradient array");
+    hipStream_t s = (hipStream_t)stream;
+    FMS_CHECK(ensure_pool_release_threshold());
+    Workspace ws(s);
+    char* w;
+    FMS_CHECK(ws.alloc(&w, adjoint_workspace_bytes(nbatch, (int)n, (int)m, d, dtype_bytes)));
+    FMS_HIP(launch_step_adjoint(X, nbatch, (int)n, S, (int)m, d, h, G, dS, dX, dtype_bytes, w, s));
+    return MS_OK;
+}
+
+int ms_seed_draw(uint64_t* state, const int32_t* pool, int32_t len, int32_t count, int32_t* out) {
+    g_err.clear();
+    if (!state || !pool || !out) return fail(MS_E_INVALID, "NULL argument");
+    if (len < 0 || count < 0 || count > len) return fail(MS_E_INVALID, "need 0 <= count <= len");
+    std::vector<int32_t> pos((size_t)count);
+    draw_positions(state, len, count, pos.data());
+    for (int32_t t = 0; t < count; ++t) out[t] = pool[pos[t]];
+    return MS_OK;
+}
+
+const char* ms_last_error(void) { return g_err.c_str(); }
+
+const char* ms_version(void) { return "libfms 0.1 (gfx950)"; }
+
+}  // extern "C"

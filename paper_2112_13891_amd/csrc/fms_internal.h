@@ -1,0 +1,124 @@
+// fms_internal.h -- declarations shared by the host control code and the
+// kernel launchers of libfms.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/fms.h"
+
+namespace fms {
+
+// Seed status values (device and host).
+enum : uint8_t { ST_ACTIVE = 0, ST_CONVERGED = 1, ST_FAILED = 2 };
+
+// Merge decision state of a batch seed.
+enum : int32_t { MG_SKIP = -3, MG_UNDECIDED = -2, MG_FOUNDER = -1 };
+
+constexpr int kMaxIterCap = 4096;   // hard cap on max_iter / n_iter
+constexpr int kMaxMergePasses = 64;
+
+// Device-resident control block of one seed batch.  Written only by kernels
+// (single designated threads or integer atomics) and read back by the host
+// through a pinned mirror.
+struct Ctl {
+    int32_t count[3];          // active-list lengths, by iteration t % 3
+    int32_t need;              // early-stop threshold ceil(gamma*B); INT_MAX disables
+    int32_t iters_run;         // iterations that processed >= 1 seed
+    int32_t pool_len;          // seed pool length after compaction
+    int32_t spare[2];
+    long long pairs;           // sum of active seeds x n over iterations
+    long long refined;         // BF16 path: pairs recomputed in FP32
+    int32_t und[kMaxMergePasses];        // merge: undecided seeds after each pass
+    int32_t conv_it[kMaxIterCap + 2];    // seeds that converged at iteration t
+};
+
+// Geometry of the fused step for one dimension class.
+struct StepShape {
+    int D;      // coordinates computed per pair (>= d, padding is zero)
+    int DP;     // row stride of the packed point / seed arrays (floats)
+    int R;      // seeds per lane
+    int TS;     // seeds per tile = 64 * R
+};
+
+// Default shape for dimension d; step_shape_for() also picks R from the
+// batch size (fewer seeds per lane for small batches).
+StepShape step_shape(int d);
+StepShape step_shape_for(int d, int B);
+
+
+// Packed device state of one batch (all pointers device memory).
+struct Batch {
+    int n;                 // points
+    int d;                 // true dimension
+    int n_seeds;           // seeds in the batch (capacity of the seed arrays)
+    StepShape sh;
+    int kernel;            // ms_kernel
+    float h;
+    float scale;           // coordinate scale of the packed points
+    float thr2;            // (tol*h)^2 in original units
+    float inv_scale;       // 1/scale
+    const float* Xp;       // n x DP packed points (scaled, zero padded)
+    float* S;              // cap x DP seed positions (original units, padded)
+    int32_t* act[2];       // active seed lists
+    uint8_t* status;       // cap
+    int32_t* iters;        // cap
+    float* shift2;         // cap
+    float* part;           // chunk partials, one (D+1)-vector per seed and chunk
+    int grid;              // workgroups of the fused step
+    Ctl* ctl;
+};
+
+long long step_part_floats(const StepShape& sh, int B, int grid);
+
+// ---- launchers (k_step.hip) ----------------------------------------------
+hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale,
+                              float* Xp, hipStream_t s);
+hipError_t launch_seed_init_from_ids(const float* X, int d, int DP,
+                                     const int32_t* ids, int B, Batch& b,
+                                     hipStream_t s);
+hipError_t launch_seed_init_from_array(const float* seeds, const uint8_t* conv_in,
+                                       int d, int m, Batch& b, hipStream_t s);
+hipError_t launch_ctl_reset(Ctl* ctl, int B, int need, int max_iter, hipStream_t s);
+hipError_t launch_iteration(Batch& b, int t, hipStream_t s);
+hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv,
+                              int32_t* iters, float* shift2, hipStream_t s);
+int step_grid(const StepShape& sh, int B, int n);
+
+// ---- launchers (k_merge.hip) ---------------------------------------------
+hipError_t launch_iota(int32_t* a, int n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
+hipError_t launch_gather_ids(const int32_t* pool, const int32_t* pos, int B,
+                             int32_t* ids, uint8_t* removed, hipStream_t s);
+hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* status,
+                                  int B, const float* modes, int K_old, float r2,
+                                  int32_t* state, hipStream_t s);
+hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old,
+                                    float r2, int32_t* state, int32_t* und_counter,
+                                    hipStream_t s);
+hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len,
+                        const float* modes, int k0, int k1, float r2,
+                        uint8_t* removed, hipStream_t s);
+hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, int len,
+                               int32_t* pool_out, int32_t* block_tmp, Ctl* ctl,
+                               hipStream_t s);
+int pool_compact_blocks(int len);
+
+// ---- launchers (k_assign.hip) --------------------------------------------
+hipError_t launch_assign(const float* X, int n, int d, const float* modes, int k,
+                         int32_t* labels, float* margin, hipStream_t s);
+hipError_t launch_check_finite(const float* X, long long count, int32_t* flag,
+                               hipStream_t s);
+
+// ---- launchers (k_adjoint.hip) -------------------------------------------
+// ws: device workspace of adjoint_workspace_bytes() bytes.
+hipError_t launch_forward_update(const void* X, int nb, int n, const void* S, int m, int d,
+                                 double h, void* S_out, int bytes, void* ws, hipStream_t s);
+hipError_t launch_step_adjoint(const void* X, int nb, int n, const void* S, int m, int d,
+                               double h, const void* G, void* dS, void* dX, int bytes,
+                               void* ws, hipStream_t s);
+size_t adjoint_workspace_bytes(int nb, int n, int m, int d, int bytes);
+
+}  // namespace fms

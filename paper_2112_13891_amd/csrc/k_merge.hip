@@ -1,0 +1,321 @@
+// k_merge.hip -- round epilogue kernels: seed gather from the pool, greedy
+// mode merging ("prune modes", Algorithms 1-2), pool coverage and stable
+// pool compaction, for gfx950.
+//
+// Merge rule (greedy, in draw order): a converged seed joins the first mode
+// (lowest index) within r = merge_radius*h, else it founds a new mode at its
+// own final position.  Modes of earlier rounds precede every new one.
+//
+// The sequential rule is evaluated in parallel passes.  A seed i is decided
+// as soon as the first seed j < i (in index order) that lies within r and is
+// a founder or still undecided is a founder (i joins j), or when there is no
+// such j (i founds a mode).  The lowest undecided seed is always decidable,
+// every decision is final, and a stale read of "undecided" only postpones a
+// decision, so the passes reproduce the sequential greedy result exactly.
+
+#include "fms_internal.h"
+
+namespace fms {
+
+namespace {
+
+constexpr int kT = 256;
+
+__global__ void gather_ids_kernel(const int32_t* __restrict__ pool,
+                                  const int32_t* __restrict__ pos, int B, int32_t* ids,
+                                  uint8_t* removed) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B) return;
+    int p = pos[t];
+    ids[t] = pool[p];
+    removed[p] = 1;
+}
+
+__global__ void iota_kernel(int32_t* a, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = i;
+}
+
+__global__ void fill_u8_kernel(uint8_t* a, int n, uint8_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+template <int D>
+__device__ __forceinline__ float dist2(const float* a, const float* b) {
+    float q = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float t = a[k] - b[k];
+        q = fmaf(t, t, q);
+    }
+    return q;
+}
+
+// state[i]: MG_SKIP for seeds that did not converge; index of the first old
+// mode within r; or MG_UNDECIDED.
+template <int D>
+__global__ __launch_bounds__(kT) void first_old_kernel(const float* __restrict__ S, int DP,
+                                                       const uint8_t* __restrict__ status, int B,
+                                                       const float* __restrict__ modes, int K_old,
+                                                       float r2, int32_t* state) {
+    __shared__ float tileM[kT * D];
+    const int i = blockIdx.x * kT + threadIdx.x;
+    const bool live = i < B && status[i] == ST_CONVERGED;
+    float s[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) s[k] = live ? S[(long long)i * DP + k] : 0.0f;
+    int found = -1;
+    for (int base = 0; base < K_old; base += kT) {
+        const int cnt = min(kT, K_old - base);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * D; e += kT)
+            tileM[e] = modes[(long long)(base + e / D) * DP + e % D];
+        __syncthreads();
+        if (live && found < 0) {
+            for (int j = 0; j < cnt; ++j) {
+                if (dist2<D>(s, tileM + j * D) <= r2) {
+                    found = base + j;
+                    break;
+                }
+            }
+        }
+        if (__syncthreads_and(!live || found >= 0)) break;
+    }
+    if (i < B) state[i] = !live ? MG_SKIP : (found >= 0 ? found : MG_UNDECIDED);
+}
+
+// One decision pass.  Joined-to-batch-seed j is stored as K_old + j.
+template <int D>
+__global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S, int DP, int B,
+                                                    int K_old, float r2, int32_t* state,
+                                                    int32_t* und_counter) {
+    __shared__ float tileS[kT * D];
+    __shared__ int32_t tileSt[kT];
+    const int i = blockIdx.x * kT + threadIdx.x;
+    int st = (i < B) ? __atomic_load_n(&state[i], __ATOMIC_RELAXED) : MG_SKIP;
+    bool todo = (st == MG_UNDECIDED);
+    float s[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) s[k] = todo ? S[(long long)i * DP + k] : 0.0f;
+    int result = MG_UNDECIDED;
+    bool decided = !todo;
+    const int i_max = min(B, (int)(blockIdx.x + 1) * kT);   // largest i in block + 1
+    for (int base = 0; base < i_max; base += kT) {
+        if (__syncthreads_and(decided)) break;
+        const int cnt = min(kT, i_max - base);
+        for (int e = threadIdx.x; e < cnt * D; e += kT)
+            tileS[e] = S[(long long)(base + e / D) * DP + e % D];
+        if (threadIdx.x < cnt) tileSt[threadIdx.x] = __atomic_load_n(&state[base + threadIdx.x], __ATOMIC_RELAXED);
+        __syncthreads();
+        if (!decided) {
+            const int jend = min(cnt, i - base);
+            for (int j = 0; j < jend; ++j) {
+                const int sj = tileSt[j];
+                if (sj != MG_FOUNDER && sj != MG_UNDECIDED) continue;
+                if (dist2<D>(s, tileS + j * D) <= r2) {
+                    decided = true;
+                    result = (sj == MG_FOUNDER) ? (K_old + base + j) : MG_UNDECIDED;
+                    break;
+                }
+            }
+            if (!decided && base + cnt >= i) {   // scanned every j < i: no conflict
+                decided = true;
+                result = MG_FOUNDER;
+            }
+        }
+        __syncthreads();
+    }
+    if (todo) {
+        if (result != MG_UNDECIDED) __atomic_store_n(&state[i], result, __ATOMIC_RELAXED);
+    }
+    // count what is still undecided (one atomic per wave)
+    const bool still = todo && result == MG_UNDECIDED;
+    unsigned long long b = __ballot(still);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(und_counter, __popcll(b));
+}
+
+// Pool coverage: entries of the pool list within r of a new mode [k0, k1)
+// are marked removed.
+template <int D>
+__global__ __launch_bounds__(kT) void cover_kernel(const float* __restrict__ X, int d,
+                                                   const int32_t* __restrict__ pool, int len,
+                                                   const float* __restrict__ modes, int DP,
+                                                   int k0, int k1, float r2, uint8_t* removed) {
+    __shared__ float tileM[kT * D];
+    const int e = blockIdx.x * kT + threadIdx.x;
+    bool todo = e < len && !removed[e];
+    float x[D];
+    if (todo) {
+        const long long id = pool[e];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = (k < d) ? X[id * d + k] : 0.0f;
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = 0.0f;
+    }
+    bool hit = false;
+    for (int base = k0; base < k1; base += kT) {
+        if (__syncthreads_and(!todo || hit)) break;
+        const int cnt = min(kT, k1 - base);
+        for (int q = threadIdx.x; q < cnt * D; q += kT)
+            tileM[q] = modes[(long long)(base + q / D) * DP + q % D];
+        __syncthreads();
+        if (todo && !hit) {
+            for (int j = 0; j < cnt; ++j)
+                if (dist2<D>(x, tileM + j * D) <= r2) {
+                    hit = true;
+                    break;
+                }
+        }
+    }
+    if (todo && hit) removed[e] = 1;
+}
+
+constexpr int kCompactBlock = 1024;
+
+__global__ __launch_bounds__(kCompactBlock) void compact_count_kernel(
+    const uint8_t* __restrict__ removed, int len, int32_t* block_cnt) {
+    __shared__ int wsum[kCompactBlock / 64];
+    const int e = blockIdx.x * kCompactBlock + threadIdx.x;
+    const bool keep = e < len && !removed[e];
+    unsigned long long b = __ballot(keep);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kCompactBlock / 64; ++w) s += wsum[w];
+        block_cnt[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the block counts by one workgroup; writes the total.
+__global__ __launch_bounds__(1024) void compact_scan_kernel(int32_t* block_cnt, int nb,
+                                                            int32_t* total) {
+    __shared__ int32_t buf[1024];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        const int e = base + threadIdx.x;
+        const int v = e < nb ? block_cnt[e] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (e < nb) block_cnt[e] = carry + buf[threadIdx.x] - v;
+        const int blk_total = buf[1023];
+        __syncthreads();
+        carry += blk_total;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(
+    const int32_t* __restrict__ pool_in, const uint8_t* __restrict__ removed, int len,
+    const int32_t* __restrict__ block_off, int32_t* pool_out) {
+    __shared__ int wbase[kCompactBlock / 64];
+    const int e = blockIdx.x * kCompactBlock + threadIdx.x;
+    const bool keep = e < len && !removed[e];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned long long b = __ballot(keep);
+    if (lane == 0) wbase[w] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int q = 0; q < kCompactBlock / 64; ++q) {
+            int c = wbase[q];
+            wbase[q] = s;
+            s += c;
+        }
+    }
+    __syncthreads();
+    if (keep)
+        pool_out[block_off[blockIdx.x] + wbase[w] + __popcll(b & ((1ull << lane) - 1ull))] =
+            pool_in[e];
+}
+
+}  // namespace
+
+hipError_t launch_iota(int32_t* a, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_ids(const int32_t* pool, const int32_t* pos, int B, int32_t* ids,
+                             uint8_t* removed, hipStream_t s) {
+    hipLaunchKernelGGL(gather_ids_kernel, dim3((B + 255) / 256), dim3(256), 0, s, pool, pos, B,
+                       ids, removed);
+    return hipGetLastError();
+}
+
+#define FMS_DSWITCH(D_, CALL)                                 \
+    switch (D_) {                                             \
+        case 1: { constexpr int DD = 1; CALL; } break;        \
+        case 2: { constexpr int DD = 2; CALL; } break;        \
+        case 3: { constexpr int DD = 3; CALL; } break;        \
+        case 4: { constexpr int DD = 4; CALL; } break;        \
+        case 8: { constexpr int DD = 8; CALL; } break;        \
+        case 16: { constexpr int DD = 16; CALL; } break;      \
+        case 32: { constexpr int DD = 32; CALL; } break;      \
+        case 64: { constexpr int DD = 64; CALL; } break;      \
+        default: return hipErrorInvalidValue;                 \
+    }
+
+hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* status, int B,
+                                  const float* modes, int K_old, float r2, int32_t* state,
+                                  hipStream_t s) {
+    const int D = step_shape(d).D;
+    FMS_DSWITCH(D, hipLaunchKernelGGL((first_old_kernel<DD>), dim3((B + kT - 1) / kT),
+                                      dim3(kT), 0, s, S, DP, status, B, modes, K_old, r2,
+                                      state));
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old, float r2,
+                                    int32_t* state, int32_t* und_counter, hipStream_t s) {
+    const int D = step_shape(d).D;
+    FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD>), dim3((B + kT - 1) / kT), dim3(kT),
+                                      0, s, S, DP, B, K_old, r2, state, und_counter));
+    return hipGetLastError();
+}
+
+hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len, const float* modes,
+                        int k0, int k1, float r2, uint8_t* removed, hipStream_t s) {
+    if (len <= 0 || k1 <= k0) return hipSuccess;
+    const StepShape sh = step_shape(d);
+    FMS_DSWITCH(sh.D, hipLaunchKernelGGL((cover_kernel<DD>), dim3((len + kT - 1) / kT),
+                                         dim3(kT), 0, s, X, d, pool, len, modes, sh.DP, k0, k1,
+                                         r2, removed));
+    return hipGetLastError();
+}
+
+int pool_compact_blocks(int len) { return (len + kCompactBlock - 1) / kCompactBlock; }
+
+hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, int len,
+                               int32_t* pool_out, int32_t* block_tmp, Ctl* ctl, hipStream_t s) {
+    const int nb = pool_compact_blocks(len);
+    if (nb == 0) {
+        hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(1024), 0, s, block_tmp, 0,
+                           &ctl->pool_len);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(compact_count_kernel, dim3(nb), dim3(kCompactBlock), 0, s, removed, len,
+                       block_tmp);
+    hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(1024), 0, s, block_tmp, nb,
+                       &ctl->pool_len);
+    hipLaunchKernelGGL(compact_scatter_kernel, dim3(nb), dim3(kCompactBlock), 0, s, pool_in,
+                       removed, len, block_tmp, pool_out);
+    return hipGetLastError();
+}
+
+}  // namespace fms

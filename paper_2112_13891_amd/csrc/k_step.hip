@@ -1,0 +1,488 @@
+// k_step.hip -- the fused mean-shift iteration (FP32 form) for gfx950: the
+// pair work, the reduction, the update, the convergence test and the
+// compaction of the active seeds, in one or two launches per iteration.
+//
+// One iteration updates every active seed s_j by the kernel-weighted mean of
+// ALL n points (Section II-B; eq. (12)-(15) for the flat window):
+//     s_j' = s_j + sum_i w_ij (x_i - s_j) / sum_i w_ij .
+// The shift form is algebraically the plain m(s) = sum w x / sum w, but keeps
+// the FP32 accumulation on small numbers.  No m x n weight matrix exists: a
+// lane holds R seeds in registers, streams the points of its range through
+// wave-uniform (scalar) loads and keeps the weights in registers.
+//
+// Work decomposition, from the device-side active count m only (so every
+// seed's arithmetic depends on m alone and is bitwise reproducible, whatever
+// order the active list has):
+//   tiles  = ceil(m / TS), TS = 64 R seeds per tile;
+//   chunks = point ranges per tile;
+//   a workgroup (4 waves) takes one (tile, chunk); each wave a quarter of the
+//   chunk; the wave sums are added in wave order into one chunk partial.
+// Reduction without floating-point atomics or in-kernel cross-workgroup
+// traffic (the L2s of the eight XCDs are not coherent with each other, so a
+// device-scope fence inside a kernel costs an L2 write-back): when a tile has
+// a single chunk, its workgroup finalizes it directly; otherwise each
+// workgroup stores one (D+1)-vector partial per seed and a second kernel
+// gives every seed one wave, whose lanes add the chunk partials in a fixed
+// lane-strided order and then in a fixed shuffle tree.  Finalizing = the
+// update, the convergence test (|shift|^2 < (tol h)^2, the "while not
+// converge" of Algorithms 1-2) and the compaction of the seeds that stay
+// active (wave64 ballot, one atomic per wave, or one per seed in the
+// per-seed kernel).  The batch early-stop rule of Section II-C is applied at
+// the start of each launch from per-iteration converged counters.
+//
+// Gaussian weights use packed coordinates pre-scaled by
+// c = sqrt(log2(e) / (2 h^2)), so w = exp2(-|c x - c s|^2) is one v_exp_f32.
+
+#include "fms_internal.h"
+
+namespace fms {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMinChunk = 256;   // points per (tile, chunk) work item, at least
+constexpr int kMaxGrid = 2048;   // 8 workgroups of 4 waves on each of 256 CUs
+
+__device__ __forceinline__ int chunks_for(int m, int TS, int n, int grid) {
+    int tiles = (m + TS - 1) / TS;
+    if (tiles >= grid) return 1;
+    int c = grid / tiles;
+    int cmax = (n + kMinChunk - 1) / kMinChunk;
+    if (c > cmax) c = cmax;
+    return c < 1 ? 1 : c;
+}
+
+__device__ __forceinline__ int active_count(const Ctl* ctl, int t) {
+    // early stop (Section II-C): once `need` seeds converged, nothing is active
+    int conv = 0;
+    for (int u = 0; u < t; ++u) conv += ctl->conv_it[u];
+    return (conv >= ctl->need) ? 0 : ctl->count[t % 3];
+}
+
+__global__ void pack_points_kernel(const float* __restrict__ X, int n, int d, int DP,
+                                   float scale, float* __restrict__ Xp) {
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long total = (long long)n * DP;
+    if (e >= total) return;
+    int i = (int)(e / DP), k = (int)(e % DP);
+    Xp[e] = (k < d) ? X[(long long)i * d + k] * scale : 0.0f;
+}
+
+__global__ void ctl_reset_kernel(Ctl* ctl, int B, int need, int max_iter) {
+    for (int u = threadIdx.x; u <= max_iter; u += blockDim.x) ctl->conv_it[u] = 0;
+    if (threadIdx.x < kMaxMergePasses) ctl->und[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        ctl->count[0] = B;
+        ctl->count[1] = 0;
+        ctl->count[2] = 0;
+        ctl->need = need;
+        ctl->iters_run = 0;
+        ctl->pool_len = 0;
+        ctl->pairs = 0;
+        ctl->refined = 0;
+    }
+}
+
+__global__ void seed_init_ids_kernel(const float* __restrict__ X, int d, int DP,
+                                     const int32_t* __restrict__ ids, int B, float* S,
+                                     int32_t* act0, uint8_t* status, int32_t* iters,
+                                     float* shift2) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= B) return;
+    long long src = (long long)ids[j] * d;
+    for (int k = 0; k < DP; ++k) S[(long long)j * DP + k] = (k < d) ? X[src + k] : 0.0f;
+    act0[j] = j;
+    status[j] = ST_ACTIVE;
+    iters[j] = 0;
+    shift2[j] = __builtin_nanf("");
+}
+
+__global__ void seed_init_array_kernel(const float* __restrict__ seeds,
+                                       const uint8_t* __restrict__ conv_in, int d, int DP,
+                                       int m, float* S, int32_t* act0, uint8_t* status,
+                                       int32_t* iters, float* shift2, Ctl* ctl) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    bool live = false;
+    if (j < m) {
+        for (int k = 0; k < DP; ++k)
+            S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] : 0.0f;
+        uint8_t st = conv_in[j];
+        status[j] = st;
+        iters[j] = 0;
+        shift2[j] = __builtin_nanf("");
+        live = (st == ST_ACTIVE);
+    }
+    // wave64 ballot compaction of the seeds that start active
+    unsigned long long mask = __ballot(live);
+    int lane = threadIdx.x & 63;
+    int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == 0 && mask) base = atomicAdd(&ctl->count[0], __popcll(mask));
+    base = __shfl(base, 0);
+    if (live) act0[base + rank] = j;
+}
+
+struct StepArgs {
+    const float* Xp;
+    int n, d;
+    float* S;
+    const int32_t* act_in;
+    int32_t* act_out;
+    uint8_t* status;
+    int32_t* iters;
+    float* shift2;
+    float* part;
+    Ctl* ctl;
+    float h2, scale, inv_scale, thr2;
+};
+
+// Update and convergence test of one seed (slot of the active list) from its
+// sums a[0..D) = sum w (x - s) (packed units) and a[D] = sum w.  Returns
+// 1 if the seed stays active, 2 if it converged, 0 otherwise.
+template <int D, int DP>
+__device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const float* v) {
+    const int j = a.act_in[slot];
+    const float W = v[D];
+    if (!(W > 0.0f) || !isfinite(W)) {
+        a.status[j] = ST_FAILED;
+        return 0;
+    }
+    float sh2 = 0.0f;
+    float* sj = a.S + (long long)j * DP;
+    bool finite = true;
+    const float inv = a.inv_scale / W;
+    for (int k = 0; k < a.d; ++k) {
+        const float dk = v[k] * inv;
+        finite = finite && isfinite(dk);
+        sh2 = fmaf(dk, dk, sh2);
+        sj[k] = sj[k] + dk;
+    }
+    a.iters[j] += 1;
+    a.shift2[j] = sh2;
+    if (!finite) {
+        a.status[j] = ST_FAILED;
+        return 0;
+    }
+    if (sh2 < a.thr2) {
+        a.status[j] = ST_CONVERGED;
+        return 2;
+    }
+    return 1;
+}
+
+// Finalize the seeds of one tile from sums[k * TS + pos] (one lane per seed).
+template <int D, int DP, int R>
+__device__ void finalize_tile(const StepArgs& a, int t, int m, int tile, const float* sums) {
+    constexpr int TS = 64 * R;
+    const int pos = threadIdx.x;
+    const int slot = tile * TS + pos;
+    int res = 0;
+    if (pos < TS && slot < m) {
+        float v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = sums[k * TS + pos];
+        res = update_seed<D, DP>(a, slot, v);
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long keep = __ballot(res == 1);
+    const unsigned long long done = __ballot(res == 2);
+    int base = 0;
+    if (lane == 0) {
+        if (keep) base = atomicAdd(&a.ctl->count[(t + 1) % 3], __popcll(keep));
+        if (done) atomicAdd(&a.ctl->conv_it[t], __popcll(done));
+    }
+    base = __shfl(base, 0);
+    if (res == 1) a.act_out[base + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
+}
+
+// One iteration over the active seeds: pair work and chunk partials.
+template <int D, int DP, int R, int KERN>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
+    constexpr int TS = 64 * R;
+    constexpr int V = TS * (D + 1);   // values per tile partial
+    Ctl* ctl = a.ctl;
+    const int n = a.n;
+    const int m = active_count(ctl, t);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(t + 2) % 3] = 0;   // output of the next iteration
+        if (m > 0) {
+            ctl->pairs += (long long)m * n;
+            ctl->iters_run = t + 1;
+        }
+    }
+    if (m == 0) return;
+    const int G = gridDim.x;
+    const int tiles = (m + TS - 1) / TS;
+    const int chunks = chunks_for(m, TS, n, G);
+    // the wave index is uniform across a wave; saying so lets the point
+    // stream use scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    __shared__ float red[(kWaves - 1) * V];   // wave partials; then the tile sums
+
+    for (int item = blockIdx.x; item < tiles * chunks; item += G) {
+        const int tile = item % tiles;
+        const int chunk = item / tiles;
+        const long long lo = (long long)n * chunk / chunks;
+        const long long hi = (long long)n * (chunk + 1) / chunks;
+        const long long len = hi - lo;
+        const int p0 = (int)(lo + len * wave / kWaves);
+        const int p1 = (int)(lo + len * (wave + 1) / kWaves);
+
+        float s[R][D];
+        float acc[R][D + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int slot = tile * TS + r * 64 + lane;
+            const int j = a.act_in[slot < m ? slot : 0];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s[r][k] = a.S[(long long)j * DP + k] * a.scale;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
+        }
+
+        const float* __restrict__ xrow = a.Xp + (long long)p0 * DP;
+#pragma unroll 2
+        for (int p = p0; p < p1; ++p, xrow += DP) {
+            float x[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) x[k] = xrow[k];   // wave-uniform: scalar loads
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float dx[D];
+                float q = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    dx[k] = x[k] - s[r][k];
+                    q = fmaf(dx[k], dx[k], q);
+                }
+                float w;
+                if (KERN == MS_KERNEL_GAUSSIAN)
+                    w = __builtin_amdgcn_exp2f(-q);
+                else
+                    w = (q <= a.h2) ? 1.0f : 0.0f;
+                acc[r][D] += w;
+#pragma unroll
+                for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
+            }
+        }
+
+        // chunk partial: the four wave sums added in wave order
+        if (wave > 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) red[(wave - 1) * V + k * TS + r * 64 + lane] = acc[r][k];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) {
+                    float v = acc[r][k];
+#pragma unroll
+                    for (int w2 = 1; w2 < kWaves; ++w2) v += red[(w2 - 1) * V + k * TS + r * 64 + lane];
+                    acc[r][k] = v;
+                }
+        }
+        __syncthreads();
+
+        if (chunks == 1) {
+            // the chunk partial is the tile sum: finalize here
+            if (wave == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) red[k * TS + r * 64 + lane] = acc[r][k];
+            }
+            __syncthreads();
+            finalize_tile<D, DP, R>(a, t, m, tile, red);
+            __syncthreads();
+        } else if (wave == 0) {
+            // one (D+1)-vector per seed: part[(tile*chunks + chunk)*TS + pos][k]
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float* dst = a.part + (((long long)tile * chunks + chunk) * TS + r * 64 + lane) * (D + 1);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) dst[k] = acc[r][k];
+            }
+        }
+    }
+}
+
+// Per-seed reduction of the chunk partials and finalize (only when chunks > 1):
+// one wave per seed, grid-strided.
+template <int D, int DP, int R>
+__global__ __launch_bounds__(kThreads) void finalize_kernel(StepArgs a, int t, int grid) {
+    constexpr int TS = 64 * R;
+    const int m = active_count(a.ctl, t);
+    if (m == 0) return;
+    const int chunks = chunks_for(m, TS, a.n, grid);
+    if (chunks == 1) return;   // finalized inside the step kernel
+    const int lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (kThreads / 64);
+    for (int slot = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); slot < m; slot += nwaves) {
+        const int tile = slot / TS, pos = slot % TS;
+        float v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+        const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+        for (int c = lane; c < chunks; c += 64) {
+            const float* p = src + (long long)c * TS * (D + 1);
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] += p[k];
+        }
+        // fixed butterfly tree over the 64 lanes
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] += __shfl_xor(v[k], off);
+        if (lane == 0) {
+            const int res = update_seed<D, DP>(a, slot, v);
+            if (res == 1) a.act_out[atomicAdd(&a.ctl->count[(t + 1) % 3], 1)] = a.act_in[slot];
+            if (res == 2) atomicAdd(&a.ctl->conv_it[t], 1);
+        }
+    }
+}
+
+__global__ void seed_export_kernel(const float* __restrict__ S, int DP, int d, int m,
+                                   const uint8_t* __restrict__ status,
+                                   const int32_t* __restrict__ it,
+                                   const float* __restrict__ sh, float* seeds,
+                                   uint8_t* conv, int32_t* iters, float* shift2) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    for (int k = 0; k < d; ++k) seeds[(long long)j * d + k] = S[(long long)j * DP + k];
+    conv[j] = status[j];
+    iters[j] = it[j];
+    if (it[j] > 0) shift2[j] = sh[j];
+}
+
+template <int D, int DP, int R>
+hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
+    StepArgs a;
+    a.Xp = b.Xp;
+    a.n = b.n;
+    a.d = b.d;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    if (b.kernel == MS_KERNEL_GAUSSIAN)
+        hipLaunchKernelGGL((step_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(b.grid),
+                           dim3(kThreads), 0, s, a, t);
+    else
+        hipLaunchKernelGGL((step_kernel<D, DP, R, MS_KERNEL_FLAT>), dim3(b.grid), dim3(kThreads),
+                           0, s, a, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the per-seed reduction exits at once when the step kernel finalized
+    const int waves = b.n_seeds < 4096 ? b.n_seeds : 4096;
+    hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3((waves + 3) / 4), dim3(kThreads), 0, s,
+                       a, t, b.grid);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+StepShape step_shape(int d) {
+    StepShape sh;
+    if (d <= 4) sh.D = d;
+    else if (d <= 8) sh.D = 8;
+    else if (d <= 16) sh.D = 16;
+    else if (d <= 32) sh.D = 32;
+    else sh.D = 64;
+    sh.DP = sh.D < 4 ? 4 : sh.D;
+    sh.R = sh.D <= 4 ? 4 : (sh.D <= 8 ? 2 : 1);
+    sh.TS = 64 * sh.R;
+    return sh;
+}
+
+StepShape step_shape_for(int d, int B) {
+    StepShape sh = step_shape(d);
+    // small batches: fewer seeds per lane keeps lanes busy
+    while (sh.R > 1 && 64 * sh.R > B) sh.R /= 2;
+    sh.TS = 64 * sh.R;
+    return sh;
+}
+
+int step_grid(const StepShape& sh, int B, int n) {
+    long long tiles = (B + sh.TS - 1) / sh.TS;
+    long long chunks = (n + kMinChunk - 1) / kMinChunk;
+    long long g = tiles * chunks;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return (int)(g < 1 ? 1 : g);
+}
+
+long long step_part_floats(const StepShape& sh, int B, int grid) {
+    // items = tiles * chunks <= max(tiles, grid) with chunks > 1 only when tiles < grid
+    const long long tiles = (B + sh.TS - 1) / sh.TS;
+    const long long items = tiles < grid ? grid : tiles;
+    return items * sh.TS * (long long)(sh.D + 1);
+}
+
+hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale, float* Xp,
+                              hipStream_t s) {
+    long long total = (long long)n * DP;
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(pack_points_kernel, dim3(blocks), dim3(256), 0, s, X, n, d, DP, scale,
+                       Xp);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_reset(Ctl* ctl, int B, int need, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(256), 0, s, ctl, B, need, max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_init_from_ids(const float* X, int d, int DP, const int32_t* ids, int B,
+                                     Batch& b, hipStream_t s) {
+    hipLaunchKernelGGL(seed_init_ids_kernel, dim3((B + 255) / 256), dim3(256), 0, s, X, d, DP,
+                       ids, B, b.S, b.act[0], b.status, b.iters, b.shift2);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_init_from_array(const float* seeds, const uint8_t* conv_in, int d,
+                                       int m, Batch& b, hipStream_t s) {
+    hipLaunchKernelGGL(seed_init_array_kernel, dim3((m + 255) / 256), dim3(256), 0, s, seeds,
+                       conv_in, d, b.sh.DP, m, b.S, b.act[0], b.status, b.iters, b.shift2,
+                       b.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv,
+                              int32_t* iters, float* shift2, hipStream_t s) {
+    hipLaunchKernelGGL(seed_export_kernel, dim3((m + 255) / 256), dim3(256), 0, s, b.S,
+                       b.sh.DP, b.d, m, b.status, b.iters, b.shift2, seeds, conv, iters,
+                       shift2);
+    return hipGetLastError();
+}
+
+// One iteration: one launch of the fused step.
+hipError_t launch_iteration(Batch& b, int t, hipStream_t s) {
+    const int D = b.sh.D, R = b.sh.R;
+#define FMS_CASE(DD, DPP, RR) \
+    if (D == DD && R == RR) return launch_step_t<DD, DPP, RR>(b, t, s);
+    FMS_CASE(1, 4, 1) FMS_CASE(1, 4, 2) FMS_CASE(1, 4, 4)
+    FMS_CASE(2, 4, 1) FMS_CASE(2, 4, 2) FMS_CASE(2, 4, 4)
+    FMS_CASE(3, 4, 1) FMS_CASE(3, 4, 2) FMS_CASE(3, 4, 4)
+    FMS_CASE(4, 4, 1) FMS_CASE(4, 4, 2) FMS_CASE(4, 4, 4)
+    FMS_CASE(8, 8, 1) FMS_CASE(8, 8, 2)
+    FMS_CASE(16, 16, 1)
+    FMS_CASE(32, 32, 1)
+    FMS_CASE(64, 64, 1)
+#undef FMS_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fms

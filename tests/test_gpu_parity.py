@@ -1,0 +1,224 @@
+"""GPU parity of the HIP library against the FP64 oracle (through the C ABI).
+
+Inputs are the seeded synthetic workloads of paper_2112_13891_amd.workloads
+at the paper-shaped sizes (2-D blobs, 200K-point 3-D mixture, 262K-point
+32-D embedding mixture), plus small ragged and degenerate cases.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from parity import MARGIN_TOL, MODE_TOL, fit_parity, step_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2112_13891_amd import api, workloads  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def blobs():
+    return workloads.blobs2d(seed=0)
+
+
+@pytest.fixture(scope="module")
+def aniso():
+    return workloads.aniso3d(seed=0)
+
+
+@pytest.fixture(scope="module")
+def embed():
+    return workloads.embed32(seed=0)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+# ---------------------------------------------------------------------------
+# ms_step trajectories
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_step_blobs2d_all_seeds(orc, blobs, kernel):
+    say("step blobs2d", kernel)
+    X = _gpu(blobs.X)
+    S, conv, it, sh = api.step(X, X, blobs.h, kernel=kernel, tol=1e-3, n_iter=100)
+    torch.cuda.synchronize()
+    rep = step_parity(orc, blobs.X, blobs.X, blobs.h, kernel, 1e-3, S.cpu().numpy(),
+                      it.cpu().numpy(), conv.cpu().numpy())
+    say(rep)
+    assert (conv.cpu().numpy() == 1).all()
+
+
+def test_step_aniso3d_sample(orc, aniso):
+    say("step aniso3d sample")
+    rng = np.random.default_rng(1)
+    idx = rng.choice(aniso.n, 2000, replace=False)
+    X = _gpu(aniso.X)
+    S0 = aniso.X[idx]
+    S, conv, it, sh = api.step(X, _gpu(S0), aniso.h, n_iter=100)
+    torch.cuda.synchronize()
+    rep = step_parity(orc, aniso.X, S0, aniso.h, "gaussian", 1e-3, S.cpu().numpy(),
+                      it.cpu().numpy(), conv.cpu().numpy())
+    say(rep)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_step_embed32_sample(orc, embed, kernel):
+    say("step embed32 sample", kernel)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(embed.n, 96, replace=False)
+    X = _gpu(embed.X)
+    S0 = embed.X[idx]
+    S, conv, it, sh = api.step(X, _gpu(S0), embed.h, kernel=kernel, n_iter=100)
+    torch.cuda.synchronize()
+    rep = step_parity(orc, embed.X, S0, embed.h, kernel, 1e-3, S.cpu().numpy(),
+                      it.cpu().numpy(), conv.cpu().numpy())
+    say(rep)
+
+
+@pytest.mark.parametrize("n,d", [(1, 1), (2, 3), (3, 2), (255, 4), (257, 5), (1000, 7),
+                                 (1031, 8), (777, 13), (513, 16), (300, 33), (129, 64),
+                                 (4099, 3)])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_step_ragged_shapes(orc, n, d, kernel):
+    say("step ragged", n, d, kernel)
+    rng = np.random.default_rng(n * 100 + d)
+    X = (rng.standard_normal((n, d)) * 2.0).astype(np.float32)
+    m = min(n, 300)
+    S0 = X[rng.choice(n, m, replace=False)]
+    h = 1.5 * np.sqrt(d)
+    for n_iter in (1, 3):
+        S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=n_iter)
+        torch.cuda.synchronize()
+        ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
+        g = S.cpu().numpy()
+        git = it.cpu().numpy()
+        same = git == oit
+        assert same.mean() > 0.98
+        err = np.abs(g[same] - ref[same]).max() if same.any() else 0.0
+        assert err <= MODE_TOL * h, (n, d, kernel, n_iter, err)
+
+
+def test_step_respects_converged_flags(orc, blobs):
+    X = _gpu(blobs.X)
+    S0 = blobs.X[:64]
+    conv0 = np.zeros(64, np.uint8)
+    conv0[::3] = 1
+    S, conv, it, sh = api.step(X, _gpu(S0), blobs.h, n_iter=5, converged=_gpu(conv0))
+    torch.cuda.synchronize()
+    g = S.cpu().numpy()
+    assert np.array_equal(g[::3], S0[::3]) and (it.cpu().numpy()[::3] == 0).all()
+    assert (it.cpu().numpy()[1::3] > 0).all()
+
+
+# ---------------------------------------------------------------------------
+# ms_fit end to end
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("all_points", [False, True])
+def test_fit_blobs2d(orc, blobs, all_points):
+    say("fit blobs2d all_points", all_points)
+    g = api.fit(_gpu(blobs.X), blobs.h, all_points=all_points, trace=True)
+    ref = orc.fit(blobs.X, blobs.h, all_points=all_points)
+    rep = fit_parity(g, ref, blobs.X, blobs.h, orc=orc)
+    say(rep, "K", g.k, "rounds", g.round_N)
+    assert g.k == 5
+
+
+def test_fit_aniso3d_pool(orc, aniso):
+    say("fit aniso3d pool")
+    g = api.fit(_gpu(aniso.X), aniso.h, trace=True)
+    ref = orc.fit(aniso.X, aniso.h)
+    rep = fit_parity(g, ref, aniso.X, aniso.h, orc=orc)
+    say(rep, "K", g.k, "rounds", g.round_N.tolist(), "pairs", g.pairs, "ms", g.total_ms)
+
+
+def test_fit_flat_kernel_small(orc):
+    rng = np.random.default_rng(7)
+    C = rng.uniform(0, 50, (6, 3))
+    y = rng.integers(0, 6, 3000)
+    X = (C[y] + 0.8 * rng.standard_normal((3000, 3))).astype(np.float32)
+    for all_points in (False, True):
+        g = api.fit(_gpu(X), 2.5, kernel="flat", all_points=all_points, trace=True)
+        ref = orc.fit(X, 2.5, kernel="flat", all_points=all_points)
+        say(fit_parity(g, ref, X, 2.5, orc=orc, kernel="flat"))
+
+
+def test_fit_gamma_early_stop(orc, aniso):
+    X = aniso.X[:20000]
+    g = api.fit(_gpu(X), aniso.h, gamma=0.75, trace=True)
+    ref = orc.fit(X, aniso.h, gamma=0.75)
+    assert np.array_equal(g.round_T, ref.round_T)
+    say(fit_parity(g, ref, X, aniso.h, orc=orc))
+
+
+def test_fit_deterministic(aniso):
+    X = _gpu(aniso.X)
+    a = api.fit(X, aniso.h, trace=True)
+    b = api.fit(X, aniso.h, trace=True)
+    assert torch.equal(a.modes, b.modes) and torch.equal(a.labels, b.labels)
+    assert np.array_equal(a.drawn_final, b.drawn_final)
+
+
+def test_fit_capacity_and_no_modes(blobs):
+    X = _gpu(blobs.X)
+    with pytest.raises(api.MeanShiftError) as e:
+        api.fit(X, blobs.h, max_modes=3)
+    assert e.value.code == api.MS_E_CAPACITY and e.value.k == 5
+    with pytest.raises(api.MeanShiftError) as e:
+        api.fit(X, blobs.h, max_iter=1, tol=1e-9)
+    assert e.value.code == api.MS_E_NO_MODES
+
+
+def test_fit_nonfinite(blobs):
+    Xh = blobs.X.copy()
+    Xh[17, 1] = np.nan
+    with pytest.raises(api.MeanShiftError) as e:
+        api.fit(_gpu(Xh), blobs.h, check_finite=True)
+    assert e.value.code == api.MS_E_NONFINITE
+
+
+def test_fit_single_point_and_tiny():
+    X = _gpu(np.array([[1.5, -2.0, 3.0]], np.float32))
+    g = api.fit(X, 1.0, trace=True)
+    assert g.k == 1 and g.labels.cpu().tolist() == [0]
+    assert np.allclose(g.modes.cpu().numpy(), [[1.5, -2.0, 3.0]])
+
+
+# ---------------------------------------------------------------------------
+# ms_assign
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,d,k", [(200_000, 3, 50), (5000, 32, 300), (1001, 2, 1),
+                                   (3000, 64, 1500), (70_000, 16, 37)])
+def test_assign_parity(orc, n, d, k):
+    rng = np.random.default_rng(n + d + k)
+    X = (rng.standard_normal((n, d)) * 10).astype(np.float32)
+    M = X[rng.choice(n, k, replace=False)] + np.float32(0.01)
+    lab, mg = api.assign(_gpu(X), _gpu(M), margin=True)
+    torch.cuda.synchronize()
+    ol, om = orc.assign(X, M.astype(np.float64))
+    gl = lab.cpu().numpy()
+    diff = gl != ol
+    assert not (diff & (om >= 1e-5)).any()
+    gm = mg.cpu().numpy()
+    fin = np.isfinite(om)
+    assert np.allclose(gm[fin], om[fin], atol=1e-3 * 10) and (~np.isfinite(gm) == ~fin).all()
+
+
+def test_assign_ties_to_lowest_index():
+    X = _gpu(np.array([[0.0], [1.0], [2.0]], np.float32))
+    M = _gpu(np.array([[0.5], [1.5], [0.5]], np.float32))
+    assert api.assign(X, M).cpu().tolist() == [0, 0, 1]
