@@ -152,7 +152,9 @@ __device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const fl
     float* sj = a.S + (long long)j * DP;
     bool finite = true;
     const float inv = a.inv_scale / W;
-    for (int k = 0; k < a.d; ++k) {
+    // padded coordinates (k >= d) carry exact zeros, so looping to D is exact
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
         const float dk = v[k] * inv;
         finite = finite && isfinite(dk);
         sh2 = fmaf(dk, dk, sh2);
@@ -312,38 +314,91 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
     }
 }
 
-// Per-seed reduction of the chunk partials and finalize (only when chunks > 1):
-// one wave per seed, grid-strided.
+// Reduction of the chunk partials and finalize (only when chunks > 1), in
+// 1024-thread blocks.  Many chunks and few seeds: one wave per seed; its lanes
+// add the partials lane-strided, then in a fixed butterfly, and the block's 16
+// seeds are finalized by 16 lanes of wave 0 (one compaction atomic per block).
+// Otherwise one lane per seed adds its partials in chunk order and each wave
+// compacts its 64 seeds with one ballot and one atomic.
+constexpr int kFinThreads = 1024;
+constexpr int kFinWaves = kFinThreads / 64;
+
+template <int D, int DP>
+__device__ __forceinline__ void compact_wave(const StepArgs& a, int t, int slot, int res) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long keep = __ballot(res == 1);
+    const unsigned long long done = __ballot(res == 2);
+    int off = 0;
+    if (lane == 0) {
+        if (keep) off = atomicAdd(&a.ctl->count[(t + 1) % 3], __popcll(keep));
+        if (done) atomicAdd(&a.ctl->conv_it[t], __popcll(done));
+    }
+    off = __shfl(off, 0);
+    if (res == 1) a.act_out[off + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
+}
+
 template <int D, int DP, int R>
-__global__ __launch_bounds__(kThreads) void finalize_kernel(StepArgs a, int t, int grid) {
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t, int grid) {
     constexpr int TS = 64 * R;
     const int m = active_count(a.ctl, t);
     if (m == 0) return;
     const int chunks = chunks_for(m, TS, a.n, grid);
     if (chunks == 1) return;   // finalized inside the step kernel
     const int lane = threadIdx.x & 63;
-    const int nwaves = gridDim.x * (kThreads / 64);
-    for (int slot = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); slot < m; slot += nwaves) {
-        const int tile = slot / TS, pos = slot % TS;
-        float v[D + 1];
+    const int wave = threadIdx.x >> 6;
+    __shared__ float sums[kFinWaves][D + 1];
+    if (chunks > 64 && m <= 8192) {
+        for (int base = blockIdx.x * kFinWaves; base < m; base += gridDim.x * kFinWaves) {
+            const int slot = base + wave;
+            if (slot < m) {
+                const int tile = slot / TS, pos = slot % TS;
+                float v[D + 1];
 #pragma unroll
-        for (int k = 0; k <= D; ++k) v[k] = 0.0f;
-        const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
-        for (int c = lane; c < chunks; c += 64) {
-            const float* p = src + (long long)c * TS * (D + 1);
+                for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+                const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+                for (int c = lane; c < chunks; c += 64) {
+                    const float* p = src + (long long)c * TS * (D + 1);
 #pragma unroll
-            for (int k = 0; k <= D; ++k) v[k] += p[k];
+                    for (int k = 0; k <= D; ++k) v[k] += p[k];
+                }
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) v[k] += __shfl_xor(v[k], off);
+                if (lane == 0) {
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) sums[wave][k] = v[k];
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                const int my = base + lane;
+                int res = 0;
+                if (lane < kFinWaves && my < m) res = update_seed<D, DP>(a, my, sums[lane]);
+                compact_wave<D, DP>(a, t, my, res);
+            }
+            __syncthreads();
         }
-        // fixed butterfly tree over the 64 lanes
+        return;
+    }
+    const int nwaves = gridDim.x * kFinWaves;
+    for (int base = (blockIdx.x * kFinWaves + wave) * 64; base < m; base += nwaves * 64) {
+        const int slot = base + lane;
+        int res = 0;
+        if (slot < m) {
+            const int tile = slot / TS, pos = slot % TS;
+            float v[D + 1];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1)
+            for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+            const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+            for (int c = 0; c < chunks; ++c) {
+                const float* p = src + (long long)c * TS * (D + 1);
 #pragma unroll
-            for (int k = 0; k <= D; ++k) v[k] += __shfl_xor(v[k], off);
-        if (lane == 0) {
-            const int res = update_seed<D, DP>(a, slot, v);
-            if (res == 1) a.act_out[atomicAdd(&a.ctl->count[(t + 1) % 3], 1)] = a.act_in[slot];
-            if (res == 2) atomicAdd(&a.ctl->conv_it[t], 1);
+                for (int k = 0; k <= D; ++k) v[k] += p[k];
+            }
+            res = update_seed<D, DP>(a, slot, v);
         }
+        compact_wave<D, DP>(a, t, slot, res);
     }
 }
 
@@ -386,10 +441,11 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
                            0, s, a, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the per-seed reduction exits at once when the step kernel finalized
-    const int waves = b.n_seeds < 4096 ? b.n_seeds : 4096;
-    hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3((waves + 3) / 4), dim3(kThreads), 0, s,
-                       a, t, b.grid);
+    // the reduction kernel exits at once when the step kernel finalized
+    int blocks = (b.n_seeds + kFinWaves - 1) / kFinWaves;
+    if (blocks > 512) blocks = 512;
+    hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3(blocks), dim3(kFinThreads), 0, s, a, t,
+                       b.grid);
     return hipGetLastError();
 }
 
