@@ -72,8 +72,11 @@ typedef struct {
                                  seeds converged (Section II-C); (0, 1] */
     int32_t n_initial;        /* initial seed count N (Section II-D: 128) */
     int32_t L;                /* stop once N >= L*M (Section II-D: 8) */
-    float refine_radius;      /* BF16 path: exact FP32 distance for pairs
-                                 whose lower bound is within refine_radius*h */
+    float refine_radius;      /* BF16 path: every pair that may lie within
+                                 refine_radius*h (rigorous bound on the bf16
+                                 estimate) gets the exact FP32 distance,
+                                 weight and accumulation; >= 1 is used for
+                                 the flat window */
     int32_t all_points_as_seeds; /* 1: Algorithm 1 (every point is a seed,
                                     one batch); 0: Algorithm 2 (pool) */
     int32_t check_finite;     /* 1: scan X for NaN/Inf first */
@@ -82,7 +85,7 @@ typedef struct {
 
 /* Fills *p with the defaults: h = 1, Gaussian, FP32, tol = 1e-3,
  * max_iter = 100, merge_radius = cover_radius = 1, gamma = 1,
- * n_initial = 128, L = 8, refine_radius = 2, pool mode, rng_seed = 0. */
+ * n_initial = 128, L = 8, refine_radius = 3, pool mode, rng_seed = 0. */
 void ms_default_params(ms_params *p);
 
 #define MS_DIAG_MAX_ROUNDS 64

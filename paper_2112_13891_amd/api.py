@@ -122,7 +122,7 @@ def _check(rc: int, k: int | None = None):
 
 def make_params(h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100,
                 merge_radius=1.0, cover_radius=1.0, gamma=1.0, n_initial=128, L=8,
-                refine_radius=2.0, all_points=False, rng_seed=0, check_finite=False) -> Params:
+                refine_radius=3.0, all_points=False, rng_seed=0, check_finite=False) -> Params:
     p = Params()
     lib().ms_default_params(ctypes.byref(p))
     p.h = float(h)
@@ -199,7 +199,7 @@ class FitResult:
 
 
 def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge_radius=1.0,
-        cover_radius=1.0, gamma=1.0, n_initial=128, L=8, refine_radius=2.0, all_points=False,
+        cover_radius=1.0, gamma=1.0, n_initial=128, L=8, refine_radius=3.0, all_points=False,
         rng_seed=0, check_finite=False, max_modes=None, labels=True, trace=False) -> FitResult:
     """Whole method on device-resident X (n x d float32).  ``trace`` also returns
     the drawn ids, per-seed iterations, status and final positions."""
@@ -244,7 +244,7 @@ def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge
 
 
 def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, converged=None,
-         refine_radius=2.0):
+         refine_radius=3.0):
     """Up to n_iter updates of the active seeds.  Returns new tensors
     (seeds, converged uint8, iters int32, shift2 float32)."""
     torch = _torch()

@@ -229,7 +229,7 @@ float packed_scale(const ms_params* p) {
 // and device (grown on demand, never shrunk).
 enum Slot {
     SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
-    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_COUNT
+    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_RANK, SL_GEOM, SL_SORTWS, SL_FEAT, SL_COUNT
 };
 
 struct DevCache {
@@ -361,9 +361,34 @@ float host_dist2(const float* a, const float* b, int d) {
     return q;
 }
 
+// Refine threshold of the BF16 form on E = -|x - s|^2 in packed units: pairs
+// within refine_radius * h are recomputed exactly (at least h for the flat
+// window, whose non-refined pairs get weight 0).
+float bf16_e_thr(const ms_params* p) {
+    if (p->kernel == MS_KERNEL_GAUSSIAN)
+        return -(float)((double)p->refine_radius * p->refine_radius * 1.4426950408889634 / 2.0);
+    const double rr = std::max(1.0, (double)p->refine_radius) * p->h;
+    return -(float)(rr * rr);
+}
+
+struct SortedPoints {
+    float* Xs = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* rank = nullptr;
+    float* geom = nullptr;
+    char* feat = nullptr;
+};
+
 void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_params* p,
-                float scale, const float* Xp, Ctl* ctl) {
+                float scale, const float* Xp, Ctl* ctl, const SortedPoints* sp = nullptr) {
     const float tolh = p->tol * p->h;
+    b.prec = p->precision;
+    b.Xs = sp ? sp->Xs : nullptr;
+    b.geom = sp ? sp->geom : nullptr;
+    b.pf = sp ? sp->feat : nullptr;
+    b.xv = sp ? sp->feat + (size_t)((n + 255) / 256) * 256 * 16 * 2 : nullptr;
+    b.e_thr = bf16_e_thr(p);
+    b.kappa = 1.0f / 1024.0f;
     b.n = n;
     b.d = d;
     b.n_seeds = B;
@@ -410,6 +435,20 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     float* Xp;
     FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_HIP(launch_pack_points(X, n, d, DP, scale, Xp, s));
+    const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
+    SortedPoints sp;
+    if (bf16) {
+        void* sws;
+        FMS_CHECK(cache_get(C, budget, SL_XS, (size_t)n * DP, &sp.Xs));
+        FMS_CHECK(cache_get(C, budget, SL_PERM, n, &sp.perm));
+        FMS_CHECK(cache_get(C, budget, SL_RANK, n, &sp.rank));
+        FMS_CHECK(cache_get(C, budget, SL_GEOM, (size_t)((n + 255) / 256) * kGeomStride, &sp.geom));
+        FMS_CHECK(cache_get(C, budget, SL_SORTWS, sort_workspace_bytes(n), (char**)&sws));
+        FMS_CHECK(cache_get(C, budget, SL_FEAT, bf16_feature_bytes(n), &sp.feat));
+        FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sws, s));
+        FMS_HIP(launch_invert_perm(sp.perm, n, sp.rank, s));
+        FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+    }
 
     int32_t* pool[2] = {nullptr, nullptr};
     uint8_t* removed = nullptr;
@@ -435,7 +474,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     uint64_t rng = p->rng_seed;
     long long N = p->n_initial;
     int K = 0, rounds = 0;
-    long long pairs = 0, drawn_total = 0;
+    long long pairs = 0, refined = 0, drawn_total = 0;
     double iterate_ms = 0.0, merge_ms = 0.0;
     int cur = 0;
     if (trace) std::fprintf(stderr, "[fms] fit n=%d d=%d setup %.3f ms\n", n, d, ms_since(t_start));
@@ -443,9 +482,9 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     for (;;) {
         const auto t_round = std::chrono::steady_clock::now();
         const int B = all ? n : (int)std::min<long long>(N, pool_len);
-        const StepShape sh = step_shape_for(d, B);
+        const StepShape sh = bf16 ? step_shape_bf16(d, B) : step_shape_for(d, B);
         Batch b;
-        fill_batch(b, n, d, B, sh, p, scale, Xp, nullptr);
+        fill_batch(b, n, d, B, sh, p, scale, Xp, nullptr, bf16 ? &sp : nullptr);
         const long long part_floats = step_part_floats(sh, B, b.grid);
         const RbLayout L = rb_layout(B, DP);
         char* rbuf;
@@ -476,6 +515,13 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             FMS_HIP(launch_gather_ids(pool[cur], dpos, B, bids, removed, s));
         }
         FMS_HIP(launch_seed_init_from_ids(X, d, DP, bids, B, b, s));
+        if (bf16) {
+            // seeds that are close in space share waves (and refine work)
+            if (all)
+                FMS_HIP(hipMemcpyAsync(b.act[0], sp.perm, (size_t)B * 4, hipMemcpyDeviceToDevice, s));
+            else
+                FMS_HIP(launch_seed_sort(bids, sp.rank, B, b.act[0], s));
+        }
         const int need = (int)std::ceil((double)p->gamma * (double)B);
         FMS_HIP(launch_ctl_reset(ctl, B, need, p->max_iter, s));
 
@@ -508,6 +554,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             iterate_ms += ms;
         }
         pairs += cs.pairs;
+        refined += cs.refined;
 
         // resolve: number the founders in seed order; a seed the device passes
         // left undecided gets the same rule here (all earlier seeds are decided
@@ -603,7 +650,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     if (diag) {
         diag->rounds = rounds;
         diag->pairs = pairs;
-        diag->refined_pairs = 0;
+        diag->refined_pairs = refined;
         diag->iterate_ms = iterate_ms;
         diag->merge_ms = merge_ms;
         if (diag->counts)
@@ -635,15 +682,27 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
               uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
-    const StepShape sh = step_shape_for(d, m);
+    const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
+    const StepShape sh = bf16 ? step_shape_bf16(d, m) : step_shape_for(d, m);
     const float scale = packed_scale(p);
     float* Xp;
     FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
     FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
+    SortedPoints sp;
+    if (bf16) {
+        char* sws;
+        FMS_CHECK(ws.alloc(&sp.Xs, (size_t)n * sh.DP));
+        FMS_CHECK(ws.alloc(&sp.perm, n));
+        FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * kGeomStride));
+        FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n)));
+        FMS_CHECK(ws.alloc(&sp.feat, bf16_feature_bytes(n)));
+        FMS_HIP(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
+        FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+    }
     Ctl* ctl;
     FMS_CHECK(ws.alloc(&ctl, 1));
     Batch b;
-    fill_batch(b, n, d, m, sh, p, scale, Xp, ctl);
+    fill_batch(b, n, d, m, sh, p, scale, Xp, ctl, bf16 ? &sp : nullptr);
     FMS_CHECK(ws.alloc(&b.S, (size_t)m * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], m));
     FMS_CHECK(ws.alloc(&b.act[1], m));
@@ -679,7 +738,7 @@ void ms_default_params(ms_params* p) {
     p->gamma = 1.0f;
     p->n_initial = 128;
     p->L = 8;
-    p->refine_radius = 2.0f;
+    p->refine_radius = 3.0f;
     p->all_points_as_seeds = 0;
     p->check_finite = 0;
 }
@@ -692,8 +751,8 @@ int ms_fit(const ms_params* p, const float* X, int64_t n, int32_t d, float* mode
     if (!modes) return fail(MS_E_INVALID, "modes is NULL");
     if (!k_out) return fail(MS_E_INVALID, "k_out is NULL");
     if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");
-    if (p->precision != MS_PREC_FP32)
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE is not available in this build");
+    if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 4 in this build");
     *k_out = 0;
     return fit_impl(p, X, (int)n, d, modes, max_modes, k_out, labels, diag, (hipStream_t)stream);
 }
@@ -707,8 +766,8 @@ int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* see
     if (n_iter < 0 || n_iter > kMaxIterCap) return fail(MS_E_INVALID, "n_iter must be in [0, 4096]");
     if (m == 0) return MS_OK;
     if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
-    if (p->precision != MS_PREC_FP32)
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE is not available in this build");
+    if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 4 in this build");
     return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
 }
 

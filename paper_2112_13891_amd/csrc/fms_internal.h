@@ -68,6 +68,13 @@ struct Batch {
     float* shift2;         // cap
     float* part;           // chunk partials, one (D+1)-vector per seed and chunk
     int grid;              // workgroups of the fused step
+    int prec;              // ms_precision
+    const float* Xs;       // BF16 form: points in Morton order (n x 4)
+    const float* geom;     // BF16 form: per 256-point block centre and radius
+    const void* pf;        // BF16 form: point features of the first product
+    const void* xv;        // BF16 form: point operand of the second product
+    float e_thr;           // BF16 form: refine threshold (packed units)
+    float kappa;           // BF16 form: error bound coefficient
     Ctl* ctl;
 };
 
@@ -86,6 +93,23 @@ hipError_t launch_iteration(Batch& b, int t, hipStream_t s);
 hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv,
                               int32_t* iters, float* shift2, hipStream_t s);
 int step_grid(const StepShape& sh, int B, int n);
+
+// ---- launchers (k_step_bf16.hip) -----------------------------------------
+StepShape step_shape_bf16(int d, int B);
+bool bf16_supported(int d);
+hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s);
+hipError_t launch_invert_perm(const int32_t* perm, int n, int32_t* rank, hipStream_t s);
+size_t bf16_feature_bytes(int n);
+hipError_t launch_bf16_features(const float* Xs, int n, int d, const float* geom, void* feat,
+                                hipStream_t s);
+hipError_t launch_seed_sort(const int32_t* ids, const int32_t* rank, int B, int32_t* act0,
+                            hipStream_t s);
+
+// ---- launchers (k_sort.hip) ----------------------------------------------
+constexpr int kGeomStride = 8;      // per-256-point block: centre[4], radius
+size_t sort_workspace_bytes(int n);
+hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
+                               float* geom, void* ws, hipStream_t s);
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);

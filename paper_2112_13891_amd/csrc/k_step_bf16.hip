@@ -1,0 +1,515 @@
+// k_step_bf16.hip -- the fused mean-shift iteration in the BF16+refine form
+// for gfx950 (D <= 4): the seed-point products on MFMA in bf16 with FP32
+// accumulation, an exact FP32 recompute for every pair that may lie within
+// refine_radius * h, and the weighted sums on MFMA as well.
+//
+// Same result as the FP32 step (the kernel-weighted mean over all n points,
+// Section II-B), computed as follows for a wave of 32 seeds and a block of 256
+// points (points in Morton order, centred on the block's reference c):
+//   E   = 2 x~.s~ - |x~|^2 - |s~|^2   (= -|x - s|^2 in packed units; x~ = x-c)
+//        one v_mfma_f32_32x32x16_bf16 per 32 points, the products split into
+//        bf16 hi/lo parts (x~h s~h + x~h s~l + x~l s~h) and the norms hi/lo;
+//   the estimate is off by at most kappa (R + |s~|)^2 (R = block radius), so
+//   every pair with E + kappa (R + |s~|)^2 >= -(refine_radius h)^2 (packed
+//   units) -- every pair that may lie within refine_radius * h -- is
+//   recomputed exactly as the FP32 step does it: direct-difference distance,
+//   FP32 weight, FP32 accumulation of w (x - s) and w;
+//   the remaining (far) pairs take their weight from the estimate (Gaussian;
+//   zero for the flat window), packed to bf16, and  sum_p w [x~h | x~l | 1]
+//   is accumulated by two more MFMAs per 32 points in FP32.
+// MFMA layouts (one wave): A (32x16) lane l holds row l%32, k = (l/32)*8..+8;
+// B (16x32) lane l holds k = (l/32)*8..+8, column l%32; C (32x32) lane l holds
+// column l%32 and rows 8(v/4) + 4(l/32) + v%4, v = 0..15.  The first product
+// puts points on rows and seeds on columns, so each lane already owns one
+// seed's weights for 16 points; using those 16 points, in that order, as the
+// K dimension of the second product needs no transpose: the point-side
+// operand of the second product is stored with the same K order.
+
+#include "step_common.h"
+
+namespace fms {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kB16Threads = 256;    // 4 waves x 32 seeds
+constexpr int kB16Seeds = 128;      // seeds per tile
+constexpr int kBlk = 256;           // points per staged block (one centre)
+
+struct Bf16Args {
+    StepArgs base;
+    const float* Xs;        // points in Morton order (n x 4, packed units)
+    const float* geom;      // per block: centre[4], radius
+    const __bf16* pf;       // per padded point: 16 first-product features
+    const __bf16* xv;       // per 32-point tile: second-product operand, K order
+    float e_thr;            // refine when E + eps >= e_thr
+    float kappa;            // error bound coefficient
+};
+
+__device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
+
+// Point-side operands, built once per fit from the sorted points and the
+// block centres.  pf[i][s]: s in [0,D) x~h, [D,2D) x~h, [2D,3D) x~l,
+// 3D: -|x~|^2 hi, 3D+1: -|x~|^2 lo, 3D+2 and 3D+3: 1 (padding points carry
+// -inf so that their weight is 0).  xv[tile][kb][hh][c][e]: column c of
+// [x~h | x~l | 1] for the point 16 kb + 8 (e/4) + 4 hh + e%4 of the tile.
+template <int D>
+__global__ void bf16_features_kernel(const float* __restrict__ Xs, int n, int npad,
+                                     const float* __restrict__ geom, __bf16* pf, __bf16* xv) {
+    constexpr int NCOL = 2 * D + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    const bool live = i < n;
+    const float* g = geom + (long long)(i / kBlk) * kGeomStride;
+    float xt[D], xh[D], xl[D], nx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xt[k] = live ? Xs[(long long)i * 4 + k] - g[k] : 0.0f;
+        xh[k] = bf(xt[k]);
+        xl[k] = bf(xt[k] - xh[k]);
+        nx = fmaf(xt[k], xt[k], nx);
+    }
+    const float nxh = bf(nx), nxl = bf(nx - nxh);
+    __bf16* out = pf + (long long)i * 16;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        float v = 0.0f;
+        if (s < D) v = xh[s];
+        else if (s < 2 * D) v = xh[s - D];
+        else if (s < 3 * D) v = xl[s - 2 * D];
+        else if (s == 3 * D) v = live ? -nxh : -__builtin_inff();
+        else if (s == 3 * D + 1) v = live ? -nxl : 0.0f;
+        else if (s < 3 * D + 4) v = 1.0f;
+        out[s] = (__bf16)v;
+    }
+    const int tile = i >> 5, p = i & 31;
+    const int kb = p >> 4, r = p & 15, hh = (r >> 2) & 1, e = ((r >> 3) << 2) | (r & 3);
+    __bf16* o2 = xv + (long long)tile * 512 + ((kb * 2 + hh) * 16) * 8 + e;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        float v = 0.0f;
+        if (c < D) v = xh[c];
+        else if (c < 2 * D) v = xl[c - D];
+        else if (c < NCOL) v = live ? 1.0f : 0.0f;
+        o2[c * 8] = (__bf16)v;
+    }
+}
+
+// Exact FP32 contribution of pair (seed shat, point row v of this lane) when
+// flagged; returns 1 if it was recomputed.
+template <int D, int KERN>
+__device__ __forceinline__ void refine_rows(const float4* __restrict__ xs4, const f32x16& E, float eps,
+                                            float e_thr, float h2, const float* shat, float* w,
+                                            float* aex, float& wex, unsigned& refined) {
+    unsigned need = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) need |= (E[v] + eps >= e_thr) ? (1u << v) : 0u;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        if (need & (1u << v)) {
+            const float4 x4 = xs4[8 * (v >> 2) + (v & 3)];
+            const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
+            float dx[D], q = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                dx[k] = xv[k] - shat[k];
+                q = fmaf(dx[k], dx[k], q);
+            }
+            const float we = (KERN == MS_KERNEL_GAUSSIAN) ? __builtin_amdgcn_exp2f(-q)
+                                                          : (q <= h2 ? 1.0f : 0.0f);
+            wex += we;
+#pragma unroll
+            for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
+            w[v] = 0.0f;   // not in the bf16 sums
+        }
+    }
+    refined += __popc(need);
+}
+
+// Seed features of the first product relative to a block centre.
+template <int D>
+__device__ __forceinline__ bf16x8 seed_frag(const float* st, float ns, int hf) {
+    float sh[D], sl[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        sh[k] = bf(st[k]);
+        sl[k] = bf(st[k] - sh[k]);
+    }
+    const float nsh = bf(ns), nsl = bf(ns - nsh);
+    auto slot_val = [&](const int s2) -> float {
+        if (s2 < D) return 2.0f * sh[s2 < D ? s2 : 0];
+        if (s2 < 2 * D) return 2.0f * sl[s2 - D < D ? s2 - D : 0];
+        if (s2 < 3 * D) return 2.0f * sh[s2 - 2 * D < D ? s2 - 2 * D : 0];
+        if (s2 < 3 * D + 2) return 1.0f;
+        if (s2 == 3 * D + 2) return -nsh;
+        if (s2 == 3 * D + 3) return -nsl;
+        return 0.0f;
+    };
+    bf16x8 f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const float lo = slot_val(q), hi = slot_val(8 + q);
+        f[q] = (__bf16)(hf ? hi : lo);
+    }
+    return f;
+}
+
+// Bytes of point operands per 256-point block: first product 256 x 32 B,
+// second product 8 tiles x 512 B.
+constexpr int kPfBytes = kBlk * 16 * 2;
+constexpr int kXvBytes = (kBlk / 32) * 512 * 2;
+constexpr int kStageVecs = (kPfBytes + kXvBytes) / 16 / kB16Threads;   // 16-byte loads per thread
+
+template <int D, int KERN, int R>
+__global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int t) {
+    constexpr int TS = kB16Seeds * R;   // 4 waves x R groups x 32 seeds
+    constexpr int NCOL = 2 * D + 1;     // [x~h | x~l | 1]
+    const StepArgs& a = A.base;
+    Ctl* ctl = a.ctl;
+    const int n = a.n;
+    const int m = active_count(ctl, t);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->count[(t + 2) % 3] = 0;
+        if (m > 0) {
+            ctl->pairs += (long long)m * n;
+            ctl->iters_run = t + 1;
+        }
+    }
+    if (m == 0) return;
+    const int G = gridDim.x;
+    const int tiles = (m + TS - 1) / TS;
+    const int chunks = chunks_for(m, TS, n, G);
+    const int nblk = (n + kBlk - 1) / kBlk;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 31, hf = lane >> 5;
+
+    __shared__ __attribute__((aligned(16))) char stage[kPfBytes + kXvBytes];
+    __shared__ float tr[kB16Threads / 64][NCOL][32];   // per-wave transpose
+    __shared__ float fin[(D + 1) * TS];
+    const __bf16* spf = reinterpret_cast<const __bf16*>(stage);
+    const __bf16* sxv = reinterpret_cast<const __bf16*>(stage + kPfBytes);
+    unsigned refined = 0;
+
+    for (int item = blockIdx.x; item < tiles * chunks; item += G) {
+        const int tile = item % tiles;
+        const int chunk = item / tiles;
+        const int b0 = (int)((long long)nblk * chunk / chunks);
+        const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
+        float shat[R][D], arun[R][D], aex[R][D], wrun[R], wex[R];
+#pragma unroll
+        for (int g = 0; g < R; ++g) {
+            const int slot = tile * TS + (wave * R + g) * 32 + col;
+            const int j = a.act_in[slot < m ? slot : 0];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                shat[g][k] = a.S[(long long)j * 4 + k] * a.scale;
+                arun[g][k] = aex[g][k] = 0.0f;
+            }
+            wrun[g] = wex[g] = 0.0f;
+        }
+        // operands of the first block of the chunk: 512 + 512 16-byte vectors,
+        // four per thread (two of each product)
+        static_assert(kStageVecs == 4 && kPfBytes / 16 == 2 * kB16Threads &&
+                      kXvBytes / 16 == 2 * kB16Threads, "stage layout");
+        uint4 n0, n1, n2, n3;
+        {
+            const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)b0 * kBlk * 16);
+            const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)b0 * (kBlk / 32) * 512);
+            n0 = pfg[threadIdx.x];
+            n1 = pfg[kB16Threads + threadIdx.x];
+            n2 = xvg[threadIdx.x];
+            n3 = xvg[kB16Threads + threadIdx.x];
+        }
+
+        for (int blk = b0; blk < b1; ++blk) {
+            __syncthreads();   // the previous block's operands are no longer read
+            reinterpret_cast<uint4*>(stage)[threadIdx.x] = n0;
+            reinterpret_cast<uint4*>(stage)[kB16Threads + threadIdx.x] = n1;
+            reinterpret_cast<uint4*>(stage)[2 * kB16Threads + threadIdx.x] = n2;
+            reinterpret_cast<uint4*>(stage)[3 * kB16Threads + threadIdx.x] = n3;
+            __syncthreads();
+            if (blk + 1 < b1) {   // next block's operands travel while this one computes
+                const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)(blk + 1) * kBlk * 16);
+                const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)(blk + 1) * (kBlk / 32) * 512);
+                n0 = pfg[threadIdx.x];
+                n1 = pfg[kB16Threads + threadIdx.x];
+                n2 = xvg[threadIdx.x];
+                n3 = xvg[kB16Threads + threadIdx.x];
+            }
+            const float* gm = A.geom + (long long)blk * kGeomStride;
+            float st[R][D], eps[R];
+            bf16x8 sfrag[R];
+#pragma unroll
+            for (int g = 0; g < R; ++g) {
+                float ns = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    st[g][k] = shat[g][k] - gm[k];
+                    ns = fmaf(st[g][k], st[g][k], ns);
+                }
+                const float rr = gm[4] + sqrtf(ns);
+                eps[g] = A.kappa * rr * rr;
+                sfrag[g] = seed_frag<D>(st[g], ns, hf);
+            }
+            f32x16 out[R];
+            bool used[R];
+#pragma unroll
+            for (int g = 0; g < R; ++g) {
+                out[g] = f32x16{};
+                used[g] = false;
+            }
+            const float4* xsb = reinterpret_cast<const float4*>(A.Xs) + (long long)blk * kBlk + 4 * hf;
+#pragma unroll 1
+            for (int tt = 0; tt < kBlk / 32; ++tt) {
+                const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(spf + (tt * 32 + col) * 16 + hf * 8);
+#pragma unroll
+                for (int g = 0; g < R; ++g) {
+                    f32x16 E = {};
+                    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag[g], E, 0, 0, 0);
+                    float emax = E[0];
+#pragma unroll
+                    for (int v = 1; v < 16; ++v) emax = fmaxf(emax, E[v]);
+                    float w[16];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) w[v] = 0.0f;
+                    if (__ballot(emax + eps[g] >= A.e_thr))
+                        refine_rows<D, KERN>(xsb + tt * 32, E, eps[g], A.e_thr, a.h2,
+                                             shat[g], w, aex[g], wex[g], refined);
+                    // far pairs (Gaussian only): weights from the estimate, unless
+                    // every weight of the lane underflows (2^-127)
+                    if (KERN == MS_KERNEL_GAUSSIAN && __ballot(emax >= -127.0f)) {
+                        // refined rows keep w = 0: recompute their mask cheaply
+#pragma unroll
+                        for (int v = 0; v < 16; ++v)
+                            if (!(E[v] + eps[g] >= A.e_thr)) w[v] = __builtin_amdgcn_exp2f(E[v]);
+                        bf16x8 w0, w1;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            w0[q] = (__bf16)w[q];
+                            w1[q] = (__bf16)w[8 + q];
+                        }
+                        bf16x8 x0 = {}, x1 = {};
+                        if (col < NCOL) {
+                            x0 = *reinterpret_cast<const bf16x8*>(sxv + tt * 512 + ((0 * 2 + hf) * 16 + col) * 8);
+                            x1 = *reinterpret_cast<const bf16x8*>(sxv + tt * 512 + ((1 * 2 + hf) * 16 + col) * 8);
+                        }
+                        out[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, x0, out[g], 0, 0, 0);
+                        out[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, x1, out[g], 0, 0, 0);
+                        used[g] = true;
+                    }
+                }
+            }
+            // ---- out[seed row][col] -> per-seed sums through a wave-local
+            // transpose (LDS operations of one wave complete in order)
+#pragma unroll
+            for (int g = 0; g < R; ++g) {
+                if (!__ballot(used[g])) continue;
+                if (col < NCOL) {
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) tr[wave][col][8 * (v >> 2) + 4 * hf + (v & 3)] = out[g][v];
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                const float Wb = tr[wave][2 * D][col];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const float sx = tr[wave][k][col] + tr[wave][D + k][col];
+                    // sum w (x~ - s~) = sum w (x - s): the block centre cancels
+                    arun[g][k] += sx - st[g][k] * Wb;
+                }
+                wrun[g] += Wb;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            }
+        }
+
+        // ---- chunk partials (one (D+1)-vector per seed): the two lane halves
+        // saw different points of the same seed
+#pragma unroll
+        for (int g = 0; g < R; ++g) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                aex[g][k] += __shfl_xor(aex[g][k], 32);
+                arun[g][k] += aex[g][k];
+            }
+            wex[g] += __shfl_xor(wex[g], 32);
+            wrun[g] += wex[g];
+        }
+        if (chunks == 1) {
+            if (hf == 0) {
+#pragma unroll
+                for (int g = 0; g < R; ++g) {
+                    const int pos = (wave * R + g) * 32 + col;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) fin[k * TS + pos] = arun[g][k];
+                    fin[D * TS + pos] = wrun[g];
+                }
+            }
+            __syncthreads();
+            finalize_tile<D, 4, R * 2>(a, t, m, tile, fin);
+            __syncthreads();
+        } else if (hf == 0) {
+#pragma unroll
+            for (int g = 0; g < R; ++g) {
+                const int pos = (wave * R + g) * 32 + col;
+                float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
+#pragma unroll
+                for (int k = 0; k < D; ++k) dst[k] = arun[g][k];
+                dst[D] = wrun[g];
+            }
+        }
+    }
+    // refined pairs: lane counts summed per wave, one atomic per wave
+    for (int off = 32; off >= 1; off >>= 1) refined += __shfl_xor(refined, off);
+    if (lane == 0 && refined)
+        atomicAdd((unsigned long long*)&ctl->refined, (unsigned long long)refined);
+}
+
+// Seed order for a batch: sort the batch slots by the seeds' positions in the
+// Morton order of the points (rank[id]), so the 32 seeds of a wave are close
+// together and share refine work.  One workgroup, bitonic sort, B <= 4096.
+constexpr int kSeedSortMax = 4096;
+
+__global__ __launch_bounds__(1024) void seed_sort_kernel(const int32_t* __restrict__ ids,
+                                                         const int32_t* __restrict__ rank, int B,
+                                                         int32_t* act0) {
+    __shared__ unsigned long long key[kSeedSortMax];
+    int P = 1;
+    while (P < B) P <<= 1;
+    for (int e = threadIdx.x; e < P; e += 1024)
+        key[e] = e < B ? (((unsigned long long)(unsigned)rank[ids[e]] << 32) | (unsigned)e)
+                       : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = threadIdx.x; e < P; e += 1024) {
+                const int o = e ^ stride;
+                if (o > e) {
+                    const bool up = (e & size) == 0;
+                    const unsigned long long x = key[e], y = key[o];
+                    if ((x > y) == up) {
+                        key[e] = y;
+                        key[o] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < B; e += 1024) act0[e] = (int32_t)(key[e] & 0xffffffffu);
+}
+
+__global__ void invert_perm_kernel(const int32_t* __restrict__ perm, int n, int32_t* rank) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rank[perm[i]] = i;
+}
+
+template <int D, int R>
+hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
+    Bf16Args A;
+    StepArgs& a = A.base;
+    a.Xp = b.Xp;
+    a.n = b.n;
+    a.d = b.d;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    A.Xs = b.Xs;
+    A.geom = b.geom;
+    A.pf = (const __bf16*)b.pf;
+    A.xv = (const __bf16*)b.xv;
+    A.e_thr = b.e_thr;
+    A.kappa = b.kappa;
+    if (b.kernel == MS_KERNEL_GAUSSIAN)
+        hipLaunchKernelGGL((step_bf16_kernel<D, MS_KERNEL_GAUSSIAN, R>), dim3(b.grid),
+                           dim3(kB16Threads), 0, s, A, t);
+    else
+        hipLaunchKernelGGL((step_bf16_kernel<D, MS_KERNEL_FLAT, R>), dim3(b.grid), dim3(kB16Threads),
+                           0, s, A, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int blocks = (b.n_seeds + kFinWaves - 1) / kFinWaves;
+    if (blocks > 512) blocks = 512;
+    hipLaunchKernelGGL((finalize_kernel<D, 4, 2 * R>), dim3(blocks), dim3(kFinThreads), 0, s, a, t,
+                       b.grid);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+StepShape step_shape_bf16(int d, int B) {
+    StepShape sh = step_shape(d);
+    // 4 waves x R groups of 32 seeds; R = 2 once the batch fills it
+    const int groups = B >= 2 * kB16Seeds ? 2 : 1;
+    sh.R = 2 * groups;     // the finalize geometry: TS = 64 * R
+    sh.TS = kB16Seeds * groups;
+    return sh;
+}
+
+bool bf16_supported(int d) { return d >= 1 && d <= 4; }
+
+hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s) {
+    const bool two = b.sh.TS == 2 * kB16Seeds;
+    switch (b.sh.D) {
+        case 1: return two ? launch_bf16_t<1, 2>(b, t, s) : launch_bf16_t<1, 1>(b, t, s);
+        case 2: return two ? launch_bf16_t<2, 2>(b, t, s) : launch_bf16_t<2, 1>(b, t, s);
+        case 3: return two ? launch_bf16_t<3, 2>(b, t, s) : launch_bf16_t<3, 1>(b, t, s);
+        case 4: return two ? launch_bf16_t<4, 2>(b, t, s) : launch_bf16_t<4, 1>(b, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t bf16_feature_bytes(int n) {
+    const size_t npad = (size_t)((n + kBlk - 1) / kBlk) * kBlk;
+    return npad * 16 * 2 + npad * 16 * 2;   // pf + xv (16 bf16 per point each)
+}
+
+hipError_t launch_bf16_features(const float* Xs, int n, int d, const float* geom, void* feat,
+                                hipStream_t s) {
+    const int npad = (n + kBlk - 1) / kBlk * kBlk;
+    __bf16* pf = (__bf16*)feat;
+    __bf16* xv = pf + (size_t)npad * 16;
+    switch (step_shape(d).D) {
+#define FMS_CASE(DD)                                                                              \
+    case DD:                                                                                       \
+        hipLaunchKernelGGL(bf16_features_kernel<DD>, dim3((npad + 255) / 256), dim3(256), 0, s, Xs, \
+                           n, npad, geom, pf, xv);                                                 \
+        break;
+        FMS_CASE(1)
+        FMS_CASE(2)
+        FMS_CASE(3)
+        FMS_CASE(4)
+#undef FMS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_perm(const int32_t* perm, int n, int32_t* rank, hipStream_t s) {
+    hipLaunchKernelGGL(invert_perm_kernel, dim3((n + 255) / 256), dim3(256), 0, s, perm, n, rank);
+    return hipGetLastError();
+}
+
+// Order the batch's active list by the seeds' Morton rank (B <= 4096; larger
+// batches keep draw order, which only costs refine work).
+hipError_t launch_seed_sort(const int32_t* ids, const int32_t* rank, int B, int32_t* act0,
+                            hipStream_t s) {
+    if (B < 2 || B > kSeedSortMax) return hipSuccess;
+    hipLaunchKernelGGL(seed_sort_kernel, dim3(1), dim3(1024), 0, s, ids, rank, B, act0);
+    return hipGetLastError();
+}
+
+}  // namespace fms
