@@ -1,0 +1,110 @@
+"""GPU checks of the differentiable form: ms_forward_update and
+ms_step_adjoint against the FP64 autograd reference, torch gradcheck in FP64
+through MeanShiftT, FP32 accuracy, checkpointing and batching."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import adjoint as adj  # noqa: E402
+from paper_2112_13891_amd import api, workloads  # noqa: E402
+from paper_2112_13891_amd.autograd import MeanShiftT  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _cloud(seed, n, d, k=3):
+    rng = np.random.default_rng(seed)
+    C = 3.0 * rng.standard_normal((k, d))
+    y = rng.integers(0, k, n)
+    X = C[y] + 0.4 * rng.standard_normal((n, d))
+    return X, C, y
+
+
+@pytest.mark.parametrize("n,m,d", [(300, 300, 4), (257, 31, 16), (64, 200, 3), (1, 1, 1), (500, 77, 33)])
+def test_forward_update_fp64(n, m, d):
+    rng = np.random.default_rng(n + m + d)
+    X = rng.standard_normal((n, d)) * 2
+    S = rng.standard_normal((m, d)) * 2
+    h = 1.2
+    ref = adj.update(torch.from_numpy(X), torch.from_numpy(S), h)
+    got = api.forward_update(torch.from_numpy(X).to(DEV), torch.from_numpy(S).to(DEV), h).cpu()
+    assert (got - ref).abs().max() < 1e-11
+
+
+@pytest.mark.parametrize("n,m,d", [(300, 300, 4), (129, 40, 16), (77, 5, 2)])
+def test_step_adjoint_fp64(n, m, d):
+    rng = np.random.default_rng(10 * n + m + d)
+    X = torch.from_numpy(rng.standard_normal((n, d)) * 1.5)
+    S = torch.from_numpy(rng.standard_normal((m, d)) * 1.5)
+    G = torch.from_numpy(rng.standard_normal((m, d)))
+    h = 0.8
+    rS, rX = adj.grad_step(X, S, h, G)
+    dS, dX = api.step_adjoint(X.to(DEV), S.to(DEV), h, G.to(DEV))
+    assert (dS.cpu() - rS).abs().max() < 1e-10 * (1 + rS.abs().max())
+    assert (dX.cpu() - rX).abs().max() < 1e-10 * (1 + rX.abs().max())
+
+
+def test_gradcheck_fp64_256x4():
+    X, C, y = _cloud(0, 256, 4)
+    Xt = torch.from_numpy(X).to(DEV).requires_grad_(True)
+    f = lambda A: MeanShiftT.apply(A, 1.0, 10)
+    assert torch.autograd.gradcheck(f, (Xt,), eps=1e-6, atol=1e-6, rtol=1e-4, fast_mode=True)
+
+
+def test_gradcheck_fp64_full_small():
+    X, C, y = _cloud(1, 24, 4)
+    Xt = torch.from_numpy(X).to(DEV).requires_grad_(True)
+    f = lambda A: MeanShiftT.apply(A, 1.0, 5)
+    assert torch.autograd.gradcheck(f, (Xt,), eps=1e-6, atol=1e-6, rtol=1e-4)
+
+
+def test_unrolled_loss_gradient_vs_reference():
+    X, C, y = _cloud(2, 400, 16, k=5)
+    T, h = 10, 1.0
+    Lr, gr = adj.grad_unrolled(torch.from_numpy(X), h, T, torch.from_numpy(C), torch.from_numpy(y))
+    for dtype, tol in ((torch.float64, 1e-9), (torch.float32, 2e-3)):
+        Xt = torch.from_numpy(X).to(DEV, dtype).requires_grad_(True)
+        S = MeanShiftT.apply(Xt, h, T)
+        L = ((S - torch.from_numpy(C).to(DEV, dtype)[torch.from_numpy(y).to(DEV)]) ** 2).sum()
+        L.backward()
+        g = Xt.grad.double().cpu()
+        rel = float((g - gr).abs().max() / gr.abs().max())
+        say(dtype, "loss", float(L), float(Lr), "grad rel err", rel)
+        assert rel < tol
+        assert abs(float(L) - float(Lr)) <= tol * abs(float(Lr)) + 1e-9
+
+
+def test_checkpointing_is_exact():
+    X, C, y = _cloud(3, 300, 8)
+    Xt = torch.from_numpy(X).to(DEV, torch.float32)
+    grads = []
+    for every in (1, 3, 10):
+        A = Xt.clone().requires_grad_(True)
+        S = MeanShiftT.apply(A, 1.0, 7, every)
+        S.pow(2).sum().backward()
+        grads.append(A.grad.clone())
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])
+
+
+def test_batched_equals_per_cloud():
+    clouds = workloads.diffclouds(seed=0, n_clouds=3, n=500, d=16)
+    Xb = torch.stack([torch.from_numpy(c[0]) for c in clouds]).to(DEV)
+    out = api.forward_update(Xb, Xb, 1.0)
+    for b in range(3):
+        one = api.forward_update(Xb[b], Xb[b], 1.0)
+        assert torch.equal(out[b], one)
+    G = torch.randn_like(Xb)
+    dS, dX = api.step_adjoint(Xb, Xb, 1.0, G)
+    for b in range(3):
+        s1, x1 = api.step_adjoint(Xb[b], Xb[b], 1.0, G[b])
+        assert torch.equal(dS[b], s1) and torch.equal(dX[b], x1)
