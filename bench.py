@@ -81,6 +81,9 @@ def main():
                     help="precision of the headline value; the other form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=20)
+    ap.add_argument("--phase", default="all", choices=["all", "kernel"],
+                    help="kernel: only the dominant-kernel launch shape (both precisions) and a "
+                         "256 MiB copy that calibrates the traffic counters; for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -98,6 +101,24 @@ def main():
     X = torch.from_numpy(w.X).cuda()
     n, d = w.X.shape
     log(f"workload aniso3d n={n} d={d} h={w.h} kernel={w.kernel}")
+
+    if args.phase == "kernel":
+        # the largest launch of the fit: 512 seeds (third round) x all points
+        rng = np.random.default_rng(0)
+        seeds = torch.from_numpy(w.X[rng.choice(n, 512, replace=False)]).cuda()
+        out = {"phase": "kernel", "launch": f"512 seeds x {n} points"}
+        for prec in ("fp32", "bf16"):
+            t = time_kernel(api, torch, X, seeds, w.h, w.kernel, prec, args.kernel_iters)
+            out[prec + "_iteration_ms"] = t
+            out[prec + "_pair_evals_per_s"] = 512 * n / (t * 1e-3)
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)   # 256 MiB read + 256 MiB written per launch
+        torch.cuda.synchronize()
+        out["copy_bytes_each_way"] = src.numel() * 4
+        print(json.dumps(out), flush=True)
+        return
 
     def one(prec):
         return api.fit(X, w.h, kernel=w.kernel, precision=prec)
