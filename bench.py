@@ -81,9 +81,10 @@ def main():
                     help="precision of the headline value; the other form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=20)
-    ap.add_argument("--phase", default="all", choices=["all", "kernel"],
+    ap.add_argument("--phase", default="all", choices=["all", "kernel", "fit"],
                     help="kernel: only the dominant-kernel launch shape (both precisions) and a "
-                         "256 MiB copy that calibrates the traffic counters; for profilers")
+                         "256 MiB copy that calibrates the traffic counters; fit: only --steps "
+                         "fits per precision; both for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -122,6 +123,22 @@ def main():
 
     def one(prec):
         return api.fit(X, w.h, kernel=w.kernel, precision=prec)
+
+    if args.phase == "fit":
+        out = {"phase": "fit"}
+        for prec in ("fp32", "bf16"):
+            for _ in range(args.warmup):
+                one(prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                r = one(prec)
+            torch.cuda.synchronize()
+            out[prec + "_ms_per_fit"] = (time.perf_counter() - t0) / args.steps * 1e3
+            out[prec + "_breakdown_ms"] = {"iterate": r.iterate_ms, "merge_and_pool": r.merge_ms,
+                                           "assign": r.assign_ms, "host_total": r.total_ms}
+        print(json.dumps(out), flush=True)
+        return
 
     results = {}
     for prec in ["fp32", "bf16"]:

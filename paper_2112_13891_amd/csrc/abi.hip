@@ -229,7 +229,7 @@ float packed_scale(const ms_params* p) {
 // and device (grown on demand, never shrunk).
 enum Slot {
     SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
-    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_RANK, SL_GEOM, SL_SORTWS, SL_FEAT, SL_COUNT
+    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_COUNT
 };
 
 struct DevCache {
@@ -374,7 +374,7 @@ float bf16_e_thr(const ms_params* p) {
 struct SortedPoints {
     float* Xs = nullptr;
     int32_t* perm = nullptr;
-    int32_t* rank = nullptr;
+    void* sws = nullptr;   // sort workspace (holds the point bounds)
     float* geom = nullptr;
     char* feat = nullptr;
 };
@@ -438,15 +438,12 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
     SortedPoints sp;
     if (bf16) {
-        void* sws;
         FMS_CHECK(cache_get(C, budget, SL_XS, (size_t)n * DP, &sp.Xs));
         FMS_CHECK(cache_get(C, budget, SL_PERM, n, &sp.perm));
-        FMS_CHECK(cache_get(C, budget, SL_RANK, n, &sp.rank));
         FMS_CHECK(cache_get(C, budget, SL_GEOM, (size_t)((n + 255) / 256) * kGeomStride, &sp.geom));
-        FMS_CHECK(cache_get(C, budget, SL_SORTWS, sort_workspace_bytes(n), (char**)&sws));
+        FMS_CHECK(cache_get(C, budget, SL_SORTWS, sort_workspace_bytes(n), (char**)&sp.sws));
         FMS_CHECK(cache_get(C, budget, SL_FEAT, bf16_feature_bytes(n), &sp.feat));
-        FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sws, s));
-        FMS_HIP(launch_invert_perm(sp.perm, n, sp.rank, s));
+        FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sp.sws, s));
         FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
     }
 
@@ -520,7 +517,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             if (all)
                 FMS_HIP(hipMemcpyAsync(b.act[0], sp.perm, (size_t)B * 4, hipMemcpyDeviceToDevice, s));
             else
-                FMS_HIP(launch_seed_sort(bids, sp.rank, B, b.act[0], s));
+                FMS_HIP(launch_seed_order(b.S, DP, b.sh.D, B, scale, b.status, sp.sws, b.act[0], s));
         }
         const int need = (int)std::ceil((double)p->gamma * (double)B);
         FMS_HIP(launch_ctl_reset(ctl, B, need, p->max_iter, s));
@@ -530,12 +527,28 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(hipEventRecord(ev[3], s));
         const auto t_merge = std::chrono::steady_clock::now();
 
-        // merge ("prune modes"): old modes first, then parallel decision passes
+        // merge ("prune modes"): old modes first, then parallel decision
+        // passes; if they decide every seed, the founders are numbered and
+        // appended to the mode store on the device, so that pool coverage and
+        // compaction follow without a host round trip
         const int K_old = K;
+        if ((long long)K_old + B > Kcap) {
+            int newcap = std::max(Kcap * 2, K_old + B);
+            newcap = std::min(newcap, n);
+            FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)newcap * DP, &modes_ws, true, s));
+            Kcap = newcap;
+        }
         FMS_HIP(launch_merge_first_old(b.S, DP, d, b.status, B, modes_ws, K_old, r2m, bstate, s));
         const int kPasses = 3;
         for (int q = 0; q < kPasses; ++q)
             FMS_HIP(launch_merge_decide_pass(b.S, DP, d, B, K_old, r2m, bstate, &ctl->und[q], s));
+        FMS_HIP(launch_merge_founders(b.S, DP, B, K_old, bstate, modes_ws, ctl, kPasses - 1, s));
+        if (!all) {
+            // seed pool: drop the drawn seeds and the points the new modes
+            // cover, keep the rest in ascending order
+            FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, 0, ctl, r2c, removed, s));
+            FMS_HIP(launch_pool_compact(pool[cur], removed, pool_len, pool[cur ^ 1], block_tmp, ctl, s));
+        }
 
         // one copy brings back the control block and the batch
         FMS_CHECK(g_pin_rb.ensure(L.total));
@@ -555,10 +568,12 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         }
         pairs += cs.pairs;
         refined += cs.refined;
+        if (!all) pool_len = cs.pool_len;
+        const bool host_merge = cs.merge_host != 0;
 
-        // resolve: number the founders in seed order; a seed the device passes
-        // left undecided gets the same rule here (all earlier seeds are decided
-        // by the time it is reached, so this is exact)
+        // number the founders in seed order; with host_merge, a seed the
+        // device passes left undecided gets the same rule here (all earlier
+        // seeds are decided by the time it is reached, so this is exact)
         std::vector<int32_t> mode_of(B, -1);
         std::vector<int32_t> founders;
         for (int i = 0; i < B; ++i) {
@@ -587,20 +602,27 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
                 counts[st] += 1;
             }
         }
-        if (K > Kcap) {
-            int newcap = Kcap;
-            while (newcap < K) newcap *= 2;
-            newcap = std::min(newcap, n);
-            FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)newcap * DP, &modes_ws, true, s));
-            Kcap = newcap;
-        }
-        if (K > K_old) {
+        if (!host_merge && K != cs.k_new)
+            return fail(MS_E_HIP, "merge: device and host founder counts differ");
+        if (host_merge && K > K_old) {
             FMS_CHECK(g_pin_modes.ensure((size_t)(K - K_old) * DP * 4));
             float* hm = (float*)g_pin_modes.p;
             for (int q = 0; q < K - K_old; ++q)
                 std::memcpy(hm + (size_t)q * DP, h_S + (size_t)founders[q] * DP, (size_t)DP * 4);
             FMS_HIP(hipMemcpyAsync(modes_ws + (size_t)K_old * DP, hm, (size_t)(K - K_old) * DP * 4,
                                    hipMemcpyHostToDevice, s));
+            if (!all && pool_len > 0) {
+                // the device covered nothing new: cover the compacted pool now
+                // and compact it back into the current buffer
+                FMS_HIP(launch_fill_u8(removed, pool_len, 0, s));
+                FMS_HIP(launch_cover(X, d, pool[cur ^ 1], pool_len, modes_ws, K_old, K, nullptr, r2c,
+                                     removed, s));
+                FMS_HIP(launch_pool_compact(pool[cur ^ 1], removed, pool_len, pool[cur], block_tmp, ctl, s));
+                FMS_HIP(hipMemcpyAsync(mirror, ctl, offsetof(Ctl, conv_it), hipMemcpyDeviceToHost, s));
+                FMS_HIP(hipStreamSynchronize(s));
+                pool_len = mirror->pool_len;
+                cur ^= 1;   // undone below: the pool is back in pool[cur]
+            }
         }
 
         if (diag) {
@@ -625,23 +647,13 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         }
         drawn_total += B;
         rounds += 1;
-        if (all) {
-            merge_ms += ms_since(t_merge);
-            break;
-        }
-
-        // seed pool: drop the drawn seeds and the points the new modes cover,
-        // keep the rest in ascending order
-        FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, K, r2c, removed, s));
-        FMS_HIP(launch_pool_compact(pool[cur], removed, pool_len, pool[cur ^ 1], block_tmp, ctl, s));
-        FMS_HIP(hipMemcpyAsync(mirror, ctl, offsetof(Ctl, conv_it), hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipStreamSynchronize(s));
-        pool_len = mirror->pool_len;
-        cur ^= 1;
         merge_ms += ms_since(t_merge);
+        if (all) break;
+        cur ^= 1;
         if (trace)
-            std::fprintf(stderr, "[fms] round %d B=%d T=%d K=%d pool=%d round %.3f ms (merge+pool %.3f)\n",
-                         rounds, B, cs.iters_run, K, pool_len, ms_since(t_round), ms_since(t_merge));
+            std::fprintf(stderr, "[fms] round %d B=%d T=%d K=%d pool=%d%s round %.3f ms (merge+pool %.3f)\n",
+                         rounds, B, cs.iters_run, K, pool_len, host_merge ? " (host merge)" : "",
+                         ms_since(t_round), ms_since(t_merge));
         if (pool_len == 0 || N >= (long long)p->L * K) break;
         N *= 2;
     }
@@ -694,8 +706,9 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
         FMS_CHECK(ws.alloc(&sp.Xs, (size_t)n * sh.DP));
         FMS_CHECK(ws.alloc(&sp.perm, n));
         FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * kGeomStride));
-        FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n)));
+        FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n > m ? n : m)));
         FMS_CHECK(ws.alloc(&sp.feat, bf16_feature_bytes(n)));
+        sp.sws = sws;
         FMS_HIP(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
         FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
     }
@@ -712,6 +725,8 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ws.alloc(&b.part, (size_t)step_part_floats(sh, m, b.grid)));
     FMS_HIP(launch_ctl_reset(ctl, 0, INT_MAX, n_iter, s));
     FMS_HIP(launch_seed_init_from_array(seeds, converged, d, m, b, s));
+    if (bf16)   // seeds that are close in space share waves (and refine work)
+        FMS_HIP(launch_seed_order(b.S, sh.DP, sh.D, m, scale, b.status, sp.sws, b.act[0], s));
     for (int t = 0; t < n_iter; ++t) FMS_HIP(launch_iteration(b, t, s));
     FMS_HIP(launch_seed_export(b, m, seeds, converged, iters, shift2, s));
     return MS_OK;

@@ -28,7 +28,8 @@ struct Ctl {
     int32_t need;              // early-stop threshold ceil(gamma*B); INT_MAX disables
     int32_t iters_run;         // iterations that processed >= 1 seed
     int32_t pool_len;          // seed pool length after compaction
-    int32_t spare[2];
+    int32_t k_new;             // merge: modes after this round's founders
+    int32_t merge_host;        // merge: 1 if the device passes left seeds undecided
     long long pairs;           // sum of active seeds x n over iterations
     long long refined;         // BF16 path: pairs recomputed in FP32
     int32_t und[kMaxMergePasses];        // merge: undecided seeds after each pass
@@ -79,6 +80,7 @@ struct Batch {
 };
 
 long long step_part_floats(const StepShape& sh, int B, int grid);
+long long step_red_offset(const StepShape& sh, int B, int grid);
 
 // ---- launchers (k_step.hip) ----------------------------------------------
 hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale,
@@ -98,18 +100,17 @@ int step_grid(const StepShape& sh, int B, int n);
 StepShape step_shape_bf16(int d, int B);
 bool bf16_supported(int d);
 hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s);
-hipError_t launch_invert_perm(const int32_t* perm, int n, int32_t* rank, hipStream_t s);
 size_t bf16_feature_bytes(int n);
 hipError_t launch_bf16_features(const float* Xs, int n, int d, const float* geom, void* feat,
                                 hipStream_t s);
-hipError_t launch_seed_sort(const int32_t* ids, const int32_t* rank, int B, int32_t* act0,
-                            hipStream_t s);
 
 // ---- launchers (k_sort.hip) ----------------------------------------------
 constexpr int kGeomStride = 8;      // per-256-point block: centre[4], radius
-size_t sort_workspace_bytes(int n);
+size_t sort_workspace_bytes(int count);
 hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
                                float* geom, void* ws, hipStream_t s);
+hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
+                             const uint8_t* status, void* ws, int32_t* act0, hipStream_t s);
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);
@@ -122,8 +123,11 @@ hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* 
 hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old,
                                     float r2, int32_t* state, int32_t* und_counter,
                                     hipStream_t s);
+hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
+                                 float* modes, Ctl* ctl, int und_slot, hipStream_t s);
+// k1 is read from ctl->k_new on the device when ctl is not NULL
 hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len,
-                        const float* modes, int k0, int k1, float r2,
+                        const float* modes, int k0, int k1, const Ctl* ctl, float r2,
                         uint8_t* removed, hipStream_t s);
 hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, int len,
                                int32_t* pool_out, int32_t* block_tmp, Ctl* ctl,

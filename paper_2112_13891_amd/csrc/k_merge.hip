@@ -52,6 +52,11 @@ __device__ __forceinline__ float dist2(const float* a, const float* b) {
     return q;
 }
 
+constexpr int kWavesT = kT / 64;
+
+// One wave per seed from here on: the lanes test 64 candidates at a time and
+// a ballot picks the first (lowest index) hit.
+
 // state[i]: MG_SKIP for seeds that did not converge; index of the first old
 // mode within r; or MG_UNDECIDED.
 template <int D>
@@ -59,30 +64,28 @@ __global__ __launch_bounds__(kT) void first_old_kernel(const float* __restrict__
                                                        const uint8_t* __restrict__ status, int B,
                                                        const float* __restrict__ modes, int K_old,
                                                        float r2, int32_t* state) {
-    __shared__ float tileM[kT * D];
-    const int i = blockIdx.x * kT + threadIdx.x;
-    const bool live = i < B && status[i] == ST_CONVERGED;
-    float s[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) s[k] = live ? S[(long long)i * DP + k] : 0.0f;
-    int found = -1;
-    for (int base = 0; base < K_old; base += kT) {
-        const int cnt = min(kT, K_old - base);
-        __syncthreads();
-        for (int e = threadIdx.x; e < cnt * D; e += kT)
-            tileM[e] = modes[(long long)(base + e / D) * DP + e % D];
-        __syncthreads();
-        if (live && found < 0) {
-            for (int j = 0; j < cnt; ++j) {
-                if (dist2<D>(s, tileM + j * D) <= r2) {
-                    found = base + j;
-                    break;
-                }
-            }
-        }
-        if (__syncthreads_and(!live || found >= 0)) break;
+    const int i = blockIdx.x * kWavesT + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= B) return;
+    if (status[i] != ST_CONVERGED) {
+        if (lane == 0) state[i] = MG_SKIP;
+        return;
     }
-    if (i < B) state[i] = !live ? MG_SKIP : (found >= 0 ? found : MG_UNDECIDED);
+    float si[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) si[k] = S[(long long)i * DP + k];
+    int found = MG_UNDECIDED;
+    for (int base = 0; base < K_old; base += 64) {
+        const int j = base + lane;
+        bool hit = false;
+        if (j < K_old) hit = dist2<D>(si, modes + (long long)j * DP) <= r2;
+        const unsigned long long bal = __ballot(hit);
+        if (bal) {
+            found = base + __ffsll((unsigned long long)bal) - 1;
+            break;
+        }
+    }
+    if (lane == 0) state[i] = found;
 }
 
 // One decision pass.  Joined-to-batch-seed j is stored as K_old + j.
@@ -90,59 +93,94 @@ template <int D>
 __global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S, int DP, int B,
                                                     int K_old, float r2, int32_t* state,
                                                     int32_t* und_counter) {
-    __shared__ float tileS[kT * D];
-    __shared__ int32_t tileSt[kT];
-    const int i = blockIdx.x * kT + threadIdx.x;
-    int st = (i < B) ? __atomic_load_n(&state[i], __ATOMIC_RELAXED) : MG_SKIP;
-    bool todo = (st == MG_UNDECIDED);
-    float s[D];
+    const int i = blockIdx.x * kWavesT + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= B) return;
+    if (__atomic_load_n(&state[i], __ATOMIC_RELAXED) != MG_UNDECIDED) return;
+    float si[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) s[k] = todo ? S[(long long)i * DP + k] : 0.0f;
-    int result = MG_UNDECIDED;
-    bool decided = !todo;
-    const int i_max = min(B, (int)(blockIdx.x + 1) * kT);   // largest i in block + 1
-    for (int base = 0; base < i_max; base += kT) {
-        if (__syncthreads_and(decided)) break;
-        const int cnt = min(kT, i_max - base);
-        for (int e = threadIdx.x; e < cnt * D; e += kT)
-            tileS[e] = S[(long long)(base + e / D) * DP + e % D];
-        if (threadIdx.x < cnt) tileSt[threadIdx.x] = __atomic_load_n(&state[base + threadIdx.x], __ATOMIC_RELAXED);
+    for (int k = 0; k < D; ++k) si[k] = S[(long long)i * DP + k];
+    int result = MG_FOUNDER;   // unless an earlier founder or undecided seed is within r
+    for (int base = 0; base < i; base += 64) {
+        const int j = base + lane;
+        int sj = MG_SKIP;
+        bool hit = false;
+        if (j < i) {
+            sj = __atomic_load_n(&state[j], __ATOMIC_RELAXED);
+            if (sj == MG_FOUNDER || sj == MG_UNDECIDED) hit = dist2<D>(si, S + (long long)j * DP) <= r2;
+        }
+        const unsigned long long bal = __ballot(hit);
+        if (bal) {
+            const int first = __ffsll((unsigned long long)bal) - 1;
+            const int sf = __shfl(sj, first);
+            result = (sf == MG_FOUNDER) ? (K_old + base + first) : MG_UNDECIDED;
+            break;
+        }
+    }
+    if (lane == 0) {
+        if (result != MG_UNDECIDED) __atomic_store_n(&state[i], result, __ATOMIC_RELAXED);
+        else atomicAdd(und_counter, 1);
+    }
+}
+
+// After the passes: if every seed is decided, number the founders in seed
+// order (mode K_old + q for the q-th founder) and append their positions to
+// the mode store; ctl->k_new = K_old + founders.  Otherwise leave the modes
+// alone and flag the round for the host (k_new = K_old, merge_host = 1).
+// One workgroup; B may exceed its size.
+constexpr int kFoundThreads = 1024;
+
+__global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __restrict__ S, int DP,
+                                                                 int B, int K_old,
+                                                                 const int32_t* __restrict__ state,
+                                                                 float* modes, Ctl* ctl, int und_slot) {
+    __shared__ int wsum[kFoundThreads / 64];
+    __shared__ int carry_s;
+    if (ctl->und[und_slot] > 0) {
+        if (threadIdx.x == 0) {
+            ctl->k_new = K_old;
+            ctl->merge_host = 1;
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < B; base += kFoundThreads) {
+        const int i = base + threadIdx.x;
+        const bool f = i < B && state[i] == MG_FOUNDER;
+        const unsigned long long bal = __ballot(f);
+        if (lane == 0) wsum[wave] = __popcll(bal);
         __syncthreads();
-        if (!decided) {
-            const int jend = min(cnt, i - base);
-            for (int j = 0; j < jend; ++j) {
-                const int sj = tileSt[j];
-                if (sj != MG_FOUNDER && sj != MG_UNDECIDED) continue;
-                if (dist2<D>(s, tileS + j * D) <= r2) {
-                    decided = true;
-                    result = (sj == MG_FOUNDER) ? (K_old + base + j) : MG_UNDECIDED;
-                    break;
-                }
-            }
-            if (!decided && base + cnt >= i) {   // scanned every j < i: no conflict
-                decided = true;
-                result = MG_FOUNDER;
-            }
+        int before = carry_s, total = 0;
+        for (int w = 0; w < kFoundThreads / 64; ++w) {
+            if (w < wave) before += wsum[w];
+            total += wsum[w];
+        }
+        if (f) {
+            const long long q = (long long)K_old + before + __popcll(bal & ((1ull << lane) - 1ull));
+            for (int k = 0; k < DP; ++k) modes[q * DP + k] = S[(long long)i * DP + k];
         }
         __syncthreads();
+        if (threadIdx.x == 0) carry_s += total;
+        __syncthreads();
     }
-    if (todo) {
-        if (result != MG_UNDECIDED) __atomic_store_n(&state[i], result, __ATOMIC_RELAXED);
+    if (threadIdx.x == 0) {
+        ctl->k_new = K_old + carry_s;
+        ctl->merge_host = 0;
     }
-    // count what is still undecided (one atomic per wave)
-    const bool still = todo && result == MG_UNDECIDED;
-    unsigned long long b = __ballot(still);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(und_counter, __popcll(b));
 }
 
 // Pool coverage: entries of the pool list within r of a new mode [k0, k1)
-// are marked removed.
+// are marked removed; k1 is read from the control block when ctl is given.
 template <int D>
 __global__ __launch_bounds__(kT) void cover_kernel(const float* __restrict__ X, int d,
                                                    const int32_t* __restrict__ pool, int len,
                                                    const float* __restrict__ modes, int DP,
-                                                   int k0, int k1, float r2, uint8_t* removed) {
+                                                   int k0, int k1, const Ctl* ctl, float r2,
+                                                   uint8_t* removed) {
     __shared__ float tileM[kT * D];
+    if (ctl) k1 = ctl->k_new;
     const int e = blockIdx.x * kT + threadIdx.x;
     bool todo = e < len && !removed[e];
     float x[D];
@@ -275,7 +313,8 @@ hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* 
                                   const float* modes, int K_old, float r2, int32_t* state,
                                   hipStream_t s) {
     const int D = step_shape(d).D;
-    FMS_DSWITCH(D, hipLaunchKernelGGL((first_old_kernel<DD>), dim3((B + kT - 1) / kT),
+    if (B <= 0) return hipSuccess;
+    FMS_DSWITCH(D, hipLaunchKernelGGL((first_old_kernel<DD>), dim3((B + kWavesT - 1) / kWavesT),
                                       dim3(kT), 0, s, S, DP, status, B, modes, K_old, r2,
                                       state));
     return hipGetLastError();
@@ -284,18 +323,26 @@ hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* 
 hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old, float r2,
                                     int32_t* state, int32_t* und_counter, hipStream_t s) {
     const int D = step_shape(d).D;
-    FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD>), dim3((B + kT - 1) / kT), dim3(kT),
-                                      0, s, S, DP, B, K_old, r2, state, und_counter));
+    if (B <= 0) return hipSuccess;
+    FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD>), dim3((B + kWavesT - 1) / kWavesT),
+                                      dim3(kT), 0, s, S, DP, B, K_old, r2, state, und_counter));
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
+                                 float* modes, Ctl* ctl, int und_slot, hipStream_t s) {
+    hipLaunchKernelGGL(founders_kernel, dim3(1), dim3(kFoundThreads), 0, s, S, DP, B, K_old, state,
+                       modes, ctl, und_slot);
     return hipGetLastError();
 }
 
 hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len, const float* modes,
-                        int k0, int k1, float r2, uint8_t* removed, hipStream_t s) {
-    if (len <= 0 || k1 <= k0) return hipSuccess;
+                        int k0, int k1, const Ctl* ctl, float r2, uint8_t* removed, hipStream_t s) {
+    if (len <= 0 || (!ctl && k1 <= k0)) return hipSuccess;
     const StepShape sh = step_shape(d);
     FMS_DSWITCH(sh.D, hipLaunchKernelGGL((cover_kernel<DD>), dim3((len + kT - 1) / kT),
                                          dim3(kT), 0, s, X, d, pool, len, modes, sh.DP, k0, k1,
-                                         r2, removed));
+                                         ctl, r2, removed));
     return hipGetLastError();
 }
 

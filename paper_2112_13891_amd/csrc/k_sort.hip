@@ -81,61 +81,104 @@ __device__ __forceinline__ unsigned spread_bits(unsigned v, int D) {
     return r;
 }
 
-__global__ void morton_kernel(const float* __restrict__ Xp, int n, int DP, int D,
-                              const float* __restrict__ bnd, unsigned* keys, int* vals) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Morton key of one row (first D coordinates, times `scale`) on the grid of
+// 2^(30/D) cells per axis spanned by the point bounds.
+__device__ __forceinline__ unsigned morton_key(const float* row, int D, float scale,
+                                               const float* __restrict__ bnd) {
     const int bits = 30 / D;
     const float cells = (float)(1u << bits);
     unsigned key = 0;
     for (int k = 0; k < D; ++k) {
         const float lo = bnd[2 * k], hi = bnd[2 * k + 1];
         const float span = hi - lo;
-        float f = span > 0.0f ? (Xp[(long long)i * DP + k] - lo) / span * cells : 0.0f;
-        int c = (int)f;
-        c = c < 0 ? 0 : (c >= (int)cells ? (int)cells - 1 : c);
-        key |= spread_bits((unsigned)c, D) << k;
+        float f = span > 0.0f ? (row[k] * scale - lo) / span * cells : 0.0f;
+        if (!(f >= 0.0f)) f = 0.0f;   // also NaN
+        if (f > cells - 1.0f) f = cells - 1.0f;
+        key |= spread_bits((unsigned)(int)f, D) << k;
     }
-    keys[i] = key;
+    return key;
+}
+
+__global__ void morton_kernel(const float* __restrict__ Xp, int n, int DP, int D,
+                              const float* __restrict__ bnd, unsigned* keys, int* vals) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = morton_key(Xp + (long long)i * DP, D, 1.0f, bnd);
     vals[i] = i;
 }
 
-// Stable LSD radix sort, 8 bits per pass.
+// Seed keys: Morton key of the seed position in the points' grid; seeds that
+// are not active get bit 30 so that they sort after every active seed.
+__global__ void seed_key_kernel(const float* __restrict__ S, int DP, int D, int m, float scale,
+                                const uint8_t* __restrict__ status, const float* __restrict__ bnd,
+                                unsigned* keys, int* vals) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    unsigned key = morton_key(S + (long long)j * DP, D, scale, bnd);
+    if (status[j] != ST_ACTIVE) key |= 1u << 30;
+    keys[j] = key;
+    vals[j] = j;
+}
+
+// Stable LSD radix sort, 8 bits per pass.  Per-block digit counts go to
+// hist (digit-major, 256 x nblocks); the digit totals are summed into dtot with
+// integer atomics (order-independent).
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const unsigned* __restrict__ keys,
                                                                   int n, int shift, int nblocks,
-                                                                  int* hist) {
+                                                                  int* hist, int* dtot) {
     __shared__ int h[256];
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int i = blockIdx.x * kSortThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
     __syncthreads();
-    if (threadIdx.x < 256) hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) {
+        const int c = h[threadIdx.x];
+        hist[threadIdx.x * nblocks + blockIdx.x] = c;
+        if (c) atomicAdd(&dtot[threadIdx.x], c);
+    }
 }
 
-// Exclusive scan of hist (digit-major, 256 * nblocks entries) in one block:
-// each thread scans a contiguous segment, one block-wide scan of the segment
-// totals, then each segment adds its offset.
-__global__ __launch_bounds__(1024) void radix_scan_kernel(int* hist, int total) {
-    __shared__ int seg[1024];
-    const int per = (total + 1023) / 1024;
-    const int lo = threadIdx.x * per;
-    const int hi = min(total, lo + per);
-    int sum = 0;
-    for (int e = lo; e < hi; ++e) sum += hist[e];
-    seg[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int add = threadIdx.x >= off ? seg[threadIdx.x - off] : 0;
-        __syncthreads();
-        seg[threadIdx.x] += add;
-        __syncthreads();
+__global__ void zero_ints_kernel(int* a, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = 0;
+}
+
+// Inclusive scan of one value per thread over a 256-thread block; returns the
+// block total in *total.
+__device__ __forceinline__ int block_scan256(int v, int* wsum, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        if (lane >= off) v += u;
     }
-    int run = seg[threadIdx.x] - sum;   // exclusive offset of this segment
-    for (int e = lo; e < hi; ++e) {
-        const int v = hist[e];
-        hist[e] = run;
-        run += v;
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return v + before;
+}
+
+// Exclusive offsets: one workgroup per digit.  The digit's base is the sum of
+// the totals of all smaller digits; its row of per-block counts is then
+// scanned in 256-wide steps (coalesced).
+__global__ __launch_bounds__(256) void radix_scan_kernel(int* hist, int nblocks,
+                                                         const int* __restrict__ dtot) {
+    __shared__ int wsum[4];
+    const int dig = blockIdx.x;
+    int base;   // sum of the totals of the digits below this one
+    (void)block_scan256(threadIdx.x < dig ? dtot[threadIdx.x] : 0, wsum, &base);
+    int* row = hist + (long long)dig * nblocks;
+    for (int c0 = 0; c0 < nblocks; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nblocks ? row[i] : 0;
+        int step;
+        const int incl = block_scan256(v, wsum, &step);
+        if (i < nblocks) row[i] = base + incl - v;
+        base += step;
     }
 }
 
@@ -237,47 +280,96 @@ __global__ __launch_bounds__(256) void block_geom_kernel(const float* __restrict
 
 }  // namespace
 
-size_t sort_workspace_bytes(int n) {
-    const size_t nblocks = (n + kSortThreads - 1) / kSortThreads;
-    // keys x2, vals x2, hist, bounds scratch (2*4 + 2*4*256 floats)
-    return (size_t)n * 4 * 4 + nblocks * 256 * 4 + (8 + 2 * 4 * 256) * 4 + 1024;
+namespace {
+
+// Sort workspace: the point bounds first (fixed offset, so a later seed sort
+// can use the bounds of the points), digit totals, then keys/values x2 and the
+// per-block histogram sized for `count` elements.
+struct SortWs {
+    float* bnd;
+    int* dtot;
+    unsigned* k0;
+    unsigned* k1;
+    int* v0;
+    int* v1;
+    int* hist;
+};
+
+constexpr size_t kBndFloats = 8 + 2 * 4 * 256;
+
+SortWs carve(void* ws, int count) {
+    SortWs w;
+    char* p = (char*)ws;
+    w.bnd = (float*)p; p += kBndFloats * 4;
+    w.dtot = (int*)p; p += 4 * 256 * 4;
+    w.k0 = (unsigned*)p; p += (size_t)count * 4;
+    w.k1 = (unsigned*)p; p += (size_t)count * 4;
+    w.v0 = (int*)p; p += (size_t)count * 4;
+    w.v1 = (int*)p; p += (size_t)count * 4;
+    w.hist = (int*)p;
+    return w;
 }
 
-// Packed points Xp (n x DP) -> sorted copy Xs, permutation perm (Xs[i] =
-// Xp[perm[i]]) and per-256-block geometry (centre, radius).
-hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
-                               float* geom, void* ws, hipStream_t s) {
+// Stable sort of (k0, v0) by the 32-bit keys, four 8-bit passes; the result
+// is back in (k0, v0).
+void radix_sort_pairs(const SortWs& w, int n, hipStream_t s) {
     const int nblocks = (n + kSortThreads - 1) / kSortThreads;
-    char* w = (char*)ws;
-    unsigned* k0 = (unsigned*)w; w += (size_t)n * 4;
-    unsigned* k1 = (unsigned*)w; w += (size_t)n * 4;
-    int* v0 = (int*)w; w += (size_t)n * 4;
-    int* v1 = perm;
-    int* vtmp = (int*)w; w += (size_t)n * 4;
-    int* hist = (int*)w; w += (size_t)nblocks * 256 * 4;
-    float* bnd = (float*)w;
-    const int bblocks = 256;
-    hipLaunchKernelGGL(bounds_kernel, dim3(bblocks), dim3(256), 0, s, Xp, n, DP, D, bnd);
-    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(256), 0, s, bnd, D, bblocks);
-    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xp, n, DP, D, bnd, k0, v0);
-    // 4 passes over 30-bit keys; the result lands in (k0, v0) after an even count
-    unsigned* ka = k0; unsigned* kb = k1;
-    int* va = v0; int* vb = vtmp;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(4), dim3(256), 0, s, w.dtot, 4 * 256);
+    unsigned* ka = w.k0; unsigned* kb = w.k1;
+    int* va = w.v0; int* vb = w.v1;
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = pass * 8;
+        int* dt = w.dtot + pass * 256;
         hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ka, n, shift,
-                           nblocks, hist);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(1), dim3(1024), 0, s, hist, 256 * nblocks);
+                           nblocks, w.hist, dt);
+        hipLaunchKernelGGL(radix_scan_kernel, dim3(256), dim3(256), 0, s, w.hist, nblocks, dt);
         hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ka, va, n,
-                           shift, nblocks, hist, kb, vb);
+                           shift, nblocks, w.hist, kb, vb);
         unsigned* tk = ka; ka = kb; kb = tk;
         int* tv = va; va = vb; vb = tv;
     }
-    hipError_t e = hipMemcpyAsync(v1, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace
+
+size_t sort_workspace_bytes(int count) {
+    const size_t nblocks = (count + kSortThreads - 1) / kSortThreads;
+    return kBndFloats * 4 + 4 * 256 * 4 + (size_t)count * 4 * 4 + nblocks * 256 * 4 + 256;
+}
+
+// Packed points Xp (n x DP) -> sorted copy Xs, permutation perm (Xs[i] =
+// Xp[perm[i]]) and per-256-block geometry (centre, radius).  Leaves the point
+// bounds in the workspace for launch_seed_order.
+hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
+                               float* geom, void* ws, hipStream_t s) {
+    const SortWs w = carve(ws, n);
+    const int bblocks = 256;
+    hipLaunchKernelGGL(bounds_kernel, dim3(bblocks), dim3(256), 0, s, Xp, n, DP, D, w.bnd);
+    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(256), 0, s, w.bnd, D, bblocks);
+    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xp, n, DP, D, w.bnd,
+                       w.k0, w.v0);
+    radix_sort_pairs(w, n, s);
+    hipError_t e = hipMemcpyAsync(perm, w.v0, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),
                        0, s, Xp, DP, perm, n, Xs);
     hipLaunchKernelGGL(block_geom_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xs, n, DP, D, geom);
+    return hipGetLastError();
+}
+
+// Active list of a batch in the Morton order of the seed positions (S in
+// original units, `scale` to packed units), active seeds first; the active
+// count in the control block is unchanged.  ws: a sort workspace of at least
+// max(n, m) elements that launch_spatial_sort filled.
+hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
+                             const uint8_t* status, void* ws, int32_t* act0, hipStream_t s) {
+    if (m < 2) return hipSuccess;
+    const SortWs w = carve(ws, m);
+    hipLaunchKernelGGL(seed_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, S, DP, D, m, scale,
+                       status, w.bnd, w.k0, w.v0);
+    radix_sort_pairs(w, m, s);
+    hipError_t e = hipMemcpyAsync(act0, w.v0, (size_t)m * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

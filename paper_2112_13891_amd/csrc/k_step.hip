@@ -244,6 +244,7 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
     a.iters = b.iters;
     a.shift2 = b.shift2;
     a.part = b.part;
+    a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
     a.ctl = b.ctl;
     a.h2 = b.h * b.h;
     a.scale = b.scale;
@@ -257,12 +258,7 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
                            0, s, a, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the reduction kernel exits at once when the step kernel finalized
-    int blocks = (b.n_seeds + kFinWaves - 1) / kFinWaves;
-    if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3(blocks), dim3(kFinThreads), 0, s, a, t,
-                       b.grid);
-    return hipGetLastError();
+    return launch_finalize<D, DP, R>(a, t, b.grid, b.n_seeds, s);
 }
 
 }  // namespace
@@ -296,11 +292,17 @@ int step_grid(const StepShape& sh, int B, int n) {
     return (int)(g < 1 ? 1 : g);
 }
 
-long long step_part_floats(const StepShape& sh, int B, int grid) {
+long long step_red_offset(const StepShape& sh, int B, int grid) {
     // items = tiles * chunks <= max(tiles, grid) with chunks > 1 only when tiles < grid
     const long long tiles = (B + sh.TS - 1) / sh.TS;
     const long long items = tiles < grid ? grid : tiles;
     return items * sh.TS * (long long)(sh.D + 1);
+}
+
+long long step_part_floats(const StepShape& sh, int B, int grid) {
+    // chunk partials, then one reduced (D+1)-vector per slot
+    const long long tiles = (B + sh.TS - 1) / sh.TS;
+    return step_red_offset(sh, B, grid) + tiles * sh.TS * (long long)(sh.D + 1);
 }
 
 hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale, float* Xp,

@@ -97,37 +97,6 @@ __global__ void bf16_features_kernel(const float* __restrict__ Xs, int n, int np
     }
 }
 
-// Exact FP32 contribution of pair (seed shat, point row v of this lane) when
-// flagged; returns 1 if it was recomputed.
-template <int D, int KERN>
-__device__ __forceinline__ void refine_rows(const float4* __restrict__ xs4, const f32x16& E, float eps,
-                                            float e_thr, float h2, const float* shat, float* w,
-                                            float* aex, float& wex, unsigned& refined) {
-    unsigned need = 0;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) need |= (E[v] + eps >= e_thr) ? (1u << v) : 0u;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        if (need & (1u << v)) {
-            const float4 x4 = xs4[8 * (v >> 2) + (v & 3)];
-            const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
-            float dx[D], q = 0.0f;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                dx[k] = xv[k] - shat[k];
-                q = fmaf(dx[k], dx[k], q);
-            }
-            const float we = (KERN == MS_KERNEL_GAUSSIAN) ? __builtin_amdgcn_exp2f(-q)
-                                                          : (q <= h2 ? 1.0f : 0.0f);
-            wex += we;
-#pragma unroll
-            for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
-            w[v] = 0.0f;   // not in the bf16 sums
-        }
-    }
-    refined += __popc(need);
-}
-
 // Seed features of the first product relative to a block centre.
 template <int D>
 __device__ __forceinline__ bf16x8 seed_frag(const float* st, float ns, int hf) {
@@ -156,16 +125,18 @@ __device__ __forceinline__ bf16x8 seed_frag(const float* st, float ns, int hf) {
     return f;
 }
 
-// Bytes of point operands per 256-point block: first product 256 x 32 B,
-// second product 8 tiles x 512 B.
+// Bytes staged per 256-point block: first-product features 256 x 32 B,
+// second-product operand 8 tiles x 512 B, FP32 points 256 x 16 B.
 constexpr int kPfBytes = kBlk * 16 * 2;
 constexpr int kXvBytes = (kBlk / 32) * 512 * 2;
-constexpr int kStageVecs = (kPfBytes + kXvBytes) / 16 / kB16Threads;   // 16-byte loads per thread
+constexpr int kXsBytes = kBlk * 16;
+constexpr int kStageVecs = (kPfBytes + kXvBytes + kXsBytes) / 16 / kB16Threads;   // per thread
 
 template <int D, int KERN, int R>
 __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int t) {
     constexpr int TS = kB16Seeds * R;   // 4 waves x R groups x 32 seeds
     constexpr int NCOL = 2 * D + 1;     // [x~h | x~l | 1]
+    constexpr bool kGauss = KERN == MS_KERNEL_GAUSSIAN;
     const StepArgs& a = A.base;
     Ctl* ctl = a.ctl;
     const int n = a.n;
@@ -186,23 +157,29 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     const int lane = threadIdx.x & 63;
     const int col = lane & 31, hf = lane >> 5;
 
-    __shared__ __attribute__((aligned(16))) char stage[kPfBytes + kXvBytes];
+    __shared__ __attribute__((aligned(16))) char stage[kPfBytes + kXvBytes + kXsBytes];
     __shared__ float tr[kB16Threads / 64][NCOL][32];   // per-wave transpose
     __shared__ float fin[(D + 1) * TS];
     const __bf16* spf = reinterpret_cast<const __bf16*>(stage);
     const __bf16* sxv = reinterpret_cast<const __bf16*>(stage + kPfBytes);
+    const float4* sxs = reinterpret_cast<const float4*>(stage + kPfBytes + kXvBytes);
     unsigned refined = 0;
 
+    static_assert(kStageVecs == 5 && kPfBytes / 16 == 2 * kB16Threads &&
+                  kXvBytes / 16 == 2 * kB16Threads && kXsBytes / 16 == kB16Threads,
+                  "stage layout");
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
         const int b0 = (int)((long long)nblk * chunk / chunks);
         const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
         float shat[R][D], arun[R][D], aex[R][D], wrun[R], wex[R];
+        bool live[R];
 #pragma unroll
         for (int g = 0; g < R; ++g) {
             const int slot = tile * TS + (wave * R + g) * 32 + col;
-            const int j = a.act_in[slot < m ? slot : 0];
+            live[g] = slot < m;
+            const int j = a.act_in[live[g] ? slot : 0];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 shat[g][k] = a.S[(long long)j * 4 + k] * a.scale;
@@ -210,18 +187,18 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             }
             wrun[g] = wex[g] = 0.0f;
         }
-        // operands of the first block of the chunk: 512 + 512 16-byte vectors,
-        // four per thread (two of each product)
-        static_assert(kStageVecs == 4 && kPfBytes / 16 == 2 * kB16Threads &&
-                      kXvBytes / 16 == 2 * kB16Threads, "stage layout");
-        uint4 n0, n1, n2, n3;
+        // operands of the first block of the chunk, five 16-byte vectors per
+        // thread: two of features, two of the second operand, one of points
+        uint4 n0, n1, n2, n3, n4;
         {
             const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)b0 * kBlk * 16);
             const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)b0 * (kBlk / 32) * 512);
+            const uint4* xsg = reinterpret_cast<const uint4*>(A.Xs) + (long long)b0 * kBlk;
             n0 = pfg[threadIdx.x];
             n1 = pfg[kB16Threads + threadIdx.x];
             n2 = xvg[threadIdx.x];
             n3 = xvg[kB16Threads + threadIdx.x];
+            n4 = (long long)b0 * kBlk + threadIdx.x < n ? xsg[threadIdx.x] : uint4{};
         }
 
         for (int blk = b0; blk < b1; ++blk) {
@@ -230,14 +207,17 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             reinterpret_cast<uint4*>(stage)[kB16Threads + threadIdx.x] = n1;
             reinterpret_cast<uint4*>(stage)[2 * kB16Threads + threadIdx.x] = n2;
             reinterpret_cast<uint4*>(stage)[3 * kB16Threads + threadIdx.x] = n3;
+            reinterpret_cast<uint4*>(stage)[4 * kB16Threads + threadIdx.x] = n4;
             __syncthreads();
             if (blk + 1 < b1) {   // next block's operands travel while this one computes
                 const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)(blk + 1) * kBlk * 16);
                 const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)(blk + 1) * (kBlk / 32) * 512);
+                const uint4* xsg = reinterpret_cast<const uint4*>(A.Xs) + (long long)(blk + 1) * kBlk;
                 n0 = pfg[threadIdx.x];
                 n1 = pfg[kB16Threads + threadIdx.x];
                 n2 = xvg[threadIdx.x];
                 n3 = xvg[kB16Threads + threadIdx.x];
+                n4 = (long long)(blk + 1) * kBlk + threadIdx.x < n ? xsg[threadIdx.x] : uint4{};
             }
             const float* gm = A.geom + (long long)blk * kGeomStride;
             float st[R][D], eps[R];
@@ -261,7 +241,6 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                 out[g] = f32x16{};
                 used[g] = false;
             }
-            const float4* xsb = reinterpret_cast<const float4*>(A.Xs) + (long long)blk * kBlk + 4 * hf;
 #pragma unroll 1
             for (int tt = 0; tt < kBlk / 32; ++tt) {
                 const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(spf + (tt * 32 + col) * 16 + hf * 8);
@@ -273,18 +252,53 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
 #pragma unroll
                     for (int v = 1; v < 16; ++v) emax = fmaxf(emax, E[v]);
                     float w[16];
+                    bool far_mfma;
+                    if (__ballot(emax + eps[g] >= A.e_thr)) {
+                        // some pair of this 32 x 32 tile may lie within the refine
+                        // radius: every row of the lane is recomputed exactly in
+                        // FP32 (points from LDS), and each pair keeps the exact
+                        // weight if and only if its own bound flags it, so the
+                        // result of a pair never depends on its tile mates
+                        const float4* xr = sxs + tt * 32 + 4 * hf;
+                        unsigned nref = 0;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) w[v] = 0.0f;
-                    if (__ballot(emax + eps[g] >= A.e_thr))
-                        refine_rows<D, KERN>(xsb + tt * 32, E, eps[g], A.e_thr, a.h2,
-                                             shat[g], w, aex[g], wex[g], refined);
-                    // far pairs (Gaussian only): weights from the estimate, unless
-                    // every weight of the lane underflows (2^-127)
-                    if (KERN == MS_KERNEL_GAUSSIAN && __ballot(emax >= -127.0f)) {
-                        // refined rows keep w = 0: recompute their mask cheaply
+                        for (int q = 0; q < 4; ++q) {
+                            float4 x4[4];
 #pragma unroll
-                        for (int v = 0; v < 16; ++v)
-                            if (!(E[v] + eps[g] >= A.e_thr)) w[v] = __builtin_amdgcn_exp2f(E[v]);
+                            for (int u = 0; u < 4; ++u) x4[u] = xr[8 * q + u];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int v = 4 * q + u;
+                                const bool need = E[v] + eps[g] >= A.e_thr;
+                                const float xv[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
+                                float dx[D], q2 = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    dx[k] = xv[k] - shat[g][k];
+                                    q2 = fmaf(dx[k], dx[k], q2);
+                                }
+                                float we = kGauss ? __builtin_amdgcn_exp2f(-q2)
+                                                  : (q2 <= a.h2 ? 1.0f : 0.0f);
+                                we = need ? we : 0.0f;
+                                wex[g] += we;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) aex[g][k] = fmaf(we, dx[k], aex[g][k]);
+                                nref += need ? 1u : 0u;
+                                w[v] = need ? 0.0f : __builtin_amdgcn_exp2f(E[v]);
+                            }
+                        }
+                        refined += live[g] ? nref : 0u;
+                        far_mfma = kGauss;
+                    } else {
+                        // far tile (Gaussian): weights from the estimate, unless
+                        // every weight of the wave underflows (2^-127)
+                        far_mfma = kGauss && __ballot(emax >= -127.0f);
+                        if (far_mfma) {
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) w[v] = __builtin_amdgcn_exp2f(E[v]);
+                        }
+                    }
+                    if (far_mfma) {
                         bf16x8 w0, w1;
 #pragma unroll
                         for (int q = 0; q < 8; ++q) {
@@ -368,45 +382,6 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
         atomicAdd((unsigned long long*)&ctl->refined, (unsigned long long)refined);
 }
 
-// Seed order for a batch: sort the batch slots by the seeds' positions in the
-// Morton order of the points (rank[id]), so the 32 seeds of a wave are close
-// together and share refine work.  One workgroup, bitonic sort, B <= 4096.
-constexpr int kSeedSortMax = 4096;
-
-__global__ __launch_bounds__(1024) void seed_sort_kernel(const int32_t* __restrict__ ids,
-                                                         const int32_t* __restrict__ rank, int B,
-                                                         int32_t* act0) {
-    __shared__ unsigned long long key[kSeedSortMax];
-    int P = 1;
-    while (P < B) P <<= 1;
-    for (int e = threadIdx.x; e < P; e += 1024)
-        key[e] = e < B ? (((unsigned long long)(unsigned)rank[ids[e]] << 32) | (unsigned)e)
-                       : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int e = threadIdx.x; e < P; e += 1024) {
-                const int o = e ^ stride;
-                if (o > e) {
-                    const bool up = (e & size) == 0;
-                    const unsigned long long x = key[e], y = key[o];
-                    if ((x > y) == up) {
-                        key[e] = y;
-                        key[o] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int e = threadIdx.x; e < B; e += 1024) act0[e] = (int32_t)(key[e] & 0xffffffffu);
-}
-
-__global__ void invert_perm_kernel(const int32_t* __restrict__ perm, int n, int32_t* rank) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) rank[perm[i]] = i;
-}
-
 template <int D, int R>
 hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     Bf16Args A;
@@ -421,6 +396,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     a.iters = b.iters;
     a.shift2 = b.shift2;
     a.part = b.part;
+    a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
     a.ctl = b.ctl;
     a.h2 = b.h * b.h;
     a.scale = b.scale;
@@ -440,11 +416,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
                            0, s, A, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int blocks = (b.n_seeds + kFinWaves - 1) / kFinWaves;
-    if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL((finalize_kernel<D, 4, 2 * R>), dim3(blocks), dim3(kFinThreads), 0, s, a, t,
-                       b.grid);
-    return hipGetLastError();
+    return launch_finalize<D, 4, 2 * R>(a, t, b.grid, b.n_seeds, s);
 }
 
 }  // namespace
@@ -495,20 +467,6 @@ hipError_t launch_bf16_features(const float* Xs, int n, int d, const float* geom
         default:
             return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_invert_perm(const int32_t* perm, int n, int32_t* rank, hipStream_t s) {
-    hipLaunchKernelGGL(invert_perm_kernel, dim3((n + 255) / 256), dim3(256), 0, s, perm, n, rank);
-    return hipGetLastError();
-}
-
-// Order the batch's active list by the seeds' Morton rank (B <= 4096; larger
-// batches keep draw order, which only costs refine work).
-hipError_t launch_seed_sort(const int32_t* ids, const int32_t* rank, int B, int32_t* act0,
-                            hipStream_t s) {
-    if (B < 2 || B > kSeedSortMax) return hipSuccess;
-    hipLaunchKernelGGL(seed_sort_kernel, dim3(1), dim3(1024), 0, s, ids, rank, B, act0);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct StepArgs {
     int32_t* iters;
     float* shift2;
     float* part;
+    float* red;        // per-slot sums reduced from many chunk partials
     Ctl* ctl;
     float h2, scale, inv_scale, thr2;
 };
@@ -105,14 +106,20 @@ __device__ void finalize_tile(const StepArgs& a, int t, int m, int tile, const f
     if (res == 1) a.act_out[base + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
 }
 
-// Reduction of the chunk partials and finalize (only when chunks > 1), in
-// 1024-thread blocks.  Many chunks and few seeds: one wave per seed; its lanes
-// add the partials lane-strided, then in a fixed butterfly, and the block's 16
-// seeds are finalized by 16 lanes of wave 0 (one compaction atomic per block).
-// Otherwise one lane per seed adds its partials in chunk order and each wave
-// compacts its 64 seeds with one ballot and one atomic.
+// Reduction of the chunk partials and finalize (only when chunks > 1).
+// Few chunks (many seeds): finalize_kernel reads the partials itself, one lane
+// per seed, adding them in chunk order.  Many chunks (few seeds): reduce_kernel
+// first spreads the sums over the whole chip -- each workgroup takes a group of
+// SG seeds (a power of two <= 16, <= 8 for D >= 32, chosen from m and the grid), its 1024 threads
+// add the partials of chunk lanes c = cl, cl + 1024/SG, ... in fixed order,
+// then a fixed butterfly inside each wave and a fixed-order sum over the 16
+// waves -- and writes one (D+1)-vector per slot to `red`; finalize_kernel then
+// reads those.  Either way each wave compacts its 64 consecutive slots with one
+// ballot and one atomic, so the active list keeps 64-slot runs in order.
 constexpr int kFinThreads = 1024;
 constexpr int kFinWaves = kFinThreads / 64;
+constexpr int kDirectChunks = 64;
+constexpr int kRedThreads = 1024;
 
 template <int D, int DP>
 __device__ __forceinline__ void compact_wave(const StepArgs& a, int t, int slot, int res) {
@@ -128,6 +135,56 @@ __device__ __forceinline__ void compact_wave(const StepArgs& a, int t, int slot,
     if (res == 1) a.act_out[off + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
 }
 
+template <int D, int R>
+__global__ __launch_bounds__(kRedThreads) void reduce_kernel(StepArgs a, int t, int grid) {
+    constexpr int TS = 64 * R;
+    constexpr int kRedMaxSG = D >= 32 ? 8 : 16;   // keeps wsum within 36 KB of LDS
+    const int m = active_count(a.ctl, t);
+    if (m == 0) return;
+    const int chunks = chunks_for(m, TS, a.n, grid);
+    if (chunks <= kDirectChunks) return;
+    const int per = (m + (int)gridDim.x - 1) / (int)gridDim.x;
+    int SG = 1;
+    while (SG < per && SG < kRedMaxSG) SG <<= 1;
+    const int CL = kRedThreads / SG;
+    const int sidx = threadIdx.x & (SG - 1), cl = threadIdx.x / SG;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ float wsum[kRedThreads / 64][kRedMaxSG][D + 1];
+    for (int g0 = blockIdx.x * SG; g0 < m; g0 += gridDim.x * SG) {
+        const int slot = g0 + sidx;
+        float v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+        if (slot < m) {
+            const int tile = slot / TS, pos = slot % TS;
+            const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+            for (int c = cl; c < chunks; c += CL) {
+                const float* p = src + (long long)c * TS * (D + 1);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) v[k] += p[k];
+            }
+        }
+        // lanes of a wave holding the same seed differ in the bits >= SG
+        for (int off = 32; off >= SG; off >>= 1)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] += __shfl_xor(v[k], off);
+        if (lane < SG) {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) wsum[wave][lane][k] = v[k];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < SG * (D + 1); e += kRedThreads) {
+            const int s2 = e / (D + 1), k = e % (D + 1);
+            if (g0 + s2 < m) {
+                float acc = 0.0f;
+                for (int w = 0; w < kRedThreads / 64; ++w) acc += wsum[w][s2][k];
+                a.red[(long long)(g0 + s2) * (D + 1) + k] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int D, int DP, int R>
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t, int grid) {
     constexpr int TS = 64 * R;
@@ -135,62 +192,49 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
     if (m == 0) return;
     const int chunks = chunks_for(m, TS, a.n, grid);
     if (chunks == 1) return;   // finalized inside the step kernel
+    const bool pre = chunks > kDirectChunks;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    __shared__ float sums[kFinWaves][D + 1];
-    if (chunks > 64 && m <= 8192) {
-        for (int base = blockIdx.x * kFinWaves; base < m; base += gridDim.x * kFinWaves) {
-            const int slot = base + wave;
-            if (slot < m) {
-                const int tile = slot / TS, pos = slot % TS;
-                float v[D + 1];
-#pragma unroll
-                for (int k = 0; k <= D; ++k) v[k] = 0.0f;
-                const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
-                for (int c = lane; c < chunks; c += 64) {
-                    const float* p = src + (long long)c * TS * (D + 1);
-#pragma unroll
-                    for (int k = 0; k <= D; ++k) v[k] += p[k];
-                }
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1)
-#pragma unroll
-                    for (int k = 0; k <= D; ++k) v[k] += __shfl_xor(v[k], off);
-                if (lane == 0) {
-#pragma unroll
-                    for (int k = 0; k <= D; ++k) sums[wave][k] = v[k];
-                }
-            }
-            __syncthreads();
-            if (wave == 0) {
-                const int my = base + lane;
-                int res = 0;
-                if (lane < kFinWaves && my < m) res = update_seed<D, DP>(a, my, sums[lane]);
-                compact_wave<D, DP>(a, t, my, res);
-            }
-            __syncthreads();
-        }
-        return;
-    }
     const int nwaves = gridDim.x * kFinWaves;
     for (int base = (blockIdx.x * kFinWaves + wave) * 64; base < m; base += nwaves * 64) {
         const int slot = base + lane;
         int res = 0;
         if (slot < m) {
-            const int tile = slot / TS, pos = slot % TS;
             float v[D + 1];
+            if (pre) {
 #pragma unroll
-            for (int k = 0; k <= D; ++k) v[k] = 0.0f;
-            const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
-            for (int c = 0; c < chunks; ++c) {
-                const float* p = src + (long long)c * TS * (D + 1);
+                for (int k = 0; k <= D; ++k) v[k] = a.red[(long long)slot * (D + 1) + k];
+            } else {
+                const int tile = slot / TS, pos = slot % TS;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) v[k] += p[k];
+                for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+                const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+                for (int c = 0; c < chunks; ++c) {
+                    const float* p = src + (long long)c * TS * (D + 1);
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) v[k] += p[k];
+                }
             }
             res = update_seed<D, DP>(a, slot, v);
         }
         compact_wave<D, DP>(a, t, slot, res);
     }
+}
+
+// Launch of the reduction (exits at once unless many chunks) and the finalize
+// (exits at once when the step kernel finalized) for a batch of B seeds.
+template <int D, int DP, int R>
+inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hipStream_t s) {
+    const int rblocks = B < 256 ? (B < 1 ? 1 : B) : 256;
+    hipLaunchKernelGGL((reduce_kernel<D, R>), dim3(rblocks), dim3(kRedThreads), 0, s, a, t, grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int fblocks = (B + kFinThreads - 1) / kFinThreads;
+    if (fblocks > 512) fblocks = 512;
+    if (fblocks < 1) fblocks = 1;
+    hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a, t,
+                       grid);
+    return hipGetLastError();
 }
 
 }  // namespace

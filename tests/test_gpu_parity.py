@@ -153,6 +153,21 @@ def test_fit_flat_kernel_small(orc):
         say(fit_parity(g, ref, X, 2.5, orc=orc, kernel="flat"))
 
 
+@pytest.mark.parametrize("all_points", [False, True])
+def test_fit_merge_chain(orc, all_points):
+    """Isolated points on a line 5h apart with merge radius 6h: each seed stays
+    on its point, and every merge decision waits on the previous link of a
+    chain far deeper than the device decision passes resolve, so the host
+    finishes the merge (and redoes the pool coverage) -- the same greedy
+    result as the sequential rule."""
+    n = 300
+    X = np.zeros((n, 2), np.float32)
+    X[:, 0] = 5.0 * np.arange(n, dtype=np.float32)
+    g = api.fit(_gpu(X), 1.0, kernel="flat", merge_radius=6.0, all_points=all_points, trace=True)
+    ref = orc.fit(X, 1.0, kernel="flat", merge_radius=6.0, all_points=all_points)
+    say(fit_parity(g, ref, X, 1.0, orc=orc, kernel="flat"), "K", g.k)
+
+
 def test_fit_gamma_early_stop(orc, aniso):
     X = aniso.X[:20000]
     g = api.fit(_gpu(X), aniso.h, gamma=0.75, trace=True)
