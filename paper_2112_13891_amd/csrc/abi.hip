@@ -10,6 +10,8 @@
 // polls a pinned copy of the device control block between chunks.
 
 #include <algorithm>
+#include <atomic>
+#include <immintrin.h>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -299,29 +301,76 @@ RbLayout rb_layout(int B, int DP) {
     return L;
 }
 
-// Enqueue up to max_iter iterations, in chunks, stopping once a snapshot of
-// the control block shows the batch finished.
-int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror, hipEvent_t ev[2]) {
-    const int kChunk = 4;
-    int t = 0, pending = -1, pending_t = 0, slot = 0;
-    while (t < max_iter) {
-        const int c = std::min(kChunk, max_iter - t);
-        for (int k = 0; k < c; ++k) FMS_HIP(launch_iteration(b, t + k, s));
-        t += c;
-        FMS_HIP(hipMemcpyAsync(&mirror[slot], b.ctl, offsetof(Ctl, conv_it) + (size_t)(t + 1) * 4,
-                               hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipEventRecord(ev[slot], s));
-        if (pending >= 0) {
-            FMS_HIP(hipEventSynchronize(ev[pending]));
-            const Ctl& cs = mirror[pending];
-            int conv = 0;
-            for (int u = 0; u < pending_t; ++u) conv += cs.conv_it[u];
-            if (conv >= cs.need || cs.count[pending_t % 3] == 0) break;
+// Host-mapped progress word of this thread's fits: the step kernel of
+// iteration t stores (t << 32 | active seeds) into it.
+struct ProgressWord {
+    unsigned long long* host = nullptr;
+    unsigned long long* dev = nullptr;
+    int ensure() {
+        if (host) return MS_OK;
+        void* p = nullptr;
+        FMS_HIP(hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent));
+        void* d = nullptr;
+        hipError_t e = hipHostGetDevicePointer(&d, p, 0);
+        if (e != hipSuccess) {
+            (void)hipHostFree(p);
+            return hip_fail(e, "hipHostGetDevicePointer");
         }
-        pending = slot;
-        pending_t = t;
-        slot ^= 1;
+        host = (unsigned long long*)p;
+        dev = (unsigned long long*)d;
+        return MS_OK;
     }
+    ~ProgressWord() {
+        if (host) (void)hipHostFree(host);
+    }
+};
+thread_local ProgressWord g_prog;
+
+// Enqueue iterations, keeping at most kAhead of them queued beyond the one the
+// device last reported starting, until an iteration reports no active seed
+// (every later one would find none either) or max_iter were enqueued.  If the
+// stream drains without a new report, the control block is read back instead.
+int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror) {
+    constexpr int kAhead = 2;
+    constexpr unsigned long long kNone = ~0ull;
+    volatile unsigned long long* word = g_prog.host;
+    *word = kNone;
+    std::atomic_thread_fence(std::memory_order_seq_cst);
+    b.prog = g_prog.dev;
+    int launched = 0;
+    for (;;) {
+        const unsigned long long w = *word;
+        const int t_obs = w == kNone ? -1 : (int)(w >> 32);
+        const int m_obs = (int)(w & 0xffffffffu);
+        if (t_obs >= 0 && m_obs == 0) break;
+        if (launched >= max_iter) break;
+        if (launched - (t_obs + 1) < kAhead) {
+            FMS_HIP(launch_iteration(b, launched, s));
+            ++launched;
+            continue;
+        }
+        // wait for the device to start another iteration
+        bool moved = false;
+        for (int spin = 0; spin < 4096 && !moved; ++spin) {
+            if (*word != w) moved = true;
+            else _mm_pause();
+        }
+        if (moved) continue;
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return hip_fail(q, "hipStreamQuery");
+        if (*word != w) continue;
+        // drained with no newer report: decide from the control block
+        FMS_HIP(hipMemcpyAsync(mirror, b.ctl, offsetof(Ctl, conv_it) + (size_t)(launched + 1) * 4,
+                               hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipStreamSynchronize(s));
+        int conv = 0;
+        for (int u = 0; u < launched; ++u) conv += mirror->conv_it[u];
+        if (conv >= mirror->need || mirror->count[launched % 3] == 0) break;
+        FMS_HIP(launch_iteration(b, launched, s));
+        ++launched;
+    }
+    b.prog = nullptr;
     return MS_OK;
 }
 
@@ -457,6 +506,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_CHECK(cache_get(C, budget, SL_REMOVED, n, &removed));
         FMS_CHECK(cache_get(C, budget, SL_BLOCKS, pool_compact_blocks(n) + 1, &block_tmp));
         FMS_HIP(launch_iota(pool[0], n, s));
+        FMS_HIP(launch_fill_u8(removed, n, 0, s));   // kept clear by each compaction
     }
 
     // device mode store (DP stride), grown on demand
@@ -467,6 +517,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
 
     FMS_CHECK(g_pin_ctl.ensure(2 * sizeof(Ctl)));
     Ctl* mirror = (Ctl*)g_pin_ctl.p;
+    FMS_CHECK(g_prog.ensure());
 
     uint64_t rng = p->rng_seed;
     long long N = p->n_initial;
@@ -499,19 +550,17 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_CHECK(cache_get(C, budget, SL_SHIFT2, B, &b.shift2));
         FMS_CHECK(cache_get(C, budget, SL_PART, (size_t)part_floats, &b.part));
 
-        if (all) {
-            FMS_HIP(launch_iota(bids, B, s));
-        } else {
-            int32_t* dpos;
+        const int need = (int)std::ceil((double)p->gamma * (double)B);
+        int32_t* dpos = nullptr;
+        if (!all) {
             FMS_CHECK(cache_get(C, budget, SL_POS, B, &dpos));
             FMS_CHECK(g_pin_pos.ensure((size_t)B * sizeof(int32_t)));
             int32_t* hpos = (int32_t*)g_pin_pos.p;
             draw_positions(&rng, pool_len, B, hpos);
             FMS_HIP(hipMemcpyAsync(dpos, hpos, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            FMS_HIP(launch_fill_u8(removed, pool_len, 0, s));
-            FMS_HIP(launch_gather_ids(pool[cur], dpos, B, bids, removed, s));
         }
-        FMS_HIP(launch_seed_init_from_ids(X, d, DP, bids, B, b, s));
+        FMS_HIP(launch_round_init(X, d, DP, all ? nullptr : pool[cur], dpos, B, bids, removed,
+                                  bstate, b, need, p->max_iter, s));
         if (bf16) {
             // seeds that are close in space share waves (and refine work)
             if (all)
@@ -519,11 +568,9 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             else
                 FMS_HIP(launch_seed_order(b.S, DP, b.sh.D, B, scale, b.status, sp.sws, b.act[0], s));
         }
-        const int need = (int)std::ceil((double)p->gamma * (double)B);
-        FMS_HIP(launch_ctl_reset(ctl, B, need, p->max_iter, s));
 
         FMS_HIP(hipEventRecord(ev[2], s));
-        FMS_CHECK(iterate_batch(b, p->max_iter, s, mirror, ev));
+        FMS_CHECK(iterate_batch(b, p->max_iter, s, mirror));
         FMS_HIP(hipEventRecord(ev[3], s));
         const auto t_merge = std::chrono::steady_clock::now();
 
@@ -538,15 +585,16 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)newcap * DP, &modes_ws, true, s));
             Kcap = newcap;
         }
-        FMS_HIP(launch_merge_first_old(b.S, DP, d, b.status, B, modes_ws, K_old, r2m, bstate, s));
         const int kPasses = 3;
         for (int q = 0; q < kPasses; ++q)
-            FMS_HIP(launch_merge_decide_pass(b.S, DP, d, B, K_old, r2m, bstate, &ctl->und[q], s));
+            FMS_HIP(launch_merge_decide_pass(b.S, DP, d, b.status, B, modes_ws, K_old, r2m, bstate,
+                                             &ctl->und[q], q == 0, s));
         FMS_HIP(launch_merge_founders(b.S, DP, B, K_old, bstate, modes_ws, ctl, kPasses - 1, s));
         if (!all) {
             // seed pool: drop the drawn seeds and the points the new modes
             // cover, keep the rest in ascending order
-            FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, 0, ctl, r2c, removed, s));
+            FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, 0, ctl, r2c, removed,
+                                 block_tmp, s));
             FMS_HIP(launch_pool_compact(pool[cur], removed, pool_len, pool[cur ^ 1], block_tmp, ctl, s));
         }
 
@@ -614,9 +662,8 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             if (!all && pool_len > 0) {
                 // the device covered nothing new: cover the compacted pool now
                 // and compact it back into the current buffer
-                FMS_HIP(launch_fill_u8(removed, pool_len, 0, s));
                 FMS_HIP(launch_cover(X, d, pool[cur ^ 1], pool_len, modes_ws, K_old, K, nullptr, r2c,
-                                     removed, s));
+                                     removed, block_tmp, s));
                 FMS_HIP(launch_pool_compact(pool[cur ^ 1], removed, pool_len, pool[cur], block_tmp, ctl, s));
                 FMS_HIP(hipMemcpyAsync(mirror, ctl, offsetof(Ctl, conv_it), hipMemcpyDeviceToHost, s));
                 FMS_HIP(hipStreamSynchronize(s));

@@ -25,6 +25,7 @@ constexpr int kMaxMergePasses = 64;
 // through a pinned mirror.
 struct Ctl {
     int32_t count[3];          // active-list lengths, by iteration t % 3
+    int32_t conv_base[3];      // seeds converged before iteration t, by t % 3
     int32_t need;              // early-stop threshold ceil(gamma*B); INT_MAX disables
     int32_t iters_run;         // iterations that processed >= 1 seed
     int32_t pool_len;          // seed pool length after compaction
@@ -76,6 +77,7 @@ struct Batch {
     const void* xv;        // BF16 form: point operand of the second product
     float e_thr;           // BF16 form: refine threshold (packed units)
     float kappa;           // BF16 form: error bound coefficient
+    unsigned long long* prog = nullptr;   // host-mapped progress word (t << 32 | m), or NULL
     Ctl* ctl;
 };
 
@@ -85,9 +87,11 @@ long long step_red_offset(const StepShape& sh, int B, int grid);
 // ---- launchers (k_step.hip) ----------------------------------------------
 hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale,
                               float* Xp, hipStream_t s);
-hipError_t launch_seed_init_from_ids(const float* X, int d, int DP,
-                                     const int32_t* ids, int B, Batch& b,
-                                     hipStream_t s);
+// Fit round start: drawn seeds (pool[pos[j]]; j itself when pos is NULL)
+// leave the pool, become the batch's seeds, and the control block is reset.
+hipError_t launch_round_init(const float* X, int d, int DP, const int32_t* pool,
+                             const int32_t* pos, int B, int32_t* ids, uint8_t* removed,
+                             int32_t* merge_state, Batch& b, int need, int max_iter, hipStream_t s);
 hipError_t launch_seed_init_from_array(const float* seeds, const uint8_t* conv_in,
                                        int d, int m, Batch& b, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int B, int need, int max_iter, hipStream_t s);
@@ -115,21 +119,23 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
-hipError_t launch_gather_ids(const int32_t* pool, const int32_t* pos, int B,
-                             int32_t* ids, uint8_t* removed, hipStream_t s);
-hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* status,
-                                  int B, const float* modes, int K_old, float r2,
-                                  int32_t* state, hipStream_t s);
-hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old,
-                                    float r2, int32_t* state, int32_t* und_counter,
-                                    hipStream_t s);
+// One merge decision pass over a batch of B seeds (the first pass also
+// settles seeds that did not converge and seeds that join an old mode).
+hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t* status, int B,
+                                    const float* modes, int K_old, float r2, int32_t* state,
+                                    int32_t* und_counter, bool first, hipStream_t s);
 hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
                                  float* modes, Ctl* ctl, int und_slot, hipStream_t s);
-// k1 is read from ctl->k_new on the device when ctl is not NULL
+// Pool coverage by the modes [k0, k1) (k1 read from ctl->k_new on the device
+// when ctl is not NULL); also writes the per-block counts that
+// launch_pool_compact consumes.
 hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len,
                         const float* modes, int k0, int k1, const Ctl* ctl, float r2,
-                        uint8_t* removed, hipStream_t s);
-hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, int len,
+                        uint8_t* removed, int32_t* block_cnt, hipStream_t s);
+// Stable compaction of the pool entries not flagged removed, from the block
+// counts launch_cover wrote; clears the flags of [0, len) for the next round.
+// Writes the new length to ctl->pool_len.
+hipError_t launch_pool_compact(const int32_t* pool_in, uint8_t* removed, int len,
                                int32_t* pool_out, int32_t* block_tmp, Ctl* ctl,
                                hipStream_t s);
 int pool_compact_blocks(int len);

@@ -21,16 +21,6 @@ namespace {
 
 constexpr int kT = 256;
 
-__global__ void gather_ids_kernel(const int32_t* __restrict__ pool,
-                                  const int32_t* __restrict__ pos, int B, int32_t* ids,
-                                  uint8_t* removed) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B) return;
-    int p = pos[t];
-    ids[t] = pool[p];
-    removed[p] = 1;
-}
-
 __global__ void iota_kernel(int32_t* a, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = i;
@@ -57,49 +47,41 @@ constexpr int kWavesT = kT / 64;
 // One wave per seed from here on: the lanes test 64 candidates at a time and
 // a ballot picks the first (lowest index) hit.
 
-// state[i]: MG_SKIP for seeds that did not converge; index of the first old
-// mode within r; or MG_UNDECIDED.
-template <int D>
-__global__ __launch_bounds__(kT) void first_old_kernel(const float* __restrict__ S, int DP,
-                                                       const uint8_t* __restrict__ status, int B,
-                                                       const float* __restrict__ modes, int K_old,
-                                                       float r2, int32_t* state) {
+// One decision pass.  Joined-to-batch-seed j is stored as K_old + j.  Every
+// state starts as MG_UNDECIDED (set when the round starts); the first pass
+// also settles seeds that did not converge (MG_SKIP) and seeds within r of an
+// old mode (the index of the first such mode).  A state another wave has not
+// settled yet reads as undecided, which only postpones a decision.
+template <int D, bool kFirst>
+__global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S, int DP,
+                                                    const uint8_t* __restrict__ status, int B,
+                                                    const float* __restrict__ modes, int K_old,
+                                                    float r2, int32_t* state, int32_t* und_counter) {
     const int i = blockIdx.x * kWavesT + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= B) return;
-    if (status[i] != ST_CONVERGED) {
-        if (lane == 0) state[i] = MG_SKIP;
+    if (kFirst && status[i] != ST_CONVERGED) {
+        if (lane == 0) __atomic_store_n(&state[i], (int32_t)MG_SKIP, __ATOMIC_RELAXED);
         return;
     }
+    if (!kFirst && __atomic_load_n(&state[i], __ATOMIC_RELAXED) != MG_UNDECIDED) return;
     float si[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) si[k] = S[(long long)i * DP + k];
-    int found = MG_UNDECIDED;
-    for (int base = 0; base < K_old; base += 64) {
-        const int j = base + lane;
-        bool hit = false;
-        if (j < K_old) hit = dist2<D>(si, modes + (long long)j * DP) <= r2;
-        const unsigned long long bal = __ballot(hit);
-        if (bal) {
-            found = base + __ffsll((unsigned long long)bal) - 1;
-            break;
+    if (kFirst) {
+        for (int base = 0; base < K_old; base += 64) {
+            const int j = base + lane;
+            bool hit = false;
+            if (j < K_old) hit = dist2<D>(si, modes + (long long)j * DP) <= r2;
+            const unsigned long long bal = __ballot(hit);
+            if (bal) {
+                if (lane == 0)
+                    __atomic_store_n(&state[i], (int32_t)(base + __ffsll((unsigned long long)bal) - 1),
+                                     __ATOMIC_RELAXED);
+                return;
+            }
         }
     }
-    if (lane == 0) state[i] = found;
-}
-
-// One decision pass.  Joined-to-batch-seed j is stored as K_old + j.
-template <int D>
-__global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S, int DP, int B,
-                                                    int K_old, float r2, int32_t* state,
-                                                    int32_t* und_counter) {
-    const int i = blockIdx.x * kWavesT + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= B) return;
-    if (__atomic_load_n(&state[i], __ATOMIC_RELAXED) != MG_UNDECIDED) return;
-    float si[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) si[k] = S[(long long)i * DP + k];
     int result = MG_FOUNDER;   // unless an earlier founder or undecided seed is within r
     for (int base = 0; base < i; base += 64) {
         const int j = base + lane;
@@ -171,17 +153,22 @@ __global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __
     }
 }
 
+constexpr int kCompactBlock = 1024;
+constexpr int kModeTile = 256;
+
 // Pool coverage: entries of the pool list within r of a new mode [k0, k1)
-// are marked removed; k1 is read from the control block when ctl is given.
+// are marked removed (k1 is read from the control block when ctl is given).
+// Workgroups are the compaction blocks: each also writes how many of its
+// entries stay in the pool.
 template <int D>
-__global__ __launch_bounds__(kT) void cover_kernel(const float* __restrict__ X, int d,
-                                                   const int32_t* __restrict__ pool, int len,
-                                                   const float* __restrict__ modes, int DP,
-                                                   int k0, int k1, const Ctl* ctl, float r2,
-                                                   uint8_t* removed) {
-    __shared__ float tileM[kT * D];
+__global__ __launch_bounds__(kCompactBlock) void cover_kernel(
+    const float* __restrict__ X, int d, const int32_t* __restrict__ pool, int len,
+    const float* __restrict__ modes, int DP, int k0, int k1, const Ctl* ctl, float r2,
+    uint8_t* removed, int32_t* block_cnt) {
+    __shared__ float tileM[kModeTile * D];
+    __shared__ int wsum[kCompactBlock / 64];
     if (ctl) k1 = ctl->k_new;
-    const int e = blockIdx.x * kT + threadIdx.x;
+    const int e = blockIdx.x * kCompactBlock + threadIdx.x;
     bool todo = e < len && !removed[e];
     float x[D];
     if (todo) {
@@ -193,10 +180,10 @@ __global__ __launch_bounds__(kT) void cover_kernel(const float* __restrict__ X, 
         for (int k = 0; k < D; ++k) x[k] = 0.0f;
     }
     bool hit = false;
-    for (int base = k0; base < k1; base += kT) {
+    for (int base = k0; base < k1; base += kModeTile) {
         if (__syncthreads_and(!todo || hit)) break;
-        const int cnt = min(kT, k1 - base);
-        for (int q = threadIdx.x; q < cnt * D; q += kT)
+        const int cnt = min(kModeTile, k1 - base);
+        for (int q = threadIdx.x; q < cnt * D; q += kCompactBlock)
             tileM[q] = modes[(long long)(base + q / D) * DP + q % D];
         __syncthreads();
         if (todo && !hit) {
@@ -208,24 +195,17 @@ __global__ __launch_bounds__(kT) void cover_kernel(const float* __restrict__ X, 
         }
     }
     if (todo && hit) removed[e] = 1;
-}
-
-constexpr int kCompactBlock = 1024;
-
-__global__ __launch_bounds__(kCompactBlock) void compact_count_kernel(
-    const uint8_t* __restrict__ removed, int len, int32_t* block_cnt) {
-    __shared__ int wsum[kCompactBlock / 64];
-    const int e = blockIdx.x * kCompactBlock + threadIdx.x;
-    const bool keep = e < len && !removed[e];
-    unsigned long long b = __ballot(keep);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(b);
+    const unsigned long long bal = __ballot(todo && !hit);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = __popcll(bal);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int s = 0;
-        for (int w = 0; w < kCompactBlock / 64; ++w) s += wsum[w];
-        block_cnt[blockIdx.x] = s;
+        int c = 0;
+        for (int w = 0; w < kCompactBlock / 64; ++w) c += wsum[w];
+        block_cnt[blockIdx.x] = c;
     }
 }
+
+
 
 // Exclusive scan of the block counts by one workgroup; writes the total.
 __global__ __launch_bounds__(1024) void compact_scan_kernel(int32_t* block_cnt, int nb,
@@ -252,11 +232,12 @@ __global__ __launch_bounds__(1024) void compact_scan_kernel(int32_t* block_cnt, 
 }
 
 __global__ __launch_bounds__(kCompactBlock) void compact_scatter_kernel(
-    const int32_t* __restrict__ pool_in, const uint8_t* __restrict__ removed, int len,
+    const int32_t* __restrict__ pool_in, uint8_t* removed, int len,
     const int32_t* __restrict__ block_off, int32_t* pool_out) {
     __shared__ int wbase[kCompactBlock / 64];
     const int e = blockIdx.x * kCompactBlock + threadIdx.x;
     const bool keep = e < len && !removed[e];
+    if (e < len && !keep) removed[e] = 0;   // leaves the flags clear for the next round
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned long long b = __ballot(keep);
     if (lane == 0) wbase[w] = __popcll(b);
@@ -289,13 +270,6 @@ hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_gather_ids(const int32_t* pool, const int32_t* pos, int B, int32_t* ids,
-                             uint8_t* removed, hipStream_t s) {
-    hipLaunchKernelGGL(gather_ids_kernel, dim3((B + 255) / 256), dim3(256), 0, s, pool, pos, B,
-                       ids, removed);
-    return hipGetLastError();
-}
-
 #define FMS_DSWITCH(D_, CALL)                                 \
     switch (D_) {                                             \
         case 1: { constexpr int DD = 1; CALL; } break;        \
@@ -309,23 +283,19 @@ hipError_t launch_gather_ids(const int32_t* pool, const int32_t* pos, int B, int
         default: return hipErrorInvalidValue;                 \
     }
 
-hipError_t launch_merge_first_old(const float* S, int DP, int d, const uint8_t* status, int B,
-                                  const float* modes, int K_old, float r2, int32_t* state,
-                                  hipStream_t s) {
+hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t* status, int B,
+                                    const float* modes, int K_old, float r2, int32_t* state,
+                                    int32_t* und_counter, bool first, hipStream_t s) {
     const int D = step_shape(d).D;
     if (B <= 0) return hipSuccess;
-    FMS_DSWITCH(D, hipLaunchKernelGGL((first_old_kernel<DD>), dim3((B + kWavesT - 1) / kWavesT),
-                                      dim3(kT), 0, s, S, DP, status, B, modes, K_old, r2,
-                                      state));
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_decide_pass(const float* S, int DP, int d, int B, int K_old, float r2,
-                                    int32_t* state, int32_t* und_counter, hipStream_t s) {
-    const int D = step_shape(d).D;
-    if (B <= 0) return hipSuccess;
-    FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD>), dim3((B + kWavesT - 1) / kWavesT),
-                                      dim3(kT), 0, s, S, DP, B, K_old, r2, state, und_counter));
+    const dim3 grid((B + kWavesT - 1) / kWavesT);
+    if (first) {
+        FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD, true>), grid, dim3(kT), 0, s, S, DP,
+                                          status, B, modes, K_old, r2, state, und_counter));
+    } else {
+        FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD, false>), grid, dim3(kT), 0, s, S, DP,
+                                          status, B, modes, K_old, r2, state, und_counter));
+    }
     return hipGetLastError();
 }
 
@@ -337,18 +307,19 @@ hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const
 }
 
 hipError_t launch_cover(const float* X, int d, const int32_t* pool, int len, const float* modes,
-                        int k0, int k1, const Ctl* ctl, float r2, uint8_t* removed, hipStream_t s) {
-    if (len <= 0 || (!ctl && k1 <= k0)) return hipSuccess;
+                        int k0, int k1, const Ctl* ctl, float r2, uint8_t* removed,
+                        int32_t* block_cnt, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
     const StepShape sh = step_shape(d);
-    FMS_DSWITCH(sh.D, hipLaunchKernelGGL((cover_kernel<DD>), dim3((len + kT - 1) / kT),
-                                         dim3(kT), 0, s, X, d, pool, len, modes, sh.DP, k0, k1,
-                                         ctl, r2, removed));
+    FMS_DSWITCH(sh.D, hipLaunchKernelGGL((cover_kernel<DD>), dim3((len + kCompactBlock - 1) / kCompactBlock),
+                                         dim3(kCompactBlock), 0, s, X, d, pool, len, modes, sh.DP,
+                                         k0, k1, ctl, r2, removed, block_cnt));
     return hipGetLastError();
 }
 
 int pool_compact_blocks(int len) { return (len + kCompactBlock - 1) / kCompactBlock; }
 
-hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, int len,
+hipError_t launch_pool_compact(const int32_t* pool_in, uint8_t* removed, int len,
                                int32_t* pool_out, int32_t* block_tmp, Ctl* ctl, hipStream_t s) {
     const int nb = pool_compact_blocks(len);
     if (nb == 0) {
@@ -356,8 +327,6 @@ hipError_t launch_pool_compact(const int32_t* pool_in, const uint8_t* removed, i
                            &ctl->pool_len);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(compact_count_kernel, dim3(nb), dim3(kCompactBlock), 0, s, removed, len,
-                       block_tmp);
     hipLaunchKernelGGL(compact_scan_kernel, dim3(1), dim3(1024), 0, s, block_tmp, nb,
                        &ctl->pool_len);
     hipLaunchKernelGGL(compact_scatter_kernel, dim3(nb), dim3(kCompactBlock), 0, s, pool_in,

@@ -120,6 +120,46 @@ __global__ void seed_key_kernel(const float* __restrict__ S, int DP, int D, int 
     vals[j] = j;
 }
 
+// Small batches (m <= 4096) in one workgroup: keys as above, then a bitonic
+// sort of (key << 32 | slot) in LDS -- the slot in the low bits makes every
+// key distinct, so the result is the stable order.
+constexpr int kSeedSortMax = 4096;
+
+__global__ __launch_bounds__(1024) void seed_order_small_kernel(
+    const float* __restrict__ S, int DP, int D, int m, float scale,
+    const uint8_t* __restrict__ status, const float* __restrict__ bnd, int32_t* act0) {
+    __shared__ unsigned long long key[kSeedSortMax];
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int e = threadIdx.x; e < P; e += 1024) {
+        unsigned long long k = ~0ull;
+        if (e < m) {
+            unsigned mk = morton_key(S + (long long)e * DP, D, scale, bnd);
+            if (status[e] != ST_ACTIVE) mk |= 1u << 30;
+            k = ((unsigned long long)mk << 32) | (unsigned)e;
+        }
+        key[e] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int e = threadIdx.x; e < P; e += 1024) {
+                const int o = e ^ stride;
+                if (o > e) {
+                    const bool up = (e & size) == 0;
+                    const unsigned long long x = key[e], y = key[o];
+                    if ((x > y) == up) {
+                        key[e] = y;
+                        key[o] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < m; e += 1024) act0[e] = (int32_t)(key[e] & 0xffffffffu);
+}
+
 // Stable LSD radix sort, 8 bits per pass.  Per-block digit counts go to
 // hist (digit-major, 256 x nblocks); the digit totals are summed into dtot with
 // integer atomics (order-independent).
@@ -365,6 +405,11 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
                              const uint8_t* status, void* ws, int32_t* act0, hipStream_t s) {
     if (m < 2) return hipSuccess;
     const SortWs w = carve(ws, m);
+    if (m <= kSeedSortMax) {
+        hipLaunchKernelGGL(seed_order_small_kernel, dim3(1), dim3(1024), 0, s, S, DP, D, m, scale,
+                           status, w.bnd, act0);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(seed_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, S, DP, D, m, scale,
                        status, w.bnd, w.k0, w.v0);
     radix_sort_pairs(w, m, s);

@@ -48,13 +48,14 @@ __global__ void pack_points_kernel(const float* __restrict__ X, int n, int d, in
     Xp[e] = (k < d) ? X[(long long)i * d + k] * scale : 0.0f;
 }
 
-__global__ void ctl_reset_kernel(Ctl* ctl, int B, int need, int max_iter) {
+__device__ void ctl_reset_body(Ctl* ctl, int B, int need, int max_iter) {
     for (int u = threadIdx.x; u <= max_iter; u += blockDim.x) ctl->conv_it[u] = 0;
     if (threadIdx.x < kMaxMergePasses) ctl->und[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         ctl->count[0] = B;
         ctl->count[1] = 0;
         ctl->count[2] = 0;
+        ctl->conv_base[0] = 0;
         ctl->need = need;
         ctl->iters_run = 0;
         ctl->pool_len = 0;
@@ -63,13 +64,31 @@ __global__ void ctl_reset_kernel(Ctl* ctl, int B, int need, int max_iter) {
     }
 }
 
-__global__ void seed_init_ids_kernel(const float* __restrict__ X, int d, int DP,
-                                     const int32_t* __restrict__ ids, int B, float* S,
-                                     int32_t* act0, uint8_t* status, int32_t* iters,
-                                     float* shift2) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void ctl_reset_kernel(Ctl* ctl, int B, int need, int max_iter) {
+    ctl_reset_body(ctl, B, need, max_iter);
+}
+
+// Start of a fit round in one launch: the B drawn seeds (pool[pos[j]], or
+// j itself when pos is NULL) leave the pool (removed flag), their positions
+// become the batch's seeds, every seed starts active and undecided for the
+// merge, and workgroup 0 resets the control block.
+__global__ void round_init_kernel(const float* __restrict__ X, int d, int DP,
+                                  const int32_t* __restrict__ pool, const int32_t* __restrict__ pos,
+                                  int B, int32_t* ids, uint8_t* removed, int32_t* merge_state,
+                                  float* S, int32_t* act0, uint8_t* status, int32_t* iters,
+                                  float* shift2, Ctl* ctl, int need, int max_iter) {
+    if (blockIdx.x == 0) ctl_reset_body(ctl, B, need, max_iter);
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= B) return;
-    long long src = (long long)ids[j] * d;
+    int id = j;
+    if (pos) {
+        const int p = pos[j];
+        id = pool[p];
+        removed[p] = 1;
+    }
+    ids[j] = id;
+    merge_state[j] = MG_UNDECIDED;
+    const long long src = (long long)id * d;
     for (int k = 0; k < DP; ++k) S[(long long)j * DP + k] = (k < d) ? X[src + k] : 0.0f;
     act0[j] = j;
     status[j] = ST_ACTIVE;
@@ -110,13 +129,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
     Ctl* ctl = a.ctl;
     const int n = a.n;
     const int m = active_count(ctl, t);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[(t + 2) % 3] = 0;   // output of the next iteration
-        if (m > 0) {
-            ctl->pairs += (long long)m * n;
-            ctl->iters_run = t + 1;
-        }
-    }
+    step_prologue(a, t, m);
     if (m == 0) return;
     const int G = gridDim.x;
     const int tiles = (m + TS - 1) / TS;
@@ -245,6 +258,7 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
     a.shift2 = b.shift2;
     a.part = b.part;
     a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
+    a.prog = b.prog;
     a.ctl = b.ctl;
     a.h2 = b.h * b.h;
     a.scale = b.scale;
@@ -319,10 +333,13 @@ hipError_t launch_ctl_reset(Ctl* ctl, int B, int need, int max_iter, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_seed_init_from_ids(const float* X, int d, int DP, const int32_t* ids, int B,
-                                     Batch& b, hipStream_t s) {
-    hipLaunchKernelGGL(seed_init_ids_kernel, dim3((B + 255) / 256), dim3(256), 0, s, X, d, DP,
-                       ids, B, b.S, b.act[0], b.status, b.iters, b.shift2);
+hipError_t launch_round_init(const float* X, int d, int DP, const int32_t* pool,
+                             const int32_t* pos, int B, int32_t* ids, uint8_t* removed,
+                             int32_t* merge_state, Batch& b, int need, int max_iter, hipStream_t s) {
+    const int blocks = B > 0 ? (B + 255) / 256 : 1;
+    hipLaunchKernelGGL(round_init_kernel, dim3(blocks), dim3(256), 0, s, X, d, DP, pool, pos, B,
+                       ids, removed, merge_state, b.S, b.act[0], b.status, b.iters, b.shift2,
+                       b.ctl, need, max_iter);
     return hipGetLastError();
 }
 

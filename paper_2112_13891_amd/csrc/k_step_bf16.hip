@@ -51,10 +51,13 @@ struct Bf16Args {
 __device__ __forceinline__ float bf(float x) { return (float)(__bf16)x; }
 
 // Point-side operands, built once per fit from the sorted points and the
-// block centres.  pf[i][s]: s in [0,D) x~h, [D,2D) x~h, [2D,3D) x~l,
-// 3D: -|x~|^2 hi, 3D+1: -|x~|^2 lo, 3D+2 and 3D+3: 1 (padding points carry
-// -inf so that their weight is 0).  xv[tile][kb][hh][c][e]: column c of
-// [x~h | x~l | 1] for the point 16 kb + 8 (e/4) + 4 hh + e%4 of the tile.
+// block centres.  Feature slots s of point i: s in [0,D) x~h, [D,2D) x~h,
+// [2D,3D) x~l, 3D: -|x~|^2 hi, 3D+1: -|x~|^2 lo, 3D+2 and 3D+3: 1 (padding
+// points carry -inf so that their weight is 0), stored as
+// pf[tile][s / 8][i % 32][s % 8] for the 32-point tile of i, so that the
+// 64 lanes of a wave read 1 KB contiguously (no LDS bank conflicts).
+// xv[tile][kb][hh][c][e]: column c of [x~h | x~l | 1] for the point
+// 16 kb + 8 (e/4) + 4 hh + e%4 of the tile.
 template <int D>
 __global__ void bf16_features_kernel(const float* __restrict__ Xs, int n, int npad,
                                      const float* __restrict__ geom, __bf16* pf, __bf16* xv) {
@@ -72,7 +75,7 @@ __global__ void bf16_features_kernel(const float* __restrict__ Xs, int n, int np
         nx = fmaf(xt[k], xt[k], nx);
     }
     const float nxh = bf(nx), nxl = bf(nx - nxh);
-    __bf16* out = pf + (long long)i * 16;
+    __bf16* out = pf + (long long)(i >> 5) * 512 + (i & 31) * 8;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         float v = 0.0f;
@@ -82,7 +85,7 @@ __global__ void bf16_features_kernel(const float* __restrict__ Xs, int n, int np
         else if (s == 3 * D) v = live ? -nxh : -__builtin_inff();
         else if (s == 3 * D + 1) v = live ? -nxl : 0.0f;
         else if (s < 3 * D + 4) v = 1.0f;
-        out[s] = (__bf16)v;
+        out[(s >> 3) * 256 + (s & 7)] = (__bf16)v;
     }
     const int tile = i >> 5, p = i & 31;
     const int kb = p >> 4, r = p & 15, hh = (r >> 2) & 1, e = ((r >> 3) << 2) | (r & 3);
@@ -141,13 +144,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     Ctl* ctl = a.ctl;
     const int n = a.n;
     const int m = active_count(ctl, t);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->count[(t + 2) % 3] = 0;
-        if (m > 0) {
-            ctl->pairs += (long long)m * n;
-            ctl->iters_run = t + 1;
-        }
-    }
+    step_prologue(a, t, m);
     if (m == 0) return;
     const int G = gridDim.x;
     const int tiles = (m + TS - 1) / TS;
@@ -158,7 +155,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     const int col = lane & 31, hf = lane >> 5;
 
     __shared__ __attribute__((aligned(16))) char stage[kPfBytes + kXvBytes + kXsBytes];
-    __shared__ float tr[kB16Threads / 64][NCOL][32];   // per-wave transpose
+    __shared__ float tr[kB16Threads / 64][NCOL][33];   // per-wave transpose (padded)
     __shared__ float fin[(D + 1) * TS];
     const __bf16* spf = reinterpret_cast<const __bf16*>(stage);
     const __bf16* sxv = reinterpret_cast<const __bf16*>(stage + kPfBytes);
@@ -243,22 +240,31 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             }
 #pragma unroll 1
             for (int tt = 0; tt < kBlk / 32; ++tt) {
-                const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(spf + (tt * 32 + col) * 16 + hf * 8);
+                const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(spf + tt * 512 + hf * 256 + col * 8);
+                // both groups' products first, so that one hides the other's latency
+                f32x16 E[R];
+                float emax[R];
+#pragma unroll
+                for (int g = 0; g < R; ++g)
+                    E[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag[g], f32x16{}, 0, 0, 0);
 #pragma unroll
                 for (int g = 0; g < R; ++g) {
-                    f32x16 E = {};
-                    E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag[g], E, 0, 0, 0);
-                    float emax = E[0];
+                    float e = E[g][0];
 #pragma unroll
-                    for (int v = 1; v < 16; ++v) emax = fmaxf(emax, E[v]);
-                    float w[16];
-                    bool far_mfma;
-                    if (__ballot(emax + eps[g] >= A.e_thr)) {
+                    for (int v = 1; v < 16; ++v) e = fmaxf(e, E[g][v]);
+                    emax[g] = e;
+                }
+#pragma unroll
+                for (int g = 0; g < R; ++g) {
+                    const bool ref = __ballot(emax[g] + eps[g] >= A.e_thr);
+                    if (ref) {
                         // some pair of this 32 x 32 tile may lie within the refine
                         // radius: every row of the lane is recomputed exactly in
                         // FP32 (points from LDS), and each pair keeps the exact
-                        // weight if and only if its own bound flags it, so the
-                        // result of a pair never depends on its tile mates
+                        // weight if and only if its own bound flags it (its
+                        // estimate is then replaced by -inf, weight 0 in the bf16
+                        // sums), so the result of a pair never depends on its
+                        // tile mates
                         const float4* xr = sxs + tt * 32 + 4 * hf;
                         unsigned nref = 0;
 #pragma unroll
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int v = 4 * q + u;
-                                const bool need = E[v] + eps[g] >= A.e_thr;
+                                const bool need = E[g][v] + eps[g] >= A.e_thr;
                                 const float xv[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
                                 float dx[D], q2 = 0.0f;
 #pragma unroll
@@ -284,26 +290,19 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
 #pragma unroll
                                 for (int k = 0; k < D; ++k) aex[g][k] = fmaf(we, dx[k], aex[g][k]);
                                 nref += need ? 1u : 0u;
-                                w[v] = need ? 0.0f : __builtin_amdgcn_exp2f(E[v]);
+                                E[g][v] = need ? -__builtin_inff() : E[g][v];
                             }
                         }
                         refined += live[g] ? nref : 0u;
-                        far_mfma = kGauss;
-                    } else {
-                        // far tile (Gaussian): weights from the estimate, unless
-                        // every weight of the wave underflows (2^-127)
-                        far_mfma = kGauss && __ballot(emax >= -127.0f);
-                        if (far_mfma) {
-#pragma unroll
-                            for (int v = 0; v < 16; ++v) w[v] = __builtin_amdgcn_exp2f(E[v]);
-                        }
                     }
-                    if (far_mfma) {
+                    // far pairs (Gaussian only): weights from the estimate, unless
+                    // every weight of the wave underflows (2^-127)
+                    if (kGauss && (ref || __ballot(emax[g] >= -127.0f))) {
                         bf16x8 w0, w1;
 #pragma unroll
                         for (int q = 0; q < 8; ++q) {
-                            w0[q] = (__bf16)w[q];
-                            w1[q] = (__bf16)w[8 + q];
+                            w0[q] = (__bf16)__builtin_amdgcn_exp2f(E[g][q]);
+                            w1[q] = (__bf16)__builtin_amdgcn_exp2f(E[g][8 + q]);
                         }
                         bf16x8 x0 = {}, x1 = {};
                         if (col < NCOL) {
@@ -397,6 +396,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     a.shift2 = b.shift2;
     a.part = b.part;
     a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
+    a.prog = b.prog;
     a.ctl = b.ctl;
     a.h2 = b.h * b.h;
     a.scale = b.scale;
@@ -423,8 +423,10 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
 
 StepShape step_shape_bf16(int d, int B) {
     StepShape sh = step_shape(d);
-    // 4 waves x R groups of 32 seeds; R = 2 once the batch fills it
-    const int groups = B >= 2 * kB16Seeds ? 2 : 1;
+    // 4 waves x R groups of 32 seeds.  Two groups share each staged block and
+    // pay off for mid-sized batches; one group needs fewer registers (4 waves
+    // per SIMD instead of 2), which wins for small and for large batches.
+    const int groups = (B >= 2 * kB16Seeds && B <= 1024) ? 2 : 1;
     sh.R = 2 * groups;     // the finalize geometry: TS = 64 * R
     sh.TS = kB16Seeds * groups;
     return sh;

@@ -25,9 +25,14 @@ __device__ __forceinline__ int chunks_for(int m, int TS, int n, int grid) {
 
 __device__ __forceinline__ int active_count(const Ctl* ctl, int t) {
     // early stop (Section II-C): once `need` seeds converged, nothing is active
-    int conv = 0;
-    for (int u = 0; u < t; ++u) conv += ctl->conv_it[u];
-    return (conv >= ctl->need) ? 0 : ctl->count[t % 3];
+    return (ctl->conv_base[t % 3] >= ctl->need) ? 0 : ctl->count[t % 3];
+}
+
+// Seeds that converged at iteration t: per-iteration count and the running
+// total that iteration t + 1 starts from.
+__device__ __forceinline__ void add_converged(Ctl* ctl, int t, int c) {
+    atomicAdd(&ctl->conv_it[t], c);
+    atomicAdd(&ctl->conv_base[(t + 1) % 3], c);
 }
 
 struct StepArgs {
@@ -41,9 +46,29 @@ struct StepArgs {
     float* shift2;
     float* part;
     float* red;        // per-slot sums reduced from many chunk partials
+    unsigned long long* prog;   // host-mapped progress word, or NULL
     Ctl* ctl;
     float h2, scale, inv_scale, thr2;
 };
+
+// Done once per iteration by thread 0 of workgroup 0 of the step kernel:
+// reset the count of the iteration after next, carry the converged total
+// into the slot of the next iteration, account the pairs, and
+// publish (t, m) to the host-mapped progress word so that the host can stop
+// enqueueing iterations once m reaches 0 (system-scope vector store).
+__device__ __forceinline__ void step_prologue(const StepArgs& a, int t, int m) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    Ctl* ctl = a.ctl;
+    ctl->count[(t + 2) % 3] = 0;
+    ctl->conv_base[(t + 1) % 3] = ctl->conv_base[t % 3];   // finalize of t adds to it
+    if (m > 0) {
+        ctl->pairs += (long long)m * a.n;
+        ctl->iters_run = t + 1;
+    }
+    if (a.prog)
+        __hip_atomic_store(a.prog, ((unsigned long long)(unsigned)t << 32) | (unsigned)m,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Update and convergence test of one seed (slot of the active list) from its
 // sums a[0..D) = sum w (x - s) (packed units) and a[D] = sum w.  Returns
@@ -100,7 +125,7 @@ __device__ void finalize_tile(const StepArgs& a, int t, int m, int tile, const f
     int base = 0;
     if (lane == 0) {
         if (keep) base = atomicAdd(&a.ctl->count[(t + 1) % 3], __popcll(keep));
-        if (done) atomicAdd(&a.ctl->conv_it[t], __popcll(done));
+        if (done) add_converged(a.ctl, t, __popcll(done));
     }
     base = __shfl(base, 0);
     if (res == 1) a.act_out[base + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
@@ -129,7 +154,7 @@ __device__ __forceinline__ void compact_wave(const StepArgs& a, int t, int slot,
     int off = 0;
     if (lane == 0) {
         if (keep) off = atomicAdd(&a.ctl->count[(t + 1) % 3], __popcll(keep));
-        if (done) atomicAdd(&a.ctl->conv_it[t], __popcll(done));
+        if (done) add_converged(a.ctl, t, __popcll(done));
     }
     off = __shfl(off, 0);
     if (res == 1) a.act_out[off + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
