@@ -18,8 +18,9 @@ Printed (one JSON line):
   cpu_baseline     the FP64 oracle on the host's cores, on the same fit.
 """
 import argparse
+import glob
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -36,14 +37,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS_MD = os.path.join(ROOT, "profiles", "counters_fused_step_aniso3d_512x200000.md")
+
+
+def source_digest():
+    """Digest of the HIP sources, recorded next to the counter figures so that
+    stale figures are never reported."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2112_13891_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_figures(prec):
+    """HBM bytes per fused-step iteration (step + reduction + finalize) at the
+    512 x 200,000 launch, from the committed FETCH_SIZE / WRITE_SIZE summary
+    (scaled by a copy kernel of known size), and the MFMA flops the step
+    kernel executed (K padded to 16); both None when the sources changed since
+    the counters were taken."""
+    try:
+        text = open(COUNTERS_MD).read()
+    except OSError:
+        return None, None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != source_digest():
+        return None, None
+    tb = vals.get(f"{prec}_traffic_bytes_per_iteration")
+    mb = vals.get(f"{prec}_mfma_flops_per_iteration")
+    return (float(tb) if tb else None), (float(mb) if mb else None)
+
+
 def flops_per_pair(d):
     # distance 2D+3, weight 2 (+1 exp, not counted), accumulate 2D+1
     return 4 * d + 6
 
 
+def algorithmic_bytes(prec, m, n):
+    """Bytes one iteration must move at m seeds x n points, D = 3: the packed
+    points once per seed tile (16 B per point; the BF16 form also reads its
+    64 B of per-point operands), plus each seed's partial sums once written
+    and once read (16 B per seed and point chunk)."""
+    if prec == "bf16":
+        groups = 2 if 256 <= m <= 1024 else 1
+        tiles = -(-m // (128 * groups))
+        chunks = max(1, 2048 // tiles) if tiles < 2048 else 1
+        chunks = min(chunks, -(-n // 256))
+        per_point = 16 + 64
+    else:
+        tiles = -(-m // 256)
+        grid = min(2048, tiles * (-(-n // 256)))
+        chunks = min(max(1, grid // tiles), -(-n // 256))
+        per_point = 16
+    return tiles * n * per_point + 2 * m * chunks * 16
+
+
 def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
     """Average duration of one fused-step iteration with every seed active:
-    (t(iters) - t(0)) / iters, HIP events on the library's stream."""
+    (t(2k iterations) - t(k)) / k, HIP events on the library's stream, so that
+    the call's set-up (packing, sorting, workspace) cancels out."""
     def run(k):
         st = torch.cuda.current_stream()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -54,9 +110,66 @@ def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
     run(iters)  # warm
-    base = min(run(0) for _ in range(3))
-    full = min(run(iters) for _ in range(3))
+    base = min(run(iters) for _ in range(3))
+    full = min(run(2 * iters) for _ in range(3))
     return (full - base) / iters
+
+
+def other_configs(api, torch, workloads):
+    """Secondary workloads of the method, each timed briefly: the 2-D blob fit,
+    the 32-D embedding fit (Gaussian, FP32), and the differentiable form
+    (64 clouds x 16,384 points x 16, T = 10 unrolled steps, forward + adjoint)."""
+    import numpy as np
+    from paper_2112_13891_amd.autograd import MeanShiftT
+    out = {}
+
+    def fit_rate(w, steps, **kw):
+        X = torch.from_numpy(w.X).cuda()
+        api.fit(X, w.h, kernel=w.kernel, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = api.fit(X, w.h, kernel=w.kernel, **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        return {"time_to_cluster_ms": dt * 1e3, "pair_evals_per_s": r.pairs / dt, "K": r.k,
+                "rounds": [int(b) for b in r.round_B], "pairs_per_fit": r.pairs}
+
+    w = workloads.blobs2d(seed=0)
+    out["blobs2d_fp32"] = fit_rate(w, 10)
+    out["blobs2d_fp32"]["workload"] = "blobs2d: 2,000 points, D=2, 5 blobs, Gaussian h=5, pool seeding"
+    out["blobs2d_bf16"] = fit_rate(w, 10, precision="bf16")
+    w = workloads.embed32(seed=0)
+    out["embed32_gaussian_fp32"] = fit_rate(w, 2)
+    out["embed32_gaussian_fp32"]["workload"] = ("embed32: 262,144 points, D=32, 100 clusters + 5% "
+                                                "outliers, Gaussian h=1.5, pool seeding")
+    # differentiable form
+    clouds = workloads.diffclouds(seed=0)
+    X = torch.from_numpy(np.stack([c[0] for c in clouds])).cuda()
+    C = torch.from_numpy(np.stack([c[2][c[1]] for c in clouds]).astype(np.float32)).cuda()
+
+    def fwd_bwd():
+        Xr = X.detach().requires_grad_(True)
+        S = MeanShiftT.apply(Xr, 1.0, 10)
+        loss = ((S - C) ** 2).sum()
+        loss.backward()
+        return Xr.grad
+
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 2
+    for _ in range(steps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    B, n, d = X.shape
+    fwd_pairs = B * n * n * 10
+    out["diffclouds_fp32"] = {"workload": "64 clouds x 16,384 points, D=16, T=10 Gaussian steps, h=1, "
+                                          "loss vs generating centres; forward + adjoint",
+                              "ms_per_step": dt * 1e3, "forward_pair_evals_per_step": fwd_pairs,
+                              "forward_pair_evals_per_s_over_step": fwd_pairs / dt}
+    return out
 
 
 def cpu_baseline(w, args):
@@ -80,6 +193,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"],
                     help="precision of the headline value; the other form is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the secondary workloads (2-D blobs, 32-D embedding, adjoint)")
     ap.add_argument("--kernel-iters", type=int, default=20)
     ap.add_argument("--phase", default="all", choices=["all", "kernel", "fit"],
                     help="kernel: only the dominant-kernel launch shape (both precisions) and a "
@@ -167,11 +282,20 @@ def main():
     t_it = time_kernel(api, torch, X, seeds, w.h, w.kernel, args.precision, args.kernel_iters)
     pairs = m * n
     achieved_tflops = pairs * flops_per_pair(d) / (t_it * 1e-3) / 1e12
+    traffic, mfma_flops = counter_figures(args.precision)
+    step_name = "step_bf16_kernel" if args.precision == "bf16" else "step_kernel"
     roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VEC_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VEC_PEAK_TFLOPS, "traffic": None,
-            "kernel": "fused step (step_kernel + finalize_kernel, one iteration)",
+            "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VEC_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": f"one fused-step iteration: {step_name} + reduce_kernel + finalize_kernel",
             "launch": f"{m} seeds x {n} points", "avg_ms": t_it,
+            "flops_per_pair": flops_per_pair(d),
+            "algorithmic_bytes": algorithmic_bytes(args.precision, m, n),
             "pair_evals_per_s": pairs / (t_it * 1e-3)}
+    if mfma_flops:
+        # matrix cores: executed (padded) bf16 MFMA work against the dense bf16 peak
+        roof["mfma_tflops_executed"] = mfma_flops / (t_it * 1e-3) / 1e12
+        roof["mfma_frac_of_bf16_peak"] = roof["mfma_tflops_executed"] / BF16_MFMA_PEAK_TFLOPS
     log(f"kernel: {t_it * 1e3:.1f} us/iteration at {m}x{n}: {pairs / (t_it * 1e-3):.3e} pairs/s, "
         f"{achieved_tflops:.2f} TFLOP/s")
 
@@ -217,6 +341,9 @@ def main():
     out[f"{other}_kernel_pair_evals_per_s"] = pairs / (t_other * 1e-3)
     out["kernel_speedup_vs_" + other] = t_other / t_it
     log(f"{other} kernel: {t_other * 1e3:.1f} us/iteration -> {pairs / (t_other * 1e-3):.3e} pairs/s")
+    if not args.no_other_configs:
+        out["other_configs"] = other_configs(api, torch, workloads)
+        log("other configs:", json.dumps(out["other_configs"]))
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, args)
         out["cpu_baseline"] = cb

@@ -43,6 +43,7 @@ struct StepShape {
     int DP;     // row stride of the packed point / seed arrays (floats)
     int R;      // seeds per lane
     int TS;     // seeds per tile = 64 * R
+    int MC;     // points per point chunk, at least
 };
 
 // Default shape for dimension d; step_shape_for() also picks R from the

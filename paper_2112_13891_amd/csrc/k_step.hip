@@ -133,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
     if (m == 0) return;
     const int G = gridDim.x;
     const int tiles = (m + TS - 1) / TS;
-    const int chunks = chunks_for(m, TS, n, G);
+    const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
     // the wave index is uniform across a wave; saying so lets the point
     // stream use scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -250,6 +250,7 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
     a.Xp = b.Xp;
     a.n = b.n;
     a.d = b.d;
+    a.min_chunk = b.sh.MC;
     a.S = b.S;
     a.act_in = b.act[t & 1];
     a.act_out = b.act[(t + 1) & 1];
@@ -277,6 +278,10 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
 
 }  // namespace
 
+// Points per point chunk, at least: smaller chunks spread a small batch of
+// seeds over more workgroups (measured best at 256 for both forms).
+constexpr int kStepMinChunk = 256;
+
 StepShape step_shape(int d) {
     StepShape sh;
     if (d <= 4) sh.D = d;
@@ -287,6 +292,7 @@ StepShape step_shape(int d) {
     sh.DP = sh.D < 4 ? 4 : sh.D;
     sh.R = sh.D <= 4 ? 4 : (sh.D <= 8 ? 2 : 1);
     sh.TS = 64 * sh.R;
+    sh.MC = kStepMinChunk;
     return sh;
 }
 
@@ -300,7 +306,7 @@ StepShape step_shape_for(int d, int B) {
 
 int step_grid(const StepShape& sh, int B, int n) {
     long long tiles = (B + sh.TS - 1) / sh.TS;
-    long long chunks = (n + kMinChunk - 1) / kMinChunk;
+    long long chunks = (n + sh.MC - 1) / sh.MC;
     long long g = tiles * chunks;
     if (g > kMaxGrid) g = kMaxGrid;
     return (int)(g < 1 ? 1 : g);

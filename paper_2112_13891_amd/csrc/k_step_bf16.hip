@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     if (m == 0) return;
     const int G = gridDim.x;
     const int tiles = (m + TS - 1) / TS;
-    const int chunks = chunks_for(m, TS, n, G);
+    const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
     const int nblk = (n + kBlk - 1) / kBlk;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -249,10 +249,13 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                     E[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag[g], f32x16{}, 0, 0, 0);
 #pragma unroll
                 for (int g = 0; g < R; ++g) {
-                    float e = E[g][0];
-#pragma unroll
-                    for (int v = 1; v < 16; ++v) e = fmaxf(e, E[g][v]);
-                    emax[g] = e;
+                    // tree of maxima (depth 3 instead of a chain of 8)
+                    const float m0 = fmaxf(fmaxf(E[g][0], E[g][1]), E[g][2]);
+                    const float m1 = fmaxf(fmaxf(E[g][3], E[g][4]), E[g][5]);
+                    const float m2 = fmaxf(fmaxf(E[g][6], E[g][7]), E[g][8]);
+                    const float m3 = fmaxf(fmaxf(E[g][9], E[g][10]), E[g][11]);
+                    const float m4 = fmaxf(fmaxf(E[g][12], E[g][13]), E[g][14]);
+                    emax[g] = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[g][15]));
                 }
 #pragma unroll
                 for (int g = 0; g < R; ++g) {
@@ -388,6 +391,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     a.Xp = b.Xp;
     a.n = b.n;
     a.d = b.d;
+    a.min_chunk = b.sh.MC;
     a.S = b.S;
     a.act_in = b.act[t & 1];
     a.act_out = b.act[(t + 1) & 1];
@@ -429,6 +433,7 @@ StepShape step_shape_bf16(int d, int B) {
     const int groups = (B >= 2 * kB16Seeds && B <= 1024) ? 2 : 1;
     sh.R = 2 * groups;     // the finalize geometry: TS = 64 * R
     sh.TS = kB16Seeds * groups;
+    sh.MC = 256;           // one staged block per point chunk, at least
     return sh;
 }
 

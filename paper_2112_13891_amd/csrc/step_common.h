@@ -11,14 +11,17 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kMinChunk = 256;   // points per (tile, chunk) work item, at least
 constexpr int kMaxGrid = 2048;   // 8 workgroups of 4 waves on each of 256 CUs
 
-__device__ __forceinline__ int chunks_for(int m, int TS, int n, int grid) {
+// Point chunks per seed tile for m active seeds: the grid split over the
+// tiles, with at least min_chunk points per chunk.  A function of (m, grid)
+// only, so every kernel of an iteration agrees and the result does not depend
+// on the order of the active list.
+__device__ __forceinline__ int chunks_for(int m, int TS, int n, int grid, int min_chunk) {
     int tiles = (m + TS - 1) / TS;
     if (tiles >= grid) return 1;
     int c = grid / tiles;
-    int cmax = (n + kMinChunk - 1) / kMinChunk;
+    int cmax = (n + min_chunk - 1) / min_chunk;
     if (c > cmax) c = cmax;
     return c < 1 ? 1 : c;
 }
@@ -38,6 +41,7 @@ __device__ __forceinline__ void add_converged(Ctl* ctl, int t, int c) {
 struct StepArgs {
     const float* Xp;
     int n, d;
+    int min_chunk;     // points per point chunk, at least
     float* S;
     const int32_t* act_in;
     int32_t* act_out;
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(StepArgs a, int t, 
     constexpr int kRedMaxSG = D >= 32 ? 8 : 16;   // keeps wsum within 36 KB of LDS
     const int m = active_count(a.ctl, t);
     if (m == 0) return;
-    const int chunks = chunks_for(m, TS, a.n, grid);
+    const int chunks = chunks_for(m, TS, a.n, grid, a.min_chunk);
     if (chunks <= kDirectChunks) return;
     const int per = (m + (int)gridDim.x - 1) / (int)gridDim.x;
     int SG = 1;
@@ -175,7 +179,12 @@ __global__ __launch_bounds__(kRedThreads) void reduce_kernel(StepArgs a, int t, 
     const int sidx = threadIdx.x & (SG - 1), cl = threadIdx.x / SG;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ float wsum[kRedThreads / 64][kRedMaxSG][D + 1];
-    for (int g0 = blockIdx.x * SG; g0 < m; g0 += gridDim.x * SG) {
+    // workgroups are dealt to the 8 XCDs round-robin; consecutive seed groups
+    // go to workgroups of one XCD so that the partial rows they share (8 seeds
+    // per 128-byte line) are fetched into one L2 only
+    int lb = blockIdx.x;
+    if (gridDim.x % 8 == 0) lb = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    for (int g0 = lb * SG; g0 < m; g0 += gridDim.x * SG) {
         const int slot = g0 + sidx;
         float v[D + 1];
 #pragma unroll
@@ -215,7 +224,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
     constexpr int TS = 64 * R;
     const int m = active_count(a.ctl, t);
     if (m == 0) return;
-    const int chunks = chunks_for(m, TS, a.n, grid);
+    const int chunks = chunks_for(m, TS, a.n, grid, a.min_chunk);
     if (chunks == 1) return;   // finalized inside the step kernel
     const bool pre = chunks > kDirectChunks;
     const int lane = threadIdx.x & 63;
