@@ -117,7 +117,7 @@ def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
 
 def other_configs(api, torch, workloads):
     """Secondary workloads of the method, each timed briefly: the 2-D blob fit,
-    the 32-D embedding fit (Gaussian, FP32), and the differentiable form
+    the 32-D embedding fit (Gaussian, both precisions), and the differentiable form
     (64 clouds x 16,384 points x 16, T = 10 unrolled steps, forward + adjoint)."""
     import numpy as np
     from paper_2112_13891_amd.autograd import MeanShiftT
@@ -143,6 +143,9 @@ def other_configs(api, torch, workloads):
     out["embed32_gaussian_fp32"] = fit_rate(w, 2)
     out["embed32_gaussian_fp32"]["workload"] = ("embed32: 262,144 points, D=32, 100 clusters + 5% "
                                                 "outliers, Gaussian h=1.5, pool seeding")
+    out["embed32_gaussian_bf16"] = fit_rate(w, 2, precision="bf16")
+    out["embed32_gaussian_bf16"]["speedup_vs_fp32"] = (
+        out["embed32_gaussian_fp32"]["time_to_cluster_ms"] / out["embed32_gaussian_bf16"]["time_to_cluster_ms"])
     # differentiable form
     clouds = workloads.diffclouds(seed=0)
     X = torch.from_numpy(np.stack([c[0] for c in clouds])).cuda()

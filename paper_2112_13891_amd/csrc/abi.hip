@@ -410,10 +410,16 @@ float host_dist2(const float* a, const float* b, int d) {
     return q;
 }
 
-// Refine threshold of the BF16 form on E = -|x - s|^2 in packed units: pairs
-// within refine_radius * h are recomputed exactly (at least h for the flat
-// window, whose non-refined pairs get weight 0).
-float bf16_e_thr(const ms_params* p) {
+// Refine threshold of the BF16 form on E = -|x - s|^2 in packed units.  For
+// D <= 4 pairs within refine_radius * h are recomputed exactly (at least h for
+// the flat window, whose non-refined pairs get weight 0); for larger D every
+// pair whose Gaussian weight may exceed 2^-127 (every pair that may lie in the
+// flat window) is computed exactly and the others contribute nothing.
+float bf16_e_thr(const ms_params* p, int D) {
+    if (D > 4) {
+        if (p->kernel == MS_KERNEL_GAUSSIAN) return -127.0f;
+        return -(float)((double)p->h * p->h);
+    }
     if (p->kernel == MS_KERNEL_GAUSSIAN)
         return -(float)((double)p->refine_radius * p->refine_radius * 1.4426950408889634 / 2.0);
     const double rr = std::max(1.0, (double)p->refine_radius) * p->h;
@@ -435,8 +441,9 @@ void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_par
     b.Xs = sp ? sp->Xs : nullptr;
     b.geom = sp ? sp->geom : nullptr;
     b.pf = sp ? sp->feat : nullptr;
-    b.xv = sp ? sp->feat + (size_t)((n + 255) / 256) * 256 * 16 * 2 : nullptr;
-    b.e_thr = bf16_e_thr(p);
+    b.xv = (sp && sh.D <= 4) ? sp->feat + (size_t)((n + 255) / 256) * 256 * 16 * 2 : nullptr;
+    b.shift = (sp && sh.D > 4) ? sort_frame_shift(sp->sws) : nullptr;
+    b.e_thr = bf16_e_thr(p, sh.D);
     b.kappa = 1.0f / 1024.0f;
     b.n = n;
     b.d = d;
@@ -489,11 +496,13 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     if (bf16) {
         FMS_CHECK(cache_get(C, budget, SL_XS, (size_t)n * DP, &sp.Xs));
         FMS_CHECK(cache_get(C, budget, SL_PERM, n, &sp.perm));
-        FMS_CHECK(cache_get(C, budget, SL_GEOM, (size_t)((n + 255) / 256) * kGeomStride, &sp.geom));
+        FMS_CHECK(cache_get(C, budget, SL_GEOM, (size_t)((n + 255) / 256) * geom_stride(base.D), &sp.geom));
         FMS_CHECK(cache_get(C, budget, SL_SORTWS, sort_workspace_bytes(n), (char**)&sp.sws));
-        FMS_CHECK(cache_get(C, budget, SL_FEAT, bf16_feature_bytes(n), &sp.feat));
+        FMS_CHECK(cache_get(C, budget, SL_FEAT, base.D <= 4 ? bf16_feature_bytes(n)
+                                                           : bf16w_feature_bytes(n, base.D), &sp.feat));
         FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sp.sws, s));
-        FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+        if (base.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+        else FMS_HIP(launch_bf16w_features(sp.Xs, n, base.D, sp.geom, sp.feat, s));
     }
 
     int32_t* pool[2] = {nullptr, nullptr};
@@ -566,7 +575,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             if (all)
                 FMS_HIP(hipMemcpyAsync(b.act[0], sp.perm, (size_t)B * 4, hipMemcpyDeviceToDevice, s));
             else
-                FMS_HIP(launch_seed_order(b.S, DP, b.sh.D, B, scale, b.status, sp.sws, b.act[0], s));
+                FMS_HIP(launch_seed_order(b.S, DP, b.sh.D, B, scale, b.status, sp.sws, b.act[0], Xp, n, s));
         }
 
         FMS_HIP(hipEventRecord(ev[2], s));
@@ -752,12 +761,13 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
         char* sws;
         FMS_CHECK(ws.alloc(&sp.Xs, (size_t)n * sh.DP));
         FMS_CHECK(ws.alloc(&sp.perm, n));
-        FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * kGeomStride));
+        FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * geom_stride(sh.D)));
         FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n > m ? n : m)));
-        FMS_CHECK(ws.alloc(&sp.feat, bf16_feature_bytes(n)));
+        FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n) : bf16w_feature_bytes(n, sh.D)));
         sp.sws = sws;
         FMS_HIP(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
-        FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+        if (sh.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+        else FMS_HIP(launch_bf16w_features(sp.Xs, n, sh.D, sp.geom, sp.feat, s));
     }
     Ctl* ctl;
     FMS_CHECK(ws.alloc(&ctl, 1));
@@ -773,7 +783,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_HIP(launch_ctl_reset(ctl, 0, INT_MAX, n_iter, s));
     FMS_HIP(launch_seed_init_from_array(seeds, converged, d, m, b, s));
     if (bf16)   // seeds that are close in space share waves (and refine work)
-        FMS_HIP(launch_seed_order(b.S, sh.DP, sh.D, m, scale, b.status, sp.sws, b.act[0], s));
+        FMS_HIP(launch_seed_order(b.S, sh.DP, sh.D, m, scale, b.status, sp.sws, b.act[0], Xp, n, s));
     for (int t = 0; t < n_iter; ++t) FMS_HIP(launch_iteration(b, t, s));
     FMS_HIP(launch_seed_export(b, m, seeds, converged, iters, shift2, s));
     return MS_OK;
@@ -814,7 +824,7 @@ int ms_fit(const ms_params* p, const float* X, int64_t n, int32_t d, float* mode
     if (!k_out) return fail(MS_E_INVALID, "k_out is NULL");
     if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 4 in this build");
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32 in this build");
     *k_out = 0;
     return fit_impl(p, X, (int)n, d, modes, max_modes, k_out, labels, diag, (hipStream_t)stream);
 }
@@ -829,7 +839,7 @@ int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* see
     if (m == 0) return MS_OK;
     if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 4 in this build");
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32 in this build");
     return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
 }
 

@@ -78,6 +78,7 @@ struct Batch {
     const void* xv;        // BF16 form: point operand of the second product
     float e_thr;           // BF16 form: refine threshold (packed units)
     float kappa;           // BF16 form: error bound coefficient
+    const float* shift = nullptr;   // BF16 form, D > 4: frame of the sorted points
     unsigned long long* prog = nullptr;   // host-mapped progress word (t << 32 | m), or NULL
     Ctl* ctl;
 };
@@ -109,13 +110,25 @@ size_t bf16_feature_bytes(int n);
 hipError_t launch_bf16_features(const float* Xs, int n, int d, const float* geom, void* feat,
                                 hipStream_t s);
 
+// ---- launchers (k_step_bf16w.hip): BF16 form for D in {8, 16, 32} ------------
+bool bf16w_dims(int D);
+hipError_t launch_iteration_bf16w(Batch& b, int t, hipStream_t s);
+size_t bf16w_feature_bytes(int n, int D);
+hipError_t launch_bf16w_features(const float* Xs, int n, int D, const float* geom, void* feat,
+                                 hipStream_t s);
+
 // ---- launchers (k_sort.hip) ----------------------------------------------
-constexpr int kGeomStride = 8;      // per-256-point block: centre[4], radius
+constexpr int kGeomStride = 8;      // per-256-point block (D <= 4): centre[4], radius
+// Floats per block geometry row: centre[D], radius (and for D > 4 the centre's norm).
+inline int geom_stride(int D) { return D <= 4 ? kGeomStride : D + 8; }
+// Frame shift (bounding-box midpoint) the D > 4 sort subtracts from the sorted points.
+const float* sort_frame_shift(const void* ws);
 size_t sort_workspace_bytes(int count);
 hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
                                float* geom, void* ws, hipStream_t s);
 hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
-                             const uint8_t* status, void* ws, int32_t* act0, hipStream_t s);
+                             const uint8_t* status, void* ws, int32_t* act0, const float* Xp, int n,
+                             hipStream_t s);
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);

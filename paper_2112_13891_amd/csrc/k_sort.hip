@@ -2,8 +2,10 @@
 //
 // The BF16 form centres every 256-point block of points on a local reference
 // so that the bf16 products stay accurate; that needs blocks that are compact
-// in space.  Points are ordered by the Morton code of their quantized
-// coordinates (D <= 4) with a stable LSD radix sort, deterministic (no
+// in space.  For D <= 4 points are ordered by the Morton code of their
+// quantized coordinates; for larger D (where a Morton code has too few bits
+// per axis) by their nearest pivot, pivots being a fixed sample of the points
+// (one per 1,024).  Both use a stable LSD radix sort, deterministic (no
 // floating-point atomics; ranks inside a block come from wave ballots in wave
 // order).  The order only changes which points share a block: the update sums
 // over all points whatever their order.
@@ -120,22 +122,28 @@ __global__ void seed_key_kernel(const float* __restrict__ S, int DP, int D, int 
     vals[j] = j;
 }
 
-// Small batches (m <= 4096) in one workgroup: keys as above, then a bitonic
+// Small batches (m <= 4096) in one workgroup: keys as above (or given), then a bitonic
 // sort of (key << 32 | slot) in LDS -- the slot in the low bits makes every
 // key distinct, so the result is the stable order.
 constexpr int kSeedSortMax = 4096;
 
 __global__ __launch_bounds__(1024) void seed_order_small_kernel(
     const float* __restrict__ S, int DP, int D, int m, float scale,
-    const uint8_t* __restrict__ status, const float* __restrict__ bnd, int32_t* act0) {
+    const uint8_t* __restrict__ status, const float* __restrict__ bnd,
+    const unsigned* __restrict__ keys_in, int32_t* act0) {
     __shared__ unsigned long long key[kSeedSortMax];
     int P = 1;
     while (P < m) P <<= 1;
     for (int e = threadIdx.x; e < P; e += 1024) {
         unsigned long long k = ~0ull;
         if (e < m) {
-            unsigned mk = morton_key(S + (long long)e * DP, D, scale, bnd);
-            if (status[e] != ST_ACTIVE) mk |= 1u << 30;
+            unsigned mk;
+            if (keys_in) {
+                mk = keys_in[e];
+            } else {
+                mk = morton_key(S + (long long)e * DP, D, scale, bnd);
+                if (status[e] != ST_ACTIVE) mk |= 1u << 30;
+            }
             k = ((unsigned long long)mk << 32) | (unsigned)e;
         }
         key[e] = k;
@@ -260,22 +268,78 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     }
 }
 
-__global__ void gather_rows_kernel(const float* __restrict__ Xp, int DP, const int* __restrict__ perm,
-                                   int n, float* Xs) {
+// Xs[i] = Xp[perm[i]] - shift (shift over the first D columns, NULL = 0).
+__global__ void gather_rows_kernel(const float* __restrict__ Xp, int DP, int D,
+                                   const int* __restrict__ perm, int n,
+                                   const float* __restrict__ shift, float* Xs) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long long)n * DP) return;
     const int i = (int)(e / DP), k = (int)(e % DP);
-    Xs[e] = Xp[(long long)perm[i] * DP + k];
+    const float v = Xp[(long long)perm[i] * DP + k];
+    Xs[e] = (shift && k < D) ? v - shift[k] : v;
+}
+
+// Midpoint of the bounding box (the frame of the sorted points for D > 4).
+__global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift) {
+    const int k = threadIdx.x;
+    if (k < D) shift[k] = 0.5f * (bnd[2 * k] + bnd[2 * k + 1]);
+}
+
+// Nearest pivot (ties to the lowest index) of each row r of `rows` (stride
+// DPr, times `scale`), pivots being the points Xp[j * n / P], j < P.  Rows
+// whose status is not active (when status is given) get bit 30, so that
+// they sort last.
+template <int D>
+__global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict__ rows, int m, int DPr,
+                                                        float scale, const float* __restrict__ Xp,
+                                                        int n, int DP, int P,
+                                                        const uint8_t* __restrict__ status,
+                                                        unsigned* keys, int* vals) {
+    constexpr int kTile = 128;
+    __shared__ float piv[kTile][D + 1];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    float x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = r < m ? rows[(long long)r * DPr + k] * scale : 0.0f;
+    float best = __builtin_inff();
+    int bi = 0;
+    for (int j0 = 0; j0 < P; j0 += kTile) {
+        const int cnt = min(kTile, P - j0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * D; e += 256) {
+            const int j = e / D, k = e % D;
+            piv[j][k] = Xp[((long long)(j0 + j) * n / P) * DP + k];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            float q = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float t = x[k] - piv[j][k];
+                q = fmaf(t, t, q);
+            }
+            if (q < best) {
+                best = q;
+                bi = j0 + j;
+            }
+        }
+    }
+    if (r >= m) return;
+    unsigned key = (unsigned)bi;
+    if (status && status[r] != ST_ACTIVE) key |= 1u << 30;
+    keys[r] = key;
+    vals[r] = r;
 }
 
 // Per 256-point block of the sorted points: centre = midpoint of the bounding
 // box, radius = max distance of a block point from the centre (FP32, rounded
 // up slightly so that it bounds the FP32 distances the step computes).
-// geom row (kGeomStride floats): centre[0..D), radius at [4].
+// geom row (geom_stride(D) floats): centre[0..D); radius at [4] for D <= 4,
+// at [D] for larger D, followed there by the centre's norm at [D + 1].
 __global__ __launch_bounds__(256) void block_geom_kernel(const float* __restrict__ Xs, int n, int DP,
-                                                         int D, float* geom) {
+                                                         int D, int gs, float* geom) {
     __shared__ float red[256];
-    __shared__ float ctr[4];
+    __shared__ float ctr[64];
     const int b = blockIdx.x;
     const int i = b * 256 + threadIdx.x;
     const bool live = i < n;
@@ -310,11 +374,19 @@ __global__ __launch_bounds__(256) void block_geom_kernel(const float* __restrict
         if (threadIdx.x < off) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + off]);
         __syncthreads();
     }
-    if (threadIdx.x < kGeomStride) {
-        float* g = geom + (long long)b * kGeomStride;
-        if (threadIdx.x < D) g[threadIdx.x] = ctr[threadIdx.x];
-        else if (threadIdx.x == 4) g[threadIdx.x] = sqrtf(red[0]) * 1.0001f + 1e-30f;
-        else g[threadIdx.x] = 0.0f;
+    const float radius = sqrtf(red[0]) * 1.0001f + 1e-30f;
+    float* g = geom + (long long)b * gs;
+    const int rpos = D <= 4 ? 4 : D;
+    for (int e = threadIdx.x; e < gs; e += 256) {
+        float v = 0.0f;
+        if (e < D) v = ctr[e];
+        else if (e == rpos) v = radius;
+        else if (e == rpos + 1 && D > 4) {
+            float c2 = 0.0f;
+            for (int k = 0; k < D; ++k) c2 = fmaf(ctr[k], ctr[k], c2);
+            v = sqrtf(c2) * 1.0001f;
+        }
+        g[e] = v;
     }
 }
 
@@ -335,7 +407,10 @@ struct SortWs {
     int* hist;
 };
 
-constexpr size_t kBndFloats = 8 + 2 * 4 * 256;
+// bounds: 2D final + 2D per bounds block (256 blocks), D <= 32; then the
+// frame shift (32 floats)
+constexpr size_t kShiftOff = 2 * 32 + 2 * 32 * 256;
+constexpr size_t kBndFloats = kShiftOff + 64;
 
 SortWs carve(void* ws, int count) {
     SortWs w;
@@ -380,38 +455,74 @@ size_t sort_workspace_bytes(int count) {
 // Packed points Xp (n x DP) -> sorted copy Xs, permutation perm (Xs[i] =
 // Xp[perm[i]]) and per-256-block geometry (centre, radius).  Leaves the point
 // bounds in the workspace for launch_seed_order.
+#define FMS_PIVOT_DSWITCH(D_, CALL)                       \
+    switch (D_) {                                         \
+        case 8: { constexpr int DD = 8; CALL; } break;    \
+        case 16: { constexpr int DD = 16; CALL; } break;  \
+        case 32: { constexpr int DD = 32; CALL; } break;  \
+        default: return hipErrorInvalidValue;             \
+    }
+
+int pivot_count(int n) {
+    int P = n / 1024;
+    return P < 1 ? 1 : (P > 1024 ? 1024 : P);
+}
+
 hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs, int* perm,
                                float* geom, void* ws, hipStream_t s) {
     const SortWs w = carve(ws, n);
     const int bblocks = 256;
     hipLaunchKernelGGL(bounds_kernel, dim3(bblocks), dim3(256), 0, s, Xp, n, DP, D, w.bnd);
     hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(256), 0, s, w.bnd, D, bblocks);
-    hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xp, n, DP, D, w.bnd,
-                       w.k0, w.v0);
+    const float* shift = nullptr;
+    if (D <= 4) {
+        hipLaunchKernelGGL(morton_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xp, n, DP, D, w.bnd,
+                           w.k0, w.v0);
+    } else {
+        float* sh = w.bnd + kShiftOff;
+        hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(64), 0, s, w.bnd, D, sh);
+        shift = sh;
+        const int P = pivot_count(n);
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
+                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, w.k0, w.v0));
+    }
     radix_sort_pairs(w, n, s);
     hipError_t e = hipMemcpyAsync(perm, w.v0, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),
-                       0, s, Xp, DP, perm, n, Xs);
-    hipLaunchKernelGGL(block_geom_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xs, n, DP, D, geom);
+                       0, s, Xp, DP, D, perm, n, shift, Xs);
+    hipLaunchKernelGGL(block_geom_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xs, n, DP, D,
+                       geom_stride(D), geom);
     return hipGetLastError();
 }
 
-// Active list of a batch in the Morton order of the seed positions (S in
-// original units, `scale` to packed units), active seeds first; the active
-// count in the control block is unchanged.  ws: a sort workspace of at least
-// max(n, m) elements that launch_spatial_sort filled.
+const float* sort_frame_shift(const void* ws) {
+    return (const float*)ws + kShiftOff;
+}
+
+// Active list of a batch in the order of the seed positions (S in original
+// units, `scale` to packed units) -- Morton order for D <= 4, nearest pivot
+// of the points Xp for larger D -- active seeds first; the active count in
+// the control block is unchanged.  ws: a sort workspace of at least max(n, m)
+// elements that launch_spatial_sort filled.
 hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
-                             const uint8_t* status, void* ws, int32_t* act0, hipStream_t s) {
+                             const uint8_t* status, void* ws, int32_t* act0, const float* Xp, int n,
+                             hipStream_t s) {
     if (m < 2) return hipSuccess;
     const SortWs w = carve(ws, m);
+    if (D > 4) {
+        const int P = pivot_count(n);
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((m + 255) / 256), dim3(256), 0,
+                                                s, S, m, DP, scale, Xp, n, DP, P, status, w.k0, w.v0));
+    }
     if (m <= kSeedSortMax) {
         hipLaunchKernelGGL(seed_order_small_kernel, dim3(1), dim3(1024), 0, s, S, DP, D, m, scale,
-                           status, w.bnd, act0);
+                           status, w.bnd, D > 4 ? w.k0 : nullptr, act0);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(seed_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, S, DP, D, m, scale,
-                       status, w.bnd, w.k0, w.v0);
+    if (D <= 4)
+        hipLaunchKernelGGL(seed_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, S, DP, D, m, scale,
+                           status, w.bnd, w.k0, w.v0);
     radix_sort_pairs(w, m, s);
     hipError_t e = hipMemcpyAsync(act0, w.v0, (size_t)m * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;

@@ -427,19 +427,25 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
 
 StepShape step_shape_bf16(int d, int B) {
     StepShape sh = step_shape(d);
+    sh.MC = 256;           // one staged block per point chunk, at least
+    if (sh.D > 4) {        // 4 waves x 32 seeds
+        sh.R = 2;
+        sh.TS = kB16Seeds;
+        return sh;
+    }
     // 4 waves x R groups of 32 seeds.  Two groups share each staged block and
     // pay off for mid-sized batches; one group needs fewer registers (4 waves
     // per SIMD instead of 2), which wins for small and for large batches.
     const int groups = (B >= 2 * kB16Seeds && B <= 1024) ? 2 : 1;
     sh.R = 2 * groups;     // the finalize geometry: TS = 64 * R
     sh.TS = kB16Seeds * groups;
-    sh.MC = 256;           // one staged block per point chunk, at least
     return sh;
 }
 
-bool bf16_supported(int d) { return d >= 1 && d <= 4; }
+bool bf16_supported(int d) { return d >= 1 && (d <= 4 || (d <= 32 && bf16w_dims(step_shape(d).D))); }
 
 hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s) {
+    if (b.sh.D > 4) return launch_iteration_bf16w(b, t, s);
     const bool two = b.sh.TS == 2 * kB16Seeds;
     switch (b.sh.D) {
         case 1: return two ? launch_bf16_t<1, 2>(b, t, s) : launch_bf16_t<1, 1>(b, t, s);

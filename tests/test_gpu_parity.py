@@ -318,7 +318,81 @@ def test_bf16_deterministic(aniso):
 
 
 def test_bf16_rejects_large_d():
-    X = _gpu(np.zeros((10, 5), np.float32))
+    X = _gpu(np.zeros((10, 33), np.float32))
     with pytest.raises(api.MeanShiftError) as e:
         api.fit(X, 1.0, precision="bf16")
     assert e.value.code == api.MS_E_INVALID
+
+
+# ---------------------------------------------------------------------------
+# BF16 screen form (8 <= D <= 32): products on MFMA screen the pairs, every
+# pair above the screen is exact -- same contract as the FP32 form
+# ---------------------------------------------------------------------------
+
+def _clustered(seed, n, d, k, sigma=0.5, spread=4.0, outliers=0.03):
+    rng = np.random.default_rng(seed)
+    C = spread * rng.standard_normal((k, d))
+    n_out = int(round(outliers * n))
+    y = rng.integers(0, k, n - n_out)
+    X = np.concatenate([C[y] + sigma * rng.standard_normal((n - n_out, d)),
+                        rng.uniform(-3 * spread, 3 * spread, (n_out, d))])
+    return X[rng.permutation(n)].astype(np.float32)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_bf16_step_embed32_sample(orc, embed, kernel):
+    say("bf16 step embed32 sample", kernel)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(embed.n, 96, replace=False)
+    S0 = embed.X[idx]
+    S, conv, it, sh = api.step(_gpu(embed.X), _gpu(S0), embed.h, kernel=kernel, precision="bf16",
+                               n_iter=100)
+    torch.cuda.synchronize()
+    rep = step_parity(orc, embed.X, S0, embed.h, kernel, 1e-3, S.cpu().numpy(),
+                      it.cpu().numpy(), conv.cpu().numpy())
+    say(rep)
+
+
+@pytest.mark.parametrize("n,d", [(1, 5), (2, 8), (257, 5), (1000, 7), (1031, 8), (777, 13),
+                                 (513, 16), (300, 17), (2049, 32), (4099, 24)])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+@pytest.mark.parametrize("layout", ["noise", "clusters"])
+def test_bf16_step_ragged_wide(orc, n, d, kernel, layout):
+    rng = np.random.default_rng(n * 100 + d + 11)
+    if layout == "noise":   # every pair near: the exact path everywhere
+        X = (rng.standard_normal((n, d)) * 2.0 + 50.0).astype(np.float32)
+        h = 1.5 * np.sqrt(d)
+    else:                   # separated clusters: most tiles below the screen
+        X = _clustered(n + d, n, d, 6) + np.float32(20.0)
+        h = 1.5
+    m = min(n, 300)
+    S0 = X[rng.choice(n, m, replace=False)]
+    for n_iter in (1, 3):
+        S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, precision="bf16",
+                                   n_iter=n_iter)
+        torch.cuda.synchronize()
+        ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
+        ties = ragged_check(X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        if ties:
+            say("flat boundary ties", ties)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+@pytest.mark.parametrize("all_points", [False, True])
+def test_bf16_fit_wide(orc, kernel, all_points):
+    X = _clustered(5, 4000, 32, 10)
+    h = 1.5 if kernel == "gaussian" else 4.0   # a flat window of h = 1.5 holds one point in 32-D
+    g = api.fit(_gpu(X), h, kernel=kernel, precision="bf16", all_points=all_points, trace=True)
+    ref = orc.fit(X, h, kernel=kernel, all_points=all_points)
+    rep = fit_parity(g, ref, X, h, orc=orc, kernel=kernel)
+    say("bf16 fit wide", kernel, all_points, rep, "K", g.k, "exact pairs", g.refined_pairs,
+        "of", g.pairs)
+    assert g.refined_pairs < g.pairs
+
+
+def test_bf16_deterministic_wide():
+    X = _gpu(_clustered(9, 6000, 16, 12))
+    a = api.fit(X, 1.0, precision="bf16", trace=True)
+    b = api.fit(X, 1.0, precision="bf16", trace=True)
+    assert torch.equal(a.modes, b.modes) and torch.equal(a.labels, b.labels)
+    assert np.array_equal(a.drawn_final, b.drawn_final)
