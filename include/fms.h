@@ -156,6 +156,31 @@ int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
             int32_t *iters, float *shift2, void *stream);
 
 /*
+ * ms_step_batched -- ms_step for many independent point clouds at once: cloud
+ * c owns the points X[x_off[c], x_off[c+1]) and the seeds
+ * seeds[s_off[c], s_off[c+1]), and each seed is updated with its own cloud's
+ * points only, as ms_step on that cloud would (Section II-B update, per-seed
+ * convergence of Algorithms 1-2; FP32 form).  Each iteration is one launch
+ * of each kernel for all clouds, over work items (cloud, seed tile, point
+ * chunk) planned on the device from per-cloud active counts.
+ *
+ *   X          device, (x_off[ncl]) x d float32, the clouds' points back to back.
+ *   x_off      host, ncl + 1 nondecreasing point offsets, x_off[0] = 0.
+ *   seeds      device, (s_off[ncl]) x d float32, in/out.
+ *   s_off      host, ncl + 1 nondecreasing seed offsets, s_off[0] = 0; a
+ *              cloud with seeds must have points.
+ *   ncl        1..8192 clouds.
+ *   converged, iters, shift2: as ms_step, one entry per seed.
+ * Uses p->h, kernel, tol; p->precision must be MS_PREC_FP32.  Stream-ordered;
+ * the call returns once the offsets are on the device (it waits for the work
+ * already queued on the stream), the iterations themselves run asynchronously.
+ */
+int ms_step_batched(const ms_params *p, const float *X, const int64_t *x_off,
+                    float *seeds, const int64_t *s_off, int32_t ncl, int32_t d,
+                    int32_t n_iter, uint8_t *converged, int32_t *iters,
+                    float *shift2, void *stream);
+
+/*
  * ms_assign -- "cluster x by the distance to modes" (Algorithm 2, last
  * loop): labels[i] = argmin_j |x_i - mode_j|^2 by FP32 direct differences,
  * ties to the lowest j.  margin (optional, may be NULL): distance to the

@@ -73,8 +73,8 @@ class Diag(ctypes.Structure):
     ]
 
 
-EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_assign", "ms_forward_update",
-           "ms_step_adjoint", "ms_seed_draw", "ms_last_error", "ms_version")
+EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_assign",
+           "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_last_error", "ms_version")
 
 _lib = None
 
@@ -95,6 +95,8 @@ def lib():
     L.ms_fit.restype = ctypes.c_int
     L.ms_step.argtypes = [ctypes.POINTER(Params), P, i64, i32, P, i32, i32, P, P, P, P]
     L.ms_step.restype = ctypes.c_int
+    L.ms_step_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P, P]
+    L.ms_step_batched.restype = ctypes.c_int
     L.ms_assign.argtypes = [P, i64, i32, P, i32, P, P, P]
     L.ms_assign.restype = ctypes.c_int
     L.ms_forward_update.argtypes = [P, i32, i64, P, i64, i32, ctypes.c_double, P, i32, P]
@@ -263,6 +265,37 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
     rc = lib().ms_step(ctypes.byref(p), Xp, n, d, ctypes.c_void_p(S.data_ptr()), m, int(n_iter),
                        ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
                        ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))
+    _check(rc)
+    return S, conv, iters, sh
+
+
+def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=1,
+                 converged=None):
+    """ms_step over many clouds: cloud c owns X[x_off[c]:x_off[c+1]] and
+    seeds[s_off[c]:s_off[c+1]].  Offsets are host sequences of ncl + 1 ints.
+    Returns new tensors (seeds, converged uint8, iters int32, shift2 float32)."""
+    import numpy as np
+    torch = _torch()
+    Xp = _dev(X, torch.float32, 2, "X")
+    d = X.shape[1]
+    S = seeds.detach().clone().contiguous()
+    _dev(S, torch.float32, 2, "seeds")
+    if S.shape[1] != d:
+        raise ValueError("seeds must be m x d")
+    xo = np.ascontiguousarray(np.asarray(x_off, dtype=np.int64))
+    so = np.ascontiguousarray(np.asarray(s_off, dtype=np.int64))
+    if xo.shape != so.shape or xo.ndim != 1:
+        raise ValueError("x_off and s_off must both have ncl + 1 entries")
+    m = S.shape[0]
+    conv = (torch.zeros(m, dtype=torch.uint8, device=X.device) if converged is None
+            else converged.detach().clone().to(torch.uint8).contiguous())
+    iters = torch.zeros(m, dtype=torch.int32, device=X.device)
+    sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
+    p = make_params(h, kernel, "fp32", tol)
+    rc = lib().ms_step_batched(ctypes.byref(p), Xp, xo.ctypes.data, ctypes.c_void_p(S.data_ptr()),
+                               so.ctypes.data, int(len(xo) - 1), d, int(n_iter),
+                               ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
+                               ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))
     _check(rc)
     return S, conv, iters, sh
 

@@ -789,6 +789,55 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     return MS_OK;
 }
 
+int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
+                      const int64_t* s_off, int ncl, int d, int n_iter, uint8_t* converged,
+                      int32_t* iters, float* shift2, hipStream_t s) {
+    FMS_CHECK(ensure_pool_release_threshold());
+    const int n = (int)x_off[ncl];
+    const int M = (int)s_off[ncl];
+    // seeds per lane from the mean seeds per cloud: small clouds waste fewer lanes
+    const StepShape sh = step_shape_for(d, std::max(1, M / ncl));
+    const float scale = packed_scale(p);
+    std::vector<long long> xo(ncl + 1);
+    std::vector<int32_t> so(ncl + 1);
+    for (int c = 0; c <= ncl; ++c) {
+        xo[c] = x_off[c];
+        so[c] = (int32_t)s_off[c];
+    }
+    const long long max_items = batched_max_items(xo.data(), so.data(), ncl, sh.TS);
+    if (max_items > INT_MAX / 2) return fail(MS_E_INVALID, "too many work items for one batch");
+    Workspace ws(s);
+    float* Xp;
+    FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
+    FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
+    long long* xo_dev;
+    int32_t* so_dev;
+    FMS_CHECK(ws.alloc(&xo_dev, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&so_dev, (size_t)ncl + 1));
+    FMS_HIP(hipMemcpyAsync(xo_dev, xo.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemcpyAsync(so_dev, so.data(), (size_t)(ncl + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    FMS_HIP(hipStreamSynchronize(s));   // the host copies of the offsets go out of scope
+    Batch b;
+    fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
+    FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
+    FMS_CHECK(ws.alloc(&b.act[0], M));
+    FMS_CHECK(ws.alloc(&b.act[1], M));
+    FMS_CHECK(ws.alloc(&b.status, M));
+    FMS_CHECK(ws.alloc(&b.iters, M));
+    FMS_CHECK(ws.alloc(&b.shift2, M));
+    int32_t *cnt, *plan, *item_cloud, *slot_cloud;
+    FMS_CHECK(ws.alloc(&cnt, (size_t)2 * ncl));
+    FMS_CHECK(ws.alloc(&plan, (size_t)4 * ncl + 2));
+    FMS_CHECK(ws.alloc(&item_cloud, (size_t)std::max(1LL, max_items)));
+    FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
+    FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));
+    FMS_HIP(launch_batched_init(seeds, converged, d, M, so_dev, ncl, cnt, b, s));
+    for (int t = 0; t < n_iter; ++t)
+        FMS_HIP(launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, s));
+    FMS_HIP(launch_seed_export(b, M, seeds, converged, iters, shift2, s));
+    return MS_OK;
+}
+
 }  // namespace
 }  // namespace fms
 
@@ -841,6 +890,33 @@ int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* see
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
         return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32 in this build");
     return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
+}
+
+int ms_step_batched(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
+                    const int64_t* s_off, int32_t ncl, int32_t d, int32_t n_iter, uint8_t* converged,
+                    int32_t* iters, float* shift2, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_params(p, false));
+    if (p->precision != MS_PREC_FP32)
+        return fail(MS_E_INVALID, "ms_step_batched computes the FP32 form only");
+    if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
+    if (ncl < 1 || ncl > batched_max_clouds()) return fail(MS_E_INVALID, "ncl must be in [1, 8192]");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (n_iter < 0 || n_iter > kMaxIterCap) return fail(MS_E_INVALID, "n_iter must be in [0, 4096]");
+    if (x_off[0] != 0 || s_off[0] != 0) return fail(MS_E_INVALID, "offsets must start at 0");
+    for (int c = 0; c < ncl; ++c) {
+        if (x_off[c + 1] < x_off[c] || s_off[c + 1] < s_off[c])
+            return fail(MS_E_INVALID, "offsets must be nondecreasing");
+        if (s_off[c + 1] > s_off[c] && x_off[c + 1] == x_off[c])
+            return fail(MS_E_INVALID, "a cloud with seeds has no points");
+    }
+    if (x_off[ncl] > INT_MAX || s_off[ncl] > INT_MAX)
+        return fail(MS_E_INVALID, "total points and seeds must be <= 2^31-1");
+    if (s_off[ncl] == 0) return MS_OK;
+    FMS_CHECK(check_common(X, x_off[ncl], d));
+    if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
+    return step_batched_impl(p, X, x_off, seeds, s_off, ncl, d, n_iter, converged, iters, shift2,
+                             (hipStream_t)stream);
 }
 
 int ms_assign(const float* X, int64_t n, int32_t d, const float* modes, int32_t k, int32_t* labels,

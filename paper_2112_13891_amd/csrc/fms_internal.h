@@ -117,6 +117,15 @@ size_t bf16w_feature_bytes(int n, int D);
 hipError_t launch_bf16w_features(const float* Xs, int n, int D, const float* geom, void* feat,
                                  hipStream_t s);
 
+// ---- launchers (k_batched.hip): FP32 step over many clouds ---------------------
+int batched_max_clouds();
+long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS);
+hipError_t launch_batched_init(const float* seeds, const uint8_t* conv_in, int d, int M,
+                               const int32_t* seg_dev, int ncl, int32_t* cnt, Batch& b, hipStream_t s);
+hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, const int32_t* seg_dev,
+                                    int ncl, int32_t* cnt, int32_t* plan, int32_t* item_cloud,
+                                    int32_t* slot_cloud, int t, hipStream_t s);
+
 // ---- launchers (k_sort.hip) ----------------------------------------------
 constexpr int kGeomStride = 8;      // per-256-point block (D <= 4): centre[4], radius
 // Floats per block geometry row: centre[D], radius (and for D > 4 the centre's norm).

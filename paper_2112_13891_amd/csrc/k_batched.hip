@@ -1,0 +1,283 @@
+// k_batched.hip -- the fused mean-shift iteration (FP32 form) for many
+// independent point clouds of uneven size in one launch per kernel.
+//
+// Cloud c owns the points Xp[x_off[c], x_off[c+1]) and the seeds
+// [seg[c], seg[c+1]) of the batch; each seed is updated with the points of
+// its own cloud only, exactly as a call per cloud would (Section II-B update,
+// per-seed convergence of Algorithms 1-2).
+//
+// One iteration is three launches:
+//   plan     one workgroup: from the per-cloud active counts, each cloud's
+//            seed tiles (64R seeds) and point chunks (kChunkPoints points),
+//            the prefix of work items and of active slots, and for every
+//            work item and active slot its cloud;
+//   step     a persistent grid over the work items (cloud, seed tile, point
+//            chunk), the same pair loop as the single-cloud step, one
+//            (D+1)-vector partial per seed and item;
+//   finalize one lane per active seed: its chunk partials added in chunk
+//            order, the update and convergence test, and the seed kept in
+//            its cloud's next active list (per-cloud counter).
+// The chunking depends only on the counts, never on the order of an active
+// list, so results are deterministic; no floating-point atomics.
+
+#include "step_common.h"
+
+namespace fms {
+
+namespace {
+
+constexpr int kPlanThreads = 1024;
+constexpr int kChunkPoints = 1024;
+constexpr int kBStepGrid = 2048;
+
+struct BatchedArgs {
+    int ncl;
+    const long long* x_off;   // ncl + 1 point offsets
+    const int32_t* seg;       // ncl + 1 seed offsets
+    int32_t* cnt;             // 2 x ncl active counts, by iteration t % 2
+    int32_t* tiles;           // ncl
+    int32_t* chunks;          // ncl
+    int32_t* item_pre;        // ncl + 1
+    int32_t* slot_pre;        // ncl + 1
+    int32_t* item_cloud;      // cloud of each work item
+    int32_t* slot_cloud;      // cloud of each active slot
+};
+
+__device__ __forceinline__ int upper_cloud(const int32_t* pre, int ncl, int v) {
+    // the cloud c with pre[c] <= v < pre[c + 1] (pre ascending, empty clouds skipped)
+    int lo = 0, hi = ncl;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Inclusive block scan of one value per thread (kPlanThreads threads).
+__device__ __forceinline__ int plan_scan(int v, int* wsum, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int w = 0; w < kPlanThreads / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        tot += wsum[w];
+    }
+    *total = tot;
+    __syncthreads();
+    return v + before;
+}
+
+constexpr int kMaxClouds = 8192;
+
+__global__ __launch_bounds__(kPlanThreads) void bplan_kernel(BatchedArgs B, int t, int TS) {
+    __shared__ int ipre[kMaxClouds + 1];
+    __shared__ int spre[kMaxClouds + 1];
+    __shared__ int wsum[kPlanThreads / 64];
+    const int* cin = B.cnt + (t & 1) * B.ncl;
+    int* cout = B.cnt + ((t + 1) & 1) * B.ncl;
+    int icarry = 0, scarry = 0;
+    for (int c0 = 0; c0 < B.ncl; c0 += kPlanThreads) {
+        const int c = c0 + threadIdx.x;
+        int items = 0, m = 0;
+        if (c < B.ncl) {
+            m = cin[c];
+            const long long n = B.x_off[c + 1] - B.x_off[c];
+            const int tl = (m + TS - 1) / TS;
+            const int ch = m > 0 ? (int)((n + kChunkPoints - 1) / kChunkPoints) : 0;
+            B.tiles[c] = tl;
+            B.chunks[c] = ch;
+            items = tl * ch;
+            cout[c] = 0;   // filled by this iteration's finalize
+        }
+        int itot, stot;
+        const int iinc = plan_scan(items, wsum, &itot);
+        const int sinc = plan_scan(m, wsum, &stot);
+        if (c < B.ncl) {
+            ipre[c] = icarry + iinc - items;
+            spre[c] = scarry + sinc - m;
+        }
+        icarry += itot;
+        scarry += stot;
+    }
+    if (threadIdx.x == 0) {
+        ipre[B.ncl] = icarry;
+        spre[B.ncl] = scarry;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c <= B.ncl; c += kPlanThreads) {
+        B.item_pre[c] = ipre[c];
+        B.slot_pre[c] = spre[c];
+    }
+    for (int i = threadIdx.x; i < icarry; i += kPlanThreads) B.item_cloud[i] = upper_cloud(ipre, B.ncl, i);
+    for (int g = threadIdx.x; g < scarry; g += kPlanThreads) B.slot_cloud[g] = upper_cloud(spre, B.ncl, g);
+}
+
+template <int D, int DP, int R, int KERN>
+__global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs B) {
+    constexpr int TS = 64 * R;
+    const int total = B.item_pre[B.ncl];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    __shared__ float red[(kWaves - 1) * TS * (D + 1)];
+    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        const int c = B.item_cloud[it];
+        const int local = it - B.item_pre[c];
+        const int tiles = B.tiles[c], chunks = B.chunks[c];
+        const int tile = local % tiles, chunk = local / tiles;
+        const long long x0 = B.x_off[c];
+        const long long n = B.x_off[c + 1] - x0;
+        const int m = B.slot_pre[c + 1] - B.slot_pre[c];
+        float acc[R][D + 1];
+        tile_sums<D, DP, R, KERN>(a, a.Xp + x0 * DP, n * chunk / chunks, n * (chunk + 1) / chunks,
+                                  a.act_in + B.seg[c], tile * TS, m, acc, red);
+        if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float* dst = a.part + ((long long)it * TS + r * 64 + lane) * (D + 1);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) dst[k] = acc[r][k];
+            }
+        }
+    }
+}
+
+template <int D, int DP, int R>
+__global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, BatchedArgs B, int t) {
+    constexpr int TS = 64 * R;
+    const int total = B.slot_pre[B.ncl];
+    int* cout = B.cnt + ((t + 1) & 1) * B.ncl;
+    for (int g = blockIdx.x * kFinThreads + threadIdx.x; g < total; g += gridDim.x * kFinThreads) {
+        const int c = B.slot_cloud[g];
+        const int q = g - B.slot_pre[c];
+        const int tile = q / TS, pos = q % TS;
+        const int tiles = B.tiles[c], chunks = B.chunks[c];
+        const int ib = B.item_pre[c];
+        float v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+        for (int ch = 0; ch < chunks; ++ch) {
+            const float* p = a.part + ((long long)(ib + ch * tiles + tile) * TS + pos) * (D + 1);
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] += p[k];
+        }
+        const int j = a.act_in[B.seg[c] + q];
+        if (update_seed_id<D, DP>(a, j, v) == 1) a.act_out[B.seg[c] + atomicAdd(&cout[c], 1)] = j;
+    }
+}
+
+// Seeds of the batch: copy (d -> DP columns), status from the caller's flags,
+// and every active seed into its cloud's first active list.
+__global__ void bseed_init_kernel(const float* __restrict__ seeds, const uint8_t* __restrict__ conv_in,
+                                  int d, int DP, int M, const int32_t* __restrict__ seg, int ncl,
+                                  float* S, int32_t* act0, uint8_t* status, int32_t* iters, float* shift2,
+                                  int32_t* cnt0) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    for (int k = 0; k < DP; ++k) S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] : 0.0f;
+    const uint8_t st = conv_in[j];
+    status[j] = st;
+    iters[j] = 0;
+    shift2[j] = __builtin_nanf("");
+    if (st == ST_ACTIVE) {
+        const int c = upper_cloud(seg, ncl, j);
+        act0[seg[c] + atomicAdd(&cnt0[c], 1)] = j;
+    }
+}
+
+__global__ void bzero_kernel(int32_t* a, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = 0;
+}
+
+template <int D, int DP, int R>
+hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
+    StepArgs a = {};
+    a.Xp = b.Xp;
+    a.n = b.n;
+    a.d = b.d;
+    a.min_chunk = kChunkPoints;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, 64 * R);
+    if (b.kernel == MS_KERNEL_GAUSSIAN)
+        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(kBStepGrid), dim3(kThreads),
+                           0, s, a, B);
+    else
+        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_FLAT>), dim3(kBStepGrid), dim3(kThreads), 0,
+                           s, a, B);
+    int fblocks = (b.n_seeds + kFinThreads - 1) / kFinThreads;
+    fblocks = fblocks < 1 ? 1 : (fblocks > 1024 ? 1024 : fblocks);
+    hipLaunchKernelGGL((bfinal_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a, B, t);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int batched_max_clouds() { return kMaxClouds; }
+
+// Work items of the first iteration (every seed active): the size of the
+// partials and of the item map.
+long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS) {
+    long long items = 0;
+    for (int c = 0; c < ncl; ++c) {
+        const long long m = seg[c + 1] - seg[c];
+        const long long n = x_off[c + 1] - x_off[c];
+        if (m > 0) items += ((m + TS - 1) / TS) * ((n + kChunkPoints - 1) / kChunkPoints);
+    }
+    return items;
+}
+
+hipError_t launch_batched_init(const float* seeds, const uint8_t* conv_in, int d, int M,
+                               const int32_t* seg_dev, int ncl, int32_t* cnt, Batch& b, hipStream_t s) {
+    hipLaunchKernelGGL(bzero_kernel, dim3((2 * ncl + 255) / 256), dim3(256), 0, s, cnt, 2 * ncl);
+    if (M > 0)
+        hipLaunchKernelGGL(bseed_init_kernel, dim3((M + 255) / 256), dim3(256), 0, s, seeds, conv_in, d,
+                           b.sh.DP, M, seg_dev, ncl, b.S, b.act[0], b.status, b.iters, b.shift2, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, const int32_t* seg_dev,
+                                    int ncl, int32_t* cnt, int32_t* plan, int32_t* item_cloud,
+                                    int32_t* slot_cloud, int t, hipStream_t s) {
+    BatchedArgs B;
+    B.ncl = ncl;
+    B.x_off = x_off_dev;
+    B.seg = seg_dev;
+    B.cnt = cnt;
+    B.tiles = plan;
+    B.chunks = plan + ncl;
+    B.item_pre = plan + 2 * ncl;
+    B.slot_pre = plan + 3 * ncl + 1;
+    B.item_cloud = item_cloud;
+    B.slot_cloud = slot_cloud;
+    const int D = b.sh.D, R = b.sh.R;
+#define FMS_BCASE(DD, DPP, RR) \
+    if (D == DD && R == RR) return bstep_t<DD, DPP, RR>(b, B, t, s);
+    FMS_BCASE(1, 4, 1) FMS_BCASE(1, 4, 2) FMS_BCASE(1, 4, 4)
+    FMS_BCASE(2, 4, 1) FMS_BCASE(2, 4, 2) FMS_BCASE(2, 4, 4)
+    FMS_BCASE(3, 4, 1) FMS_BCASE(3, 4, 2) FMS_BCASE(3, 4, 4)
+    FMS_BCASE(4, 4, 1) FMS_BCASE(4, 4, 2) FMS_BCASE(4, 4, 4)
+    FMS_BCASE(8, 8, 1) FMS_BCASE(8, 8, 2)
+    FMS_BCASE(16, 16, 1) FMS_BCASE(32, 32, 1) FMS_BCASE(64, 64, 1)
+#undef FMS_BCASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fms

@@ -125,7 +125,6 @@ __global__ void seed_init_array_kernel(const float* __restrict__ seeds,
 template <int D, int DP, int R, int KERN>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
     constexpr int TS = 64 * R;
-    constexpr int V = TS * (D + 1);   // values per tile partial
     Ctl* ctl = a.ctl;
     const int n = a.n;
     const int m = active_count(ctl, t);
@@ -134,79 +133,16 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a, int t) {
     const int G = gridDim.x;
     const int tiles = (m + TS - 1) / TS;
     const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
-    // the wave index is uniform across a wave; saying so lets the point
-    // stream use scalar loads
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    __shared__ float red[(kWaves - 1) * V];   // wave partials; then the tile sums
+    const int wave = threadIdx.x >> 6;
+    __shared__ float red[(kWaves - 1) * TS * (D + 1)];   // wave partials; then the tile sums
 
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
-        const long long lo = (long long)n * chunk / chunks;
-        const long long hi = (long long)n * (chunk + 1) / chunks;
-        const long long len = hi - lo;
-        const int p0 = (int)(lo + len * wave / kWaves);
-        const int p1 = (int)(lo + len * (wave + 1) / kWaves);
-
-        float s[R][D];
         float acc[R][D + 1];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int slot = tile * TS + r * 64 + lane;
-            const int j = a.act_in[slot < m ? slot : 0];
-#pragma unroll
-            for (int k = 0; k < D; ++k) s[r][k] = a.S[(long long)j * DP + k] * a.scale;
-#pragma unroll
-            for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
-        }
-
-        const float* __restrict__ xrow = a.Xp + (long long)p0 * DP;
-#pragma unroll 2
-        for (int p = p0; p < p1; ++p, xrow += DP) {
-            float x[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) x[k] = xrow[k];   // wave-uniform: scalar loads
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                float dx[D];
-                float q = 0.0f;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    dx[k] = x[k] - s[r][k];
-                    q = fmaf(dx[k], dx[k], q);
-                }
-                float w;
-                if (KERN == MS_KERNEL_GAUSSIAN)
-                    w = __builtin_amdgcn_exp2f(-q);
-                else
-                    w = (q <= a.h2) ? 1.0f : 0.0f;
-                acc[r][D] += w;
-#pragma unroll
-                for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
-            }
-        }
-
-        // chunk partial: the four wave sums added in wave order
-        if (wave > 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k <= D; ++k) red[(wave - 1) * V + k * TS + r * 64 + lane] = acc[r][k];
-        }
-        __syncthreads();
-        if (wave == 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int k = 0; k <= D; ++k) {
-                    float v = acc[r][k];
-#pragma unroll
-                    for (int w2 = 1; w2 < kWaves; ++w2) v += red[(w2 - 1) * V + k * TS + r * 64 + lane];
-                    acc[r][k] = v;
-                }
-        }
-        __syncthreads();
+        tile_sums<D, DP, R, KERN>(a, a.Xp, (long long)n * chunk / chunks,
+                                  (long long)n * (chunk + 1) / chunks, a.act_in, tile * TS, m, acc, red);
 
         if (chunks == 1) {
             // the chunk partial is the tile sum: finalize here

@@ -74,12 +74,11 @@ __device__ __forceinline__ void step_prologue(const StepArgs& a, int t, int m) {
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Update and convergence test of one seed (slot of the active list) from its
-// sums a[0..D) = sum w (x - s) (packed units) and a[D] = sum w.  Returns
-// 1 if the seed stays active, 2 if it converged, 0 otherwise.
+// Update and convergence test of seed j from its sums v[0..D) = sum w (x - s)
+// (packed units) and v[D] = sum w.  Returns 1 if the seed stays active, 2 if
+// it converged, 0 otherwise.  update_seed takes a slot of the active list.
 template <int D, int DP>
-__device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const float* v) {
-    const int j = a.act_in[slot];
+__device__ __forceinline__ int update_seed_id(const StepArgs& a, int j, const float* v) {
     const float W = v[D];
     if (!(W > 0.0f) || !isfinite(W)) {
         a.status[j] = ST_FAILED;
@@ -108,6 +107,87 @@ __device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const fl
         return 2;
     }
     return 1;
+}
+
+template <int D, int DP>
+__device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const float* v) {
+    return update_seed_id<D, DP>(a, a.act_in[slot], v);
+}
+
+// Sums of one work item of the FP32 step: the seeds act[slot0 .. slot0+TS)
+// (slots >= m padded with the first seed, their sums unused) over the points
+// Xp[lo, hi) (packed, stride DP).  The four waves take consecutive quarters of
+// the points, each lane R seeds; the wave sums are added in wave order and
+// wave 0 returns them in acc.  `red` is LDS of (kWaves - 1) * TS * (D + 1)
+// floats.  All threads of the workgroup must call it.
+template <int D, int DP, int R, int KERN>
+__device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __restrict__ Xp, long long lo,
+                                          long long hi, const int32_t* __restrict__ act, int slot0, int m,
+                                          float (&acc)[R][D + 1], float* red) {
+    constexpr int TS = 64 * R;
+    constexpr int V = TS * (D + 1);
+    // the wave index is uniform across a wave; saying so lets the point
+    // stream use scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const long long len = hi - lo;
+    const int p0 = (int)(lo + len * wave / kWaves);
+    const int p1 = (int)(lo + len * (wave + 1) / kWaves);
+    float s[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int slot = slot0 + r * 64 + lane;
+        const int j = act[slot < m ? slot : slot0];
+#pragma unroll
+        for (int k = 0; k < D; ++k) s[r][k] = a.S[(long long)j * DP + k] * a.scale;
+#pragma unroll
+        for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
+    }
+    const float* __restrict__ xrow = Xp + (long long)p0 * DP;
+#pragma unroll 2
+    for (int p = p0; p < p1; ++p, xrow += DP) {
+        float x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = xrow[k];   // wave-uniform: scalar loads
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float dx[D];
+            float q = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                dx[k] = x[k] - s[r][k];
+                q = fmaf(dx[k], dx[k], q);
+            }
+            float w;
+            if (KERN == MS_KERNEL_GAUSSIAN)
+                w = __builtin_amdgcn_exp2f(-q);
+            else
+                w = (q <= a.h2) ? 1.0f : 0.0f;
+            acc[r][D] += w;
+#pragma unroll
+            for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
+        }
+    }
+    // the four wave sums added in wave order
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) red[(wave - 1) * V + k * TS + r * 64 + lane] = acc[r][k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) {
+                float v = acc[r][k];
+#pragma unroll
+                for (int w2 = 1; w2 < kWaves; ++w2) v += red[(w2 - 1) * V + k * TS + r * 64 + lane];
+                acc[r][k] = v;
+            }
+    }
+    __syncthreads();
 }
 
 // Finalize the seeds of one tile from sums[k * TS + pos] (one lane per seed).

@@ -134,3 +134,29 @@ def test_seed_draw_matches_oracle(api, orc):
         assert np.array_equal(a, b) and sa == sb
     with pytest.raises(api.MeanShiftError):
         api.seed_draw(0, np.arange(3, dtype=np.int32), 4)
+
+
+def test_step_batched_rejects_bad_arguments(api):
+    L = api.lib()
+    I64 = ctypes.c_int64 * 4
+
+    def call(xo, so, ncl=3, d=2, n_iter=1, prec="fp32"):
+        p = api.make_params(1.0, precision=prec)
+        return L.ms_step_batched(ctypes.byref(p), FAKE, I64(*xo), FAKE, I64(*so), ncl, d, n_iter,
+                                 FAKE, FAKE, FAKE, None)
+
+    good_x, good_s = (0, 5, 9, 12), (0, 2, 2, 4)
+    assert call((0, 5, 9, 12), (0, 0, 0, 0)) == 0     # no seeds: nothing to do
+    cases = [
+        (dict(xo=good_x, so=good_s, prec="bf16"), "FP32 form only"),
+        (dict(xo=good_x, so=good_s, ncl=0), "ncl must"),
+        (dict(xo=good_x, so=good_s, ncl=9000), "ncl must"),
+        (dict(xo=(1, 5, 9, 12), so=good_s), "start at 0"),
+        (dict(xo=(0, 5, 4, 12), so=good_s), "nondecreasing"),
+        (dict(xo=(0, 5, 5, 12), so=(0, 2, 3, 4)), "no points"),
+        (dict(xo=good_x, so=good_s, d=65), "d must"),
+        (dict(xo=good_x, so=good_s, n_iter=5000), "n_iter"),
+    ]
+    for kw, msg in cases:
+        assert call(**kw) == api.MS_E_INVALID, kw
+        assert msg in api.last_error(), (kw, api.last_error())

@@ -1,0 +1,126 @@
+"""GPU parity of ms_step_batched -- many independent clouds of uneven size in
+one launch per kernel -- against the FP64 oracle run on each cloud alone."""
+import sys
+
+import numpy as np
+import pytest
+
+from parity import ragged_check, step_parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2112_13891_amd import api, workloads  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _batch(seed, sizes, d, max_seeds=150):
+    """Clouds of the batched recipe (2..40 clusters, sigma 0.4 around centres
+    N(0, 9 I)) with the given sizes; seeds drawn from each cloud's points."""
+    rng = np.random.default_rng(seed)
+    Xs, Ss = [], []
+    for n in sizes:
+        if n == 0:
+            Xs.append(np.zeros((0, d), np.float32))
+            Ss.append(np.zeros((0, d), np.float32))
+            continue
+        X, _, _ = workloads.cloud16(rng, n, d)
+        m = int(min(n, rng.integers(0, max_seeds + 1)))
+        Xs.append(X)
+        Ss.append(X[rng.choice(n, m, replace=False)] if m else np.zeros((0, d), np.float32))
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+    return Xs, Ss, xo, so
+
+
+def _run(Xs, Ss, xo, so, h, kernel, n_iter, converged=None):
+    Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+    return api.step_batched(Xa, xo, Sa, so, h, kernel=kernel, n_iter=n_iter, converged=converged)
+
+
+SIZES = [1, 2, 300, 0, 1500, 64, 2047, 4100, 17, 1025]
+
+
+@pytest.mark.parametrize("d", [2, 3, 16])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_batched_fixed_iterations(orc, d, kernel):
+    Xs, Ss, xo, so = _batch(d * 10 + (kernel == "flat"), SIZES, d)
+    h = 1.0
+    for n_iter in (1, 3):
+        S, conv, it, sh = _run(Xs, Ss, xo, so, h, kernel, n_iter)
+        torch.cuda.synchronize()
+        S, it = S.cpu().numpy(), it.cpu().numpy()
+        for c in range(len(Xs)):
+            a, b = so[c], so[c + 1]
+            if a == b:
+                continue
+            ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), h, kernel, tol=1e-3,
+                                          n_iter=n_iter)
+            ties = ragged_check(Xs[c], Ss[c], h, kernel, n_iter, S[a:b], it[a:b], ref, oit)
+            if ties:
+                say("cloud", c, "flat boundary ties", ties)
+
+
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_batched_to_convergence(orc, kernel):
+    Xs, Ss, xo, so = _batch(77, SIZES, 3)
+    h = 1.0
+    S, conv, it, sh = _run(Xs, Ss, xo, so, h, kernel, 100)
+    torch.cuda.synchronize()
+    S, conv, it = S.cpu().numpy(), conv.cpu().numpy(), it.cpu().numpy()
+    for c in range(len(Xs)):
+        a, b = so[c], so[c + 1]
+        if a == b:
+            continue
+        rep = step_parity(orc, Xs[c], Ss[c], h, kernel, 1e-3, S[a:b], it[a:b], conv[a:b])
+        say("cloud", c, rep)
+
+
+def test_batched_keeps_converged_seeds_and_matches_single_cloud_calls():
+    Xs, Ss, xo, so = _batch(5, [500, 3000, 40], 16)
+    M = int(so[-1])
+    rng = np.random.default_rng(1)
+    conv0 = (rng.random(M) < 0.3).astype(np.uint8)
+    S, conv, it, sh = _run(Xs, Ss, xo, so, 1.0, "gaussian", 2,
+                           converged=torch.from_numpy(conv0).to(DEV))
+    torch.cuda.synchronize()
+    S, conv, it = S.cpu().numpy(), conv.cpu().numpy(), it.cpu().numpy()
+    S0 = np.concatenate(Ss)
+    kept = conv0 == 1
+    assert np.array_equal(S[kept], S0[kept]) and (it[kept] == 0).all() and (conv[kept] == 1).all()
+    # the same seeds through ms_step, one cloud at a time
+    for c in range(len(Xs)):
+        a, b = so[c], so[c + 1]
+        Sc, cc, ic, _ = api.step(torch.from_numpy(Xs[c]).to(DEV), torch.from_numpy(Ss[c]).to(DEV), 1.0,
+                                 n_iter=2, converged=torch.from_numpy(conv0[a:b]).to(DEV))
+        torch.cuda.synchronize()
+        assert np.array_equal(ic.cpu().numpy(), it[a:b])
+        assert np.abs(Sc.cpu().numpy() - S[a:b]).max() < 1e-5
+
+
+def test_batched_uneven_clouds_workload_shape():
+    """A slice of the batched recipe (clouds of 1,000..65,536 points, D = 16):
+    every seed moves toward its own cloud's mass and never leaves its cloud's
+    bounding box (a seed fed another cloud's points would)."""
+    clouds = workloads.clouds16(seed=3, n_clouds=24)
+    Xs = [c[0] for c in clouds]
+    rng = np.random.default_rng(0)
+    Ss = [X[rng.choice(len(X), min(len(X), 64), replace=False)] for X in Xs]
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+    S, conv, it, sh = _run(Xs, Ss, xo, so, 1.0, "gaussian", 50)
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    for c in range(len(Xs)):
+        lo, hi = Xs[c].min(0), Xs[c].max(0)
+        seg = S[so[c]:so[c + 1]]
+        assert ((seg >= lo - 1e-4) & (seg <= hi + 1e-4)).all(), c
+    assert conv.cpu().numpy().mean() > 0.9
