@@ -117,7 +117,8 @@ def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
 
 def other_configs(api, torch, workloads):
     """Secondary workloads of the method, each timed briefly: the 2-D blob fit,
-    the 32-D embedding fit (Gaussian, both precisions), and the differentiable form
+    the 32-D embedding fit (Gaussian, both precisions), 512 uneven clouds in one
+    batched step, and the differentiable form
     (64 clouds x 16,384 points x 16, T = 10 unrolled steps, forward + adjoint)."""
     import numpy as np
     from paper_2112_13891_amd.autograd import MeanShiftT
@@ -146,6 +147,48 @@ def other_configs(api, torch, workloads):
     out["embed32_gaussian_bf16"] = fit_rate(w, 2, precision="bf16")
     out["embed32_gaussian_bf16"]["speedup_vs_fp32"] = (
         out["embed32_gaussian_fp32"]["time_to_cluster_ms"] / out["embed32_gaussian_bf16"]["time_to_cluster_ms"])
+    # many uneven clouds in one batched call (FP32): 512 clouds of 1,000..65,536
+    # points, D = 16, up to 256 seeds each, 10 iterations with every seed active
+    clouds = workloads.clouds16(seed=0)
+    Xs = [c[0] for c in clouds]
+    rng = np.random.default_rng(0)
+    Ss = [X[rng.choice(len(X), min(len(X), 256), replace=False)] for X in Xs]
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+    Xa = torch.from_numpy(np.concatenate(Xs)).cuda()
+    Sa = torch.from_numpy(np.concatenate(Ss)).cuda()
+    pairs = sum(len(s) * len(x) for s, x in zip(Ss, Xs))
+
+    def batched(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    batched(2)
+    t_it = (min(batched(20) for _ in range(2)) - min(batched(10) for _ in range(2))) / 10
+    Xc = [torch.from_numpy(x).cuda() for x in Xs]
+    Sc = [torch.from_numpy(s).cuda() for s in Ss]
+
+    def per_cloud(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for x, s_ in zip(Xc, Sc):
+            api.step(x, s_, 1.0, tol=1e-30, n_iter=k)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    per_cloud(1)
+    t_pc = (per_cloud(4) - per_cloud(2)) / 2
+    out["clouds16_batched_fp32"] = {
+        "workload": "512 clouds, sizes log-uniform in [1000, 65536] (%d points), D=16, 2..40 "
+                    "clusters each, Gaussian h=1, min(n, 256) seeds per cloud" % int(xo[-1]),
+        "ms_per_iteration": t_it * 1e3, "pair_evals_per_iteration": pairs,
+        "pair_evals_per_s": pairs / t_it,
+        "per_cloud_calls_ms_per_iteration": t_pc * 1e3,
+        "speedup_vs_per_cloud_calls": t_pc / t_it}
+
     # differentiable form
     clouds = workloads.diffclouds(seed=0)
     X = torch.from_numpy(np.stack([c[0] for c in clouds])).cuda()
