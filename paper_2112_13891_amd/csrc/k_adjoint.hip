@@ -42,14 +42,22 @@ struct Row {
     T v[D];
 };
 
-template <typename T, int D>
+// Row `row` of a d-column array, zero-padded to D.  EXACT (d == D) loads
+// with compile-time offsets, which lets wave-uniform rows become wide scalar
+// loads; otherwise each column is guarded.
+template <typename T, int D, bool EXACT>
 __device__ __forceinline__ void load_row(const T* __restrict__ A, long long row, int d, T* out) {
+    if constexpr (EXACT) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) out[k] = (k < d) ? A[row * d + k] : T(0);
+        for (int k = 0; k < D; ++k) out[k] = A[row * D + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) out[k] = (k < d) ? A[row * d + k] : T(0);
+    }
 }
 
 // Forward partials: lane = seed j, chunk of points.  part[(b*kP + c)*(D+1) + k][m]
-template <typename T, int D>
+template <typename T, int D, bool EXACT>
 __global__ __launch_bounds__(kT) void fwd_partial_kernel(const T* __restrict__ X, int n,
                                                          const T* __restrict__ S, int m, int d,
                                                          T c, T* __restrict__ part) {
@@ -57,13 +65,13 @@ __global__ __launch_bounds__(kT) void fwd_partial_kernel(const T* __restrict__ X
     const int j = blockIdx.x * kT + threadIdx.x;
     const T* Xb = X + (long long)b * n * d;
     T s[D], acc[D + 1];
-    load_row<T, D>(S + (long long)b * m * d, j < m ? j : 0, d, s);
+    load_row<T, D, EXACT>(S + (long long)b * m * d, j < m ? j : 0, d, s);
 #pragma unroll
     for (int k = 0; k <= D; ++k) acc[k] = T(0);
     const int p0 = (int)((long long)n * chunk / kP), p1 = (int)((long long)n * (chunk + 1) / kP);
     for (int i = p0; i < p1; ++i) {
         T x[D];
-        load_row<T, D>(Xb, i, d, x);
+        load_row<T, D, EXACT>(Xb, i, d, x);
         T dx[D], q = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -108,12 +116,13 @@ __global__ void fwd_reduce_kernel(const T* __restrict__ part, const T* __restric
 }
 
 // dS partials: lane = seed j, chunk of points.
-template <typename T, int D>
+template <typename T, int D, bool EXACT>
 __global__ __launch_bounds__(kT) void ds_partial_kernel(const T* __restrict__ X, int n,
                                                         const T* __restrict__ S, int m, int d,
                                                         T c, T inv_h2, const T* __restrict__ G,
                                                         const T* __restrict__ delta,
                                                         const T* __restrict__ invW,
+                                                        T* __restrict__ gdel_out,
                                                         T* __restrict__ part) {
     const int b = blockIdx.z, chunk = blockIdx.y;
     const int j = blockIdx.x * kT + threadIdx.x;
@@ -121,17 +130,18 @@ __global__ __launch_bounds__(kT) void ds_partial_kernel(const T* __restrict__ X,
     const long long row = (long long)b * m + jj;
     const T* Xb = X + (long long)b * n * d;
     T s[D], g[D], acc[D];
-    load_row<T, D>(S + (long long)b * m * d, jj, d, s);
-    load_row<T, D>(G + (long long)b * m * d, jj, d, g);
+    load_row<T, D, EXACT>(S + (long long)b * m * d, jj, d, s);
+    load_row<T, D, EXACT>(G + (long long)b * m * d, jj, d, g);
     T gdel = T(0);
     for (int k = 0; k < d; ++k) gdel = fma(g[k], delta[row * d + k], gdel);
+    if (chunk == 0 && j < m) gdel_out[row] = gdel;   // g_j . delta_j, read by the dX pass
     const T coef = inv_h2 * invW[row];
 #pragma unroll
     for (int k = 0; k < D; ++k) acc[k] = T(0);
     const int p0 = (int)((long long)n * chunk / kP), p1 = (int)((long long)n * (chunk + 1) / kP);
     for (int i = p0; i < p1; ++i) {
         T x[D];
-        load_row<T, D>(Xb, i, d, x);
+        load_row<T, D, EXACT>(Xb, i, d, x);
         T dx[D], q = T(0), gdx = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -152,41 +162,40 @@ __global__ __launch_bounds__(kT) void ds_partial_kernel(const T* __restrict__ X,
 }
 
 // dX partials: lane = point i, chunk of seeds.
-template <typename T, int D>
+template <typename T, int D, bool EXACT>
 __global__ __launch_bounds__(kT) void dx_partial_kernel(const T* __restrict__ X, int n,
                                                         const T* __restrict__ S, int m, int d,
                                                         T c, T inv_h2, const T* __restrict__ G,
-                                                        const T* __restrict__ delta,
+                                                        const T* __restrict__ gdel,
                                                         const T* __restrict__ invW,
                                                         T* __restrict__ part) {
     const int b = blockIdx.z, chunk = blockIdx.y;
     const int i = blockIdx.x * kT + threadIdx.x;
     const T* Sb = S + (long long)b * m * d;
     const T* Gb = G + (long long)b * m * d;
-    const T* Db = delta + (long long)b * m * d;
+    const T* Eb = gdel + (long long)b * m;
     const T* Wb = invW + (long long)b * m;
     T x[D], acc[D];
-    load_row<T, D>(X + (long long)b * n * d, i < n ? i : 0, d, x);
+    load_row<T, D, EXACT>(X + (long long)b * n * d, i < n ? i : 0, d, x);
 #pragma unroll
     for (int k = 0; k < D; ++k) acc[k] = T(0);
     const int j0 = (int)((long long)m * chunk / kP), j1 = (int)((long long)m * (chunk + 1) / kP);
     for (int j = j0; j < j1; ++j) {
-        T s[D], g[D], del[D];
-        load_row<T, D>(Sb, j, d, s);
-        load_row<T, D>(Gb, j, d, g);
-        load_row<T, D>(Db, j, d, del);
+        T s[D], g[D];
+        load_row<T, D, EXACT>(Sb, j, d, s);
+        load_row<T, D, EXACT>(Gb, j, d, g);
         const T iw = Wb[j];
-        T dx[D], q = T(0), gdx = T(0), gdel = T(0);
+        const T gd = Eb[j];
+        T dx[D], q = T(0), gdx = T(0);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             dx[k] = x[k] - s[k];
             q = fma(dx[k], dx[k], q);
             gdx = fma(g[k], dx[k], gdx);
-            gdel = fma(g[k], del[k], gdel);
         }
         const T w = expw<T>(q, c);
         const T a = w * iw;                              // w_ij / W_j
-        const T beta = a * (gdx - gdel) * inv_h2;        // beta_ij
+        const T beta = a * (gdx - gd) * inv_h2;          // beta_ij
 #pragma unroll
         for (int k = 0; k < D; ++k) acc[k] = fma(a, g[k], fma(-beta, dx[k], acc[k]));
     }
@@ -219,35 +228,46 @@ template <typename T, int D>
 hipError_t fwd_t(const T* X, int nb, int n, const T* S, int m, int d, double h, T* S_out,
                  T* delta, T* invW, T* part, hipStream_t s) {
     dim3 g1((m + kT - 1) / kT, kP, nb);
-    hipLaunchKernelGGL((fwd_partial_kernel<T, D>), g1, dim3(kT), 0, s, X, n, S, m, d,
-                       weight_coef<T>(h), part);
+    if (d == D)
+        hipLaunchKernelGGL((fwd_partial_kernel<T, D, true>), g1, dim3(kT), 0, s, X, n, S, m, d,
+                           weight_coef<T>(h), part);
+    else
+        hipLaunchKernelGGL((fwd_partial_kernel<T, D, false>), g1, dim3(kT), 0, s, X, n, S, m, d,
+                           weight_coef<T>(h), part);
     dim3 g2((m + 255) / 256, nb);
     hipLaunchKernelGGL((fwd_reduce_kernel<T, D>), g2, dim3(256), 0, s, part, S, m, d, S_out,
                        delta, invW);
     return hipGetLastError();
 }
 
+template <typename T, int D, bool EXACT>
+void adj_passes(const T* X, int nb, int n, const T* S, int m, int d, T c, T ih2, const T* G,
+                const T* delta, const T* invW, T* gdel, T* part, T* dS, T* dX, hipStream_t s) {
+    hipLaunchKernelGGL((ds_partial_kernel<T, D, EXACT>), dim3((m + kT - 1) / kT, kP, nb), dim3(kT), 0,
+                       s, X, n, S, m, d, c, ih2, G, delta, invW, gdel, part);
+    hipLaunchKernelGGL((add_reduce_kernel<T, D>), dim3((m + 255) / 256, nb), dim3(256), 0, s,
+                       part, m, d, dS);
+    hipLaunchKernelGGL((dx_partial_kernel<T, D, EXACT>), dim3((n + kT - 1) / kT, kP, nb), dim3(kT), 0,
+                       s, X, n, S, m, d, c, ih2, G, gdel, invW, part);
+    hipLaunchKernelGGL((add_reduce_kernel<T, D>), dim3((n + 255) / 256, nb), dim3(256), 0, s,
+                       part, n, d, dX);
+}
+
 template <typename T, int D>
 hipError_t adj_t(const T* X, int nb, int n, const T* S, int m, int d, double h, const T* G,
-                 T* dS, T* dX, T* delta, T* invW, T* part, hipStream_t s) {
+                 T* dS, T* dX, T* delta, T* invW, T* gdel, T* part, hipStream_t s) {
     hipError_t e = fwd_t<T, D>(X, nb, n, S, m, d, h, nullptr, delta, invW, part, s);
     if (e != hipSuccess) return e;
     const T c = weight_coef<T>(h);
     const T ih2 = T(1.0 / (h * h));
-    hipLaunchKernelGGL((ds_partial_kernel<T, D>), dim3((m + kT - 1) / kT, kP, nb), dim3(kT), 0,
-                       s, X, n, S, m, d, c, ih2, G, delta, invW, part);
-    hipLaunchKernelGGL((add_reduce_kernel<T, D>), dim3((m + 255) / 256, nb), dim3(256), 0, s,
-                       part, m, d, dS);
-    hipLaunchKernelGGL((dx_partial_kernel<T, D>), dim3((n + kT - 1) / kT, kP, nb), dim3(kT), 0,
-                       s, X, n, S, m, d, c, ih2, G, delta, invW, part);
-    hipLaunchKernelGGL((add_reduce_kernel<T, D>), dim3((n + 255) / 256, nb), dim3(256), 0, s,
-                       part, n, d, dX);
+    if (d == D) adj_passes<T, D, true>(X, nb, n, S, m, d, c, ih2, G, delta, invW, gdel, part, dS, dX, s);
+    else adj_passes<T, D, false>(X, nb, n, S, m, d, c, ih2, G, delta, invW, gdel, part, dS, dX, s);
     return hipGetLastError();
 }
 
 struct Ws {
     char* base;
-    size_t part, delta, invw;
+    size_t part, delta, invw, gdel;
 };
 
 Ws carve(void* ws, int nb, int n, int m, int d, int bytes) {
@@ -262,6 +282,9 @@ Ws carve(void* ws, int nb, int n, int m, int d, int bytes) {
     off += (size_t)nb * m * d * bytes;
     off = (off + 255) & ~(size_t)255;
     w.invw = off;
+    off += (size_t)nb * m * bytes;
+    off = (off + 255) & ~(size_t)255;
+    w.gdel = off;
     return w;
 }
 
@@ -282,7 +305,7 @@ Ws carve(void* ws, int nb, int n, int m, int d, int bytes) {
 
 size_t adjoint_workspace_bytes(int nb, int n, int m, int d, int bytes) {
     Ws w = carve(nullptr, nb, n, m, d, bytes);
-    return w.invw + (size_t)nb * m * bytes + 256;
+    return w.gdel + (size_t)nb * m * bytes + 256;
 }
 
 hipError_t launch_forward_update(const void* X, int nb, int n, const void* S, int m, int d,
@@ -309,12 +332,14 @@ hipError_t launch_step_adjoint(const void* X, int nb, int n, const void* S, int 
                                              (const float*)G, (float*)dS, (float*)dX,
                                              (float*)(w.base + w.delta),
                                              (float*)(w.base + w.invw),
+                                             (float*)(w.base + w.gdel),
                                              (float*)(w.base + w.part), s)));
     }
     FMS_ADJ_DSWITCH(D, (adj_t<double, DD>((const double*)X, nb, n, (const double*)S, m, d, h,
                                           (const double*)G, (double*)dS, (double*)dX,
                                           (double*)(w.base + w.delta),
                                           (double*)(w.base + w.invw),
+                                          (double*)(w.base + w.gdel),
                                           (double*)(w.base + w.part), s)));
 }
 
