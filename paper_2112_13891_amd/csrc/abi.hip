@@ -441,7 +441,7 @@ void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_par
     b.Xs = sp ? sp->Xs : nullptr;
     b.geom = sp ? sp->geom : nullptr;
     b.pf = sp ? sp->feat : nullptr;
-    b.xv = (sp && sh.D <= 4) ? sp->feat + (size_t)((n + 255) / 256) * 256 * 16 * 2 : nullptr;
+    b.xv = (sp && sp->feat && sh.D <= 4) ? sp->feat + (size_t)((n + 255) / 256) * 256 * 16 * 2 : nullptr;
     b.shift = (sp && sh.D > 4) ? sort_frame_shift(sp->sws) : nullptr;
     b.e_thr = bf16_e_thr(p, sh.D);
     b.kappa = 1.0f / 1024.0f;
@@ -492,15 +492,20 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_HIP(launch_pack_points(X, n, d, DP, scale, Xp, s));
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
+    // FP32 with d <= 4 on enough points: spatially ordered points and block culling
+    const bool cull = !bf16 && cull_supported(d, n);
+    const bool sorted = bf16 || cull;
     SortedPoints sp;
-    if (bf16) {
+    if (sorted) {
         FMS_CHECK(cache_get(C, budget, SL_XS, (size_t)n * DP, &sp.Xs));
         FMS_CHECK(cache_get(C, budget, SL_PERM, n, &sp.perm));
         FMS_CHECK(cache_get(C, budget, SL_GEOM, (size_t)((n + 255) / 256) * geom_stride(base.D), &sp.geom));
         FMS_CHECK(cache_get(C, budget, SL_SORTWS, sort_workspace_bytes(n), (char**)&sp.sws));
+        FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sp.sws, s));
+    }
+    if (bf16) {
         FMS_CHECK(cache_get(C, budget, SL_FEAT, base.D <= 4 ? bf16_feature_bytes(n)
                                                            : bf16w_feature_bytes(n, base.D), &sp.feat));
-        FMS_HIP(launch_spatial_sort(Xp, n, DP, base.D, sp.Xs, sp.perm, sp.geom, sp.sws, s));
         if (base.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
         else FMS_HIP(launch_bf16w_features(sp.Xs, n, base.D, sp.geom, sp.feat, s));
     }
@@ -539,9 +544,10 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     for (;;) {
         const auto t_round = std::chrono::steady_clock::now();
         const int B = all ? n : (int)std::min<long long>(N, pool_len);
-        const StepShape sh = bf16 ? step_shape_bf16(d, B) : step_shape_for(d, B);
+        const StepShape sh = bf16 ? step_shape_bf16(d, B)
+                                  : (cull ? step_shape_cull(d, B, n) : step_shape_for(d, B));
         Batch b;
-        fill_batch(b, n, d, B, sh, p, scale, Xp, nullptr, bf16 ? &sp : nullptr);
+        fill_batch(b, n, d, B, sh, p, scale, Xp, nullptr, sorted ? &sp : nullptr);
         const long long part_floats = step_part_floats(sh, B, b.grid);
         const RbLayout L = rb_layout(B, DP);
         char* rbuf;
@@ -570,8 +576,8 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         }
         FMS_HIP(launch_round_init(X, d, DP, all ? nullptr : pool[cur], dpos, B, bids, removed,
                                   bstate, b, need, p->max_iter, s));
-        if (bf16) {
-            // seeds that are close in space share waves (and refine work)
+        if (sorted) {
+            // seeds that are close in space share waves (refine work, culled blocks)
             if (all)
                 FMS_HIP(hipMemcpyAsync(b.act[0], sp.perm, (size_t)B * 4, hipMemcpyDeviceToDevice, s));
             else
@@ -751,28 +757,33 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
-    const StepShape sh = bf16 ? step_shape_bf16(d, m) : step_shape_for(d, m);
+    const bool cull = !bf16 && cull_supported(d, n);
+    const bool sorted = bf16 || cull;
+    const StepShape sh = bf16 ? step_shape_bf16(d, m)
+                              : (cull ? step_shape_cull(d, m, n) : step_shape_for(d, m));
     const float scale = packed_scale(p);
     float* Xp;
     FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
     FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
     SortedPoints sp;
-    if (bf16) {
+    if (sorted) {
         char* sws;
         FMS_CHECK(ws.alloc(&sp.Xs, (size_t)n * sh.DP));
         FMS_CHECK(ws.alloc(&sp.perm, n));
         FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * geom_stride(sh.D)));
         FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n > m ? n : m)));
-        FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n) : bf16w_feature_bytes(n, sh.D)));
         sp.sws = sws;
         FMS_HIP(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
+    }
+    if (bf16) {
+        FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n) : bf16w_feature_bytes(n, sh.D)));
         if (sh.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
         else FMS_HIP(launch_bf16w_features(sp.Xs, n, sh.D, sp.geom, sp.feat, s));
     }
     Ctl* ctl;
     FMS_CHECK(ws.alloc(&ctl, 1));
     Batch b;
-    fill_batch(b, n, d, m, sh, p, scale, Xp, ctl, bf16 ? &sp : nullptr);
+    fill_batch(b, n, d, m, sh, p, scale, Xp, ctl, sorted ? &sp : nullptr);
     FMS_CHECK(ws.alloc(&b.S, (size_t)m * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], m));
     FMS_CHECK(ws.alloc(&b.act[1], m));
@@ -782,7 +793,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ws.alloc(&b.part, (size_t)step_part_floats(sh, m, b.grid)));
     FMS_HIP(launch_ctl_reset(ctl, 0, INT_MAX, n_iter, s));
     FMS_HIP(launch_seed_init_from_array(seeds, converged, d, m, b, s));
-    if (bf16)   // seeds that are close in space share waves (and refine work)
+    if (sorted)   // seeds that are close in space share waves (refine work, culled blocks)
         FMS_HIP(launch_seed_order(b.S, sh.DP, sh.D, m, scale, b.status, sp.sws, b.act[0], Xp, n, s));
     for (int t = 0; t < n_iter; ++t) FMS_HIP(launch_iteration(b, t, s));
     FMS_HIP(launch_seed_export(b, m, seeds, converged, iters, shift2, s));

@@ -72,8 +72,8 @@ struct Batch {
     float* part;           // chunk partials, one (D+1)-vector per seed and chunk
     int grid;              // workgroups of the fused step
     int prec;              // ms_precision
-    const float* Xs;       // BF16 form: points in Morton order (n x 4)
-    const float* geom;     // BF16 form: per 256-point block centre and radius
+    const float* Xs;       // BF16 and culled FP32 forms: points in spatial order (n x DP)
+    const float* geom;     // BF16 and culled FP32 forms: per 256-point block centre and radius
     const void* pf;        // BF16 form: point features of the first product
     const void* xv;        // BF16 form: point operand of the second product
     float e_thr;           // BF16 form: refine threshold (packed units)
@@ -101,6 +101,11 @@ hipError_t launch_iteration(Batch& b, int t, hipStream_t s);
 hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv,
                               int32_t* iters, float* shift2, hipStream_t s);
 int step_grid(const StepShape& sh, int B, int n);
+
+// ---- launchers (k_step_cull.hip): FP32 step over Morton-ordered points, d <= 4 --
+bool cull_supported(int d, int n);
+StepShape step_shape_cull(int d, int B, int n);
+hipError_t launch_iteration_cull(Batch& b, int t, hipStream_t s);
 
 // ---- launchers (k_step_bf16.hip) -----------------------------------------
 StepShape step_shape_bf16(int d, int B);

@@ -304,6 +304,7 @@ hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv
 // One iteration: the fused step (and the partial reduction when needed).
 hipError_t launch_iteration(Batch& b, int t, hipStream_t s) {
     if (b.prec == MS_PREC_BF16_REFINE) return launch_iteration_bf16(b, t, s);
+    if (b.Xs && b.geom) return launch_iteration_cull(b, t, s);
     const int D = b.sh.D, R = b.sh.R;
 #define FMS_CASE(DD, DPP, RR) \
     if (D == DD && R == RR) return launch_step_t<DD, DPP, RR>(b, t, s);

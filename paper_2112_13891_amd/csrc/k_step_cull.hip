@@ -1,0 +1,250 @@
+// k_step_cull.hip -- FP32 fused step for d <= 4 over spatially ordered points,
+// skipping the point blocks whose weights are exactly zero for a whole wave.
+//
+// The update is the one of Section II-B (every seed against ALL n points,
+// s' = s + sum w (x - s) / sum w).  The points are in Morton order and cut
+// into 256-point blocks, each with a centre c_b and a radius r_b (rounded up);
+// the active seeds are in Morton order too, so the 64 R seeds of a wave are
+// close to each other.  For a seed s, every point of block b lies at distance
+// at least |s - c_b| - r_b.  If that bound puts every pair of the block past
+// the point where the weight is exactly zero in FP32 -- Gaussian:
+// |c s - c x|^2 >= kCullGauss in exp2 units, so exp2(-q) underflows to +0;
+// flat window: |s - x|^2 > h^2 with a relative margin far above the FP32
+// rounding of the bound -- for all seeds of the wave, the wave skips the
+// block.  The skipped pairs would add +0 to every sum, so the result is the
+// one of evaluating all pairs, and it does not depend on which seeds share
+// a wave.
+//
+// Work decomposition (from the active count m only, as in the plain step):
+// tiles of TS = 64 R seeds, chunks of at least 4 whole blocks; a workgroup
+// of 4 waves takes one (tile, chunk).  All four waves hold the tile's seeds,
+// so they agree on which blocks are live; each live block is staged in LDS
+// with one coalesced vector load per thread (the next live block's load is in
+// flight while the current one computes), wave w takes its points
+// [64 w, 64 w + 64) as broadcast reads, and the four wave sums are added in
+// wave order.  Chunk partials are reduced as in the plain step.
+
+#include "step_common.h"
+
+namespace fms {
+
+namespace {
+
+constexpr int kCullBlk = 256;            // points per block of the geometry
+constexpr float kCullGauss = 160.0f;     // exp2(-q) == +0 in FP32 for q >= 150
+constexpr float kCullFlatMargin = 1.001f;
+constexpr int kCullMinPoints = 16384;     // below this the sort costs more than it saves
+
+// Next block at or after blk (below b1) that some seed of the wave may see
+// with a nonzero weight; b1 if none.
+template <int D, int R>
+__device__ __forceinline__ int next_live_block(const float* __restrict__ geom, int blk, int b1,
+                                               const float (&s)[R][D], const bool (&live)[R],
+                                               float qcull) {
+    for (; blk < b1; ++blk) {
+        // wave-uniform block geometry (scalar loads): centre[0..D), radius at [4]
+        const float* gm = geom + (long long)blk * kGeomStride;
+        bool near = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            float d2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const float u = s[r][k] - gm[k];
+                d2 = fmaf(u, u, d2);
+            }
+            const float lb = sqrtf(d2) - gm[4];
+            near = near || (live[r] && !(lb > 0.0f && lb * lb > qcull));
+        }
+        if (__ballot(near)) break;
+    }
+    return blk;
+}
+
+template <int D, int R, int KERN>
+__global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const float* __restrict__ geom,
+                                                             float qcull, int t) {
+    constexpr int TS = 64 * R;
+    constexpr int DP = 4;
+    constexpr int PW = kCullBlk / kWaves;   // points of a block per wave
+    Ctl* ctl = a.ctl;
+    const int n = a.n;
+    const int m = active_count(ctl, t);
+    step_prologue(a, t, m);
+    if (m == 0) return;
+    const int G = gridDim.x;
+    const int tiles = (m + TS - 1) / TS;
+    const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
+    const int nblk = (n + kCullBlk - 1) / kCullBlk;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int V = TS * (D + 1);
+    __shared__ float red[(kWaves - 1) * V];
+    __shared__ float4 xs[kCullBlk];   // the staged block, one point per thread
+    const float4* __restrict__ X4 = reinterpret_cast<const float4*>(a.Xp);
+
+    for (int item = blockIdx.x; item < tiles * chunks; item += G) {
+        const int tile = item % tiles;
+        const int chunk = item / tiles;
+        const int b0 = (int)((long long)nblk * chunk / chunks);
+        const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
+        // every wave holds the same TS seeds, so every wave takes the same
+        // culling decisions and the block loop below is uniform over the
+        // workgroup
+        float s[R][D], acc[R][D + 1];
+        bool live[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int slot = tile * TS + r * 64 + lane;
+            live[r] = slot < m;
+            const int j = a.act_in[live[r] ? slot : tile * TS];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s[r][k] = a.S[(long long)j * DP + k] * a.scale;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
+        }
+        int blk = next_live_block<D, R>(geom, b0, b1, s, live, qcull);
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 v = z;
+        if (blk < b1) {
+            const long long p = (long long)blk * kCullBlk + threadIdx.x;
+            v = p < n ? X4[p] : z;
+        }
+        while (blk < b1) {
+            __syncthreads();   // the previous block is no longer read
+            xs[threadIdx.x] = v;
+            __syncthreads();
+            const int nxt = next_live_block<D, R>(geom, blk + 1, b1, s, live, qcull);
+            if (nxt < b1) {   // in flight while this block computes
+                const long long p = (long long)nxt * kCullBlk + threadIdx.x;
+                v = p < n ? X4[p] : z;
+            }
+            const int lo = wave * PW;
+            const int hi = min(lo + PW, n - blk * kCullBlk);
+#pragma unroll 4
+            for (int p = lo; p < hi; ++p) {
+                const float4 xp = xs[p];   // same address in every lane: broadcast
+                const float x[4] = {xp.x, xp.y, xp.z, xp.w};
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    float dx[D];
+                    float q = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        dx[k] = x[k] - s[r][k];
+                        q = fmaf(dx[k], dx[k], q);
+                    }
+                    float w;
+                    if (KERN == MS_KERNEL_GAUSSIAN)
+                        w = __builtin_amdgcn_exp2f(-q);
+                    else
+                        w = (q <= a.h2) ? 1.0f : 0.0f;
+                    acc[r][D] += w;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
+                }
+            }
+            blk = nxt;
+        }
+        // the four wave sums added in wave order
+        if (wave > 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) red[(wave - 1) * V + k * TS + r * 64 + lane] = acc[r][k];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) {
+                    float v = acc[r][k];
+#pragma unroll
+                    for (int w2 = 1; w2 < kWaves; ++w2) v += red[(w2 - 1) * V + k * TS + r * 64 + lane];
+                    acc[r][k] = v;
+                }
+        }
+        __syncthreads();
+        if (chunks == 1) {
+            if (wave == 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) red[k * TS + r * 64 + lane] = acc[r][k];
+            }
+            __syncthreads();
+            finalize_tile<D, DP, R>(a, t, m, tile, red);
+            __syncthreads();
+        } else if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float* dst = a.part + (((long long)tile * chunks + chunk) * TS + r * 64 + lane) * (D + 1);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) dst[k] = acc[r][k];
+            }
+        }
+    }
+}
+
+template <int D, int R>
+hipError_t launch_cull_t(Batch& b, int t, hipStream_t s) {
+    StepArgs a;
+    a.Xp = b.Xs;
+    a.n = b.n;
+    a.d = b.d;
+    a.min_chunk = b.sh.MC;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
+    a.prog = b.prog;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    if (b.kernel == MS_KERNEL_GAUSSIAN)
+        hipLaunchKernelGGL((step_cull_kernel<D, R, MS_KERNEL_GAUSSIAN>), dim3(b.grid), dim3(kThreads), 0,
+                           s, a, b.geom, kCullGauss, t);
+    else
+        hipLaunchKernelGGL((step_cull_kernel<D, R, MS_KERNEL_FLAT>), dim3(b.grid), dim3(kThreads), 0, s,
+                           a, b.geom, a.h2 * kCullFlatMargin, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize<D, 4, R>(a, t, b.grid, b.n_seeds, s);
+}
+
+}  // namespace
+
+bool cull_supported(int d, int n) {
+    return d <= 4 && n >= kCullMinPoints;
+}
+
+StepShape step_shape_cull(int d, int B, int n) {
+    StepShape sh;
+    sh.D = d;
+    sh.DP = 4;
+    sh.R = 1;
+    sh.TS = 64 * sh.R;
+    sh.MC = 4 * kCullBlk;   // whole blocks per chunk, at least four
+    (void)B;
+    (void)n;
+    return sh;
+}
+
+hipError_t launch_iteration_cull(Batch& b, int t, hipStream_t s) {
+    const int D = b.sh.D, R = b.sh.R;
+#define FMS_CASE(DD, RR) \
+    if (D == DD && R == RR) return launch_cull_t<DD, RR>(b, t, s);
+    FMS_CASE(1, 1) FMS_CASE(2, 1) FMS_CASE(3, 1) FMS_CASE(4, 1)
+    FMS_CASE(1, 2) FMS_CASE(2, 2) FMS_CASE(3, 2) FMS_CASE(4, 2)
+#undef FMS_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fms

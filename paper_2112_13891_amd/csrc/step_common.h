@@ -323,10 +323,23 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
 #pragma unroll
                 for (int k = 0; k <= D; ++k) v[k] = 0.0f;
                 const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
-                for (int c = 0; c < chunks; ++c) {
-                    const float* p = src + (long long)c * TS * (D + 1);
+                // U chunks' loads in flight at once, added in chunk order
+                constexpr int U = D <= 4 ? 16 : (D <= 8 ? 8 : (D <= 16 ? 4 : (D <= 32 ? 2 : 1)));
+                for (int c0 = 0; c0 < chunks; c0 += U) {
+                    float tmp[U][D + 1];
 #pragma unroll
-                    for (int k = 0; k <= D; ++k) v[k] += p[k];
+                    for (int u = 0; u < U; ++u) {
+                        const float* p = src + (long long)(c0 + u < chunks ? c0 + u : c0) * TS * (D + 1);
+#pragma unroll
+                        for (int k = 0; k <= D; ++k) tmp[u][k] = p[k];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (c0 + u < chunks) {
+#pragma unroll
+                            for (int k = 0; k <= D; ++k) v[k] += tmp[u][k];
+                        }
+                    }
                 }
             }
             res = update_seed<D, DP>(a, slot, v);
@@ -337,12 +350,17 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
 
 // Launch of the reduction (exits at once unless many chunks) and the finalize
 // (exits at once when the step kernel finalized) for a batch of B seeds.
+// may_reduce = false: the caller's shape never has more than kDirectChunks
+// chunks per tile, and the reduction launch is left out.
 template <int D, int DP, int R>
-inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hipStream_t s) {
-    const int rblocks = B < 256 ? (B < 1 ? 1 : B) : 256;
-    hipLaunchKernelGGL((reduce_kernel<D, R>), dim3(rblocks), dim3(kRedThreads), 0, s, a, t, grid);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hipStream_t s,
+                                  bool may_reduce = true) {
+    if (may_reduce) {
+        const int rblocks = B < 256 ? (B < 1 ? 1 : B) : 256;
+        hipLaunchKernelGGL((reduce_kernel<D, R>), dim3(rblocks), dim3(kRedThreads), 0, s, a, t, grid);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     int fblocks = (B + kFinThreads - 1) / kFinThreads;
     if (fblocks > 512) fblocks = 512;
     if (fblocks < 1) fblocks = 1;
