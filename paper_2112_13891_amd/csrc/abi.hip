@@ -331,7 +331,9 @@ thread_local ProgressWord g_prog;
 // (every later one would find none either) or max_iter were enqueued.  If the
 // stream drains without a new report, the control block is read back instead.
 int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror) {
-    constexpr int kAhead = 2;
+    // one iteration queued behind the running one: an iteration lasts longer
+    // than the host needs to see it start and enqueue the next
+    constexpr int kAhead = 1;
     constexpr unsigned long long kNone = ~0ull;
     volatile unsigned long long* word = g_prog.host;
     *word = kNone;

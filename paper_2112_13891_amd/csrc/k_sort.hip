@@ -101,11 +101,15 @@ __device__ __forceinline__ unsigned morton_key(const float* row, int D, float sc
     return key;
 }
 
+constexpr int kPointKeyDrop = 6;   // Morton bits dropped from the point keys
+
 __global__ void morton_kernel(const float* __restrict__ Xp, int n, int DP, int D,
                               const float* __restrict__ bnd, unsigned* keys, int* vals) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    keys[i] = morton_key(Xp + (long long)i * DP, D, 1.0f, bnd);
+    // the top 24 bits of the Morton code (256 cells per axis for D = 3):
+    // three radix passes instead of four
+    keys[i] = morton_key(Xp + (long long)i * DP, D, 1.0f, bnd) >> kPointKeyDrop;
     vals[i] = i;
 }
 
@@ -427,12 +431,15 @@ SortWs carve(void* ws, int count) {
 
 // Stable sort of (k0, v0) by the 32-bit keys, four 8-bit passes; the result
 // is back in (k0, v0).
-void radix_sort_pairs(const SortWs& w, int n, hipStream_t s) {
+// LSD radix sort of (key, value) pairs on the low 8 * passes bits of the keys;
+// returns the array that holds the sorted values (v0 after an even number of
+// passes, v1 after an odd one).
+int* radix_sort_pairs(const SortWs& w, int n, hipStream_t s, int passes = 4) {
     const int nblocks = (n + kSortThreads - 1) / kSortThreads;
     hipLaunchKernelGGL(zero_ints_kernel, dim3(4), dim3(256), 0, s, w.dtot, 4 * 256);
     unsigned* ka = w.k0; unsigned* kb = w.k1;
     int* va = w.v0; int* vb = w.v1;
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
         const int shift = pass * 8;
         int* dt = w.dtot + pass * 256;
         hipLaunchKernelGGL(radix_hist_kernel, dim3(nblocks), dim3(kSortThreads), 0, s, ka, n, shift,
@@ -443,6 +450,7 @@ void radix_sort_pairs(const SortWs& w, int n, hipStream_t s) {
         unsigned* tk = ka; ka = kb; kb = tk;
         int* tv = va; va = vb; vb = tv;
     }
+    return va;
 }
 
 }  // namespace
@@ -486,8 +494,9 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
                                                 s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, w.k0, w.v0));
     }
-    radix_sort_pairs(w, n, s);
-    hipError_t e = hipMemcpyAsync(perm, w.v0, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+    // point keys: 24-bit Morton codes (D <= 4) or pivot indices below 1024
+    const int* sorted = radix_sort_pairs(w, n, s, D <= 4 ? 3 : 2);
+    hipError_t e = hipMemcpyAsync(perm, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),
                        0, s, Xp, DP, D, perm, n, shift, Xs);
@@ -523,8 +532,8 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
     if (D <= 4)
         hipLaunchKernelGGL(seed_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, S, DP, D, m, scale,
                            status, w.bnd, w.k0, w.v0);
-    radix_sort_pairs(w, m, s);
-    hipError_t e = hipMemcpyAsync(act0, w.v0, (size_t)m * 4, hipMemcpyDeviceToDevice, s);
+    const int* sorted = radix_sort_pairs(w, m, s);
+    hipError_t e = hipMemcpyAsync(act0, sorted, (size_t)m * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }

@@ -35,7 +35,7 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kB16Threads = 256;    // 4 waves x 32 seeds
-constexpr int kB16Seeds = 128;      // seeds per tile
+constexpr int kB16Seeds = 128;      // seeds per tile of the finalize for D > 4
 constexpr int kBlk = 256;           // points per staged block (one centre)
 
 struct Bf16Args {
@@ -128,18 +128,61 @@ __device__ __forceinline__ bf16x8 seed_frag(const float* st, float ns, int hf) {
     return f;
 }
 
-// Bytes staged per 256-point block: first-product features 256 x 32 B,
-// second-product operand 8 tiles x 512 B, FP32 points 256 x 16 B.
-constexpr int kPfBytes = kBlk * 16 * 2;
-constexpr int kXvBytes = (kBlk / 32) * 512 * 2;
-constexpr int kXsBytes = kBlk * 16;
-constexpr int kStageVecs = (kPfBytes + kXvBytes + kXsBytes) / 16 / kB16Threads;   // per thread
+// Block culling.  For a seed s~ (packed units) and block b (centre c, radius
+// R_b), every point lies at squared distance q >= lb^2, lb = |s~ - c| - R_b,
+// and the estimate satisfies E <= -q + eps (eps = kappa (R_b + |s~ - c|)^2,
+// the same bound the refine test uses).  When lb^2 exceeds both -e_thr + 2 eps
+// and (Gaussian) 127 + eps, no pair of the block can pass the refine test or
+// the far test, so the tile loop would add nothing for this seed: a group of
+// 32 seeds skips the block when all of its seeds are that far, and the wave
+// skips the block when both groups do.  The result is the one of the unculled
+// loop.  Every wave of a workgroup holds the same seeds, so every wave takes
+// the same decisions.
+template <int D, int R, bool kGauss>
+__device__ __forceinline__ bool bf16_block_near(const float* __restrict__ gm, const float (&shat)[R][D],
+                                                const bool (&live)[R], float kappa, float e_thr,
+                                                bool (&gnear)[R]) {
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < R; ++g) {
+        float ns = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float u = shat[g][k] - gm[k];
+            ns = fmaf(u, u, ns);
+        }
+        const float dist = sqrtf(ns);
+        const float rr = gm[4] + dist;
+        const float ep = kappa * rr * rr;
+        float need = -e_thr + 2.0f * ep;
+        if (kGauss) need = fmaxf(need, 127.0f + ep);
+        need = need * 1.001f + 1e-3f;
+        const float lb = dist - gm[4];
+        const bool nl = live[g] && !(lb > 0.0f && lb * lb > need);
+        gnear[g] = __ballot(nl) != 0ull;
+        any = any || gnear[g];
+    }
+    return any;
+}
+
+// One iteration of the BF16 form.  A workgroup takes a tile of 64 seeds (two
+// groups of 32) and a chunk of whole blocks.  Wave w holds group w / 2 and
+// computes the 32-point tiles 4 (w % 2) .. 4 (w % 2) + 3 (points
+// [128 (w % 2), 128 (w % 2) + 128)) of every block of the chunk that some seed
+// of its group may see, with no barrier across waves: the first- and
+// second-product operands come from global memory straight into the MFMA
+// registers (one tile ahead), the wave's 128 FP32 points for the exact path
+// through a wave-private LDS slice.  The two half-block sums of a seed are
+// added in wave order.
+constexpr int kTilesPerWave = kBlk / 32 / 2;   // 32-point MFMA tiles per wave and block
+constexpr int kPtsPerWave = kBlk / 2;
 
 template <int D, int KERN, int R>
 __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int t) {
-    constexpr int TS = kB16Seeds * R;   // 4 waves x R groups x 32 seeds
-    constexpr int NCOL = 2 * D + 1;     // [x~h | x~l | 1]
+    constexpr int TS = 64;
+    constexpr int NCOL = 2 * D + 1;
     constexpr bool kGauss = KERN == MS_KERNEL_GAUSSIAN;
+    static_assert(R == 1, "one group of 32 seeds per wave");
     const StepArgs& a = A.base;
     Ctl* ctl = a.ctl;
     const int n = a.n;
@@ -151,181 +194,154 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
     const int nblk = (n + kBlk - 1) / kBlk;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = wave >> 1, half = wave & 1;
     const int lane = threadIdx.x & 63;
     const int col = lane & 31, hf = lane >> 5;
 
-    __shared__ __attribute__((aligned(16))) char stage[kPfBytes + kXvBytes + kXsBytes];
-    __shared__ float tr[kB16Threads / 64][NCOL][33];   // per-wave transpose (padded)
-    __shared__ float fin[(D + 1) * TS];
-    const __bf16* spf = reinterpret_cast<const __bf16*>(stage);
-    const __bf16* sxv = reinterpret_cast<const __bf16*>(stage + kPfBytes);
-    const float4* sxs = reinterpret_cast<const float4*>(stage + kPfBytes + kXvBytes);
+    __shared__ float4 sxs_all[kWaves][kPtsPerWave];
+    __shared__ float tr[kWaves][NCOL][33];   // per-wave transpose (padded)
+    __shared__ float red[kWaves][D + 1][32]; // per-wave seed sums
+    float4* sxs = sxs_all[wave];
+    const float4* __restrict__ xsg = reinterpret_cast<const float4*>(A.Xs);
     unsigned refined = 0;
 
-    static_assert(kStageVecs == 5 && kPfBytes / 16 == 2 * kB16Threads &&
-                  kXvBytes / 16 == 2 * kB16Threads && kXsBytes / 16 == kB16Threads,
-                  "stage layout");
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
         const int b0 = (int)((long long)nblk * chunk / chunks);
         const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
-        float shat[R][D], arun[R][D], aex[R][D], wrun[R], wex[R];
-        bool live[R];
-#pragma unroll
-        for (int g = 0; g < R; ++g) {
-            const int slot = tile * TS + (wave * R + g) * 32 + col;
-            live[g] = slot < m;
-            const int j = a.act_in[live[g] ? slot : 0];
+        float shat[1][D], arun[D], aex[D], wrun = 0.0f, wex = 0.0f;
+        bool live[1];
+        {
+            const int slot = tile * TS + grp * 32 + col;
+            live[0] = slot < m;
+            const int j = a.act_in[live[0] ? slot : tile * TS];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                shat[g][k] = a.S[(long long)j * 4 + k] * a.scale;
-                arun[g][k] = aex[g][k] = 0.0f;
+                shat[0][k] = a.S[(long long)j * 4 + k] * a.scale;
+                arun[k] = aex[k] = 0.0f;
             }
-            wrun[g] = wex[g] = 0.0f;
         }
-        // operands of the first block of the chunk, five 16-byte vectors per
-        // thread: two of features, two of the second operand, one of points
-        uint4 n0, n1, n2, n3, n4;
-        {
-            const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)b0 * kBlk * 16);
-            const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)b0 * (kBlk / 32) * 512);
-            const uint4* xsg = reinterpret_cast<const uint4*>(A.Xs) + (long long)b0 * kBlk;
-            n0 = pfg[threadIdx.x];
-            n1 = pfg[kB16Threads + threadIdx.x];
-            n2 = xvg[threadIdx.x];
-            n3 = xvg[kB16Threads + threadIdx.x];
-            n4 = (long long)b0 * kBlk + threadIdx.x < n ? xsg[threadIdx.x] : uint4{};
-        }
+        bool gn[1];
+        int blk = b0;
+        while (blk < b1 && !bf16_block_near<D, 1, kGauss>(A.geom + (long long)blk * kGeomStride, shat, live,
+                                                           A.kappa, A.e_thr, gn))
+            ++blk;
+        float4 p0 = {}, p1 = {};
+        auto fetch_pts = [&](int bb) {
+            const long long p = (long long)bb * kBlk + half * kPtsPerWave + lane;
+            p0 = p < n ? xsg[p] : float4{};
+            p1 = p + 64 < n ? xsg[p + 64] : float4{};
+        };
+        if (blk < b1) fetch_pts(blk);
 
-        for (int blk = b0; blk < b1; ++blk) {
-            __syncthreads();   // the previous block's operands are no longer read
-            reinterpret_cast<uint4*>(stage)[threadIdx.x] = n0;
-            reinterpret_cast<uint4*>(stage)[kB16Threads + threadIdx.x] = n1;
-            reinterpret_cast<uint4*>(stage)[2 * kB16Threads + threadIdx.x] = n2;
-            reinterpret_cast<uint4*>(stage)[3 * kB16Threads + threadIdx.x] = n3;
-            reinterpret_cast<uint4*>(stage)[4 * kB16Threads + threadIdx.x] = n4;
-            __syncthreads();
-            if (blk + 1 < b1) {   // next block's operands travel while this one computes
-                const uint4* pfg = reinterpret_cast<const uint4*>(A.pf + (long long)(blk + 1) * kBlk * 16);
-                const uint4* xvg = reinterpret_cast<const uint4*>(A.xv + (long long)(blk + 1) * (kBlk / 32) * 512);
-                const uint4* xsg = reinterpret_cast<const uint4*>(A.Xs) + (long long)(blk + 1) * kBlk;
-                n0 = pfg[threadIdx.x];
-                n1 = pfg[kB16Threads + threadIdx.x];
-                n2 = xvg[threadIdx.x];
-                n3 = xvg[kB16Threads + threadIdx.x];
-                n4 = (long long)(blk + 1) * kBlk + threadIdx.x < n ? xsg[threadIdx.x] : uint4{};
-            }
+        while (blk < b1) {
+            // the previous block's points are no longer read (LDS operations
+            // of one wave complete in order)
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            sxs[lane] = p0;
+            sxs[64 + lane] = p1;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            int nxt = blk + 1;
+            while (nxt < b1 && !bf16_block_near<D, 1, kGauss>(A.geom + (long long)nxt * kGeomStride, shat,
+                                                               live, A.kappa, A.e_thr, gn))
+                ++nxt;
+            if (nxt < b1) fetch_pts(nxt);   // next live block's points travel while this one computes
+
             const float* gm = A.geom + (long long)blk * kGeomStride;
-            float st[R][D], eps[R];
-            bf16x8 sfrag[R];
+            float st[D];
+            float ns = 0.0f;
 #pragma unroll
-            for (int g = 0; g < R; ++g) {
-                float ns = 0.0f;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    st[g][k] = shat[g][k] - gm[k];
-                    ns = fmaf(st[g][k], st[g][k], ns);
-                }
-                const float rr = gm[4] + sqrtf(ns);
-                eps[g] = A.kappa * rr * rr;
-                sfrag[g] = seed_frag<D>(st[g], ns, hf);
+            for (int k = 0; k < D; ++k) {
+                st[k] = shat[0][k] - gm[k];
+                ns = fmaf(st[k], st[k], ns);
             }
-            f32x16 out[R];
-            bool used[R];
-#pragma unroll
-            for (int g = 0; g < R; ++g) {
-                out[g] = f32x16{};
-                used[g] = false;
-            }
+            const float rr = gm[4] + sqrtf(ns);
+            const float eps = A.kappa * rr * rr;
+            const bf16x8 sfrag = seed_frag<D>(st, ns, hf);
+            f32x16 out = f32x16{};
+            bool used = false;
+            const long long tt0 = (long long)blk * (kBlk / 32) + half * kTilesPerWave;
+            const __bf16* pfb = A.pf + tt0 * 512 + hf * 256 + col * 8;
+            const __bf16* xvb = A.xv + tt0 * 512 + (hf * 16 + col) * 8;
+            bf16x8 anext = *reinterpret_cast<const bf16x8*>(pfb);
 #pragma unroll 1
-            for (int tt = 0; tt < kBlk / 32; ++tt) {
-                const bf16x8 afrag = *reinterpret_cast<const bf16x8*>(spf + tt * 512 + hf * 256 + col * 8);
-                // both groups' products first, so that one hides the other's latency
-                f32x16 E[R];
-                float emax[R];
-#pragma unroll
-                for (int g = 0; g < R; ++g)
-                    E[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag[g], f32x16{}, 0, 0, 0);
-#pragma unroll
-                for (int g = 0; g < R; ++g) {
-                    // tree of maxima (depth 3 instead of a chain of 8)
-                    const float m0 = fmaxf(fmaxf(E[g][0], E[g][1]), E[g][2]);
-                    const float m1 = fmaxf(fmaxf(E[g][3], E[g][4]), E[g][5]);
-                    const float m2 = fmaxf(fmaxf(E[g][6], E[g][7]), E[g][8]);
-                    const float m3 = fmaxf(fmaxf(E[g][9], E[g][10]), E[g][11]);
-                    const float m4 = fmaxf(fmaxf(E[g][12], E[g][13]), E[g][14]);
-                    emax[g] = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[g][15]));
+            for (int tt = 0; tt < kTilesPerWave; ++tt) {
+                const bf16x8 afrag = anext;
+                if (tt + 1 < kTilesPerWave) anext = *reinterpret_cast<const bf16x8*>(pfb + (tt + 1) * 512);
+                bf16x8 x0 = {}, x1 = {};
+                if (kGauss && col < NCOL) {
+                    x0 = *reinterpret_cast<const bf16x8*>(xvb + tt * 512);
+                    x1 = *reinterpret_cast<const bf16x8*>(xvb + tt * 512 + 2 * 16 * 8);
                 }
+                f32x16 E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag, f32x16{}, 0, 0, 0);
+                // tree of maxima (depth 3 instead of a chain of 8)
+                const float m0 = fmaxf(fmaxf(E[0], E[1]), E[2]);
+                const float m1 = fmaxf(fmaxf(E[3], E[4]), E[5]);
+                const float m2 = fmaxf(fmaxf(E[6], E[7]), E[8]);
+                const float m3 = fmaxf(fmaxf(E[9], E[10]), E[11]);
+                const float m4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
+                const float emax = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[15]));
+                const bool ref = __ballot(emax + eps >= A.e_thr);
+                if (ref) {
+                    // some pair of this 32 x 32 tile may lie within the refine
+                    // radius: every row of the lane is recomputed exactly in
+                    // FP32 (points from LDS), and each pair keeps the exact
+                    // weight if and only if its own bound flags it (its
+                    // estimate is then replaced by -inf, weight 0 in the bf16
+                    // sums), so the result of a pair never depends on its
+                    // tile mates
+                    const float4* xr = sxs + tt * 32 + 4 * hf;
+                    unsigned nref = 0;
 #pragma unroll
-                for (int g = 0; g < R; ++g) {
-                    const bool ref = __ballot(emax[g] + eps[g] >= A.e_thr);
-                    if (ref) {
-                        // some pair of this 32 x 32 tile may lie within the refine
-                        // radius: every row of the lane is recomputed exactly in
-                        // FP32 (points from LDS), and each pair keeps the exact
-                        // weight if and only if its own bound flags it (its
-                        // estimate is then replaced by -inf, weight 0 in the bf16
-                        // sums), so the result of a pair never depends on its
-                        // tile mates
-                        const float4* xr = sxs + tt * 32 + 4 * hf;
-                        unsigned nref = 0;
+                    for (int q = 0; q < 4; ++q) {
+                        float4 x4[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            float4 x4[4];
+                        for (int u = 0; u < 4; ++u) x4[u] = xr[8 * q + u];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) x4[u] = xr[8 * q + u];
+                        for (int u = 0; u < 4; ++u) {
+                            const int v = 4 * q + u;
+                            const bool need = E[v] + eps >= A.e_thr;
+                            const float xv[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
+                            float dx[D], q2 = 0.0f;
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const int v = 4 * q + u;
-                                const bool need = E[g][v] + eps[g] >= A.e_thr;
-                                const float xv[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
-                                float dx[D], q2 = 0.0f;
-#pragma unroll
-                                for (int k = 0; k < D; ++k) {
-                                    dx[k] = xv[k] - shat[g][k];
-                                    q2 = fmaf(dx[k], dx[k], q2);
-                                }
-                                float we = kGauss ? __builtin_amdgcn_exp2f(-q2)
-                                                  : (q2 <= a.h2 ? 1.0f : 0.0f);
-                                we = need ? we : 0.0f;
-                                wex[g] += we;
-#pragma unroll
-                                for (int k = 0; k < D; ++k) aex[g][k] = fmaf(we, dx[k], aex[g][k]);
-                                nref += need ? 1u : 0u;
-                                E[g][v] = need ? -__builtin_inff() : E[g][v];
+                            for (int k = 0; k < D; ++k) {
+                                dx[k] = xv[k] - shat[0][k];
+                                q2 = fmaf(dx[k], dx[k], q2);
                             }
-                        }
-                        refined += live[g] ? nref : 0u;
-                    }
-                    // far pairs (Gaussian only): weights from the estimate, unless
-                    // every weight of the wave underflows (2^-127)
-                    if (kGauss && (ref || __ballot(emax[g] >= -127.0f))) {
-                        bf16x8 w0, w1;
+                            float we = kGauss ? __builtin_amdgcn_exp2f(-q2) : (q2 <= a.h2 ? 1.0f : 0.0f);
+                            we = need ? we : 0.0f;
+                            wex += we;
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            w0[q] = (__bf16)__builtin_amdgcn_exp2f(E[g][q]);
-                            w1[q] = (__bf16)__builtin_amdgcn_exp2f(E[g][8 + q]);
+                            for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
+                            nref += need ? 1u : 0u;
+                            E[v] = need ? -__builtin_inff() : E[v];
                         }
-                        bf16x8 x0 = {}, x1 = {};
-                        if (col < NCOL) {
-                            x0 = *reinterpret_cast<const bf16x8*>(sxv + tt * 512 + ((0 * 2 + hf) * 16 + col) * 8);
-                            x1 = *reinterpret_cast<const bf16x8*>(sxv + tt * 512 + ((1 * 2 + hf) * 16 + col) * 8);
-                        }
-                        out[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, x0, out[g], 0, 0, 0);
-                        out[g] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, x1, out[g], 0, 0, 0);
-                        used[g] = true;
                     }
+                    refined += live[0] ? nref : 0u;
+                }
+                // far pairs (Gaussian only): weights from the estimate, unless
+                // every weight of the wave underflows (2^-127)
+                if (kGauss && (ref || __ballot(emax >= -127.0f))) {
+                    bf16x8 w0, w1;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        w0[q] = (__bf16)__builtin_amdgcn_exp2f(E[q]);
+                        w1[q] = (__bf16)__builtin_amdgcn_exp2f(E[8 + q]);
+                    }
+                    out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w0, x0, out, 0, 0, 0);
+                    out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, x1, out, 0, 0, 0);
+                    used = true;
                 }
             }
             // ---- out[seed row][col] -> per-seed sums through a wave-local
             // transpose (LDS operations of one wave complete in order)
-#pragma unroll
-            for (int g = 0; g < R; ++g) {
-                if (!__ballot(used[g])) continue;
+            if (__ballot(used)) {
                 if (col < NCOL) {
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) tr[wave][col][8 * (v >> 2) + 4 * hf + (v & 3)] = out[g][v];
+                    for (int v = 0; v < 16; ++v) tr[wave][col][8 * (v >> 2) + 4 * hf + (v & 3)] = out[v];
                 }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -334,48 +350,52 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                 for (int k = 0; k < D; ++k) {
                     const float sx = tr[wave][k][col] + tr[wave][D + k][col];
                     // sum w (x~ - s~) = sum w (x - s): the block centre cancels
-                    arun[g][k] += sx - st[g][k] * Wb;
+                    arun[k] += sx - st[k] * Wb;
                 }
-                wrun[g] += Wb;
+                wrun += Wb;
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
+            blk = nxt;
         }
 
-        // ---- chunk partials (one (D+1)-vector per seed): the two lane halves
-        // saw different points of the same seed
+        // ---- this wave's sums per seed: the two lane halves saw different
+        // points of the same seed
 #pragma unroll
-        for (int g = 0; g < R; ++g) {
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                aex[g][k] += __shfl_xor(aex[g][k], 32);
-                arun[g][k] += aex[g][k];
-            }
-            wex[g] += __shfl_xor(wex[g], 32);
-            wrun[g] += wex[g];
+        for (int k = 0; k < D; ++k) {
+            aex[k] += __shfl_xor(aex[k], 32);
+            arun[k] += aex[k];
         }
+        wex += __shfl_xor(wex, 32);
+        wrun += wex;
+        if (hf == 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) red[wave][k][col] = arun[k];
+            red[wave][D][col] = wrun;
+        }
+        __syncthreads();
+        // the two half-block sums of seed pos = 32 g + c, first half first
+        float v[D + 1];
+        const int pos = threadIdx.x;
+        if (pos < TS) {
+            const int g = pos >> 5, c = pos & 31;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) v[k] = red[2 * g][k][c] + red[2 * g + 1][k][c];
+        }
+        __syncthreads();
         if (chunks == 1) {
-            if (hf == 0) {
+            float* sums = &red[0][0][0];   // (D + 1) x 64 floats: sums[k * TS + pos]
+            if (pos < TS) {
 #pragma unroll
-                for (int g = 0; g < R; ++g) {
-                    const int pos = (wave * R + g) * 32 + col;
-#pragma unroll
-                    for (int k = 0; k < D; ++k) fin[k * TS + pos] = arun[g][k];
-                    fin[D * TS + pos] = wrun[g];
-                }
+                for (int k = 0; k <= D; ++k) sums[k * TS + pos] = v[k];
             }
             __syncthreads();
-            finalize_tile<D, 4, R * 2>(a, t, m, tile, fin);
+            finalize_tile<D, 4, 1>(a, t, m, tile, sums);
             __syncthreads();
-        } else if (hf == 0) {
+        } else if (pos < TS) {
+            float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
 #pragma unroll
-            for (int g = 0; g < R; ++g) {
-                const int pos = (wave * R + g) * 32 + col;
-                float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
-#pragma unroll
-                for (int k = 0; k < D; ++k) dst[k] = arun[g][k];
-                dst[D] = wrun[g];
-            }
+            for (int k = 0; k <= D; ++k) dst[k] = v[k];
         }
     }
     // refined pairs: lane counts summed per wave, one atomic per wave
@@ -420,7 +440,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
                            0, s, A, t);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_finalize<D, 4, 2 * R>(a, t, b.grid, b.n_seeds, s);
+    return launch_finalize<D, 4, 1>(a, t, b.grid, b.n_seeds, s);
 }
 
 }  // namespace
@@ -433,12 +453,12 @@ StepShape step_shape_bf16(int d, int B) {
         sh.TS = kB16Seeds;
         return sh;
     }
-    // 4 waves x R groups of 32 seeds.  Two groups share each staged block and
-    // pay off for mid-sized batches; one group needs fewer registers (4 waves
-    // per SIMD instead of 2), which wins for small and for large batches.
-    const int groups = (B >= 2 * kB16Seeds && B <= 1024) ? 2 : 1;
-    sh.R = 2 * groups;     // the finalize geometry: TS = 64 * R
-    sh.TS = kB16Seeds * groups;
+    // a tile of 64 seeds (two groups of 32) held by all four waves, chunks
+    // of at least two blocks
+    sh.R = 1;              // the finalize geometry: TS = 64 * R
+    sh.TS = 64;
+    sh.MC = 2 * kBlk;
+    (void)B;
     return sh;
 }
 
@@ -446,12 +466,11 @@ bool bf16_supported(int d) { return d >= 1 && (d <= 4 || (d <= 32 && bf16w_dims(
 
 hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s) {
     if (b.sh.D > 4) return launch_iteration_bf16w(b, t, s);
-    const bool two = b.sh.TS == 2 * kB16Seeds;
     switch (b.sh.D) {
-        case 1: return two ? launch_bf16_t<1, 2>(b, t, s) : launch_bf16_t<1, 1>(b, t, s);
-        case 2: return two ? launch_bf16_t<2, 2>(b, t, s) : launch_bf16_t<2, 1>(b, t, s);
-        case 3: return two ? launch_bf16_t<3, 2>(b, t, s) : launch_bf16_t<3, 1>(b, t, s);
-        case 4: return two ? launch_bf16_t<4, 2>(b, t, s) : launch_bf16_t<4, 1>(b, t, s);
+        case 1: return launch_bf16_t<1, 1>(b, t, s);
+        case 2: return launch_bf16_t<2, 1>(b, t, s);
+        case 3: return launch_bf16_t<3, 1>(b, t, s);
+        case 4: return launch_bf16_t<4, 1>(b, t, s);
         default: return hipErrorInvalidValue;
     }
 }

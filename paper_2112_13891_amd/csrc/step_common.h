@@ -217,7 +217,7 @@ __device__ void finalize_tile(const StepArgs& a, int t, int m, int tile, const f
 
 // Reduction of the chunk partials and finalize (only when chunks > 1).
 // Few chunks (many seeds): finalize_kernel reads the partials itself, one lane
-// per seed, adding them in chunk order.  Many chunks (few seeds): reduce_kernel
+// per seed, adding them in chunk order (all loads in flight at once).  Many chunks (few seeds): reduce_kernel
 // first spreads the sums over the whole chip -- each workgroup takes a group of
 // SG seeds (a power of two <= 16, <= 8 for D >= 32, chosen from m and the grid), its 1024 threads
 // add the partials of chunk lanes c = cl, cl + 1024/SG, ... in fixed order,
@@ -227,7 +227,7 @@ __device__ void finalize_tile(const StepArgs& a, int t, int m, int tile, const f
 // ballot and one atomic, so the active list keeps 64-slot runs in order.
 constexpr int kFinThreads = 1024;
 constexpr int kFinWaves = kFinThreads / 64;
-constexpr int kDirectChunks = 64;
+constexpr int kDirectChunks = 16;   // one round of loads per seed in the finalize
 constexpr int kRedThreads = 1024;
 
 template <int D, int DP>
