@@ -228,6 +228,20 @@ int ms_step_adjoint(const void *X, int32_t nbatch, int64_t n, const void *S,
 int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
                  int32_t count, int32_t *out);
 
+/*
+ * ms_seed_count_next -- seed-count adaptation across the frames of a
+ * sequence (video, tracking; Section II-D).  A frame starts with the seed
+ * count N the previous frame ended with (ms_params.n_initial; ms_fit still
+ * doubles it while N < L*M), and a count that grew above H times the mode
+ * count is cut by one mode count per frame:
+ *     *n_next = N - M  if N > H*M,  else N   (and at least 1),
+ * with N = n_last, the seed count of the previous frame's last round
+ * (ms_diag.round_N[rounds - 1]), and M = modes, its mode count.  The paper
+ * uses H = 32.  MS_E_INVALID unless n_last >= 1, modes >= 0 and H >= 1.
+ * Host only; no GPU needed.
+ */
+int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t *n_next);
+
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char *ms_last_error(void);
 

@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 with the HIP library in ``paper_2112_13891_amd`` and never imports it.
 
 The arithmetic lives in ``fms_oracle.c`` (plain C, FP64, index-order sums); this
-module only loads it with ctypes and marshals numpy arrays.  ``adjoint.py`` holds
+module loads it with ctypes, marshals numpy arrays, and holds the host-side
+seed-count rule for frame sequences (integer logic, Section II-D).  ``adjoint.py`` holds
 the FP64 reference for the differentiated step, written with plain PyTorch CPU
 ops.
 """
@@ -210,3 +211,26 @@ def fit(X, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_radius=1.0,
                      rN[:R].copy(), rB[:R].copy(), rM[:R].copy(), rT[:R].copy(),
                      drawn[:tot].copy(), diters[:tot].copy(), dstat[:tot].copy(),
                      dfinal[:tot].copy(), int(pairs[0]))
+
+
+def next_seed_count(N: int, M: int, H: int = 32) -> int:
+    """Section II-D (video / tracking): the seed count a frame starts with is
+    the previous frame's final N, lowered by M (that frame's mode count)
+    whenever it exceeds H * M, so that a count grown for a busy scene falls
+    back gradually once the scene is quiet again; never below one seed."""
+    if N > H * M:
+        N = N - M
+    return max(1, N)
+
+
+def fit_sequence(frames, h, H: int = 32, n_initial: int = 128, **kw):
+    """The method frame by frame, each fit warm-started with the seed count the
+    previous one ended with (Section II-D).  Returns (results, start counts)."""
+    results, starts = [], []
+    N = int(n_initial)
+    for X in frames:
+        starts.append(N)
+        r = fit(X, h, n_initial=N, **kw)
+        results.append(r)
+        N = next_seed_count(int(r.round_N[-1]), r.k, H)
+    return results, starts

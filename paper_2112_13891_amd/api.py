@@ -74,7 +74,8 @@ class Diag(ctypes.Structure):
 
 
 EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_assign",
-           "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_last_error", "ms_version")
+           "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
+           "ms_last_error", "ms_version")
 
 _lib = None
 
@@ -105,6 +106,8 @@ def lib():
     L.ms_step_adjoint.restype = ctypes.c_int
     L.ms_seed_draw.argtypes = [P, P, i32, i32, P]
     L.ms_seed_draw.restype = ctypes.c_int
+    L.ms_seed_count_next.argtypes = [i32, i32, i32, P]
+    L.ms_seed_count_next.restype = ctypes.c_int
     L.ms_last_error.argtypes = []
     L.ms_last_error.restype = ctypes.c_char_p
     L.ms_version.argtypes = []
@@ -369,3 +372,26 @@ def seed_draw(rng_state: int, pool, count: int):
                             int(count), out.ctypes.data_as(ctypes.c_void_p))
     _check(rc)
     return out, int(st.value)
+
+
+def seed_count_next(n_last: int, modes: int, H: int = 32) -> int:
+    """Seed count the next frame of a sequence starts with (Section II-D):
+    n_last - modes when n_last > H * modes, else n_last."""
+    out = ctypes.c_int32(0)
+    _check(lib().ms_seed_count_next(int(n_last), int(modes), int(H), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fit_sequence(frames, h, H: int = 32, n_initial: int = 128, **kw):
+    """The method over a sequence of point sets (frames of a video or a
+    tracking run): each frame is one ms_fit that starts from the seed count
+    the previous frame ended with, adapted by seed_count_next.  Returns the
+    per-frame FitResults and the seed count each frame started with."""
+    results, starts = [], []
+    N = int(n_initial)
+    for X in frames:
+        starts.append(N)
+        r = fit(X, h, n_initial=N, **kw)
+        results.append(r)
+        N = seed_count_next(int(r.round_N[-1]), r.k, H)
+    return results, starts

@@ -992,6 +992,18 @@ int ms_seed_draw(uint64_t* state, const int32_t* pool, int32_t len, int32_t coun
     return MS_OK;
 }
 
+int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t* n_next) {
+    g_err.clear();
+    if (!n_next) return fail(MS_E_INVALID, "NULL argument");
+    if (n_last < 1 || modes < 0 || H < 1) return fail(MS_E_INVALID, "need n_last >= 1, modes >= 0, H >= 1");
+    // Section II-D, frame sequences: a count above H times the mode count is
+    // too expensive and shrinks by one mode count per frame
+    long long next = n_last;
+    if ((long long)n_last > (long long)H * modes) next = (long long)n_last - modes;
+    *n_next = (int32_t)std::max(1LL, next);
+    return MS_OK;
+}
+
 const char* ms_last_error(void) { return g_err.c_str(); }
 
 const char* ms_version(void) { return "libfms 0.1 (gfx950)"; }

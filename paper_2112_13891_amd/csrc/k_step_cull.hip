@@ -16,7 +16,7 @@
 // a wave.
 //
 // Work decomposition (from the active count m only, as in the plain step):
-// tiles of TS = 64 R seeds, chunks of at least 4 whole blocks; a workgroup
+// tiles of TS = 64 R seeds, chunks of at least 2 whole blocks; a workgroup
 // of 4 waves takes one (tile, chunk).  All four waves hold the tile's seeds,
 // so they agree on which blocks are live; each live block is staged in LDS
 // with one coalesced vector load per thread (the next live block's load is in
@@ -231,7 +231,7 @@ StepShape step_shape_cull(int d, int B, int n) {
     sh.DP = 4;
     sh.R = 1;
     sh.TS = 64 * sh.R;
-    sh.MC = 4 * kCullBlk;   // whole blocks per chunk, at least four
+    sh.MC = 2 * kCullBlk;   // whole blocks per chunk, at least two
     (void)B;
     (void)n;
     return sh;

@@ -22,6 +22,13 @@ Workloads
                plus 5 % uniform outliers in [-12,12]^32; flat or Gaussian, h=1.5.
 ``clouds16``   many independent D=16 clouds with log-uniform sizes, 2..40
                clusters each (centres N(0,9 I), sigma 0.4); Gaussian, h=1.
+``image_rgb``  an RGB image as side^2 colour 3-vectors in [0,255]: a Voronoi
+               partition into coloured regions plus per-channel noise, pixels
+               in raster order (the segmentation shape of Section I, Fig. 1);
+               Gaussian, h=12.
+``frames2d``   a sequence of 2-D frames (video / tracking, Section II-D):
+               drifting blobs, and from one frame on a quieter scene with
+               fewer blobs; Gaussian, h=5.
 """
 from __future__ import annotations
 
@@ -123,6 +130,49 @@ def diffclouds(seed: int = 0, n_clouds: int = 64, n: int = 16384, d: int = 16):
     """Equal-size clouds for the differentiable form. Returns a list of (X, y, centres)."""
     rng = np.random.default_rng(seed)
     return [cloud16(rng, n, d) for _ in range(n_clouds)]
+
+
+def image_rgb(seed: int = 0, side: int = 512, regions: int = 24, noise: float = 6.0) -> Workload:
+    """side x side pixels: region sites uniform in the image, each pixel takes
+    the colour (uniform in [0,255]^3) of its nearest site, plus N(0, noise^2)
+    per channel, clipped to [0,255].  Raster order, not shuffled: an image is
+    stored that way."""
+    rng = np.random.default_rng(seed)
+    sites = rng.uniform(0.0, float(side), (regions, 2))
+    colours = rng.uniform(0.0, 255.0, (regions, 3))
+    yy, xx = np.meshgrid(np.arange(side, dtype=np.float64) + 0.5, np.arange(side, dtype=np.float64) + 0.5,
+                         indexing="ij")
+    pix = np.stack([yy.ravel(), xx.ravel()], axis=1)
+    y = np.empty(pix.shape[0], np.int64)
+    for a in range(0, pix.shape[0], 1 << 16):   # nearest site, in slices
+        d2 = ((pix[a:a + (1 << 16), None, :] - sites[None, :, :]) ** 2).sum(axis=2)
+        y[a:a + (1 << 16)] = d2.argmin(axis=1)
+    X = colours[y] + noise * rng.standard_normal((pix.shape[0], 3))
+    X = np.clip(X, 0.0, 255.0)
+    return Workload(f"image_rgb{side}", np.ascontiguousarray(X, dtype=np.float32),
+                    np.ascontiguousarray(y, dtype=np.int32), h=12.0, kernel="gaussian",
+                    extra={"sites": sites, "colours": colours, "side": side})
+
+
+def frames2d(seed: int = 0, n: int = 20_000, k: int = 40, n_frames: int = 6, change_at: int = 3,
+             k_after: int = 4, drift: float = 0.5, sigma: float = 2.0, box: float = 400.0):
+    """A frame sequence: k blobs (sigma 2, centres uniform in [0, box]^2) whose
+    centres move by N(0, drift^2 I) from frame to frame; from frame change_at on
+    only the first k_after blobs hold points.  n points per frame, each frame
+    drawn and shuffled in turn.  Returns a list of Workloads."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, box, (k, 2))
+    out = []
+    for f in range(n_frames):
+        if f > 0:
+            centres = centres + drift * rng.standard_normal((k, 2))
+        kk = k if f < change_at else k_after
+        y = rng.integers(0, kk, n)
+        X = centres[y] + sigma * rng.standard_normal((n, 2))
+        X, y = _finish(rng, X, y)
+        out.append(Workload(f"frames2d[{f}]", X, y, h=5.0, kernel="gaussian",
+                            extra={"centres": centres[:kk].copy()}))
+    return out
 
 
 WORKLOADS = {
