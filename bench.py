@@ -143,6 +143,38 @@ def other_configs(api, torch, workloads):
     out["embed32_gaussian_bf16"] = fit_rate(w, 2, precision="bf16")
     out["embed32_gaussian_bf16"]["speedup_vs_fp32"] = (
         out["embed32_gaussian_fp32"]["time_to_cluster_ms"] / out["embed32_gaussian_bf16"]["time_to_cluster_ms"])
+    # cosine metric on 32-D embeddings (unit directions, chord bandwidth 0.3)
+    w = workloads.embed_cos(seed=0)
+    for prec in ("fp32", "bf16"):
+        out[f"embed32_cosine_{prec}"] = fit_rate(w, 2, precision=prec, metric="cosine")
+    out["embed32_cosine_fp32"]["workload"] = ("embed_cos: 262,144 rows, D=32, 100 directions (angular "
+                                              "spread 0.2) + 5% uniform directions, cosine metric, "
+                                              "Gaussian chord h=0.3")
+    # RGB images (the segmentation shape of Section I): 512^2 and 1024^2 pixels
+    for side in (512, 1024):
+        w = workloads.image_rgb(seed=0, side=side)
+        for prec in ("fp32", "bf16"):
+            key = f"image_rgb{side}_{prec}"
+            out[key] = fit_rate(w, 5, precision=prec)
+            if prec == "fp32":
+                out[key]["workload"] = (f"image_rgb: {side}x{side} RGB pixels ({side * side:,} points, "
+                                        "D=3), 24 Voronoi colour regions + N(0, 6^2) noise, Gaussian h=12")
+    # frame sequence with seed-count adaptation (Section II-D): 6 frames
+    frames = workloads.frames2d(seed=0, n=200_000)
+    Xf = [torch.from_numpy(f.X).cuda() for f in frames]
+    for prec in ("fp32", "bf16"):
+        api.fit_sequence(Xf, 5.0, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, starts = api.fit_sequence(Xf, 5.0, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"frames2d_sequence_{prec}"] = {
+            "ms_per_frame": dt / len(Xf) * 1e3, "start_N": starts,
+            "rounds_per_frame": [len(r.round_N) for r in res], "K": [r.k for r in res]}
+    out["frames2d_sequence_fp32"]["workload"] = (
+        "frames2d: 6 frames x 200,000 points, D=2, 40 drifting blobs then 4 from frame 3, Gaussian h=5, "
+        "each frame warm-started from the previous seed count (H=32)")
     # many uneven clouds in one batched call (FP32): 512 clouds of 1,000..65,536
     # points, D = 16, up to 256 seeds each, 10 iterations with every seed active
     clouds = workloads.clouds16(seed=0)

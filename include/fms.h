@@ -52,6 +52,20 @@ typedef enum {
 } ms_kernel;
 
 typedef enum {
+    /* Euclidean distance (the paper's method) */
+    MS_METRIC_EUCLIDEAN = 0,
+    /* cosine metric (the authors' earlier Faster Mean Shift on cosine
+       embeddings): every row x of X is replaced by its direction x/|x|, seeds
+       are unit vectors, every distance is the chord between unit vectors,
+       |s - u|^2 = 2 - 2 cos(s, u) (so the flat window keeps cos >= 1 - h^2/2
+       and the Gaussian weight is exp((cos - 1)/h^2)), the update is the
+       weighted mean direction sum w u / |sum w u|, and tol, the merge and
+       cover radii and the labels use chords (labels: largest cosine).
+       Modes are unit vectors. */
+    MS_METRIC_COSINE = 1
+} ms_metric;
+
+typedef enum {
     MS_PREC_FP32 = 0,        /* FP32 direct differences, FP32 accumulation */
     MS_PREC_BF16_REFINE = 1  /* BF16 MFMA products, FP32 recompute within
                                 refine_radius*h, FP32 accumulation */
@@ -80,12 +94,15 @@ typedef struct {
     int32_t all_points_as_seeds; /* 1: Algorithm 1 (every point is a seed,
                                     one batch); 0: Algorithm 2 (pool) */
     int32_t check_finite;     /* 1: scan X for NaN/Inf first */
-    int32_t reserved[4];      /* must be 0 */
+    int32_t metric;           /* ms_metric (ms_fit, ms_step); ms_step_batched,
+                                 ms_assign: Euclidean only */
+    int32_t reserved[3];      /* must be 0 */
 } ms_params;
 
 /* Fills *p with the defaults: h = 1, Gaussian, FP32, tol = 1e-3,
  * max_iter = 100, merge_radius = cover_radius = 1, gamma = 1,
- * n_initial = 128, L = 8, refine_radius = 3, pool mode, rng_seed = 0. */
+ * n_initial = 128, L = 8, refine_radius = 3, pool mode, rng_seed = 0,
+ * Euclidean metric. */
 void ms_default_params(ms_params *p);
 
 #define MS_DIAG_MAX_ROUNDS 64
@@ -128,6 +145,9 @@ typedef struct {
  *   labels  device, n int32 (may be NULL); nearest mode, ties to the lowest
  *           index.
  *   diag    host, optional (NULL to skip).
+ * With p->metric = MS_METRIC_COSINE the method runs on the directions of the
+ * rows of X (a row of length 0 makes the call fail with MS_E_INVALID) and the
+ * modes are unit vectors.
  * Host-synchronous: returns when K is on the host and labels are written.
  * Errors: MS_E_INVALID, MS_E_NONFINITE, MS_E_CAPACITY, MS_E_NO_MODES,
  * MS_E_NOMEM, MS_E_HIP.  On error the contents of modes/labels are
@@ -149,7 +169,10 @@ int ms_fit(const ms_params *p, const float *X, int64_t n, int32_t d,
  *   iters      device, m int32, out: updates applied during this call.
  *   shift2     device, m float32, out: squared length of the last update
  *              (unchanged for seeds that received none).
- * Uses p->h, kernel, precision, tol, refine_radius; other fields ignored.
+ * Uses p->h, kernel, precision, tol, refine_radius, metric; other fields
+ * ignored.  Cosine metric: the seeds are made unit vectors on entry and stay
+ * unit vectors; a row of X of length 0 has no direction and makes every seed
+ * that sees it fail.
  */
 int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
             float *seeds, int32_t m, int32_t n_iter, uint8_t *converged,

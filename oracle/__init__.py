@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "libfms_oracle.so")
 FLAT = 0
 GAUSSIAN = 1
 KERNELS = {"flat": FLAT, "gaussian": GAUSSIAN}
+METRICS = {"euclidean": 0, "cosine": 1}
 
 ACTIVE, CONVERGED, FAILED = 0, 1, 2
 
@@ -59,16 +60,22 @@ def lib():
         L.orc_step.argtypes = [P, i64, ctypes.c_int, f64, ctypes.c_int, f64, P, i32, i32,
                                P, P, P, ctypes.c_int]
         L.orc_step.restype = ctypes.c_int
+        L.orc_step_metric.argtypes = L.orc_step.argtypes + [ctypes.c_int]
+        L.orc_step_metric.restype = ctypes.c_int
         L.orc_splitmix64.argtypes = [P]
         L.orc_splitmix64.restype = u64
         L.orc_draw.argtypes = [P, P, i32, i32]
         L.orc_draw.restype = None
         L.orc_assign.argtypes = [P, i64, ctypes.c_int, P, i32, P, P, ctypes.c_int]
         L.orc_assign.restype = ctypes.c_int
+        L.orc_assign_metric.argtypes = L.orc_assign.argtypes + [ctypes.c_int]
+        L.orc_assign_metric.restype = ctypes.c_int
         L.orc_fit.argtypes = ([P, i64, ctypes.c_int, f64, ctypes.c_int, f64, i32, f64, f64,
                                f64, i32, i32, i32, u64, ctypes.c_int, i32, P, P, P, P, P,
                                i32] + [P] * 10)
         L.orc_fit.restype = ctypes.c_int
+        L.orc_fit_metric.argtypes = L.orc_fit.argtypes + [ctypes.c_int]
+        L.orc_fit_metric.restype = ctypes.c_int
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
@@ -105,8 +112,9 @@ def mean(X, s, h, kernel="gaussian"):
 
 
 def step(X, seeds, h, kernel="gaussian", tol=1e-3, n_iter=1, status=None,
-         nthreads=None):
-    """Up to n_iter updates of the active seeds (status 0).
+         nthreads=None, metric="euclidean"):
+    """Up to n_iter updates of the active seeds (status 0).  With
+    ``metric="cosine"`` points and seeds are taken as their directions.
 
     Returns (seeds', status', iters, shift2)."""
     X = _f32(X)
@@ -115,9 +123,9 @@ def step(X, seeds, h, kernel="gaussian", tol=1e-3, n_iter=1, status=None,
     st = np.zeros(m, np.uint8) if status is None else np.array(status, np.uint8, copy=True)
     iters = np.zeros(m, np.int32)
     sh = np.full(m, np.nan, np.float64)
-    rc = lib().orc_step(_ptr(X), X.shape[0], X.shape[1], float(h), KERNELS[kernel],
-                        float(tol), _ptr(S), m, int(n_iter), _ptr(st), _ptr(iters),
-                        _ptr(sh), threads(nthreads))
+    rc = lib().orc_step_metric(_ptr(X), X.shape[0], X.shape[1], float(h), KERNELS[kernel],
+                               float(tol), _ptr(S), m, int(n_iter), _ptr(st), _ptr(iters),
+                               _ptr(sh), threads(nthreads), METRICS[metric])
     if rc != 0:
         raise ValueError(f"orc_step failed: {rc}")
     return S, st, iters, sh
@@ -136,13 +144,13 @@ def draw(seed: int, pool, count: int):
     return a[:count].copy(), int(state[0])
 
 
-def assign(X, modes, nthreads=None):
+def assign(X, modes, nthreads=None, metric="euclidean"):
     X = _f32(X)
     M = np.ascontiguousarray(modes, dtype=np.float64).reshape(-1, X.shape[1])
     labels = np.empty(X.shape[0], np.int32)
     margin = np.empty(X.shape[0], np.float64)
-    rc = lib().orc_assign(_ptr(X), X.shape[0], X.shape[1], _ptr(M), M.shape[0],
-                          _ptr(labels), _ptr(margin), threads(nthreads))
+    rc = lib().orc_assign_metric(_ptr(X), X.shape[0], X.shape[1], _ptr(M), M.shape[0],
+                                 _ptr(labels), _ptr(margin), threads(nthreads), METRICS[metric])
     if rc != 0:
         raise ValueError(f"orc_assign failed: {rc}")
     return labels, margin
@@ -177,8 +185,10 @@ class FitResult:
 
 def fit(X, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_radius=1.0,
         cover_radius=1.0, gamma=1.0, n_initial=128, L=8, all_points=False,
-        rng_seed=0, max_modes=None, nthreads=None, max_rounds=64) -> FitResult:
-    """The whole method (Algorithm 2; Algorithm 1 with ``all_points``)."""
+        rng_seed=0, max_modes=None, nthreads=None, max_rounds=64,
+        metric="euclidean") -> FitResult:
+    """The whole method (Algorithm 2; Algorithm 1 with ``all_points``), on the
+    points or, with ``metric="cosine"``, on their directions."""
     X = _f32(X)
     n, d = X.shape
     max_modes = int(max_modes or n)
@@ -195,14 +205,14 @@ def fit(X, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_radius=1.0,
     dfinal = np.zeros((n, d), np.float64)
     pairs = np.zeros(1, np.int64)
     # gamma, tol and radii are taken as the float32 values the library sees
-    rc = lib().orc_fit(_ptr(X), n, d, float(np.float32(h)), KERNELS[kernel],
+    rc = lib().orc_fit_metric(_ptr(X), n, d, float(np.float32(h)), KERNELS[kernel],
                        float(np.float32(tol)), int(max_iter), float(np.float32(merge_radius)),
                        float(np.float32(cover_radius)), float(np.float32(gamma)),
                        int(n_initial), int(L), int(bool(all_points)), int(rng_seed) & (2**64 - 1),
                        threads(nthreads), max_modes, _ptr(modes), _ptr(counts), _ptr(k),
                        _ptr(labels), _ptr(margin), max_rounds, _ptr(nr), _ptr(rN), _ptr(rB),
                        _ptr(rM), _ptr(rT), _ptr(drawn), _ptr(diters), _ptr(dstat),
-                       _ptr(dfinal), _ptr(pairs))
+                       _ptr(dfinal), _ptr(pairs), METRICS[metric])
     K = int(k[0])
     R = int(nr[0])
     tot = int(rB[:R].sum())

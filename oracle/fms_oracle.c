@@ -42,6 +42,15 @@
  *     otherwise N doubles and a new batch is drawn.
  *   - labelling (Algorithm 2, last loop): nearest mode, ties to the lowest
  *     index.
+ *   - cosine metric (the authors' earlier Faster Mean Shift on cosine
+ *     embeddings; the method itself is unchanged): every point is replaced by
+ *     its direction u = x / |x|, a seed is a unit vector s, and every distance
+ *     of the Euclidean form becomes the chord between unit vectors,
+ *     |s - u|^2 = 2 - 2 cos(s, u) = 2 - 2 s.u.  So the flat window keeps the
+ *     points with cos >= 1 - h^2/2, the Gaussian weight is exp((cos - 1)/h^2),
+ *     the update is the weighted mean direction s' = sum w u / |sum w u|, and
+ *     the convergence, merge, coverage and labelling radii are chords
+ *     (labels: largest cosine, ties to the lowest index).
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +63,9 @@
 
 #define ORC_FLAT 0
 #define ORC_GAUSSIAN 1
+
+#define ORC_EUCLIDEAN 0
+#define ORC_COSINE 1
 
 #define ORC_OK 0
 #define ORC_E_INVALID (-1)
@@ -91,6 +103,24 @@ static double sq_dist_dd(const double *a, const double *b, int d)
     return q;
 }
 
+static double dot_dd(const double *a, const double *b, int d)
+{
+    double c = 0.0;
+    for (int k = 0; k < d; ++k)
+        c += a[k] * b[k];
+    return c;
+}
+
+/* The squared distance the method works with, between a point row x and a
+ * position s (both FP64): Euclidean, or for the cosine metric the squared
+ * chord 2 - 2 s.x between unit vectors. */
+static double pair_q(const double *x, const double *s, int d, int metric)
+{
+    if (metric == ORC_COSINE)
+        return 2.0 - 2.0 * dot_dd(x, s, d);
+    return sq_dist_dd(x, s, d);
+}
+
 /* Kernel weight for squared distance q: flat window of eq. (12), inclusive
  * at q == h^2, or the Gaussian profile exp(-q/(2h^2)). */
 double orc_weight(double q, double h, int kernel)
@@ -123,16 +153,74 @@ double orc_mean(const float *X, int64_t n, int d, const double *s, double h,
     return wsum;
 }
 
+/* The same update on FP64 point rows P (n x d) for either metric: the
+ * weighted mean, or for the cosine metric the weighted mean direction
+ * sum w u / |sum w u|.  Returns sum_i w_i, or 0 when the update is undefined
+ * (no weight, or a zero mean vector of directions); out is then unchanged. */
+static double mean_rows(const double *P, int64_t n, int d, const double *s, double h,
+                        int kernel, int metric, double *out)
+{
+    double acc[256];
+    double wsum = 0.0;
+    for (int k = 0; k < d; ++k)
+        acc[k] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *x = P + i * (int64_t)d;
+        double w = orc_weight(pair_q(x, s, d, metric), h, kernel);
+        wsum += w;
+        for (int k = 0; k < d; ++k)
+            acc[k] += w * x[k];
+    }
+    if (!(wsum > 0.0))
+        return 0.0;
+    if (metric == ORC_COSINE) {
+        double norm = sqrt(dot_dd(acc, acc, d));
+        if (!(norm > 0.0))
+            return 0.0;
+        for (int k = 0; k < d; ++k)
+            out[k] = acc[k] / norm;
+    } else {
+        for (int k = 0; k < d; ++k)
+            out[k] = acc[k] / wsum;
+    }
+    return wsum;
+}
+
+/* FP64 point rows for a metric: the exact widening of X, or the unit
+ * directions x / |x| for the cosine metric (NULL if a row has no direction
+ * or allocation fails). */
+static double *point_rows(const float *X, int64_t n, int d, int metric)
+{
+    double *P = (double *)malloc(sizeof(double) * (size_t)n * (size_t)d);
+    if (!P)
+        return NULL;
+    for (int64_t i = 0; i < n; ++i) {
+        double *p = P + i * (int64_t)d;
+        for (int k = 0; k < d; ++k)
+            p[k] = (double)X[i * (int64_t)d + k];
+        if (metric == ORC_COSINE) {
+            double norm = sqrt(dot_dd(p, p, d));
+            if (!(norm > 0.0) || !isfinite(norm)) {
+                free(P);
+                return NULL;
+            }
+            for (int k = 0; k < d; ++k)
+                p[k] /= norm;
+        }
+    }
+    return P;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Fixed-budget iteration of caller-given seeds                              */
 /* ------------------------------------------------------------------------ */
 
 /* Advance one seed by one update.  Returns the new status. */
-static int advance(const float *X, int64_t n, int d, double h, int kernel,
+static int advance(const double *P, int64_t n, int d, double h, int kernel, int metric,
                    double tol, double *s, double *shift2_out)
 {
     double next[256];
-    double wsum = orc_mean(X, n, d, s, h, kernel, next);
+    double wsum = mean_rows(P, n, d, s, h, kernel, metric, next);
     if (!(wsum > 0.0))
         return ORC_FAILED;
     double delta2 = sq_dist_dd(next, s, d);
@@ -146,23 +234,49 @@ static int advance(const float *X, int64_t n, int d, double h, int kernel,
  * inner while loop).  seeds: m x d in/out; status in/out; iters out = updates
  * applied during this call; shift2 out = last squared shift (untouched seeds
  * keep their value). */
-int orc_step(const float *X, int64_t n, int d, double h, int kernel, double tol,
-             double *seeds, int32_t m, int32_t n_iter, uint8_t *status,
-             int32_t *iters, double *shift2, int nthreads)
+int orc_step_metric(const float *X, int64_t n, int d, double h, int kernel, double tol,
+                    double *seeds, int32_t m, int32_t n_iter, uint8_t *status,
+                    int32_t *iters, double *shift2, int nthreads, int metric)
 {
-    if (d < 1 || d > 256 || n < 1 || m < 0 || n_iter < 0 || !(h > 0.0))
+    if (d < 1 || d > 256 || n < 1 || m < 0 || n_iter < 0 || !(h > 0.0) ||
+        (metric != ORC_EUCLIDEAN && metric != ORC_COSINE))
         return ORC_E_INVALID;
+    double *P = point_rows(X, n, d, metric);
+    if (!P)
+        return ORC_E_INVALID;
+    if (metric == ORC_COSINE) {
+        /* caller seeds become unit vectors */
+        for (int32_t j = 0; j < m; ++j) {
+            double *s = seeds + (int64_t)j * d;
+            double norm = sqrt(dot_dd(s, s, d));
+            if (!(norm > 0.0)) {
+                free(P);
+                return ORC_E_INVALID;
+            }
+            for (int k = 0; k < d; ++k)
+                s[k] /= norm;
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int32_t j = 0; j < m; ++j) {
         iters[j] = 0;
         for (int32_t t = 0; t < n_iter && status[j] == ORC_ACTIVE; ++t) {
-            status[j] = (uint8_t)advance(X, n, d, h, kernel, tol,
+            status[j] = (uint8_t)advance(P, n, d, h, kernel, metric, tol,
                                          seeds + (int64_t)j * d, shift2 + j);
             if (status[j] != ORC_FAILED)
                 iters[j] += 1;
         }
     }
+    free(P);
     return ORC_OK;
+}
+
+int orc_step(const float *X, int64_t n, int d, double h, int kernel, double tol,
+             double *seeds, int32_t m, int32_t n_iter, uint8_t *status,
+             int32_t *iters, double *shift2, int nthreads)
+{
+    return orc_step_metric(X, n, d, h, kernel, tol, seeds, m, n_iter, status, iters,
+                           shift2, nthreads, ORC_EUCLIDEAN);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -203,18 +317,18 @@ void orc_draw(uint64_t *state, int32_t *a, int32_t len, int32_t count)
 /* Labelling (Algorithm 2, final loop)                                        */
 /* ------------------------------------------------------------------------ */
 
-int orc_assign(const float *X, int64_t n, int d, const double *modes, int32_t K,
-               int32_t *labels, double *margin, int nthreads)
+static int assign_rows(const double *P, int64_t n, int d, const double *modes, int32_t K,
+                       int metric, int32_t *labels, double *margin, int nthreads)
 {
     if (K < 1 || d < 1)
         return ORC_E_INVALID;
 #pragma omp parallel for schedule(static) num_threads(nthreads)
     for (int64_t i = 0; i < n; ++i) {
-        const float *x = X + i * (int64_t)d;
+        const double *x = P + i * (int64_t)d;
         double best = INFINITY, second = INFINITY;
         int32_t arg = 0;
         for (int32_t j = 0; j < K; ++j) {
-            double q = sq_dist(x, modes + (int64_t)j * d, d);
+            double q = pair_q(x, modes + (int64_t)j * d, d, metric);
             if (q < best) {
                 second = best;
                 best = q;
@@ -225,9 +339,26 @@ int orc_assign(const float *X, int64_t n, int d, const double *modes, int32_t K,
         }
         labels[i] = arg;
         if (margin)
-            margin[i] = (K > 1) ? sqrt(second) - sqrt(best) : INFINITY;
+            margin[i] = (K > 1) ? sqrt(fmax(second, 0.0)) - sqrt(fmax(best, 0.0)) : INFINITY;
     }
     return ORC_OK;
+}
+
+int orc_assign_metric(const float *X, int64_t n, int d, const double *modes, int32_t K,
+                      int32_t *labels, double *margin, int nthreads, int metric)
+{
+    double *P = point_rows(X, n, d, metric);
+    if (!P)
+        return ORC_E_INVALID;
+    int rc = assign_rows(P, n, d, modes, K, metric, labels, margin, nthreads);
+    free(P);
+    return rc;
+}
+
+int orc_assign(const float *X, int64_t n, int d, const double *modes, int32_t K,
+               int32_t *labels, double *margin, int nthreads)
+{
+    return orc_assign_metric(X, n, d, modes, K, labels, margin, nthreads, ORC_EUCLIDEAN);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -252,7 +383,7 @@ typedef struct {
 /* Iterate one batch of B seeds (Algorithm 2 lines "for each seed / while not
  * converge" with the early-stopping rule of Section II-C).  pos: B x d in/out,
  * status out, iters out.  Returns the number of iterations run. */
-static int32_t run_batch(const float *X, int64_t n, int d, double h, int kernel,
+static int32_t run_batch(const double *P, int64_t n, int d, double h, int kernel, int metric,
                          double tol, int32_t max_iter, double gamma, int32_t B,
                          double *pos, int8_t *status, int32_t *iters,
                          int64_t *pairs, int nthreads)
@@ -278,7 +409,7 @@ static int32_t run_batch(const float *X, int64_t n, int d, double h, int kernel,
             if (status[j] != ORC_ACTIVE)
                 continue;
             double s2 = 0.0;
-            int st = advance(X, n, d, h, kernel, tol, pos + (int64_t)j * d, &s2);
+            int st = advance(P, n, d, h, kernel, metric, tol, pos + (int64_t)j * d, &s2);
             if (st != ORC_FAILED)
                 iters[j] += 1;
             status[j] = (int8_t)st;
@@ -295,7 +426,7 @@ static int32_t run_batch(const float *X, int64_t n, int d, double h, int kernel,
 /* Greedy merge of one batch into the mode list, in draw order ("prune
  * modes").  Returns the new mode count, or -1 when max_modes is exceeded
  * (the count keeps growing in *k_needed). */
-static int32_t merge_batch(int d, double radius, int32_t B, const double *pos,
+static int32_t merge_batch(int d, int metric, double radius, int32_t B, const double *pos,
                            const int8_t *status, int32_t K, int32_t max_modes,
                            double *modes, int32_t *counts, int32_t *k_needed)
 {
@@ -307,7 +438,7 @@ static int32_t merge_batch(int d, double radius, int32_t B, const double *pos,
         int32_t join = -1;
         int32_t kk = (K < max_modes) ? K : max_modes;
         for (int32_t j = 0; j < kk; ++j) {
-            if (sq_dist_dd(p, modes + (int64_t)j * d, d) <= r2) {
+            if (pair_q(p, modes + (int64_t)j * d, d, metric) <= r2) {
                 join = j;
                 break;
             }
@@ -326,20 +457,23 @@ static int32_t merge_batch(int d, double radius, int32_t B, const double *pos,
     return K;
 }
 
-int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
-            int32_t max_iter, double merge_r, double cover_r, double gamma,
-            int32_t n_initial, int32_t L, int32_t all_points, uint64_t rng_seed,
-            int nthreads, int32_t max_modes, double *modes, int32_t *counts,
-            int32_t *k_out, int32_t *labels, double *margin, int32_t max_rounds,
-            int32_t *n_rounds, int32_t *round_N, int32_t *round_B,
-            int32_t *round_M, int32_t *round_T, int32_t *drawn,
-            int32_t *drawn_iters, int8_t *drawn_status, double *drawn_final,
-            int64_t *pairs)
+int orc_fit_metric(const float *X, int64_t n, int d, double h, int kernel, double tol,
+                   int32_t max_iter, double merge_r, double cover_r, double gamma,
+                   int32_t n_initial, int32_t L, int32_t all_points, uint64_t rng_seed,
+                   int nthreads, int32_t max_modes, double *modes, int32_t *counts,
+                   int32_t *k_out, int32_t *labels, double *margin, int32_t max_rounds,
+                   int32_t *n_rounds, int32_t *round_N, int32_t *round_B,
+                   int32_t *round_M, int32_t *round_T, int32_t *drawn,
+                   int32_t *drawn_iters, int8_t *drawn_status, double *drawn_final,
+                   int64_t *pairs, int metric)
 {
     if (d < 1 || d > 256 || n < 1 || n > 0x7fffffffLL || !(h > 0.0) ||
         max_iter < 1 || !(gamma > 0.0 && gamma <= 1.0) || n_initial < 1 ||
-        L < 1 || max_modes < 1)
+        L < 1 || max_modes < 1 || (metric != ORC_EUCLIDEAN && metric != ORC_COSINE))
         return ORC_E_INVALID;
+    double *P = point_rows(X, n, d, metric);
+    if (!P)
+        return (metric == ORC_COSINE) ? ORC_E_INVALID : ORC_E_NOMEM;
 
     int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     int32_t *batch = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -348,7 +482,7 @@ int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
     int8_t *status = (int8_t *)malloc((size_t)n);
     int32_t *iters = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     if (!pool || !batch || !gone || !pos || !status || !iters) {
-        free(pool); free(batch); free(gone); free(pos); free(status); free(iters);
+        free(pool); free(batch); free(gone); free(pos); free(status); free(iters); free(P);
         return ORC_E_NOMEM;
     }
 
@@ -376,12 +510,12 @@ int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
         }
         for (int32_t j = 0; j < B; ++j)
             for (int k = 0; k < d; ++k)
-                pos[(int64_t)j * d + k] = (double)X[(int64_t)batch[j] * d + k];
+                pos[(int64_t)j * d + k] = P[(int64_t)batch[j] * d + k];
 
-        int32_t T = run_batch(X, n, d, h, kernel, tol, max_iter, gamma, B, pos,
+        int32_t T = run_batch(P, n, d, h, kernel, metric, tol, max_iter, gamma, B, pos,
                               status, iters, pairs, nthreads);
         int32_t K_before = K;
-        K = merge_batch(d, merge_r * h, B, pos, status, K, max_modes, modes,
+        K = merge_batch(d, metric, merge_r * h, B, pos, status, K, max_modes, modes,
                         counts, &k_needed);
 
         if (rounds < max_rounds) {
@@ -418,7 +552,7 @@ int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
                 int32_t i = pool[p];
                 int covered = 0;
                 for (int32_t j = k0; j < kk && !covered; ++j)
-                    covered = sq_dist(X + (int64_t)i * d, modes + (int64_t)j * d, d) <= rc2;
+                    covered = pair_q(P + (int64_t)i * d, modes + (int64_t)j * d, d, metric) <= rc2;
                 gone[i] = (uint8_t)covered;
             }
             /* the pool is kept in ascending index order */
@@ -441,10 +575,27 @@ int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
     else if (K == 0)
         rc = ORC_E_NO_MODES;
     else if (labels)
-        orc_assign(X, n, d, modes, K, labels, margin, nthreads);
+        assign_rows(P, n, d, modes, K, metric, labels, margin, nthreads);
 
-    free(pool); free(batch); free(gone); free(pos); free(status); free(iters);
+    free(pool); free(batch); free(gone); free(pos); free(status); free(iters); free(P);
     return rc;
+}
+
+int orc_fit(const float *X, int64_t n, int d, double h, int kernel, double tol,
+            int32_t max_iter, double merge_r, double cover_r, double gamma,
+            int32_t n_initial, int32_t L, int32_t all_points, uint64_t rng_seed,
+            int nthreads, int32_t max_modes, double *modes, int32_t *counts,
+            int32_t *k_out, int32_t *labels, double *margin, int32_t max_rounds,
+            int32_t *n_rounds, int32_t *round_N, int32_t *round_B,
+            int32_t *round_M, int32_t *round_T, int32_t *drawn,
+            int32_t *drawn_iters, int8_t *drawn_status, double *drawn_final,
+            int64_t *pairs)
+{
+    return orc_fit_metric(X, n, d, h, kernel, tol, max_iter, merge_r, cover_r, gamma,
+                          n_initial, L, all_points, rng_seed, nthreads, max_modes, modes,
+                          counts, k_out, labels, margin, max_rounds, n_rounds, round_N,
+                          round_B, round_M, round_T, drawn, drawn_iters, drawn_status,
+                          drawn_final, pairs, ORC_EUCLIDEAN);
 }
 
 /* Squared-distance helper exported for tests of the oracle itself. */

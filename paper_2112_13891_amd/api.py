@@ -20,6 +20,7 @@ MS_OK, MS_E_INVALID, MS_E_NONFINITE, MS_E_CAPACITY, MS_E_NO_MODES, MS_E_NOMEM, M
     0, -1, -2, -3, -4, -5, -6)
 KERNELS = {"flat": 0, "gaussian": 1}
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16_refine": 1}
+METRICS = {"euclidean": 0, "cosine": 1}
 DIAG_MAX_ROUNDS = 64
 
 
@@ -46,7 +47,8 @@ class Params(ctypes.Structure):
         ("refine_radius", ctypes.c_float),
         ("all_points_as_seeds", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("metric", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -127,7 +129,8 @@ def _check(rc: int, k: int | None = None):
 
 def make_params(h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100,
                 merge_radius=1.0, cover_radius=1.0, gamma=1.0, n_initial=128, L=8,
-                refine_radius=3.0, all_points=False, rng_seed=0, check_finite=False) -> Params:
+                refine_radius=3.0, all_points=False, rng_seed=0, check_finite=False,
+                metric="euclidean") -> Params:
     p = Params()
     lib().ms_default_params(ctypes.byref(p))
     p.h = float(h)
@@ -144,6 +147,7 @@ def make_params(h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100,
     p.all_points_as_seeds = int(bool(all_points))
     p.rng_seed = int(rng_seed) & (2 ** 64 - 1)
     p.check_finite = int(bool(check_finite))
+    p.metric = METRICS[metric] if isinstance(metric, str) else int(metric)
     return p
 
 
@@ -205,15 +209,17 @@ class FitResult:
 
 def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge_radius=1.0,
         cover_radius=1.0, gamma=1.0, n_initial=128, L=8, refine_radius=3.0, all_points=False,
-        rng_seed=0, check_finite=False, max_modes=None, labels=True, trace=False) -> FitResult:
+        rng_seed=0, check_finite=False, max_modes=None, labels=True, trace=False,
+        metric="euclidean") -> FitResult:
     """Whole method on device-resident X (n x d float32).  ``trace`` also returns
-    the drawn ids, per-seed iterations, status and final positions."""
+    the drawn ids, per-seed iterations, status and final positions.
+    ``metric="cosine"`` clusters the directions of the rows (unit-vector modes)."""
     torch = _torch()
     Xp = _dev(X, torch.float32, 2, "X")
     n, d = X.shape
     max_modes = int(max_modes or n)
     p = make_params(h, kernel, precision, tol, max_iter, merge_radius, cover_radius, gamma,
-                    n_initial, L, refine_radius, all_points, rng_seed, check_finite)
+                    n_initial, L, refine_radius, all_points, rng_seed, check_finite, metric)
     modes = torch.empty((max_modes, d), dtype=torch.float32, device=X.device)
     lab = torch.empty((n,), dtype=torch.int32, device=X.device) if labels else None
     k = ctypes.c_int32(0)
@@ -249,7 +255,7 @@ def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge
 
 
 def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, converged=None,
-         refine_radius=3.0):
+         refine_radius=3.0, metric="euclidean"):
     """Up to n_iter updates of the active seeds.  Returns new tensors
     (seeds, converged uint8, iters int32, shift2 float32)."""
     torch = _torch()
@@ -264,7 +270,7 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
             else converged.detach().clone().to(torch.uint8).contiguous())
     iters = torch.zeros(m, dtype=torch.int32, device=X.device)
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
-    p = make_params(h, kernel, precision, tol, refine_radius=refine_radius)
+    p = make_params(h, kernel, precision, tol, refine_radius=refine_radius, metric=metric)
     rc = lib().ms_step(ctypes.byref(p), Xp, n, d, ctypes.c_void_p(S.data_ptr()), m, int(n_iter),
                        ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
                        ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))

@@ -203,7 +203,9 @@ int check_params(const ms_params* p, bool for_fit) {
         return fail(MS_E_INVALID, "tol*h must be a positive finite float");
     if (p->precision == MS_PREC_BF16_REFINE && !(std::isfinite(p->refine_radius) && p->refine_radius >= 0.0f))
         return fail(MS_E_INVALID, "refine_radius must be finite and >= 0");
-    for (int i = 0; i < 4; ++i)
+    if (p->metric != MS_METRIC_EUCLIDEAN && p->metric != MS_METRIC_COSINE)
+        return fail(MS_E_INVALID, "unknown metric");
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
     if (!for_fit) return MS_OK;
     if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
@@ -231,7 +233,7 @@ float packed_scale(const ms_params* p) {
 // and device (grown on demand, never shrunk).
 enum Slot {
     SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
-    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_COUNT
+    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN, SL_COUNT
 };
 
 struct DevCache {
@@ -458,6 +460,7 @@ void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_par
     b.thr2 = tolh * tolh;
     b.Xp = Xp;
     b.grid = step_grid(sh, B, n);
+    b.metric = p->metric;
     b.ctl = ctl;
 }
 
@@ -481,6 +484,20 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         FMS_HIP(hipStreamSynchronize(s));
         if (hflag) return fail(MS_E_NONFINITE, "X contains NaN or Inf");
+    }
+    if (p->metric == MS_METRIC_COSINE) {
+        // the method runs on the directions of the rows
+        float* Xn;
+        int32_t* flag;
+        FMS_CHECK(cache_get(C, budget, SL_XN, (size_t)n * d, &Xn));
+        FMS_CHECK(cache_get(C, budget, SL_FLAG, 1, &flag));
+        FMS_HIP(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+        FMS_HIP(launch_normalize_rows(X, n, d, Xn, flag, s));
+        int32_t hflag = 0;
+        FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipStreamSynchronize(s));
+        if (hflag) return fail(MS_E_INVALID, "cosine metric: a row of X has no direction (length 0 or not finite)");
+        X = Xn;
     }
 
     const StepShape base = step_shape(d);
@@ -764,6 +781,14 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     const StepShape sh = bf16 ? step_shape_bf16(d, m)
                               : (cull ? step_shape_cull(d, m, n) : step_shape_for(d, m));
     const float scale = packed_scale(p);
+    if (p->metric == MS_METRIC_COSINE) {
+        // the directions of the rows (a row of length 0 gives NaN directions,
+        // and every seed that sees it fails)
+        float* Xn;
+        FMS_CHECK(ws.alloc(&Xn, (size_t)n * d));
+        FMS_HIP(launch_normalize_rows(X, n, d, Xn, nullptr, s));
+        X = Xn;
+    }
     float* Xp;
     FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
     FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
@@ -912,6 +937,8 @@ int ms_step_batched(const ms_params* p, const float* X, const int64_t* x_off, fl
     FMS_CHECK(check_params(p, false));
     if (p->precision != MS_PREC_FP32)
         return fail(MS_E_INVALID, "ms_step_batched computes the FP32 form only");
+    if (p->metric != MS_METRIC_EUCLIDEAN)
+        return fail(MS_E_INVALID, "ms_step_batched computes the Euclidean metric only");
     if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
     if (ncl < 1 || ncl > batched_max_clouds()) return fail(MS_E_INVALID, "ncl must be in [1, 8192]");
     if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");

@@ -80,6 +80,7 @@ struct Batch {
     float kappa;           // BF16 form: error bound coefficient
     const float* shift = nullptr;   // BF16 form, D > 4: frame of the sorted points
     unsigned long long* prog = nullptr;   // host-mapped progress word (t << 32 | m), or NULL
+    int metric = MS_METRIC_EUCLIDEAN;     // cosine: seeds are renormalized after each update
     Ctl* ctl;
 };
 
@@ -89,6 +90,9 @@ long long step_red_offset(const StepShape& sh, int B, int grid);
 // ---- launchers (k_step.hip) ----------------------------------------------
 hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale,
                               float* Xp, hipStream_t s);
+// Cosine metric: Xn = rows of X divided by their length; *bad (if not NULL)
+// is set to 1 when a row has no finite nonzero length.
+hipError_t launch_normalize_rows(const float* X, int n, int d, float* Xn, int32_t* bad, hipStream_t s);
 // Fit round start: drawn seeds (pool[pos[j]]; j itself when pos is NULL)
 // leave the pool, become the batch's seeds, and the control block is reset.
 hipError_t launch_round_init(const float* X, int d, int DP, const int32_t* pool,

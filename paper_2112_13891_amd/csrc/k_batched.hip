@@ -215,6 +215,7 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     a.scale = b.scale;
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
+    a.metric = b.metric;
     hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, 64 * R);
     if (b.kernel == MS_KERNEL_GAUSSIAN)
         hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(kBStepGrid), dim3(kThreads),

@@ -48,6 +48,23 @@ __global__ void pack_points_kernel(const float* __restrict__ X, int n, int d, in
     Xp[e] = (k < d) ? X[(long long)i * d + k] * scale : 0.0f;
 }
 
+// Cosine metric: each row divided by its length (FP32); a row without a
+// finite nonzero length raises *bad.
+__global__ void normalize_rows_kernel(const float* __restrict__ X, int n, int d, float* __restrict__ Xn,
+                                      int32_t* bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* x = X + (long long)i * d;
+    float nn = 0.0f;
+    for (int k = 0; k < d; ++k) nn = fmaf(x[k], x[k], nn);
+    const float r = 1.0f / sqrtf(nn);
+    if (!(nn > 0.0f) || !isfinite(r)) {
+        if (bad) *bad = 1;
+    }
+    float* o = Xn + (long long)i * d;
+    for (int k = 0; k < d; ++k) o[k] = x[k] * r;
+}
+
 __device__ void ctl_reset_body(Ctl* ctl, int B, int need, int max_iter) {
     for (int u = threadIdx.x; u <= max_iter; u += blockDim.x) ctl->conv_it[u] = 0;
     if (threadIdx.x < kMaxMergePasses) ctl->und[threadIdx.x] = 0;
@@ -98,13 +115,19 @@ __global__ void round_init_kernel(const float* __restrict__ X, int d, int DP,
 
 __global__ void seed_init_array_kernel(const float* __restrict__ seeds,
                                        const uint8_t* __restrict__ conv_in, int d, int DP,
-                                       int m, float* S, int32_t* act0, uint8_t* status,
+                                       int m, int unit, float* S, int32_t* act0, uint8_t* status,
                                        int32_t* iters, float* shift2, Ctl* ctl) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     bool live = false;
     if (j < m) {
+        float r = 1.0f;   // cosine metric: seeds start as unit vectors
+        if (unit) {
+            float nn = 0.0f;
+            for (int k = 0; k < d; ++k) nn = fmaf(seeds[(long long)j * d + k], seeds[(long long)j * d + k], nn);
+            r = 1.0f / sqrtf(nn);
+        }
         for (int k = 0; k < DP; ++k)
-            S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] : 0.0f;
+            S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] * r : 0.0f;
         uint8_t st = conv_in[j];
         status[j] = st;
         iters[j] = 0;
@@ -201,6 +224,7 @@ hipError_t launch_step_t(Batch& b, int t, hipStream_t s) {
     a.scale = b.scale;
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
+    a.metric = b.metric;
     if (b.kernel == MS_KERNEL_GAUSSIAN)
         hipLaunchKernelGGL((step_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(b.grid),
                            dim3(kThreads), 0, s, a, t);
@@ -261,6 +285,11 @@ long long step_part_floats(const StepShape& sh, int B, int grid) {
     return step_red_offset(sh, B, grid) + tiles * sh.TS * (long long)(sh.D + 1);
 }
 
+hipError_t launch_normalize_rows(const float* X, int n, int d, float* Xn, int32_t* bad, hipStream_t s) {
+    hipLaunchKernelGGL(normalize_rows_kernel, dim3((n + 255) / 256), dim3(256), 0, s, X, n, d, Xn, bad);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_points(const float* X, int n, int d, int DP, float scale, float* Xp,
                               hipStream_t s) {
     long long total = (long long)n * DP;
@@ -288,8 +317,8 @@ hipError_t launch_round_init(const float* X, int d, int DP, const int32_t* pool,
 hipError_t launch_seed_init_from_array(const float* seeds, const uint8_t* conv_in, int d,
                                        int m, Batch& b, hipStream_t s) {
     hipLaunchKernelGGL(seed_init_array_kernel, dim3((m + 255) / 256), dim3(256), 0, s, seeds,
-                       conv_in, d, b.sh.DP, m, b.S, b.act[0], b.status, b.iters, b.shift2,
-                       b.ctl);
+                       conv_in, d, b.sh.DP, m, b.metric == MS_METRIC_COSINE ? 1 : 0, b.S, b.act[0],
+                       b.status, b.iters, b.shift2, b.ctl);
     return hipGetLastError();
 }
 

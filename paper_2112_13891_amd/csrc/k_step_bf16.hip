@@ -426,6 +426,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     a.scale = b.scale;
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
+    a.metric = b.metric;
     A.Xs = b.Xs;
     A.geom = b.geom;
     A.pf = (const __bf16*)b.pf;

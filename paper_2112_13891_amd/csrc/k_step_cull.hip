@@ -208,6 +208,7 @@ hipError_t launch_cull_t(Batch& b, int t, hipStream_t s) {
     a.scale = b.scale;
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
+    a.metric = b.metric;
     if (b.kernel == MS_KERNEL_GAUSSIAN)
         hipLaunchKernelGGL((step_cull_kernel<D, R, MS_KERNEL_GAUSSIAN>), dim3(b.grid), dim3(kThreads), 0,
                            s, a, b.geom, kCullGauss, t);

@@ -53,6 +53,7 @@ struct StepArgs {
     unsigned long long* prog;   // host-mapped progress word, or NULL
     Ctl* ctl;
     float h2, scale, inv_scale, thr2;
+    int metric = MS_METRIC_EUCLIDEAN;   // cosine: the updated seed is renormalized
 };
 
 // Done once per iteration by thread 0 of workgroup 0 of the step kernel:
@@ -88,13 +89,34 @@ __device__ __forceinline__ int update_seed_id(const StepArgs& a, int j, const fl
     float* sj = a.S + (long long)j * DP;
     bool finite = true;
     const float inv = a.inv_scale / W;
-    // padded coordinates (k >= d) carry exact zeros, so looping to D is exact
+    if (a.metric == MS_METRIC_COSINE) {
+        // the weighted mean direction: s' = (s + shift) / |s + shift|, and the
+        // shift that counts is the one to the renormalized seed
+        float nx[D], nn = 0.0f;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        const float dk = v[k] * inv;
-        finite = finite && isfinite(dk);
-        sh2 = fmaf(dk, dk, sh2);
-        sj[k] = sj[k] + dk;
+        for (int k = 0; k < D; ++k) {
+            nx[k] = sj[k] + v[k] * inv;
+            nn = fmaf(nx[k], nx[k], nn);
+        }
+        const float rn = 1.0f / sqrtf(nn);
+        finite = nn > 0.0f && isfinite(rn);
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float uk = nx[k] * rn;
+            const float dk = uk - sj[k];
+            finite = finite && isfinite(uk);
+            sh2 = fmaf(dk, dk, sh2);
+            sj[k] = uk;
+        }
+    } else {
+        // padded coordinates (k >= d) carry exact zeros, so looping to D is exact
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float dk = v[k] * inv;
+            finite = finite && isfinite(dk);
+            sh2 = fmaf(dk, dk, sh2);
+            sj[k] = sj[k] + dk;
+        }
     }
     a.iters[j] += 1;
     a.shift2[j] = sh2;

@@ -26,6 +26,10 @@ Workloads
                partition into coloured regions plus per-channel noise, pixels
                in raster order (the segmentation shape of Section I, Fig. 1);
                Gaussian, h=12.
+``embed_cos``  cosine-metric embeddings, D=32: 100 random unit directions,
+               points at angular spread ~0.2 rad around them plus 5 % uniform
+               directions, every row scaled by a length in [0.5, 2] (only the
+               direction counts); chord bandwidth h=0.3.
 ``frames2d``   a sequence of 2-D frames (video / tracking, Section II-D):
                drifting blobs, and from one frame on a quieter scene with
                fewer blobs; Gaussian, h=5.
@@ -152,6 +156,27 @@ def image_rgb(seed: int = 0, side: int = 512, regions: int = 24, noise: float = 
     return Workload(f"image_rgb{side}", np.ascontiguousarray(X, dtype=np.float32),
                     np.ascontiguousarray(y, dtype=np.int32), h=12.0, kernel="gaussian",
                     extra={"sites": sites, "colours": colours, "side": side})
+
+
+def embed_cos(seed: int = 0, n: int = 262_144, k: int = 100, d: int = 32, spread: float = 0.2,
+              outlier_frac: float = 0.05) -> Workload:
+    """Directions u = (c + sigma g) / |c + sigma g| around unit centres c, with
+    sigma = spread / sqrt(d - 1) (angular spread ~ spread), outliers uniform on
+    the sphere; each row is then multiplied by a length uniform in [0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    centres = rng.standard_normal((k, d))
+    centres /= np.linalg.norm(centres, axis=1, keepdims=True)
+    n_out = int(round(outlier_frac * n))
+    n_in = n - n_out
+    y_in = rng.integers(0, k, n_in)
+    U = centres[y_in] + (spread / math.sqrt(d - 1)) * rng.standard_normal((n_in, d))
+    U_out = rng.standard_normal((n_out, d))
+    U = np.concatenate([U, U_out], axis=0)
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    X = U * rng.uniform(0.5, 2.0, (n, 1))
+    y = np.concatenate([y_in, -np.ones(n_out, dtype=np.int64)])
+    X, y = _finish(rng, X, y)
+    return Workload("embed_cos", X, y, h=0.3, kernel="gaussian", extra={"centres": centres, "metric": "cosine"})
 
 
 def frames2d(seed: int = 0, n: int = 20_000, k: int = 40, n_frames: int = 6, change_at: int = 3,

@@ -16,10 +16,12 @@ MARGIN_TOL = 1e-5
 TIE_BAND = 1e-2
 
 
-def step_parity(orc, X, seeds0, h, kernel, tol, gpu_S, gpu_iters, gpu_status, nthreads=None):
+def step_parity(orc, X, seeds0, h, kernel, tol, gpu_S, gpu_iters, gpu_status, nthreads=None,
+                metric="euclidean"):
     """Returns a report dict; raises AssertionError on a real mismatch."""
     S0 = np.asarray(seeds0, np.float64)
-    oS, ost, oit, osh = orc.step(X, S0, h, kernel, tol=tol, n_iter=10_000, nthreads=nthreads)
+    oS, ost, oit, osh = orc.step(X, S0, h, kernel, tol=tol, n_iter=10_000, nthreads=nthreads,
+                                 metric=metric)
     gS = np.asarray(gpu_S, np.float64)
     git = np.asarray(gpu_iters)
     gst = np.asarray(gpu_status)
@@ -28,12 +30,13 @@ def step_parity(orc, X, seeds0, h, kernel, tol, gpu_S, gpu_iters, gpu_status, nt
     mism = np.nonzero(git != oit)[0]
     for j in mism:
         k = int(min(git[j], oit[j]))
-        _, _, _, sh = orc.step(X, S0[j:j + 1], h, kernel, tol=1e-30, n_iter=k, nthreads=1)
+        _, _, _, sh = orc.step(X, S0[j:j + 1], h, kernel, tol=1e-30, n_iter=k, nthreads=1, metric=metric)
         delta = float(np.sqrt(sh[0]))
         assert abs(delta - tol * h) <= TIE_BAND * tol * h, (
             f"seed {j}: iterations gpu {git[j]} vs oracle {oit[j]}, shift {delta} vs {tol * h}")
         ties += 1
-        ref, _, _, _ = orc.step(X, S0[j:j + 1], h, kernel, tol=1e-30, n_iter=int(git[j]), nthreads=1)
+        ref, _, _, _ = orc.step(X, S0[j:j + 1], h, kernel, tol=1e-30, n_iter=int(git[j]), nthreads=1,
+                                metric=metric)
         err = float(np.abs(ref[0] - gS[j]).max())
         worst = max(worst, err)
         assert err <= MODE_TOL * h, (j, err)
