@@ -95,9 +95,17 @@ def algorithmic_bytes(prec, m, n):
 def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
     """Average duration of one fused-step iteration with every seed active:
     (t(2k iterations) - t(k)) / k, HIP events on the library's stream, so that
-    the call's set-up (packing, sorting, workspace) cancels out."""
+    the call's set-up (packing, sorting, workspace) cancels out.  A few
+    milliseconds of fill kernels are queued ahead of each timed call, so the
+    host has enqueued the whole call before the GPU reaches it and the events
+    see GPU time only (a slow host, e.g. under a tracer, cannot hide the first
+    iterations behind its own set-up)."""
+    pad = torch.empty(1 << 28, dtype=torch.float32, device=X.device)
+
     def run(k):
         st = torch.cuda.current_stream()
+        for _ in range(16):
+            pad.fill_(0.0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(st)
@@ -108,6 +116,7 @@ def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
     run(iters)  # warm
     base = min(run(iters) for _ in range(3))
     full = min(run(2 * iters) for _ in range(3))
+    del pad
     return (full - base) / iters
 
 

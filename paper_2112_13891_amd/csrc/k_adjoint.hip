@@ -108,10 +108,13 @@ __global__ void fwd_reduce_kernel(const T* __restrict__ part, const T* __restric
     const T iw = T(1) / a[D];
     const long long row = (long long)b * m + j;
     if (invW) invW[row] = iw;
-    for (int k = 0; k < d; ++k) {
-        const T dk = a[k] * iw;
-        if (delta) delta[row * d + k] = dk;
-        if (S_out) S_out[row * d + k] = S[row * d + k] + dk;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {   // constant indices keep a[] in registers
+        if (k < d) {
+            const T dk = a[k] * iw;
+            if (delta) delta[row * d + k] = dk;
+            if (S_out) S_out[row * d + k] = S[row * d + k] + dk;
+        }
     }
 }
 
@@ -133,7 +136,9 @@ __global__ __launch_bounds__(kT) void ds_partial_kernel(const T* __restrict__ X,
     load_row<T, D, EXACT>(S + (long long)b * m * d, jj, d, s);
     load_row<T, D, EXACT>(G + (long long)b * m * d, jj, d, g);
     T gdel = T(0);
-    for (int k = 0; k < d; ++k) gdel = fma(g[k], delta[row * d + k], gdel);
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+        if (k < d) gdel = fma(g[k], delta[row * d + k], gdel);
     if (chunk == 0 && j < m) gdel_out[row] = gdel;   // g_j . delta_j, read by the dX pass
     const T coef = inv_h2 * invW[row];
 #pragma unroll

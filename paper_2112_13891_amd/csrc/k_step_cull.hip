@@ -104,21 +104,21 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
             for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
         }
         int blk = next_live_block<D, R>(geom, b0, b1, s, live, qcull);
-        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float4 v = z;
-        if (blk < b1) {
-            const long long p = (long long)blk * kCullBlk + threadIdx.x;
-            v = p < n ? X4[p] : z;
-        }
+        // one point per thread; past the last point a clamped (valid) row is
+        // loaded and replaced by zeros, so no address is ever selected
+        auto load_pt = [&](int bb) -> float4 {
+            const long long p = (long long)bb * kCullBlk + threadIdx.x;
+            const float4 t = X4[p < n ? p : (long long)n - 1];
+            return p < n ? t : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        };
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (blk < b1) v = load_pt(blk);
         while (blk < b1) {
             __syncthreads();   // the previous block is no longer read
             xs[threadIdx.x] = v;
             __syncthreads();
             const int nxt = next_live_block<D, R>(geom, blk + 1, b1, s, live, qcull);
-            if (nxt < b1) {   // in flight while this block computes
-                const long long p = (long long)nxt * kCullBlk + threadIdx.x;
-                v = p < n ? X4[p] : z;
-            }
+            if (nxt < b1) v = load_pt(nxt);   // in flight while this block computes
             const int lo = wave * PW;
             const int hi = min(lo + PW, n - blk * kCullBlk);
 #pragma unroll 4

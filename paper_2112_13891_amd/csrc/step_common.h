@@ -92,17 +92,19 @@ __device__ __forceinline__ int update_seed_id(const StepArgs& a, int j, const fl
     if (a.metric == MS_METRIC_COSINE) {
         // the weighted mean direction: s' = (s + shift) / |s + shift|, and the
         // shift that counts is the one to the renormalized seed
-        float nx[D], nn = 0.0f;
+        // (the unnormalized coordinates are recomputed in the second pass, not
+        // kept, so wide seeds need no extra registers)
+        float nn = 0.0f;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            nx[k] = sj[k] + v[k] * inv;
-            nn = fmaf(nx[k], nx[k], nn);
+            const float t = sj[k] + v[k] * inv;
+            nn = fmaf(t, t, nn);
         }
         const float rn = 1.0f / sqrtf(nn);
         finite = nn > 0.0f && isfinite(rn);
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const float uk = nx[k] * rn;
+            const float uk = (sj[k] + v[k] * inv) * rn;
             const float dk = uk - sj[k];
             finite = finite && isfinite(uk);
             sh2 = fmaf(dk, dk, sh2);
@@ -347,6 +349,13 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
                 const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
                 // U chunks' loads in flight at once, added in chunk order
                 constexpr int U = D <= 4 ? 16 : (D <= 8 ? 8 : (D <= 16 ? 4 : (D <= 32 ? 2 : 1)));
+                if constexpr (U == 1) {   // wide seeds: no staging registers
+                    for (int c = 0; c < chunks; ++c) {
+                        const float* p = src + (long long)c * TS * (D + 1);
+#pragma unroll
+                        for (int k = 0; k <= D; ++k) v[k] += p[k];
+                    }
+                } else
                 for (int c0 = 0; c0 < chunks; c0 += U) {
                     float tmp[U][D + 1];
 #pragma unroll
