@@ -144,6 +144,23 @@ __device__ __forceinline__ int update_seed(const StepArgs& a, int slot, const fl
 // the points, each lane R seeds; the wave sums are added in wave order and
 // wave 0 returns them in acc.  `red` is LDS of (kWaves - 1) * TS * (D + 1)
 // floats.  All threads of the workgroup must call it.
+// A value every lane of the wave holds, moved to scalar registers (so that
+// addresses built from it give scalar loads).
+__device__ __forceinline__ long long wave_uniform(long long v) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)v >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Read-only data at a wave-uniform address, seen through the constant
+// address space: loads from it are scalar (s_load) and shared by the wave.
+// Only for data no kernel of the launch writes.
+typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+
+__device__ __forceinline__ const_f32_ptr wave_uniform_const(const float* p) {
+    return (const_f32_ptr)(uintptr_t)wave_uniform((long long)reinterpret_cast<uintptr_t>(p));
+}
+
 template <int D, int DP, int R, int KERN>
 __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __restrict__ Xp, long long lo,
                                           long long hi, const int32_t* __restrict__ act, int slot0, int m,
@@ -154,9 +171,12 @@ __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __rest
     // stream use scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    // the bounds and the base are the same in every lane (they derive from
+    // the active count and the work item, which the compiler cannot see)
     const long long len = hi - lo;
-    const int p0 = (int)(lo + len * wave / kWaves);
-    const int p1 = (int)(lo + len * (wave + 1) / kWaves);
+    const int p0 = __builtin_amdgcn_readfirstlane((int)(lo + len * wave / kWaves));
+    const int p1 = __builtin_amdgcn_readfirstlane((int)(lo + len * (wave + 1) / kWaves));
+    const const_f32_ptr xs = wave_uniform_const(Xp);
     float s[R][D];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -167,7 +187,7 @@ __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __rest
 #pragma unroll
         for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
     }
-    const float* __restrict__ xrow = Xp + (long long)p0 * DP;
+    const_f32_ptr xrow = xs + (long long)p0 * DP;
 #pragma unroll 2
     for (int p = p0; p < p1; ++p, xrow += DP) {
         float x[D];
