@@ -139,7 +139,7 @@ __device__ __forceinline__ bf16x8 seed_frag(const float* st, float ns, int hf) {
 // loop.  Every wave of a workgroup holds the same seeds, so every wave takes
 // the same decisions.
 template <int D, int R, bool kGauss>
-__device__ __forceinline__ bool bf16_block_near(const float* __restrict__ gm, const float (&shat)[R][D],
+__device__ __forceinline__ bool bf16_block_near(const_f32_ptr gm, const float (&shat)[R][D],
                                                 const bool (&live)[R], float kappa, float e_thr,
                                                 bool (&gnear)[R]) {
     bool any = false;
@@ -205,11 +205,12 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     const float4* __restrict__ xsg = reinterpret_cast<const float4*>(A.Xs);
     unsigned refined = 0;
 
+    const const_f32_ptr gq = wave_uniform_const(A.geom);
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
-        const int b0 = (int)((long long)nblk * chunk / chunks);
-        const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
+        const int b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
+        const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
         float shat[1][D], arun[D], aex[D], wrun = 0.0f, wex = 0.0f;
         bool live[1];
         {
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
         }
         bool gn[1];
         int blk = b0;
-        while (blk < b1 && !bf16_block_near<D, 1, kGauss>(A.geom + (long long)blk * kGeomStride, shat, live,
+        while (blk < b1 && !bf16_block_near<D, 1, kGauss>(gq + (long long)blk * kGeomStride, shat, live,
                                                            A.kappa, A.e_thr, gn))
             ++blk;
         float4 p0 = {}, p1 = {};
@@ -245,12 +246,12 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             int nxt = blk + 1;
-            while (nxt < b1 && !bf16_block_near<D, 1, kGauss>(A.geom + (long long)nxt * kGeomStride, shat,
+            while (nxt < b1 && !bf16_block_near<D, 1, kGauss>(gq + (long long)nxt * kGeomStride, shat,
                                                                live, A.kappa, A.e_thr, gn))
                 ++nxt;
             if (nxt < b1) fetch_pts(nxt);   // next live block's points travel while this one computes
 
-            const float* gm = A.geom + (long long)blk * kGeomStride;
+            const const_f32_ptr gm = gq + (long long)blk * kGeomStride;
             float st[D];
             float ns = 0.0f;
 #pragma unroll

@@ -117,11 +117,12 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
     const float* sxs = reinterpret_cast<const float*>(stage + Sh::PF_BYTES);
     unsigned refined = 0;
 
+    const const_f32_ptr gq = wave_uniform_const(A.geom);   // block geometry: scalar loads
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
-        const int b0 = (int)((long long)nblk * chunk / chunks);
-        const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
+        const int b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
+        const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
         const int slot = tile * TS + wave * 32 + col;
         const bool live = slot < m;
         const int j = a.act_in[live ? slot : 0];
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
             }
             if (blk + 1 < b1) FMS_PF_LOAD(blk + 1);   // travels while this block computes
 #undef FMS_PF_LOAD
-            const float* gm = A.geom + (long long)blk * A.gs;
+            const const_f32_ptr gm = gq + (long long)blk * A.gs;
             const float R = gm[D], cn = gm[D + 1];
             float st2 = 0.0f;
 #pragma unroll

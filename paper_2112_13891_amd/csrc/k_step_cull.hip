@@ -38,12 +38,12 @@ constexpr int kCullMinPoints = 16384;     // below this the sort costs more than
 // Next block at or after blk (below b1) that some seed of the wave may see
 // with a nonzero weight; b1 if none.
 template <int D, int R>
-__device__ __forceinline__ int next_live_block(const float* __restrict__ geom, int blk, int b1,
+__device__ __forceinline__ int next_live_block(const_f32_ptr geom, int blk, int b1,
                                                const float (&s)[R][D], const bool (&live)[R],
                                                float qcull) {
     for (; blk < b1; ++blk) {
         // wave-uniform block geometry (scalar loads): centre[0..D), radius at [4]
-        const float* gm = geom + (long long)blk * kGeomStride;
+        const const_f32_ptr gm = geom + (long long)blk * kGeomStride;
         bool near = false;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -83,11 +83,14 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
     __shared__ float4 xs[kCullBlk];   // the staged block, one point per thread
     const float4* __restrict__ X4 = reinterpret_cast<const float4*>(a.Xp);
 
+    const const_f32_ptr gq = wave_uniform_const(geom);
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
         const int tile = item % tiles;
         const int chunk = item / tiles;
-        const int b0 = (int)((long long)nblk * chunk / chunks);
-        const int b1 = (int)((long long)nblk * (chunk + 1) / chunks);
+        // uniform over the workgroup (the compiler cannot see it: chunks
+        // derives from the active count)
+        const int b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
+        const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
         // every wave holds the same TS seeds, so every wave takes the same
         // culling decisions and the block loop below is uniform over the
         // workgroup
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
 #pragma unroll
             for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
         }
-        int blk = next_live_block<D, R>(geom, b0, b1, s, live, qcull);
+        int blk = next_live_block<D, R>(gq, b0, b1, s, live, qcull);
         // one point per thread; past the last point a clamped (valid) row is
         // loaded and replaced by zeros, so no address is ever selected
         auto load_pt = [&](int bb) -> float4 {
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
             __syncthreads();   // the previous block is no longer read
             xs[threadIdx.x] = v;
             __syncthreads();
-            const int nxt = next_live_block<D, R>(geom, blk + 1, b1, s, live, qcull);
+            const int nxt = next_live_block<D, R>(gq, blk + 1, b1, s, live, qcull);
             if (nxt < b1) v = load_pt(nxt);   // in flight while this block computes
             const int lo = wave * PW;
             const int hi = min(lo + PW, n - blk * kCullBlk);
