@@ -511,8 +511,10 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_HIP(launch_pack_points(X, n, d, DP, scale, Xp, s));
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
-    // FP32 with d <= 4 on enough points: spatially ordered points and block culling
-    const bool cull = !bf16 && cull_supported(d, n);
+    // FP32 on enough points: spatially ordered points and block culling
+    // (directions are at most 2 apart: nothing to cull when the reach is 2)
+    const bool cull = !bf16 && cull_supported(d, n) &&
+                      !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
     const bool sorted = bf16 || cull;
     SortedPoints sp;
     if (sorted) {
@@ -776,7 +778,8 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
-    const bool cull = !bf16 && cull_supported(d, n);
+    const bool cull = !bf16 && cull_supported(d, n) &&
+                      !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
     const bool sorted = bf16 || cull;
     const StepShape sh = bf16 ? step_shape_bf16(d, m)
                               : (cull ? step_shape_cull(d, m, n) : step_shape_for(d, m));

@@ -108,6 +108,8 @@ int step_grid(const StepShape& sh, int B, int n);
 
 // ---- launchers (k_step_cull.hip): FP32 step over Morton-ordered points, d <= 4 --
 bool cull_supported(int d, int n);
+// Distance beyond which the culled step may skip pairs (original units).
+double cull_reach(int kernel, double h);
 StepShape step_shape_cull(int d, int B, int n);
 hipError_t launch_iteration_cull(Batch& b, int t, hipStream_t s);
 

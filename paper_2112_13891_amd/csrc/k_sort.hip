@@ -290,9 +290,12 @@ __global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift)
 }
 
 // Nearest pivot (ties to the lowest index) of each row r of `rows` (stride
-// DPr, times `scale`), pivots being the points Xp[j * n / P], j < P.  Rows
-// whose status is not active (when status is given) get bit 30, so that
-// they sort last.
+// DPr, times `scale`), pivots being the points Xp[j * n / P], j < P.  Key =
+// pivot index << 14 | the top 14 bits of the squared distance's FP32 pattern
+// (monotone in the distance), so that a pivot's rows run from near to far and
+// its few distant rows (outliers) share the last blocks instead of widening
+// every block of the pivot.  Rows whose status is not active (when status is
+// given) get bit 30, so that they sort last.
 template <int D>
 __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict__ rows, int m, int DPr,
                                                         float scale, const float* __restrict__ Xp,
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict_
         }
     }
     if (r >= m) return;
-    unsigned key = (unsigned)bi;
+    unsigned key = ((unsigned)bi << 14) | (__float_as_uint(best) >> 17);
     if (status && status[r] != ST_ACTIVE) key |= 1u << 30;
     keys[r] = key;
     vals[r] = r;
@@ -494,8 +497,9 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
                                                 s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, w.k0, w.v0));
     }
-    // point keys: 24-bit Morton codes (D <= 4) or pivot indices below 1024
-    const int* sorted = radix_sort_pairs(w, n, s, D <= 4 ? 3 : 2);
+    // point keys: 24-bit Morton codes (D <= 4) or pivot index and distance
+    // (10 + 14 bits)
+    const int* sorted = radix_sort_pairs(w, n, s, 3);
     hipError_t e = hipMemcpyAsync(perm, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),

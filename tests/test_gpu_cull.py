@@ -1,5 +1,5 @@
 """GPU parity of the spatially ordered forms against the FP64 oracle: the FP32
-step with block culling (d <= 4, n >= 16,384) and the BF16 form with its block
+step with block culling (d <= 32, n >= 16,384) and the BF16 form with its block
 culling, on clustered layouts where most blocks are far from most seeds (so
 whole blocks are skipped) and on ragged point counts (partial last block)."""
 import sys
@@ -28,6 +28,8 @@ def _gpu(a):
 
 
 def clustered(seed, n, d, k=30, box=200.0, sigma=1.0):
+    """k blobs far apart relative to h = 1.5 (box 200 per axis), so that most
+    blocks are far from most seeds."""
     rng = np.random.default_rng(seed)
     C = rng.uniform(0.0, box, (k, d))
     y = rng.integers(0, k, n)
@@ -36,7 +38,7 @@ def clustered(seed, n, d, k=30, box=200.0, sigma=1.0):
 
 
 @pytest.mark.parametrize("n", [16384, 16385, 20011, 65537])
-@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 6, 16, 29, 32])
 @pytest.mark.parametrize("kernel", ["gaussian", "flat"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_culled_step_ragged(orc, n, d, kernel, precision):
