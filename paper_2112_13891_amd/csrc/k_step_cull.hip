@@ -7,8 +7,9 @@
 // order for d <= 4; for D = 8, 16, 32 by nearest pivot, shifted by the frame
 // midpoint, the seeds shifted alike) and cut into 256-point blocks, each
 // with a centre c_b and a radius r_b (rounded up); the active seeds are in the
-// same order, so the 64 R seeds of a wave are close to each other.  For a seed s, every point of block b lies at distance
-// at least |s - c_b| - r_b.  If that bound puts every pair of the block past
+// same order, so the 64 R seeds of a wave are close to each other.  For a
+// seed s, every point of block b lies at distance at least |s - c_b| - r_b.
+// If that bound puts every pair of the block past
 // the point where the weight is exactly zero in FP32 -- Gaussian:
 // |c s - c x|^2 >= kCullGauss in exp2 units, so exp2(-q) underflows to +0;
 // flat window: |s - x|^2 > h^2 with a relative margin far above the FP32
@@ -40,8 +41,6 @@ constexpr float kCullGauss = 160.0f;     // exp2(-q) == +0 in FP32 for q >= 150
 constexpr float kCullFlatMargin = 1.001f;
 constexpr int kCullMinPoints = 16384;     // below this the sort costs more than it saves
 
-// Next block at or after blk (below b1) that some seed of the wave may see
-// with a nonzero weight; b1 if none.
 // One point against the lane's R seeds: Gaussian exp2(-q) in packed units or
 // the flat window, accumulated into sum w (x - s) and sum w.
 template <int D, int R, int KERN>
@@ -75,6 +74,8 @@ struct CullGeom {
     static constexpr int kRadius = D <= 4 ? 4 : D;
 };
 
+// Next block at or after blk (below b1) that some seed of the wave may see
+// with a nonzero weight; b1 if none.
 template <int D, int R>
 __device__ __forceinline__ int next_live_block(const_f32_ptr geom, int blk, int b1,
                                                const float (&s)[R][D], const bool (&live)[R],
@@ -145,7 +146,8 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
             // the sorted points of the wide form are shifted by the frame
             // midpoint; the seeds take the same shift
 #pragma unroll
-            for (int k = 0; k < D; ++k) s[r][k] = a.S[(long long)j * DP + k] * a.scale - (shift ? shift[k] : 0.0f);
+            for (int k = 0; k < D; ++k)
+                s[r][k] = a.S[(long long)j * DP + k] * a.scale - (shift ? shift[k] : 0.0f);
 #pragma unroll
             for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
         }
