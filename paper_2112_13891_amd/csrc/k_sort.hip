@@ -303,27 +303,48 @@ __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict_
                                                         const uint8_t* __restrict__ status,
                                                         unsigned* keys, int* vals) {
     constexpr int kTile = 128;
-    __shared__ float piv[kTile][D + 1];
+    constexpr int kPer = kTile * D / 256;   // pivot coordinates each thread stages per tile
+    static_assert(D % 4 == 0 && (kTile * D) % 256 == 0, "pivot tile layout");
+    __shared__ __attribute__((aligned(16))) float piv[kTile][D];
+    __shared__ long long prow[kTile];
     const int r = blockIdx.x * 256 + threadIdx.x;
+    // rows past m load a valid row (their key is never written)
+    const long long rr = r < m ? r : m - 1;
     float x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = r < m ? rows[(long long)r * DPr + k] * scale : 0.0f;
+    for (int k = 0; k < D; ++k) x[k] = rows[rr * DPr + k] * scale;
     float best = __builtin_inff();
     int bi = 0;
     for (int j0 = 0; j0 < P; j0 += kTile) {
         const int cnt = min(kTile, P - j0);
+        __syncthreads();   // the previous tile is no longer read
+        if (threadIdx.x < cnt) prow[threadIdx.x] = (long long)(j0 + threadIdx.x) * n / P;
         __syncthreads();
-        for (int e = threadIdx.x; e < cnt * D; e += 256) {
+        float v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {   // all loads first, then the stores
+            const int e = u * 256 + threadIdx.x;
             const int j = e / D, k = e % D;
-            piv[j][k] = Xp[((long long)(j0 + j) * n / P) * DP + k];
+            v[u] = j < cnt ? Xp[prow[j] * DP + k] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = u * 256 + threadIdx.x;
+            piv[e / D][e % D] = v[u];
         }
         __syncthreads();
         for (int j = 0; j < cnt; ++j) {
+            const float4* pj = reinterpret_cast<const float4*>(piv[j]);   // broadcast reads
             float q = 0.0f;
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                const float t = x[k] - piv[j][k];
-                q = fmaf(t, t, q);
+            for (int k4 = 0; k4 < D / 4; ++k4) {
+                const float4 pv = pj[k4];
+                const float t0 = x[4 * k4] - pv.x, t1 = x[4 * k4 + 1] - pv.y;
+                const float t2 = x[4 * k4 + 2] - pv.z, t3 = x[4 * k4 + 3] - pv.w;
+                q = fmaf(t0, t0, q);
+                q = fmaf(t1, t1, q);
+                q = fmaf(t2, t2, q);
+                q = fmaf(t3, t3, q);
             }
             if (q < best) {
                 best = q;
