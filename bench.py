@@ -196,15 +196,17 @@ def other_configs(api, torch, workloads):
     Sa = torch.from_numpy(np.concatenate(Ss)).cuda()
     pairs = sum(len(s) * len(x) for s, x in zip(Ss, Xs))
 
-    def batched(k):
+    def batched(k, graph=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=k)
+        api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=k, graph=graph)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
     batched(2)
+    batched(2, True)
     t_it = (min(batched(20) for _ in range(2)) - min(batched(10) for _ in range(2))) / 10
+    t_itg = (min(batched(20, True) for _ in range(2)) - min(batched(10, True) for _ in range(2))) / 10
     Xc = [torch.from_numpy(x).cuda() for x in Xs]
     Sc = [torch.from_numpy(s).cuda() for s in Ss]
 
@@ -221,10 +223,28 @@ def other_configs(api, torch, workloads):
     out["clouds16_batched_fp32"] = {
         "workload": "512 clouds, sizes log-uniform in [1000, 65536] (%d points), D=16, 2..40 "
                     "clusters each, Gaussian h=1, min(n, 256) seeds per cloud" % int(xo[-1]),
-        "ms_per_iteration": t_it * 1e3, "pair_evals_per_iteration": pairs,
-        "pair_evals_per_s": pairs / t_it,
+        "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_itg * 1e3,
+        "pair_evals_per_iteration": pairs, "pair_evals_per_s": pairs / t_it,
         "per_cloud_calls_ms_per_iteration": t_pc * 1e3,
         "speedup_vs_per_cloud_calls": t_pc / t_it}
+    # many small clouds, where the launches rather than the arithmetic set the
+    # pace: whole-call time of 30 iterations launched eagerly and as one graph
+    rng = np.random.default_rng(1)
+    Xs = [workloads.cloud16(rng, int(n), 2)[0] for n in rng.integers(200, 2000, 256)]
+    Ss = [X[rng.choice(len(X), 32, replace=False)] for X in Xs]
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+    Xa = torch.from_numpy(np.concatenate(Xs)).cuda()
+    Sa = torch.from_numpy(np.concatenate(Ss)).cuda()
+    batched(2)
+    batched(2, True)
+    t_e = min(batched(30) for _ in range(5))
+    t_g = min(batched(30, True) for _ in range(5))
+    out["small_clouds2_batched_fp32"] = {
+        "workload": "256 clouds of 200..2000 points (%d points), D=2, 32 seeds each, Gaussian h=1, "
+                    "30 iterations per call" % int(xo[-1]),
+        "ms_per_call_eager": t_e * 1e3, "ms_per_call_graph": t_g * 1e3,
+        "graph_speedup": t_e / t_g}
 
     # differentiable form
     clouds = workloads.diffclouds(seed=0)

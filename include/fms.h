@@ -96,7 +96,12 @@ typedef struct {
     int32_t check_finite;     /* 1: scan X for NaN/Inf first */
     int32_t metric;           /* ms_metric (ms_fit, ms_step); ms_step_batched,
                                  ms_assign: Euclidean only */
-    int32_t reserved[3];      /* must be 0 */
+    int32_t graph;            /* ms_step_batched: 1 = capture the n_iter
+                                 iterations in one HIP graph and launch it
+                                 once (the call then returns when it is done);
+                                 0 = launch kernel by kernel.  Other calls
+                                 ignore it */
+    int32_t reserved[2];      /* must be 0 */
 } ms_params;
 
 /* Fills *p with the defaults: h = 1, Gaussian, FP32, tol = 1e-3,
@@ -194,9 +199,12 @@ int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
  *              cloud with seeds must have points.
  *   ncl        1..8192 clouds.
  *   converged, iters, shift2: as ms_step, one entry per seed.
- * Uses p->h, kernel, tol; p->precision must be MS_PREC_FP32.  Stream-ordered;
- * the call returns once the offsets are on the device (it waits for the work
- * already queued on the stream), the iterations themselves run asynchronously.
+ * Uses p->h, kernel, tol, graph; p->precision must be MS_PREC_FP32.
+ * Stream-ordered; the call returns once the offsets are on the device (it
+ * waits for the work already queued on the stream), the iterations
+ * themselves run asynchronously -- with p->graph = 1 they are captured on a
+ * private stream as one HIP graph (3 kernels per iteration, no memory
+ * nodes), launched on `stream`, and the call returns when the graph is done.
  */
 int ms_step_batched(const ms_params *p, const float *X, const int64_t *x_off,
                     float *seeds, const int64_t *s_off, int32_t ncl, int32_t d,

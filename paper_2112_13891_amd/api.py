@@ -48,7 +48,8 @@ class Params(ctypes.Structure):
         ("all_points_as_seeds", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
         ("metric", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -279,9 +280,10 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
 
 
 def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=1,
-                 converged=None):
+                 converged=None, graph=False):
     """ms_step over many clouds: cloud c owns X[x_off[c]:x_off[c+1]] and
     seeds[s_off[c]:s_off[c+1]].  Offsets are host sequences of ncl + 1 ints.
+    graph=True runs the n_iter iterations as one captured HIP graph.
     Returns new tensors (seeds, converged uint8, iters int32, shift2 float32)."""
     import numpy as np
     torch = _torch()
@@ -301,6 +303,7 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
     iters = torch.zeros(m, dtype=torch.int32, device=X.device)
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
     p = make_params(h, kernel, "fp32", tol)
+    p.graph = 1 if graph else 0
     rc = lib().ms_step_batched(ctypes.byref(p), Xp, xo.ctypes.data, ctypes.c_void_p(S.data_ptr()),
                                so.ctypes.data, int(len(xo) - 1), d, int(n_iter),
                                ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),

@@ -19,7 +19,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "fms_internal.h"
@@ -70,21 +69,44 @@ struct SplitMix64 {
 // touched positions are stored.  pos[t] receives the position that ends up in
 // slot t (slot t is final after its own swap, since later swaps only touch
 // slots > t).  Swap partner of slot t: t + floor(r * (len - t) / 2^64).
+// The touched positions live in an open-addressing table (linear probing,
+// at most 2 * count keys in at least 4 * count entries), reused per thread.
+struct TouchedPositions {
+    std::vector<uint64_t> slot;   // (key << 32 | value), kEmpty when unused
+    uint32_t mask = 0;
+    static constexpr uint64_t kEmpty = ~0ull;
+    void reset(int32_t count) {
+        size_t cap = 16;
+        while (cap < (size_t)count * 4) cap <<= 1;
+        slot.assign(cap, kEmpty);
+        mask = (uint32_t)cap - 1;
+    }
+    uint64_t* find(int32_t key) {
+        uint32_t i = ((uint32_t)key * 0x9E3779B1u) & mask;
+        for (;;) {
+            uint64_t& e = slot[i];
+            if (e == kEmpty || (int32_t)(uint32_t)(e >> 32) == key) return &e;
+            i = (i + 1) & mask;
+        }
+    }
+    int32_t get(int32_t key) {
+        const uint64_t e = *find(key);
+        return e == kEmpty ? key : (int32_t)(uint32_t)e;
+    }
+    void put(int32_t key, int32_t v) { *find(key) = ((uint64_t)(uint32_t)key << 32) | (uint32_t)v; }
+};
+
 void draw_positions(uint64_t* state, int32_t len, int32_t count, int32_t* pos) {
     SplitMix64 g{*state};
-    std::unordered_map<int32_t, int32_t> moved;
-    moved.reserve((size_t)count * 2 + 1);
-    auto at = [&](int32_t p) {
-        auto it = moved.find(p);
-        return it == moved.end() ? p : it->second;
-    };
+    static thread_local TouchedPositions moved;
+    moved.reset(count);
     for (int32_t t = 0; t < count; ++t) {
         const uint64_t r = g.next();
         const int32_t j =
             t + (int32_t)(((unsigned __int128)r * (unsigned __int128)(uint64_t)(len - t)) >> 64);
-        const int32_t vt = at(t), vj = at(j);
-        moved[j] = vt;
-        moved[t] = vj;
+        const int32_t vt = moved.get(t), vj = moved.get(j);
+        moved.put(j, vt);
+        moved.put(t, vj);
         pos[t] = vj;
     }
     *state = g.state;
@@ -205,7 +227,8 @@ int check_params(const ms_params* p, bool for_fit) {
         return fail(MS_E_INVALID, "refine_radius must be finite and >= 0");
     if (p->metric != MS_METRIC_EUCLIDEAN && p->metric != MS_METRIC_COSINE)
         return fail(MS_E_INVALID, "unknown metric");
-    for (int i = 0; i < 3; ++i)
+    if (p->graph != 0 && p->graph != 1) return fail(MS_E_INVALID, "graph must be 0 or 1");
+    for (int i = 0; i < 2; ++i)
         if (p->reserved[i] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
     if (!for_fit) return MS_OK;
     if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
@@ -328,6 +351,17 @@ struct ProgressWord {
 };
 thread_local ProgressWord g_prog;
 
+// Waits for the work queued on the stream by polling it.  The fit's host
+// decisions wait on short device tails, where the wake-up of a blocking wait
+// costs more than the tail itself.
+hipError_t wait_stream(hipStream_t s) {
+    for (;;) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q != hipErrorNotReady) return q;
+        for (int i = 0; i < 64; ++i) _mm_pause();
+    }
+}
+
 // Enqueue iterations, keeping at most kAhead of them queued beyond the one the
 // device last reported starting, until an iteration reports no active seed
 // (every later one would find none either) or max_iter were enqueued.  If the
@@ -367,7 +401,7 @@ int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror) {
         // drained with no newer report: decide from the control block
         FMS_HIP(hipMemcpyAsync(mirror, b.ctl, offsetof(Ctl, conv_it) + (size_t)(launched + 1) * 4,
                                hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipStreamSynchronize(s));
+        FMS_HIP(wait_stream(s));
         int conv = 0;
         for (int u = 0; u < launched; ++u) conv += mirror->conv_it[u];
         if (conv >= mirror->need || mirror->count[launched % 3] == 0) break;
@@ -482,7 +516,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_check_finite(X, (long long)n * d, flag, s));
         int32_t hflag = 0;
         FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipStreamSynchronize(s));
+        FMS_HIP(wait_stream(s));
         if (hflag) return fail(MS_E_NONFINITE, "X contains NaN or Inf");
     }
     if (p->metric == MS_METRIC_COSINE) {
@@ -495,7 +529,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_normalize_rows(X, n, d, Xn, flag, s));
         int32_t hflag = 0;
         FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipStreamSynchronize(s));
+        FMS_HIP(wait_stream(s));
         if (hflag) return fail(MS_E_INVALID, "cosine metric: a row of X has no direction (length 0 or not finite)");
         X = Xn;
     }
@@ -638,7 +672,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_CHECK(g_pin_rb.ensure(L.total));
         char* hrb = (char*)g_pin_rb.p;
         FMS_HIP(hipMemcpyAsync(hrb, rbuf, L.total, hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipStreamSynchronize(s));
+        FMS_HIP(wait_stream(s));
         const Ctl& cs = *(const Ctl*)hrb;
         const int32_t* h_state = (const int32_t*)(hrb + L.state);
         const int32_t* h_ids = (const int32_t*)(hrb + L.ids);
@@ -702,7 +736,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
                                      removed, block_tmp, s));
                 FMS_HIP(launch_pool_compact(pool[cur ^ 1], removed, pool_len, pool[cur], block_tmp, ctl, s));
                 FMS_HIP(hipMemcpyAsync(mirror, ctl, offsetof(Ctl, conv_it), hipMemcpyDeviceToHost, s));
-                FMS_HIP(hipStreamSynchronize(s));
+                FMS_HIP(wait_stream(s));
                 pool_len = mirror->pool_len;
                 cur ^= 1;   // undone below: the pool is back in pool[cur]
             }
@@ -761,7 +795,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_assign(X, n, d, modes, K, labels, nullptr, s));
         FMS_HIP(hipEventRecord(ev[3], s));
     }
-    FMS_HIP(hipStreamSynchronize(s));
+    FMS_HIP(wait_stream(s));
     if (diag) {
         float ms = 0.0f;
         if (labels) FMS_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
@@ -873,8 +907,31 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
     FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));
     FMS_HIP(launch_batched_init(seeds, converged, d, M, so_dev, ncl, cnt, b, s));
-    for (int t = 0; t < n_iter; ++t)
-        FMS_HIP(launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, s));
+    if (p->graph && n_iter > 0) {
+        // every iteration captured on a private stream (capture is not allowed
+        // on the null stream), then one graph launch on the caller's stream
+        hipStream_t cs = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        FMS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int t = 0; t < n_iter && e == hipSuccess; ++t)
+                e = launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, cs);
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ge, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the graph is done before it is destroyed
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return hip_fail(e, "batched iterations as a graph");
+    } else {
+        for (int t = 0; t < n_iter; ++t)
+            FMS_HIP(launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, s));
+    }
     FMS_HIP(launch_seed_export(b, M, seeds, converged, iters, shift2, s));
     return MS_OK;
 }

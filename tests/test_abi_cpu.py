@@ -97,9 +97,13 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_fit(ctypes.byref(p), None, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert L.ms_fit(None, FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 0, ctypes.byref(k), None, None, None) == -1
-    p.reserved[2] = 1
+    p.reserved[1] = 1
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert "reserved" in api.last_error()
+    p = api.make_params(1.0)
+    p.graph = 2
+    assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
+    assert "graph" in api.last_error()
     p = api.make_params(1.0)
     assert L.ms_step(ctypes.byref(p), FAKE, 10, 2, FAKE, -1, 1, FAKE, FAKE, FAKE, None) == -1
     assert L.ms_step(ctypes.byref(p), FAKE, 10, 2, FAKE, 3, 5000, FAKE, FAKE, FAKE, None) == -1

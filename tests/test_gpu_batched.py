@@ -124,3 +124,28 @@ def test_batched_uneven_clouds_workload_shape():
         seg = S[so[c]:so[c + 1]]
         assert ((seg >= lo - 1e-4) & (seg <= hi + 1e-4)).all(), c
     assert conv.cpu().numpy().mean() > 0.9
+
+
+def test_batched_graph_matches_eager_launches():
+    """graph=1 captures the iterations as one HIP graph: every call, with
+    eager work and synchronisations between the calls, gives bitwise the
+    outputs of the kernel-by-kernel launches of the same call."""
+    cases = [(_batch(31, SIZES, 3), "gaussian", 7), (_batch(32, SIZES[:6], 16), "flat", 3),
+             (_batch(33, [4100, 1, 2047], 2), "gaussian", 25)]
+    for rep in range(2):
+        for (Xs, Ss, xo, so), kernel, n_iter in cases:
+            say("graph case", len(Xs), "clouds", kernel, "n_iter", n_iter, "rep", rep)
+            Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+            Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+            ref = api.step_batched(Xa, xo, Sa, so, 1.0, kernel=kernel, n_iter=n_iter)
+            torch.cuda.synchronize()
+            ref = [t.cpu() for t in ref]
+            # unrelated eager work on the same stream between the two calls
+            api.step(Xa, Sa[:5].contiguous(), 1.0, n_iter=2)
+            junk = torch.randn(4096, device=DEV).cumsum(0)
+            torch.cuda.synchronize()
+            got = api.step_batched(Xa, xo, Sa, so, 1.0, kernel=kernel, n_iter=n_iter, graph=True)
+            torch.cuda.synchronize()
+            for a, b in zip(ref, got):
+                torch.testing.assert_close(b.cpu(), a, rtol=0, atol=0, equal_nan=True)
+            del junk
