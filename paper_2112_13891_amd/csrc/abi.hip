@@ -894,6 +894,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_HIP(hipStreamSynchronize(s));   // the host copies of the offsets go out of scope
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
+    b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
     FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], M));
     FMS_CHECK(ws.alloc(&b.act[1], M));

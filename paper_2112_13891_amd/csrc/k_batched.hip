@@ -168,7 +168,25 @@ __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, Batched
             for (int k = 0; k <= D; ++k) v[k] += p[k];
         }
         const int j = a.act_in[B.seg[c] + q];
-        if (update_seed_id<D, DP>(a, j, v) == 1) a.act_out[B.seg[c] + atomicAdd(&cout[c], 1)] = j;
+        const bool keep = update_seed_id<D, DP>(a, j, v) == 1;
+        // the kept seeds of the wave, one cloud at a time: one atomic per
+        // cloud and wave, slots in lane order
+        unsigned long long pend = __ballot(keep);
+        while (pend) {
+            const int leader = __builtin_ctzll(pend);
+            const int lc = __shfl(c, leader);
+            const bool mine = keep && c == lc;
+            const unsigned long long mask = __ballot(mine);
+            int base = 0;
+            if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&cout[lc], __popcll(mask));
+            base = __shfl(base, leader);
+            if (mine) {
+                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                a.act_out[B.seg[c] + base + below] = j;
+            }
+            pend &= ~mask;
+        }
     }
 }
 
@@ -217,11 +235,14 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     a.thr2 = b.thr2;
     a.metric = b.metric;
     hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, 64 * R);
+    // no more workgroups than the first iteration has work items (seeds only
+    // ever leave the active lists)
+    const int grid = std::max(1, std::min(kBStepGrid, b.grid));
     if (b.kernel == MS_KERNEL_GAUSSIAN)
-        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(kBStepGrid), dim3(kThreads),
+        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(grid), dim3(kThreads),
                            0, s, a, B);
     else
-        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_FLAT>), dim3(kBStepGrid), dim3(kThreads), 0,
+        hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_FLAT>), dim3(grid), dim3(kThreads), 0,
                            s, a, B);
     int fblocks = (b.n_seeds + kFinThreads - 1) / kFinThreads;
     fblocks = fblocks < 1 ? 1 : (fblocks > 1024 ? 1024 : fblocks);

@@ -324,8 +324,18 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                     refined += live[0] ? nref : 0u;
                 }
                 // far pairs (Gaussian only): weights from the estimate, unless
-                // every weight of the wave underflows (2^-127)
-                if (kGauss && (ref || __ballot(emax >= -127.0f))) {
+                // every weight of the wave left to them underflows (2^-127;
+                // the refined pairs now carry -inf)
+                float fmax = emax;
+                if (ref) {
+                    const float r0 = fmaxf(fmaxf(E[0], E[1]), E[2]);
+                    const float r1 = fmaxf(fmaxf(E[3], E[4]), E[5]);
+                    const float r2 = fmaxf(fmaxf(E[6], E[7]), E[8]);
+                    const float r3 = fmaxf(fmaxf(E[9], E[10]), E[11]);
+                    const float r4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
+                    fmax = fmaxf(fmaxf(fmaxf(r0, r1), r2), fmaxf(fmaxf(r3, r4), E[15]));
+                }
+                if (kGauss && __ballot(fmax >= -127.0f)) {
                     bf16x8 w0, w1;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {

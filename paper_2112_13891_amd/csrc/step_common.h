@@ -187,12 +187,8 @@ __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __rest
 #pragma unroll
         for (int k = 0; k <= D; ++k) acc[r][k] = 0.0f;
     }
-    const_f32_ptr xrow = xs + (long long)p0 * DP;
-#pragma unroll 2
-    for (int p = p0; p < p1; ++p, xrow += DP) {
-        float x[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = xrow[k];   // wave-uniform: scalar loads
+    // one point's contribution to every seed of the lane
+    auto pair = [&](const float (&x)[D]) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             float dx[D];
@@ -211,6 +207,42 @@ __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __rest
 #pragma unroll
             for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
         }
+    };
+    // points in groups of U (32 floats), the next group's scalar loads issued
+    // before the current group is used: with few waves per SIMD nothing else
+    // hides their latency.  Points are taken in order, as one at a time.
+    constexpr int U = DP <= 4 ? 8 : (DP <= 8 ? 4 : (DP <= 16 ? 2 : 1));
+    const_f32_ptr xrow = xs + (long long)p0 * DP;
+    int p = p0;
+    if (p1 - p >= U) {
+        float xn[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];
+        xrow += U * DP;
+        for (; p + 2 * U <= p1; p += U, xrow += U * DP) {
+            float xc[U][D];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k) xc[u][k] = xn[u][k];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];   // wave-uniform: scalar loads
+#pragma unroll
+            for (int u = 0; u < U; ++u) pair(xc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) pair(xn[u]);
+        p += U;
+    }
+    for (; p < p1; ++p, xrow += DP) {
+        float x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = xrow[k];
+        pair(x);
     }
     // the four wave sums added in wave order
     if (wave > 0) {
