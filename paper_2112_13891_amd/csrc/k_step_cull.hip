@@ -184,14 +184,8 @@ __global__ __launch_bounds__(kThreads) void step_cull_kernel(StepArgs a, const f
             while (blk < b1) {
                 const int p0 = blk * kCullBlk + wave * PWD;
                 const int p1 = min(p0 + PWD, n);
-                const_f32_ptr xrow = xq + (long long)p0 * DP;
-#pragma unroll 2
-                for (int p = p0; p < p1; ++p, xrow += DP) {
-                    float x[D];
-#pragma unroll
-                    for (int k = 0; k < D; ++k) x[k] = xrow[k];
-                    pair_acc<D, R, KERN>(x, s, acc, a.h2);
-                }
+                stream_rows<D, DP>(xq + (long long)p0 * DP, p1 - p0,
+                                   [&](const float (&x)[D]) { pair_acc<D, R, KERN>(x, s, acc, a.h2); });
                 blk = next_live_block<D, R>(gq, blk + 1, b1, s, live, qcull);
             }
         }

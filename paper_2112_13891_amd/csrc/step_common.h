@@ -161,6 +161,48 @@ __device__ __forceinline__ const_f32_ptr wave_uniform_const(const float* p) {
     return (const_f32_ptr)(uintptr_t)wave_uniform((long long)reinterpret_cast<uintptr_t>(p));
 }
 
+// Calls f(x) for the rows xrow[0 .. count) in order (row stride DP, the first
+// D entries of each), the rows being wave-uniform: scalar loads, in groups of
+// U rows (32 floats), the next group's loads issued before the current group
+// is used.  With few waves per SIMD nothing else hides their latency.
+// Rows wider than 32 floats are loaded one at a time.
+template <int D, int DP, typename F>
+__device__ __forceinline__ void stream_rows(const_f32_ptr xrow, int count, F&& f) {
+    constexpr int kGroup = DP <= 4 ? 8 : (DP <= 8 ? 4 : (DP <= 16 ? 2 : (DP <= 32 ? 1 : 0)));
+    constexpr int U = kGroup > 0 ? kGroup : 1;
+    int p = 0;
+    if (kGroup > 0 && count >= U) {
+        float xn[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];
+        xrow += U * DP;
+        for (; p + 2 * U <= count; p += U, xrow += U * DP) {
+            float xc[U][D];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k) xc[u][k] = xn[u][k];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];
+#pragma unroll
+            for (int u = 0; u < U; ++u) f(xc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) f(xn[u]);
+        p += U;
+    }
+    for (; p < count; ++p, xrow += DP) {
+        float x[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) x[k] = xrow[k];
+        f(x);
+    }
+}
+
 template <int D, int DP, int R, int KERN>
 __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __restrict__ Xp, long long lo,
                                           long long hi, const int32_t* __restrict__ act, int slot0, int m,
@@ -208,42 +250,7 @@ __device__ __forceinline__ void tile_sums(const StepArgs& a, const float* __rest
             for (int k = 0; k < D; ++k) acc[r][k] = fmaf(w, dx[k], acc[r][k]);
         }
     };
-    // points in groups of U (32 floats), the next group's scalar loads issued
-    // before the current group is used: with few waves per SIMD nothing else
-    // hides their latency.  Points are taken in order, as one at a time.
-    constexpr int U = DP <= 4 ? 8 : (DP <= 8 ? 4 : (DP <= 16 ? 2 : 1));
-    const_f32_ptr xrow = xs + (long long)p0 * DP;
-    int p = p0;
-    if (p1 - p >= U) {
-        float xn[U][D];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];
-        xrow += U * DP;
-        for (; p + 2 * U <= p1; p += U, xrow += U * DP) {
-            float xc[U][D];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int k = 0; k < D; ++k) xc[u][k] = xn[u][k];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-                for (int k = 0; k < D; ++k) xn[u][k] = xrow[u * DP + k];   // wave-uniform: scalar loads
-#pragma unroll
-            for (int u = 0; u < U; ++u) pair(xc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) pair(xn[u]);
-        p += U;
-    }
-    for (; p < p1; ++p, xrow += DP) {
-        float x[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = xrow[k];
-        pair(x);
-    }
+    stream_rows<D, DP>(xs + (long long)p0 * DP, p1 - p0, pair);
     // the four wave sums added in wave order
     if (wave > 0) {
 #pragma unroll
