@@ -101,7 +101,13 @@ typedef struct {
                                  once (the call then returns when it is done);
                                  0 = launch kernel by kernel.  Other calls
                                  ignore it */
-    int32_t reserved[2];      /* must be 0 */
+    int32_t tile_R;           /* ms_step_batched: seeds per lane of a seed
+                                 tile (1, 2 or 4, as the padded dimension
+                                 allows: D <= 4 any, D = 8 1 or 2, D >= 16
+                                 1); 0 = the shape ms_tune_batched chose for
+                                 inputs of this kind, else a default.  The
+                                 results do not depend on it */
+    int32_t reserved[1];      /* must be 0 */
 } ms_params;
 
 /* Fills *p with the defaults: h = 1, Gaussian, FP32, tol = 1e-3,
@@ -199,7 +205,7 @@ int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
  *              cloud with seeds must have points.
  *   ncl        1..8192 clouds.
  *   converged, iters, shift2: as ms_step, one entry per seed.
- * Uses p->h, kernel, tol, graph; p->precision must be MS_PREC_FP32.
+ * Uses p->h, kernel, tol, graph, tile_R; p->precision must be MS_PREC_FP32.
  * Stream-ordered; the call returns once the offsets are on the device (it
  * waits for the work already queued on the stream), the iterations
  * themselves run asynchronously -- with p->graph = 1 they are captured on a
@@ -258,6 +264,31 @@ int ms_step_adjoint(const void *X, int32_t nbatch, int64_t n, const void *S,
  */
 int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
                  int32_t count, int32_t *out);
+
+/*
+ * ms_tune_batched -- tile-shape tuning for ms_step_batched.
+ *
+ * Times `trials` iterations (every seed active) of each seed tile shape that
+ * the padded dimension allows (the seeds per lane R, see ms_params.tile_R) on
+ * this input, keeps the fastest, and records it for the rest of the process
+ * under the input's kind: padded dimension, floor(log2) of the mean points
+ * per cloud and floor(log2) of the mean seeds per cloud.  Later
+ * ms_step_batched calls with tile_R = 0 on inputs of that kind use it.  The
+ * iterations run on private copies of the seeds: nothing the caller passed is
+ * written, and since the results of ms_step_batched do not depend on R,
+ * tuning never changes them.
+ *   p, X, x_off, seeds, s_off, ncl, d: as ms_step_batched (p->tile_R and
+ *              p->graph are ignored); at least one cloud must have seeds.
+ *   trials     1..64 iterations per candidate.
+ *   best_R     host, may be NULL: the chosen R.
+ *   ms_per_iter host, may be NULL: 3 entries, the measured milliseconds per
+ *              iteration for R = 1, 2, 4 (-1 where R is not a candidate).
+ * Synchronous (returns once the candidates are timed).  Allocates device
+ * workspace on `stream`.
+ */
+int ms_tune_batched(const ms_params *p, const float *X, const int64_t *x_off,
+                    const float *seeds, const int64_t *s_off, int32_t ncl, int32_t d,
+                    int32_t trials, int32_t *best_R, float *ms_per_iter, void *stream);
 
 /*
  * ms_seed_count_next -- seed-count adaptation across the frames of a

@@ -49,7 +49,8 @@ class Params(ctypes.Structure):
         ("check_finite", ctypes.c_int32),
         ("metric", ctypes.c_int32),
         ("graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("tile_R", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -76,7 +77,7 @@ class Diag(ctypes.Structure):
     ]
 
 
-EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_assign",
+EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_tune_batched", "ms_assign",
            "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
            "ms_last_error", "ms_version")
 
@@ -101,6 +102,8 @@ def lib():
     L.ms_step.restype = ctypes.c_int
     L.ms_step_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P, P]
     L.ms_step_batched.restype = ctypes.c_int
+    L.ms_tune_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P]
+    L.ms_tune_batched.restype = ctypes.c_int
     L.ms_assign.argtypes = [P, i64, i32, P, i32, P, P, P]
     L.ms_assign.restype = ctypes.c_int
     L.ms_forward_update.argtypes = [P, i32, i64, P, i64, i32, ctypes.c_double, P, i32, P]
@@ -280,10 +283,11 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
 
 
 def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=1,
-                 converged=None, graph=False):
+                 converged=None, graph=False, tile_R=0):
     """ms_step over many clouds: cloud c owns X[x_off[c]:x_off[c+1]] and
     seeds[s_off[c]:s_off[c+1]].  Offsets are host sequences of ncl + 1 ints.
-    graph=True runs the n_iter iterations as one captured HIP graph.
+    graph=True runs the n_iter iterations as one captured HIP graph; tile_R
+    forces the seeds per lane (0: tuned or default shape).
     Returns new tensors (seeds, converged uint8, iters int32, shift2 float32)."""
     import numpy as np
     torch = _torch()
@@ -304,12 +308,35 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
     p = make_params(h, kernel, "fp32", tol)
     p.graph = 1 if graph else 0
+    p.tile_R = int(tile_R)
     rc = lib().ms_step_batched(ctypes.byref(p), Xp, xo.ctypes.data, ctypes.c_void_p(S.data_ptr()),
                                so.ctypes.data, int(len(xo) - 1), d, int(n_iter),
                                ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
                                ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))
     _check(rc)
     return S, conv, iters, sh
+
+
+def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=4):
+    """ms_tune_batched: time each seeds-per-lane shape on this input and keep
+    the fastest for later step_batched calls on inputs of the same kind.
+    Returns (best R, {R: ms per iteration})."""
+    import numpy as np
+    torch = _torch()
+    Xp = _dev(X, torch.float32, 2, "X")
+    Sp = _dev(seeds, torch.float32, 2, "seeds")
+    xo = np.ascontiguousarray(np.asarray(x_off, dtype=np.int64))
+    so = np.ascontiguousarray(np.asarray(s_off, dtype=np.int64))
+    if xo.shape != so.shape or xo.ndim != 1:
+        raise ValueError("x_off and s_off must both have ncl + 1 entries")
+    p = make_params(h, kernel, "fp32", tol)
+    best = ctypes.c_int32(0)
+    ms = (ctypes.c_float * 3)()
+    rc = lib().ms_tune_batched(ctypes.byref(p), Xp, xo.ctypes.data, Sp, so.ctypes.data,
+                               int(len(xo) - 1), X.shape[1], int(trials), ctypes.byref(best), ms,
+                               _stream_ptr(X))
+    _check(rc)
+    return best.value, {r: ms[c] for c, r in enumerate((1, 2, 4)) if ms[c] >= 0}
 
 
 def assign(X, modes, margin=False):

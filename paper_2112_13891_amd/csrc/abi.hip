@@ -12,6 +12,9 @@
 #include <algorithm>
 #include <atomic>
 #include <immintrin.h>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -228,8 +231,9 @@ int check_params(const ms_params* p, bool for_fit) {
     if (p->metric != MS_METRIC_EUCLIDEAN && p->metric != MS_METRIC_COSINE)
         return fail(MS_E_INVALID, "unknown metric");
     if (p->graph != 0 && p->graph != 1) return fail(MS_E_INVALID, "graph must be 0 or 1");
-    for (int i = 0; i < 2; ++i)
-        if (p->reserved[i] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
+    if (p->tile_R != 0 && p->tile_R != 1 && p->tile_R != 2 && p->tile_R != 4)
+        return fail(MS_E_INVALID, "tile_R must be 0, 1, 2 or 4");
+    if (p->reserved[0] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
     if (!for_fit) return MS_OK;
     if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
         return fail(MS_E_INVALID, "max_iter must be in [1, 4096]");
@@ -864,14 +868,55 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     return MS_OK;
 }
 
+// Seeds per lane that the batched step is built for, by padded dimension.
+bool batched_R_ok(int D, int R) {
+    if (R == 1) return true;
+    if (R == 2) return D <= 8;
+    if (R == 4) return D <= 4;
+    return false;
+}
+
+// Tuned seeds per lane, by input kind (padded dimension, floor(log2) of the
+// mean points and of the mean seeds per cloud), for the whole process.
+using TuneKey = std::tuple<int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+int ilog2_ll(long long v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+TuneKey tune_key(int d, long long n, long long M, int ncl) {
+    return TuneKey(step_shape(d).D, ilog2_ll(std::max(1LL, n / ncl)), ilog2_ll(std::max(1LL, M / ncl)));
+}
+
+// R_force = 0: the tuned shape for this kind of input, else seeds per lane
+// from the mean seeds per cloud (small clouds waste fewer lanes).  With
+// ev != NULL the iterations are bracketed by ev[0] and ev[1].
 int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
                       const int64_t* s_off, int ncl, int d, int n_iter, uint8_t* converged,
-                      int32_t* iters, float* shift2, hipStream_t s) {
+                      int32_t* iters, float* shift2, hipStream_t s, int R_force = 0,
+                      hipEvent_t* ev = nullptr) {
     FMS_CHECK(ensure_pool_release_threshold());
     const int n = (int)x_off[ncl];
     const int M = (int)s_off[ncl];
-    // seeds per lane from the mean seeds per cloud: small clouds waste fewer lanes
-    const StepShape sh = step_shape_for(d, std::max(1, M / ncl));
+    StepShape sh = step_shape_for(d, std::max(1, M / ncl));
+    int R = R_force;
+    if (R == 0) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune.find(tune_key(d, n, M, ncl));
+        if (it != g_tune.end()) R = it->second;
+    }
+    if (R != 0) {
+        if (!batched_R_ok(sh.D, R)) return fail(MS_E_INVALID, "tile_R is not built for this dimension");
+        sh.R = R;
+        sh.TS = 64 * R;
+    }
     const float scale = packed_scale(p);
     std::vector<long long> xo(ncl + 1);
     std::vector<int32_t> so(ncl + 1);
@@ -908,6 +953,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
     FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));
     FMS_HIP(launch_batched_init(seeds, converged, d, M, so_dev, ncl, cnt, b, s));
+    if (ev) FMS_HIP(hipEventRecord(ev[0], s));
     if (p->graph && n_iter > 0) {
         // every iteration captured on a private stream (capture is not allowed
         // on the null stream), then one graph launch on the caller's stream
@@ -933,7 +979,60 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         for (int t = 0; t < n_iter; ++t)
             FMS_HIP(launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, s));
     }
+    if (ev) FMS_HIP(hipEventRecord(ev[1], s));
     FMS_HIP(launch_seed_export(b, M, seeds, converged, iters, shift2, s));
+    return MS_OK;
+}
+
+// Times each candidate R on private copies of the seeds; records the fastest.
+int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,
+                      const int64_t* s_off, int ncl, int d, int trials, int32_t* best_R,
+                      float* ms_per_iter, hipStream_t s) {
+    const long long n = x_off[ncl], M = s_off[ncl];
+    const int D = step_shape(d).D;
+    Workspace ws(s);
+    float* S;
+    uint8_t* conv;
+    int32_t* it;
+    float* sh2;
+    FMS_CHECK(ws.alloc(&S, (size_t)M * d));
+    FMS_CHECK(ws.alloc(&conv, (size_t)M));
+    FMS_CHECK(ws.alloc(&it, (size_t)M));
+    FMS_CHECK(ws.alloc(&sh2, (size_t)M));
+    FMS_CHECK(g_events.create());
+    hipEvent_t* ev = g_events.e;
+    ms_params q = *p;
+    q.graph = 0;
+    q.tile_R = 0;
+    const int cand[3] = {1, 2, 4};
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        if (ms_per_iter) ms_per_iter[c] = -1.0f;
+        if (!batched_R_ok(D, cand[c])) continue;
+        float ms = 0.0f;
+        // one untimed pass (first launch of the shape), then the timed one
+        for (int pass = 0; pass < 2; ++pass) {
+            FMS_HIP(hipMemcpyAsync(S, seeds, (size_t)M * d * 4, hipMemcpyDeviceToDevice, s));
+            FMS_HIP(launch_fill_u8(conv, (int)M, 0, s));
+            FMS_CHECK(step_batched_impl(&q, X, x_off, S, s_off, ncl, d, pass ? trials : 1, conv, it, sh2, s,
+                                        cand[c], pass ? ev : nullptr));
+        }
+        FMS_HIP(hipEventSynchronize(ev[1]));
+        FMS_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        ms /= (float)trials;
+        if (ms_per_iter) ms_per_iter[c] = ms;
+        if (best == 0 || ms < best_ms) {
+            best = cand[c];
+            best_ms = ms;
+        }
+    }
+    FMS_HIP(hipStreamSynchronize(s));
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(d, n, M, ncl)] = best;
+    }
+    if (best_R) *best_R = best;
     return MS_OK;
 }
 
@@ -941,6 +1040,34 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
 }  // namespace fms
 
 using namespace fms;
+
+namespace {
+
+// Arguments of ms_step_batched and ms_tune_batched.
+int check_batched_args(const ms_params* p, const float* X, const int64_t* x_off, const int64_t* s_off,
+                       int32_t ncl, int32_t d) {
+    FMS_CHECK(check_params(p, false));
+    if (p->precision != MS_PREC_FP32)
+        return fail(MS_E_INVALID, "ms_step_batched computes the FP32 form only");
+    if (p->metric != MS_METRIC_EUCLIDEAN)
+        return fail(MS_E_INVALID, "ms_step_batched computes the Euclidean metric only");
+    if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
+    if (ncl < 1 || ncl > batched_max_clouds()) return fail(MS_E_INVALID, "ncl must be in [1, 8192]");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (x_off[0] != 0 || s_off[0] != 0) return fail(MS_E_INVALID, "offsets must start at 0");
+    for (int c = 0; c < ncl; ++c) {
+        if (x_off[c + 1] < x_off[c] || s_off[c + 1] < s_off[c])
+            return fail(MS_E_INVALID, "offsets must be nondecreasing");
+        if (s_off[c + 1] > s_off[c] && x_off[c + 1] == x_off[c])
+            return fail(MS_E_INVALID, "a cloud with seeds has no points");
+    }
+    if (x_off[ncl] > INT_MAX || s_off[ncl] > INT_MAX)
+        return fail(MS_E_INVALID, "total points and seeds must be <= 2^31-1");
+    if (s_off[ncl] > 0) FMS_CHECK(check_common(X, x_off[ncl], d));
+    return MS_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -995,28 +1122,23 @@ int ms_step_batched(const ms_params* p, const float* X, const int64_t* x_off, fl
                     const int64_t* s_off, int32_t ncl, int32_t d, int32_t n_iter, uint8_t* converged,
                     int32_t* iters, float* shift2, void* stream) {
     g_err.clear();
-    FMS_CHECK(check_params(p, false));
-    if (p->precision != MS_PREC_FP32)
-        return fail(MS_E_INVALID, "ms_step_batched computes the FP32 form only");
-    if (p->metric != MS_METRIC_EUCLIDEAN)
-        return fail(MS_E_INVALID, "ms_step_batched computes the Euclidean metric only");
-    if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
-    if (ncl < 1 || ncl > batched_max_clouds()) return fail(MS_E_INVALID, "ncl must be in [1, 8192]");
-    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    FMS_CHECK(check_batched_args(p, X, x_off, s_off, ncl, d));
     if (n_iter < 0 || n_iter > kMaxIterCap) return fail(MS_E_INVALID, "n_iter must be in [0, 4096]");
-    if (x_off[0] != 0 || s_off[0] != 0) return fail(MS_E_INVALID, "offsets must start at 0");
-    for (int c = 0; c < ncl; ++c) {
-        if (x_off[c + 1] < x_off[c] || s_off[c + 1] < s_off[c])
-            return fail(MS_E_INVALID, "offsets must be nondecreasing");
-        if (s_off[c + 1] > s_off[c] && x_off[c + 1] == x_off[c])
-            return fail(MS_E_INVALID, "a cloud with seeds has no points");
-    }
-    if (x_off[ncl] > INT_MAX || s_off[ncl] > INT_MAX)
-        return fail(MS_E_INVALID, "total points and seeds must be <= 2^31-1");
     if (s_off[ncl] == 0) return MS_OK;
-    FMS_CHECK(check_common(X, x_off[ncl], d));
     if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
     return step_batched_impl(p, X, x_off, seeds, s_off, ncl, d, n_iter, converged, iters, shift2,
+                             (hipStream_t)stream, p->tile_R);
+}
+
+int ms_tune_batched(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,
+                    const int64_t* s_off, int32_t ncl, int32_t d, int32_t trials, int32_t* best_R,
+                    float* ms_per_iter, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_batched_args(p, X, x_off, s_off, ncl, d));
+    if (trials < 1 || trials > 64) return fail(MS_E_INVALID, "trials must be in [1, 64]");
+    if (s_off[ncl] == 0) return fail(MS_E_INVALID, "no cloud has seeds");
+    if (!seeds) return fail(MS_E_INVALID, "seeds is NULL");
+    return tune_batched_impl(p, X, x_off, seeds, s_off, ncl, d, trials, best_R, ms_per_iter,
                              (hipStream_t)stream);
 }
 

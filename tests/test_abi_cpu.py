@@ -97,9 +97,13 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_fit(ctypes.byref(p), None, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert L.ms_fit(None, FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 0, ctypes.byref(k), None, None, None) == -1
-    p.reserved[1] = 1
+    p.reserved[0] = 1
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert "reserved" in api.last_error()
+    p = api.make_params(1.0)
+    p.tile_R = 3
+    assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
+    assert "tile_R" in api.last_error()
     p = api.make_params(1.0)
     p.graph = 2
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
@@ -113,6 +117,23 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_forward_update(FAKE, 1, 10, FAKE, 10, 2, 1.0, FAKE, 2, None) == -1
     assert L.ms_step_adjoint(FAKE, 1, 10, FAKE, 10, 2, -1.0, FAKE, FAKE, FAKE, 4, None) == -1
     assert "h must" in api.last_error()
+    xo = (ctypes.c_int64 * 3)(0, 5, 10)
+    so = (ctypes.c_int64 * 3)(0, 0, 0)
+    best = ctypes.c_int32(0)
+    assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
+                             None) == -1
+    assert "no cloud has seeds" in api.last_error()
+    so = (ctypes.c_int64 * 3)(0, 2, 4)
+    assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 0, ctypes.byref(best), None,
+                             None) == -1
+    assert "trials" in api.last_error()
+    assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, None, so, 2, 2, 4, ctypes.byref(best), None,
+                             None) == -1
+    assert "seeds is NULL" in api.last_error()
+    p.precision = api.PRECISIONS["bf16"]
+    assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
+                             None) == -1
+    assert "FP32 form only" in api.last_error()
 
 
 def test_error_message_is_thread_local_and_cleared(api):

@@ -149,3 +149,38 @@ def test_batched_graph_matches_eager_launches():
             for a, b in zip(ref, got):
                 torch.testing.assert_close(b.cpu(), a, rtol=0, atol=0, equal_nan=True)
             del junk
+
+
+@pytest.mark.parametrize("d,Rs", [(2, (1, 2, 4)), (8, (1, 2)), (16, (1,))])
+def test_batched_tile_shapes_give_identical_results(d, Rs):
+    """The seeds per lane change how seeds share a workgroup, never the order
+    in which a seed's sums are formed: every shape gives the same bits."""
+    Xs, Ss, xo, so = _batch(40 + d, SIZES, d, max_seeds=300)
+    Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+    outs = []
+    for R in Rs:
+        say("tile_R", R, "d", d)
+        outs.append([t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=4, tile_R=R)])
+        torch.cuda.synchronize()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            torch.testing.assert_close(b, a, rtol=0, atol=0, equal_nan=True)
+    if 4 not in Rs:
+        with pytest.raises(api.MeanShiftError, match="tile_R"):
+            api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=1, tile_R=4)
+
+
+def test_batched_tuner_picks_a_built_shape_and_keeps_results():
+    Xs, Ss, xo, so = _batch(50, SIZES, 3, max_seeds=300)
+    Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+    ref = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5, tile_R=1)]
+    S_before = Sa.cpu().clone()
+    best, ms = api.tune_batched(Xa, xo, Sa, so, 1.0, trials=3)
+    say("tuned R", best, ms)
+    assert best in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
+    assert torch.equal(Sa.cpu(), S_before)   # the caller's seeds are not written
+    got = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5)]
+    for a, b in zip(ref, got):
+        torch.testing.assert_close(b, a, rtol=0, atol=0, equal_nan=True)
