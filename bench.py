@@ -92,7 +92,7 @@ def algorithmic_bytes(prec, m, n):
     return tiles * n * per_point + 2 * m * chunks * 16
 
 
-def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
+def time_kernel(api, torch, X, seeds, h, kernel, precision, iters, plain=False):
     """Average duration of one fused-step iteration with every seed active:
     (t(2k iterations) - t(k)) / k, HIP events on the library's stream, so that
     the call's set-up (packing, sorting, workspace) cancels out.  A few
@@ -109,7 +109,7 @@ def time_kernel(api, torch, X, seeds, h, kernel, precision, iters):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        api.step(X, seeds, h, kernel=kernel, precision=precision, tol=1e-30, n_iter=k)
+        api.step(X, seeds, h, kernel=kernel, precision=precision, tol=1e-30, n_iter=k, plain=plain)
         e1.record(st)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
@@ -343,8 +343,8 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    def one(prec):
-        return api.fit(X, w.h, kernel=w.kernel, precision=prec)
+    def one(prec, plain=False):
+        return api.fit(X, w.h, kernel=w.kernel, precision=prec, plain=plain)
 
     if args.phase == "fit":
         out = {"phase": "fit"}
@@ -377,6 +377,17 @@ def main():
         log(f"{prec}: {dt / args.steps * 1e3:.3f} ms/fit, K={last.k}, pairs={last.pairs}, "
             f"iterate_ms={last.iterate_ms:.3f} merge_ms={last.merge_ms:.3f} "
             f"assign_ms={last.assign_ms:.3f} total_ms={last.total_ms:.3f}")
+
+    # the plain FP32 form (every pair, input order) for comparison
+    for _ in range(args.warmup):
+        one("fp32", plain=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plast = one("fp32", plain=True)
+    torch.cuda.synchronize()
+    plain_dt = time.perf_counter() - t0
+    log(f"plain fp32: {plain_dt / args.steps * 1e3:.3f} ms/fit, K={plast.k}")
 
     dt, last = results[args.precision]
     ms_per_step = dt / args.steps * 1e3
@@ -448,6 +459,13 @@ def main():
     out[f"{other}_kernel_pair_evals_per_s"] = pairs / (t_other * 1e-3)
     out["kernel_speedup_vs_" + other] = t_other / t_it
     log(f"{other} kernel: {t_other * 1e3:.1f} us/iteration -> {pairs / (t_other * 1e-3):.3e} pairs/s")
+    t_plain = time_kernel(api, torch, X, seeds, w.h, w.kernel, "fp32", args.kernel_iters, plain=True)
+    out["plain_fp32_time_to_cluster_ms"] = plain_dt / args.steps * 1e3
+    out["plain_fp32_K"] = plast.k
+    out["speedup_time_to_cluster_vs_plain_fp32"] = plain_dt / dt
+    out["plain_fp32_kernel_pair_evals_per_s"] = pairs / (t_plain * 1e-3)
+    out["kernel_speedup_vs_plain_fp32"] = t_plain / t_it
+    log(f"plain fp32 kernel: {t_plain * 1e3:.1f} us/iteration")
     if not args.no_other_configs:
         out["other_configs"] = other_configs(api, torch, workloads)
         log("other configs:", json.dumps(out["other_configs"]))

@@ -107,6 +107,12 @@ typedef struct {
                                  1); 0 = the shape ms_tune_batched chose for
                                  inputs of this kind, else a default.  The
                                  results do not depend on it */
+    int32_t plain;            /* ms_fit, ms_step with MS_PREC_FP32: 1 = the
+                                 plain step, every pair computed in input
+                                 order (no spatial order, no block culling;
+                                 the skipped blocks contribute exact zeros,
+                                 so only the summation order differs); for
+                                 comparison.  Ignored by the BF16 form */
     int32_t reserved[1];      /* must be 0 */
 } ms_params;
 

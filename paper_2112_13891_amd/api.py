@@ -50,6 +50,7 @@ class Params(ctypes.Structure):
         ("metric", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("tile_R", ctypes.c_int32),
+        ("plain", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 1),
     ]
 
@@ -214,16 +215,19 @@ class FitResult:
 def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge_radius=1.0,
         cover_radius=1.0, gamma=1.0, n_initial=128, L=8, refine_radius=3.0, all_points=False,
         rng_seed=0, check_finite=False, max_modes=None, labels=True, trace=False,
-        metric="euclidean") -> FitResult:
+        metric="euclidean", plain=False) -> FitResult:
     """Whole method on device-resident X (n x d float32).  ``trace`` also returns
     the drawn ids, per-seed iterations, status and final positions.
-    ``metric="cosine"`` clusters the directions of the rows (unit-vector modes)."""
+    ``metric="cosine"`` clusters the directions of the rows (unit-vector modes).
+    ``plain=True`` runs the FP32 step over every pair in input order (no
+    spatial order or block culling), for comparison."""
     torch = _torch()
     Xp = _dev(X, torch.float32, 2, "X")
     n, d = X.shape
     max_modes = int(max_modes or n)
     p = make_params(h, kernel, precision, tol, max_iter, merge_radius, cover_radius, gamma,
                     n_initial, L, refine_radius, all_points, rng_seed, check_finite, metric)
+    p.plain = int(bool(plain))
     modes = torch.empty((max_modes, d), dtype=torch.float32, device=X.device)
     lab = torch.empty((n,), dtype=torch.int32, device=X.device) if labels else None
     k = ctypes.c_int32(0)
@@ -259,7 +263,7 @@ def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge
 
 
 def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, converged=None,
-         refine_radius=3.0, metric="euclidean"):
+         refine_radius=3.0, metric="euclidean", plain=False):
     """Up to n_iter updates of the active seeds.  Returns new tensors
     (seeds, converged uint8, iters int32, shift2 float32)."""
     torch = _torch()
@@ -275,6 +279,7 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
     iters = torch.zeros(m, dtype=torch.int32, device=X.device)
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
     p = make_params(h, kernel, precision, tol, refine_radius=refine_radius, metric=metric)
+    p.plain = int(bool(plain))
     rc = lib().ms_step(ctypes.byref(p), Xp, n, d, ctypes.c_void_p(S.data_ptr()), m, int(n_iter),
                        ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
                        ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))

@@ -233,6 +233,7 @@ int check_params(const ms_params* p, bool for_fit) {
     if (p->graph != 0 && p->graph != 1) return fail(MS_E_INVALID, "graph must be 0 or 1");
     if (p->tile_R != 0 && p->tile_R != 1 && p->tile_R != 2 && p->tile_R != 4)
         return fail(MS_E_INVALID, "tile_R must be 0, 1, 2 or 4");
+    if (p->plain != 0 && p->plain != 1) return fail(MS_E_INVALID, "plain must be 0 or 1");
     if (p->reserved[0] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
     if (!for_fit) return MS_OK;
     if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
@@ -551,7 +552,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
     // FP32 on enough points: spatially ordered points and block culling
     // (directions are at most 2 apart: nothing to cull when the reach is 2)
-    const bool cull = !bf16 && cull_supported(d, n) &&
+    const bool cull = !bf16 && !p->plain && cull_supported(d, n) &&
                       !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
     const bool sorted = bf16 || cull;
     SortedPoints sp;
@@ -816,7 +817,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
     const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
-    const bool cull = !bf16 && cull_supported(d, n) &&
+    const bool cull = !bf16 && !p->plain && cull_supported(d, n) &&
                       !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
     const bool sorted = bf16 || cull;
     const StepShape sh = bf16 ? step_shape_bf16(d, m)

@@ -105,6 +105,10 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert "tile_R" in api.last_error()
     p = api.make_params(1.0)
+    p.plain = 2
+    assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
+    assert "plain" in api.last_error()
+    p = api.make_params(1.0)
     p.graph = 2
     assert L.ms_fit(ctypes.byref(p), FAKE, 10, 2, FAKE, 4, ctypes.byref(k), None, None, None) == -1
     assert "graph" in api.last_error()

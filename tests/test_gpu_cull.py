@@ -89,3 +89,26 @@ def test_culled_step_deterministic():
         b = api.step(X, S0, 1.5, precision=precision, n_iter=4)[0]
         torch.cuda.synchronize()
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("d", [3, 16])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_plain_fp32_form_matches_oracle_and_culled_form(orc, d, kernel):
+    """plain=1 runs every pair in input order: oracle parity, and the culled
+    form differs from it only by summation order (culled blocks add exact
+    zeros)."""
+    n = 20011
+    say("plain form", d, kernel)
+    X = clustered(700 + d, n, d)
+    rng = np.random.default_rng(d)
+    S0 = X[rng.choice(n, 300, replace=False)]
+    h = 1.5
+    Sp, cp, ip, _ = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=3, plain=True)
+    Sc, cc, ic, _ = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=3)
+    torch.cuda.synchronize()
+    ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=3)
+    ragged_check(X, S0, h, kernel, 3, Sp.cpu().numpy(), ip.cpu().numpy(), ref, oit)
+    assert np.abs(Sp.cpu().numpy() - Sc.cpu().numpy()).max() <= 1e-4 * h
+    rp = api.fit(_gpu(X), h, kernel=kernel, plain=True)
+    rc = api.fit(_gpu(X), h, kernel=kernel)
+    assert rp.k == rc.k
