@@ -153,6 +153,34 @@ __global__ __launch_bounds__(1024) void seed_order_small_kernel(
         key[e] = k;
     }
     __syncthreads();
+    if (P <= 1024) {
+        // one key per thread: exchanges within a wave through lane shuffles,
+        // the others through LDS (one barrier per such stage)
+        const int e = threadIdx.x;
+        unsigned long long k = e < P ? key[e] : ~0ull;
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                unsigned long long y;
+                if (stride < 64) {
+                    const unsigned lo = __shfl_xor((unsigned)k, stride);
+                    const unsigned hi = __shfl_xor((unsigned)(k >> 32), stride);
+                    y = ((unsigned long long)hi << 32) | lo;
+                } else {
+                    __syncthreads();
+                    if (e < P) key[e] = k;
+                    __syncthreads();
+                    y = e < P ? key[e ^ stride] : ~0ull;
+                }
+                // the lower element of an ascending pair keeps the minimum
+                const bool up = (e & size) == 0;
+                const bool lower = (e & stride) == 0;
+                const unsigned long long lo_v = k < y ? k : y, hi_v = k < y ? y : k;
+                k = (lower == up) ? lo_v : hi_v;
+            }
+        }
+        if (e < m) act0[e] = (int32_t)(k & 0xffffffffu);
+        return;
+    }
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int e = threadIdx.x; e < P; e += 1024) {
