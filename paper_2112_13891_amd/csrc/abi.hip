@@ -690,7 +690,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             iterate_ms += ms;
         }
         pairs += cs.pairs;
-        refined += cs.refined;
+        refined += ctl_refined(cs);
         if (!all) pool_len = cs.pool_len;
         const bool host_merge = cs.merge_host != 0;
 

@@ -19,6 +19,12 @@ enum : int32_t { MG_SKIP = -3, MG_UNDECIDED = -2, MG_FOUNDER = -1 };
 
 constexpr int kMaxIterCap = 4096;   // hard cap on max_iter / n_iter
 constexpr int kMaxMergePasses = 64;
+// BF16 forms: the refined-pair count is spread over counters 128 bytes apart
+// (a workgroup adds its count to counter workgroup % kRefinedSlots), so that
+// the workgroups of a launch do not queue on one address at the end of the
+// kernel.
+constexpr int kRefinedSlots = 64;
+constexpr int kRefinedStride = 16;   // long longs: 128 bytes
 
 // Device-resident control block of one seed batch.  Written only by kernels
 // (single designated threads or integer atomics) and read back by the host
@@ -32,10 +38,17 @@ struct Ctl {
     int32_t k_new;             // merge: modes after this round's founders
     int32_t merge_host;        // merge: 1 if the device passes left seeds undecided
     long long pairs;           // sum of active seeds x n over iterations
-    long long refined;         // BF16 path: pairs recomputed in FP32
+    long long refined[kRefinedSlots * kRefinedStride];   // BF16 path: pairs recomputed in
+                                                         // FP32, at [slot * kRefinedStride]
     int32_t und[kMaxMergePasses];        // merge: undecided seeds after each pass
     int32_t conv_it[kMaxIterCap + 2];    // seeds that converged at iteration t
 };
+
+inline long long ctl_refined(const Ctl& c) {
+    long long r = 0;
+    for (int i = 0; i < kRefinedSlots; ++i) r += c.refined[i * kRefinedStride];
+    return r;
+}
 
 // Geometry of the fused step for one dimension class.
 struct StepShape {

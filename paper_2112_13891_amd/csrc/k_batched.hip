@@ -54,6 +54,30 @@ __device__ __forceinline__ int upper_cloud(const int32_t* pre, int ncl, int v) {
     return lo;
 }
 
+// Appends seed j to the active list of its cloud c (slots seg[c] + cnt[c]++)
+// for every lane with keep set: the wave's seeds one cloud at a time, one
+// atomic per cloud and wave, slots in lane order.  Every active lane of the
+// wave must call it.
+__device__ __forceinline__ void append_by_cloud(bool keep, int c, int j, int32_t* cnt, const int32_t* seg,
+                                                int32_t* act) {
+    unsigned long long pend = __ballot(keep);
+    while (pend) {
+        const int leader = __builtin_ctzll(pend);
+        const int lc = __shfl(c, leader);
+        const bool mine = keep && c == lc;
+        const unsigned long long mask = __ballot(mine);
+        int base = 0;
+        if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&cnt[lc], __popcll(mask));
+        base = __shfl(base, leader);
+        if (mine) {
+            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            act[seg[c] + base + below] = j;
+        }
+        pend &= ~mask;
+    }
+}
+
 // Inclusive block scan of one value per thread (kPlanThreads threads).
 __device__ __forceinline__ int plan_scan(int v, int* wsum, int* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -169,24 +193,7 @@ __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, Batched
         }
         const int j = a.act_in[B.seg[c] + q];
         const bool keep = update_seed_id<D, DP>(a, j, v) == 1;
-        // the kept seeds of the wave, one cloud at a time: one atomic per
-        // cloud and wave, slots in lane order
-        unsigned long long pend = __ballot(keep);
-        while (pend) {
-            const int leader = __builtin_ctzll(pend);
-            const int lc = __shfl(c, leader);
-            const bool mine = keep && c == lc;
-            const unsigned long long mask = __ballot(mine);
-            int base = 0;
-            if ((int)(threadIdx.x & 63) == leader) base = atomicAdd(&cout[lc], __popcll(mask));
-            base = __shfl(base, leader);
-            if (mine) {
-                const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-                a.act_out[B.seg[c] + base + below] = j;
-            }
-            pend &= ~mask;
-        }
+        append_by_cloud(keep, c, j, cout, B.seg, a.act_out);
     }
 }
 
@@ -197,16 +204,18 @@ __global__ void bseed_init_kernel(const float* __restrict__ seeds, const uint8_t
                                   float* S, int32_t* act0, uint8_t* status, int32_t* iters, float* shift2,
                                   int32_t* cnt0) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    for (int k = 0; k < DP; ++k) S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] : 0.0f;
-    const uint8_t st = conv_in[j];
-    status[j] = st;
-    iters[j] = 0;
-    shift2[j] = __builtin_nanf("");
-    if (st == ST_ACTIVE) {
-        const int c = upper_cloud(seg, ncl, j);
-        act0[seg[c] + atomicAdd(&cnt0[c], 1)] = j;
+    bool active = false;
+    int c = 0;
+    if (j < M) {
+        for (int k = 0; k < DP; ++k) S[(long long)j * DP + k] = (k < d) ? seeds[(long long)j * d + k] : 0.0f;
+        const uint8_t st = conv_in[j];
+        status[j] = st;
+        iters[j] = 0;
+        shift2[j] = __builtin_nanf("");
+        active = st == ST_ACTIVE;
+        if (active) c = upper_cloud(seg, ncl, j);
     }
+    append_by_cloud(active, c, j, cnt0, seg, act0);
 }
 
 __global__ void bzero_kernel(int32_t* a, int count) {

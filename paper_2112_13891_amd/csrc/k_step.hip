@@ -68,6 +68,7 @@ __global__ void normalize_rows_kernel(const float* __restrict__ X, int n, int d,
 __device__ void ctl_reset_body(Ctl* ctl, int B, int need, int max_iter) {
     for (int u = threadIdx.x; u <= max_iter; u += blockDim.x) ctl->conv_it[u] = 0;
     if (threadIdx.x < kMaxMergePasses) ctl->und[threadIdx.x] = 0;
+    if (threadIdx.x < kRefinedSlots) ctl->refined[threadIdx.x * kRefinedStride] = 0;
     if (threadIdx.x == 0) {
         ctl->count[0] = B;
         ctl->count[1] = 0;
@@ -77,7 +78,6 @@ __device__ void ctl_reset_body(Ctl* ctl, int B, int need, int max_iter) {
         ctl->iters_run = 0;
         ctl->pool_len = 0;
         ctl->pairs = 0;
-        ctl->refined = 0;
     }
 }
 

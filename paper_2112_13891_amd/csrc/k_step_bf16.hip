@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
     __shared__ float red[kWaves][D + 1][32]; // per-wave seed sums
     float4* sxs = sxs_all[wave];
     const float4* __restrict__ xsg = reinterpret_cast<const float4*>(A.Xs);
-    unsigned refined = 0;
+    unsigned long long refined = 0;   // wave-uniform: counted from ballots
 
     const const_f32_ptr gq = wave_uniform_const(A.geom);
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
@@ -223,6 +223,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                 arun[k] = aex[k] = 0.0f;
             }
         }
+        const unsigned long long lmask = __ballot(live[0]);   // lanes holding a seed
         bool gn[1];
         int blk = b0;
         while (blk < b1 && !bf16_block_near<D, 1, kGauss>(gq + (long long)blk * kGeomStride, shat, live,
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                     // sums), so the result of a pair never depends on its
                     // tile mates
                     const float4* xr = sxs + tt * 32 + 4 * hf;
-                    unsigned nref = 0;
+                    unsigned long long nref = 0;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         float4 x4[4];
@@ -317,11 +318,11 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                             wex += we;
 #pragma unroll
                             for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
-                            nref += need ? 1u : 0u;
+                            nref += __popcll(__ballot(need) & lmask);   // scalar unit
                             E[v] = need ? -__builtin_inff() : E[v];
                         }
                     }
-                    refined += live[0] ? nref : 0u;
+                    refined += nref;
                 }
                 // far pairs (Gaussian only): weights from the estimate, unless
                 // every weight of the wave left to them underflows (2^-127;
@@ -409,10 +410,16 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             for (int k = 0; k <= D; ++k) dst[k] = v[k];
         }
     }
-    // refined pairs: lane counts summed per wave, one atomic per wave
-    for (int off = 32; off >= 1; off >>= 1) refined += __shfl_xor(refined, off);
-    if (lane == 0 && refined)
-        atomicAdd((unsigned long long*)&ctl->refined, (unsigned long long)refined);
+    // refined pairs: wave counts summed per workgroup, one atomic per
+    // workgroup on one of the spread counters
+    __shared__ unsigned long long wref[kWaves];
+    if (lane == 0) wref[threadIdx.x >> 6] = refined;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0;
+        for (int w = 0; w < kWaves; ++w) r += wref[w];
+        if (r) atomicAdd((unsigned long long*)&ctl->refined[(blockIdx.x % kRefinedSlots) * kRefinedStride], r);
+    }
 }
 
 template <int D, int R>

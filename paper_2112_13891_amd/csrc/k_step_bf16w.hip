@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
     __shared__ float fin[(D + 1) * TS];
     const __bf16* spf = reinterpret_cast<const __bf16*>(stage);
     const float* sxs = reinterpret_cast<const float*>(stage + Sh::PF_BYTES);
-    unsigned refined = 0;
+    unsigned long long refined = 0;   // wave-uniform: counted from ballots
 
     const const_f32_ptr gq = wave_uniform_const(A.geom);   // block geometry: scalar loads
     for (int item = blockIdx.x; item < tiles * chunks; item += G) {
@@ -125,6 +125,7 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
         const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
         const int slot = tile * TS + wave * 32 + col;
         const bool live = slot < m;
+        const unsigned long long lmask = __ballot(live);   // lanes holding a seed
         const int j = a.act_in[live ? slot : 0];
         float shat[D], aex[D];
         float wex = 0.0f, ns2 = 0.0f;
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
                 const float m4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
                 const float emax = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[15]));
                 if (!__ballot(emax + eps >= A.e_thr)) continue;
-                unsigned nref = 0;
+                unsigned long long nref = 0;
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const bool need = E[v] + eps >= A.e_thr;
@@ -256,9 +257,9 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
                         aex[k4 + 2] = fmaf(we, x4.z - shat[k4 + 2], aex[k4 + 2]);
                         aex[k4 + 3] = fmaf(we, x4.w - shat[k4 + 3], aex[k4 + 3]);
                     }
-                    nref += need ? 1u : 0u;
+                    nref += __popcll(__ballot(need) & lmask);   // scalar unit
                 }
-                refined += live ? nref : 0u;
+                refined += nref;
             }
         }
 
@@ -283,9 +284,16 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
             dst[D] = wex;
         }
     }
-    for (int off = 32; off >= 1; off >>= 1) refined += __shfl_xor(refined, off);
-    if (lane == 0 && refined)
-        atomicAdd((unsigned long long*)&ctl->refined, (unsigned long long)refined);
+    // refined pairs: wave counts summed per workgroup, one atomic per
+    // workgroup on one of the spread counters
+    __shared__ unsigned long long wref[kWaves];
+    if (lane == 0) wref[threadIdx.x >> 6] = refined;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0;
+        for (int w = 0; w < kWaves; ++w) r += wref[w];
+        if (r) atomicAdd((unsigned long long*)&ctl->refined[(blockIdx.x % kRefinedSlots) * kRefinedStride], r);
+    }
 }
 
 template <int D>
