@@ -438,13 +438,93 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
     }
 }
 
-// Launch of the reduction (exits at once unless many chunks) and the finalize
-// (exits at once when the step kernel finalized) for a batch of B seeds.
+// Reduction and finalize in one launch, for narrow seeds (D <= 8) whose
+// partials per 64-slot run are few enough for one workgroup (at most
+// kFusedFloats floats per slot: chunks x (D+1)).  A workgroup takes a run of
+// 64 consecutive active slots: wave w adds the partials of chunks w, w + 16,
+// w + 32, ... of every slot of the run (lane = slot, so each chunk's 64
+// partials are one contiguous read), U chunks' loads in flight, in chunk
+// order; the 16 wave sums are added in wave order through LDS; wave 0 then
+// updates the 64 seeds and compacts them with one ballot and one atomic, as
+// finalize_kernel does.  No second launch, no reduced copy in memory.
+constexpr int kFusedFloats = 2048;
+
+template <int D, int DP, int R>
+__global__ __launch_bounds__(kFinThreads) void finalize_fused_kernel(StepArgs a, int t, int grid) {
+    static_assert(D <= 8, "the wave sums of wide seeds do not fit in LDS");
+    constexpr int TS = 64 * R;
+    constexpr int U = D <= 4 ? 8 : 4;
+    const int m = active_count(a.ctl, t);
+    if (m == 0) return;
+    const int chunks = chunks_for(m, TS, a.n, grid, a.min_chunk);
+    if (chunks == 1) return;   // finalized inside the step kernel
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ float wsum[kFinWaves - 1][D + 1][64];
+    for (int base = blockIdx.x * 64; base < m; base += gridDim.x * 64) {
+        const int slot = base + lane;
+        float v[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) v[k] = 0.0f;
+        if (slot < m) {
+            const int tile = slot / TS, pos = slot % TS;
+            const float* src = a.part + ((long long)tile * chunks * TS + pos) * (D + 1);
+            for (int c0 = wave; c0 < chunks; c0 += U * kFinWaves) {
+                float tmp[U][D + 1];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = c0 + u * kFinWaves;
+                    const float* p = src + (long long)(c < chunks ? c : c0) * TS * (D + 1);
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) tmp[u][k] = p[k];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (c0 + u * kFinWaves < chunks) {
+#pragma unroll
+                        for (int k = 0; k <= D; ++k) v[k] += tmp[u][k];
+                    }
+                }
+            }
+        }
+        if (wave > 0) {
+#pragma unroll
+            for (int k = 0; k <= D; ++k) wsum[wave - 1][k][lane] = v[k];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int w = 1; w < kFinWaves; ++w)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) v[k] += wsum[w - 1][k][lane];
+            const int res = slot < m ? update_seed<D, DP>(a, slot, v) : 0;
+            compact_wave<D, DP>(a, t, slot, res);
+        }
+        __syncthreads();
+    }
+}
+
+// Launch of the reduction and the finalize for a batch of B seeds.  Narrow
+// seeds whose partials fit the fused kernel for every active count (the most
+// chunks a tile can have is that of a one-tile batch) take the one launch of
+// finalize_fused_kernel.  Otherwise: the reduction (exits at once unless many
+// chunks) and the finalize (exits at once when the step kernel finalized);
 // may_reduce = false: the caller's shape never has more than kDirectChunks
 // chunks per tile, and the reduction launch is left out.
 template <int D, int DP, int R>
 inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hipStream_t s,
                                   bool may_reduce = true) {
+    if constexpr (D <= 8) {
+        const long long cmax = std::min<long long>(grid, ((long long)a.n + a.min_chunk - 1) / a.min_chunk);
+        if (cmax * (D + 1) <= kFusedFloats) {
+            int fblocks = (B + 63) / 64;
+            if (fblocks > 4096) fblocks = 4096;
+            if (fblocks < 1) fblocks = 1;
+            hipLaunchKernelGGL((finalize_fused_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a,
+                               t, grid);
+            return hipGetLastError();
+        }
+    }
     if (may_reduce) {
         const int rblocks = B < 256 ? (B < 1 ? 1 : B) : 256;
         hipLaunchKernelGGL((reduce_kernel<D, R>), dim3(rblocks), dim3(kRedThreads), 0, s, a, t, grid);
