@@ -51,7 +51,7 @@ def source_digest():
 
 
 def counter_figures(prec):
-    """HBM bytes per fused-step iteration (step + reduction + finalize) at the
+    """HBM bytes per fused-step iteration (step + reduction and finalize) at the
     512 x 200,000 launch, from the committed FETCH_SIZE / WRITE_SIZE summary
     (scaled by a copy kernel of known size), and the MFMA flops the step
     kernel executed (K padded to 16); both None when the sources changed since
@@ -405,7 +405,8 @@ def main():
     roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VEC_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VEC_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": f"one fused-step iteration: {step_name} + reduce_kernel + finalize_kernel",
+            "kernel": f"one fused-step iteration: {step_name} + finalize_fused_kernel "
+                      "(chunk reduction and finalize in one launch)",
             "launch": f"{m} seeds x {n} points", "avg_ms": t_it,
             "flops_per_pair": flops_per_pair(d),
             "algorithmic_bytes": algorithmic_bytes(args.precision, m, n),
