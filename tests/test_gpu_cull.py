@@ -112,3 +112,22 @@ def test_plain_fp32_form_matches_oracle_and_culled_form(orc, d, kernel):
     rp = api.fit(_gpu(X), h, kernel=kernel, plain=True)
     rc = api.fit(_gpu(X), h, kernel=kernel)
     assert rp.k == rc.k
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("m", [64, 700])
+def test_reduce_paths_at_many_chunks(orc, plain, m):
+    """D = 3 at 300,007 points: up to 1,172 (plain, 256-point chunks) or 586
+    (culled, 512-point chunks) chunk partials per seed, more than the
+    one-launch reduce-and-finalize takes (2,048 floats per slot), so the
+    spread reduction and the separate finalize run (every smaller case here
+    takes the one-launch form).  Both match the oracle."""
+    n, d, h = 300007, 3, 1.5
+    say("reduce paths", "plain" if plain else "culled", m)
+    X = clustered(4242, n, d, k=60, box=400.0)
+    rng = np.random.default_rng(m)
+    S0 = X[rng.choice(n, m, replace=False)]
+    S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, n_iter=2, plain=plain)
+    torch.cuda.synchronize()
+    ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, "gaussian", tol=1e-3, n_iter=2)
+    ragged_check(X, S0, h, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
