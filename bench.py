@@ -152,6 +152,15 @@ def other_configs(api, torch, workloads):
     out["embed32_gaussian_bf16"] = fit_rate(w, 2, precision="bf16")
     out["embed32_gaussian_bf16"]["speedup_vs_fp32"] = (
         out["embed32_gaussian_fp32"]["time_to_cluster_ms"] / out["embed32_gaussian_bf16"]["time_to_cluster_ms"])
+    # the flat window on the same embeddings: no two points share a window, so
+    # every point founds its own mode (K = n) and merge and labels are n^2
+    # problems; a throughput case (one fit per precision after one warm-up)
+    w = workloads.embed32(seed=0, kernel="flat")
+    for prec in ("fp32", "bf16"):
+        r = fit_rate(w, 1, precision=prec)
+        out[f"embed32_flat_{prec}"] = r
+    out["embed32_flat_fp32"]["workload"] = ("embed32: 262,144 points, D=32, 100 clusters + 5% outliers, "
+                                            "flat h=1.5 (every window a singleton: K = n)")
     # cosine metric on 32-D embeddings (unit directions, chord bandwidth 0.3)
     w = workloads.embed_cos(seed=0)
     for prec in ("fp32", "bf16"):

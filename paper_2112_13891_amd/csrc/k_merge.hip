@@ -105,6 +105,81 @@ __global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S,
     }
 }
 
+// Tiled form of one decision pass, for large batches (the degenerate case of
+// a window so narrow that every seed founds a mode makes every seed scan
+// every mode and every earlier seed).  A workgroup takes kT consecutive
+// seeds, one per lane, and streams the old modes (first pass) and then the
+// earlier seeds through LDS, kDecideRows rows per tile, so that each row is
+// read once per workgroup instead of once per seed.  A lane scans a tile in
+// index order and stops at its first hit; the workgroup leaves a loop once no
+// lane searches.  The decisions are exactly those of decide_kernel: the same
+// first-hit rule, and a state staged before another workgroup settles it can
+// only read as undecided, which postpones a decision.
+constexpr int kDecideRows = 64;
+constexpr int kDecideTiledMinBatch = 16384;
+
+template <int D, bool kFirst>
+__global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restrict__ S, int DP,
+                                                          const uint8_t* __restrict__ status, int B,
+                                                          const float* __restrict__ modes, int K_old,
+                                                          float r2, int32_t* state, int32_t* und_counter) {
+    __shared__ float rows[kDecideRows][D];
+    __shared__ int32_t rst[kDecideRows];
+    const int i0 = blockIdx.x * kT;
+    const int i = i0 + threadIdx.x;
+    bool todo = false;   // this lane decides seed i in this pass
+    if (i < B) {
+        if (kFirst && status[i] != ST_CONVERGED) __atomic_store_n(&state[i], (int32_t)MG_SKIP, __ATOMIC_RELAXED);
+        else todo = kFirst || __atomic_load_n(&state[i], __ATOMIC_RELAXED) == MG_UNDECIDED;
+    }
+    const bool owner = todo;
+    float si[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) si[k] = todo ? S[(long long)i * DP + k] : 0.0f;
+    int result = MG_FOUNDER;   // unless an old mode or an earlier founder / undecided seed is within r
+    if (kFirst) {
+        for (int base = 0; base < K_old; base += kDecideRows) {
+            if (!__syncthreads_or(todo)) break;
+            const int cnt = min(kDecideRows, K_old - base);
+            for (int e = threadIdx.x; e < cnt * D; e += kT)
+                rows[e / D][e % D] = modes[(long long)(base + e / D) * DP + e % D];
+            __syncthreads();
+            if (todo) {
+                for (int q = 0; q < cnt; ++q) {
+                    if (dist2<D>(si, rows[q]) <= r2) {
+                        result = base + q;
+                        todo = false;
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    const int ilast = min(i0 + kT, B) - 1;   // the workgroup's last seed: candidates j < ilast
+    for (int base = 0; base < ilast; base += kDecideRows) {
+        if (!__syncthreads_or(todo)) break;
+        const int cnt = min(kDecideRows, ilast - base);
+        for (int e = threadIdx.x; e < cnt * D; e += kT)
+            rows[e / D][e % D] = S[(long long)(base + e / D) * DP + e % D];
+        if (threadIdx.x < cnt) rst[threadIdx.x] = __atomic_load_n(&state[base + threadIdx.x], __ATOMIC_RELAXED);
+        __syncthreads();
+        if (todo) {
+            const int qend = min(cnt, i - base);   // j < i
+            for (int q = 0; q < qend; ++q) {
+                const int sj = rst[q];
+                if ((sj == MG_FOUNDER || sj == MG_UNDECIDED) && dist2<D>(si, rows[q]) <= r2) {
+                    result = (sj == MG_FOUNDER) ? (K_old + base + q) : MG_UNDECIDED;
+                    todo = false;
+                    break;
+                }
+            }
+        }
+    }
+    if (owner && result != MG_UNDECIDED) __atomic_store_n(&state[i], result, __ATOMIC_RELAXED);
+    const unsigned long long und = __ballot(owner && result == MG_UNDECIDED);
+    if ((threadIdx.x & 63) == 0 && und) atomicAdd(und_counter, __popcll(und));
+}
+
 // After the passes: if every seed is decided, number the founders in seed
 // order (mode K_old + q for the q-th founder) and append their positions to
 // the mode store; ctl->k_new = K_old + founders.  Otherwise leave the modes
@@ -288,6 +363,17 @@ hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t
                                     int32_t* und_counter, bool first, hipStream_t s) {
     const int D = step_shape(d).D;
     if (B <= 0) return hipSuccess;
+    if (B >= kDecideTiledMinBatch) {
+        const dim3 tgrid((B + kT - 1) / kT);
+        if (first) {
+            FMS_DSWITCH(D, hipLaunchKernelGGL((decide_tiled_kernel<DD, true>), tgrid, dim3(kT), 0, s, S, DP,
+                                              status, B, modes, K_old, r2, state, und_counter));
+        } else {
+            FMS_DSWITCH(D, hipLaunchKernelGGL((decide_tiled_kernel<DD, false>), tgrid, dim3(kT), 0, s, S, DP,
+                                              status, B, modes, K_old, r2, state, und_counter));
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((B + kWavesT - 1) / kWavesT);
     if (first) {
         FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD, true>), grid, dim3(kT), 0, s, S, DP,
