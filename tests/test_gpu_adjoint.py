@@ -108,3 +108,51 @@ def test_batched_equals_per_cloud():
     for b in range(3):
         s1, x1 = api.step_adjoint(Xb[b], Xb[b], 1.0, G[b])
         assert torch.equal(dS[b], s1) and torch.equal(dX[b], x1)
+
+
+def test_full_size_trajectories_and_gradients(orc):
+    """The differentiable workload at full size (64 clouds x 16,384 points,
+    D = 16, T = 10, h = 1), in the launch shape the bench times: sampled
+    trajectories against the FP64 oracle (each S_T row follows its own
+    point through T updates over the fixed cloud); on one whole cloud, the
+    FP32 gradient of the loss against the FP64 one, and the FP64 gradient
+    against a central finite difference of the loss along a random
+    direction."""
+    clouds = workloads.diffclouds(seed=0)
+    X = np.stack([c[0] for c in clouds])
+    Cn = np.stack([c[2][c[1]] for c in clouds])
+    T, h = 10, 1.0
+    say("full-size forward", X.shape)
+    S = MeanShiftT.apply(torch.from_numpy(X).to(DEV), h, T).cpu().numpy()
+    rng = np.random.default_rng(5)
+    for c in (0, 37, 63):
+        idx = rng.choice(X.shape[1], 16, replace=False)
+        ref, ost, oit, osh = orc.step(X[c], X[c][idx].astype(np.float64), h, "gaussian", tol=1e-30, n_iter=T)
+        assert (oit == T).all()
+        err = np.abs(S[c][idx] - ref).max()
+        say("cloud", c, "trajectory err / h", err / h)
+        assert err <= 1e-4 * h
+
+    c = 11
+    Xc = torch.from_numpy(X[c]).to(DEV, torch.float64)
+    Cc = torch.from_numpy(Cn[c]).to(DEV, torch.float64)
+
+    def loss(A):
+        return ((MeanShiftT.apply(A, h, T) - Cc.to(A.dtype)) ** 2).sum()
+
+    A = Xc.clone().requires_grad_(True)
+    L = loss(A)
+    L.backward()
+    g64 = A.grad.clone()
+    A32 = Xc.float().clone().requires_grad_(True)
+    loss(A32).backward()
+    rel = float((A32.grad.double() - g64).abs().max() / g64.abs().max())
+    say("full-size FP32 grad rel err", rel)
+    assert rel < 2e-3
+    V = torch.randn(Xc.shape, dtype=torch.float64, device=DEV, generator=torch.Generator(DEV).manual_seed(3))
+    eps = 1e-5
+    with torch.no_grad():
+        fd = (loss(Xc + eps * V) - loss(Xc - eps * V)) / (2 * eps)
+    dd = float((g64 * V).sum())
+    say("directional derivative", dd, "finite difference", float(fd))
+    assert abs(dd - float(fd)) <= 1e-5 * abs(dd) + 1e-8

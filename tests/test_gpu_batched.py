@@ -184,3 +184,26 @@ def test_batched_tuner_picks_a_built_shape_and_keeps_results():
     got = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5)]
     for a, b in zip(ref, got):
         torch.testing.assert_close(b, a, rtol=0, atol=0, equal_nan=True)
+
+
+def test_batched_full_size_sampled(orc):
+    """The batched workload at full size (512 clouds of 1,000..65,536 points,
+    D = 16, min(n, 256) seeds per cloud), in the launch shape the bench
+    times: after 3 iterations, the seeds of sampled clouds (the smallest,
+    the largest and two others) against the oracle run on each cloud alone."""
+    clouds = workloads.clouds16(seed=0)
+    Xs = [c[0] for c in clouds]
+    rng = np.random.default_rng(0)
+    Ss = [X[rng.choice(len(X), min(len(X), 256), replace=False)] for X in Xs]
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+    say("full-size batched", len(Xs), "clouds", int(xo[-1]), "points")
+    S, conv, it, sh = _run(Xs, Ss, xo, so, 1.0, "gaussian", 3)
+    torch.cuda.synchronize()
+    S, it = S.cpu().numpy(), it.cpu().numpy()
+    sizes = np.array([len(x) for x in Xs])
+    for c in sorted({int(sizes.argmin()), int(sizes.argmax()), 100, 400}):
+        a, b = so[c], so[c + 1]
+        ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), 1.0, "gaussian", tol=1e-3, n_iter=3)
+        say("cloud", c, "n", len(Xs[c]))
+        ragged_check(Xs[c], Ss[c], 1.0, "gaussian", 3, S[a:b], it[a:b], ref, oit)
