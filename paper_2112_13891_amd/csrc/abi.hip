@@ -358,7 +358,8 @@ thread_local ProgressWord g_prog;
 
 // Waits for the work queued on the stream by polling it.  The fit's host
 // decisions wait on short device tails, where the wake-up of a blocking wait
-// costs more than the tail itself.
+// costs more than the tail itself.  Only for work whose host-side results are
+// in pinned memory (copies to pageable memory keep hipStreamSynchronize).
 hipError_t wait_stream(hipStream_t s) {
     for (;;) {
         const hipError_t q = hipStreamQuery(s);
@@ -521,7 +522,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_check_finite(X, (long long)n * d, flag, s));
         int32_t hflag = 0;
         FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        FMS_HIP(wait_stream(s));
+        FMS_HIP(hipStreamSynchronize(s));   // pageable destination: the blocking wait
         if (hflag) return fail(MS_E_NONFINITE, "X contains NaN or Inf");
     }
     if (p->metric == MS_METRIC_COSINE) {
@@ -534,7 +535,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_normalize_rows(X, n, d, Xn, flag, s));
         int32_t hflag = 0;
         FMS_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        FMS_HIP(wait_stream(s));
+        FMS_HIP(hipStreamSynchronize(s));   // pageable destination: the blocking wait
         if (hflag) return fail(MS_E_INVALID, "cosine metric: a row of X has no direction (length 0 or not finite)");
         X = Xn;
     }
