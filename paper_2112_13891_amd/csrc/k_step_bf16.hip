@@ -13,7 +13,12 @@
 //   every pair with E + kappa (R + |s~|)^2 >= -(refine_radius h)^2 (packed
 //   units) -- every pair that may lie within refine_radius * h -- is
 //   recomputed exactly as the FP32 step does it: direct-difference distance,
-//   FP32 weight, FP32 accumulation of w (x - s) and w;
+//   FP32 weight, FP32 accumulation of w (x - s) and w.  When the block's
+//   bound (its radius and the seed's distance to its centre) admits such a
+//   pair for some seed of the wave, the wave computes every pair of its half
+//   block that way and no product at all (the live blocks near the seeds are
+//   mostly within the radius anyway); otherwise no pair of the block can
+//   need it and the products alone are used;
 //   the remaining (far) pairs take their weight from the estimate (Gaussian;
 //   zero for the flat window), packed to bf16, and  sum_p w [x~h | x~l | 1]
 //   is accumulated by two more MFMAs per 32 points in FP32.
@@ -262,6 +267,49 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             }
             const float rr = gm[4] + sqrtf(ns);
             const float eps = A.kappa * rr * rr;
+            {
+                // some seed of the group may have a pair of this block within
+                // the refine radius: the wave's half block is computed exactly
+                // in FP32 (points from LDS), every pair, as the FP32 step does
+                // it; otherwise the bf16 products alone (no pair can need the
+                // recompute)
+                const float lbk = sqrtf(ns) - gm[4];
+                const bool may = live[0] && !(lbk > 0.0f && lbk * lbk > -A.e_thr + 2.0f * eps);
+                if (__ballot(may)) {
+                    const long long pb = (long long)blk * kBlk + half * kPtsPerWave;
+                    unsigned long long nex = 0;
+#pragma unroll 1
+                    for (int tt = 0; tt < kTilesPerWave; ++tt) {
+                        const float4* xr = sxs + tt * 32 + 4 * hf;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            float4 x4[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) x4[u] = xr[8 * q + u];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const bool valid = pb + tt * 32 + 8 * q + 4 * hf + u < n;
+                                const float xv[4] = {x4[u].x, x4[u].y, x4[u].z, x4[u].w};
+                                float dx[D], q2 = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    dx[k] = xv[k] - shat[0][k];
+                                    q2 = fmaf(dx[k], dx[k], q2);
+                                }
+                                float we = kGauss ? __builtin_amdgcn_exp2f(-q2) : (q2 <= a.h2 ? 1.0f : 0.0f);
+                                we = valid ? we : 0.0f;
+                                wex += we;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
+                                nex += __popcll(__ballot(valid) & lmask);
+                            }
+                        }
+                    }
+                    refined += nex;
+                    blk = nxt;
+                    continue;
+                }
+            }
             const bf16x8 sfrag = seed_frag<D>(st, ns, hf);
             f32x16 out = f32x16{};
             bool used = false;
