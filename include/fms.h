@@ -272,6 +272,41 @@ int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
                  int32_t count, int32_t *out);
 
 /*
+ * ms_fit_batched -- the whole method (Algorithm 2 with the seed pool of
+ * Section II-D; Algorithm 1 with all_points_as_seeds) for every cloud of a
+ * batch, as ms_fit on each cloud alone would run it, the clouds' rounds
+ * advancing together: every round's iterations of all clouds run through
+ * the batched fused step (ms_step_batched's kernels), the seeds of cloud c
+ * are drawn with the SplitMix64 state rng_seed + c, each cloud merges its
+ * converged seeds into its own modes, coverage and compaction act on its own
+ * pool, and its seed-count rule is its own.  Labels are the nearest mode
+ * within the point's cloud.
+ *   p          as ms_fit; p->precision must be MS_PREC_FP32, metric
+ *              Euclidean and gamma 1 (every round runs until each seed
+ *              converged, failed or made max_iter updates).
+ *   X          device, n x d row-major float32, the clouds' points
+ *              concatenated; cloud c is rows x_off[c] .. x_off[c+1].
+ *   x_off      host, ncl + 1 nondecreasing offsets, x_off[0] = 0, at
+ *              least one point in total.
+ *   ncl, d     1..8192 clouds, 1 <= d <= 64.
+ *   modes      device, max_modes x d float32 out: cloud c's modes are rows
+ *              k_off[c] .. k_off[c+1], in creation order.
+ *   max_modes  rows of modes, >= 1.
+ *   k_off      host, ncl + 1 out: mode offsets (filled on MS_E_CAPACITY too,
+ *              so the caller can size modes).
+ *   labels     device, n int32 out (may be NULL): index of the point's mode
+ *              within its cloud, ties to the lowest index.
+ *   rounds     host, may be NULL: rounds run (the most any cloud ran).
+ * Errors: MS_E_INVALID (arguments), MS_E_CAPACITY (more modes than
+ * max_modes), MS_E_NO_MODES (a cloud with points has no converged seed),
+ * MS_E_NOMEM, MS_E_HIP.  Host-synchronous (the host merges between rounds).
+ * Allocates device workspace on `stream`.
+ */
+int ms_fit_batched(const ms_params *p, const float *X, const int64_t *x_off, int32_t ncl, int32_t d,
+                   float *modes, int64_t max_modes, int64_t *k_off, int32_t *labels, int32_t *rounds,
+                   void *stream);
+
+/*
  * ms_tune_batched -- tile-shape tuning for ms_step_batched.
  *
  * Times `trials` iterations (every seed active) of each seed tile shape that

@@ -78,7 +78,8 @@ class Diag(ctypes.Structure):
     ]
 
 
-EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_tune_batched", "ms_assign",
+EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_tune_batched", "ms_fit_batched",
+           "ms_assign",
            "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
            "ms_last_error", "ms_version")
 
@@ -105,6 +106,8 @@ def lib():
     L.ms_step_batched.restype = ctypes.c_int
     L.ms_tune_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P]
     L.ms_tune_batched.restype = ctypes.c_int
+    L.ms_fit_batched.argtypes = [ctypes.POINTER(Params), P, P, i32, i32, P, i64, P, P, P, P]
+    L.ms_fit_batched.restype = ctypes.c_int
     L.ms_assign.argtypes = [P, i64, i32, P, i32, P, P, P]
     L.ms_assign.restype = ctypes.c_int
     L.ms_forward_update.argtypes = [P, i32, i64, P, i64, i32, ctypes.c_double, P, i32, P]
@@ -320,6 +323,37 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
                                ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))
     _check(rc)
     return S, conv, iters, sh
+
+
+def fit_batched(X, x_off, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_radius=1.0,
+                cover_radius=1.0, n_initial=128, L=8, all_points=False, rng_seed=0, max_modes=None,
+                labels=True):
+    """ms_fit_batched: the whole method on every cloud of a CSR batch (cloud c
+    owns X[x_off[c]:x_off[c+1]] and draws with SplitMix64 state rng_seed + c).
+    Returns (modes list of per-cloud tensors, labels tensor or None, k_off
+    numpy array, rounds)."""
+    import numpy as np
+    torch = _torch()
+    Xp = _dev(X, torch.float32, 2, "X")
+    n, d = X.shape
+    xo = np.ascontiguousarray(np.asarray(x_off, dtype=np.int64))
+    if xo.ndim != 1 or len(xo) < 2:
+        raise ValueError("x_off must have ncl + 1 entries")
+    ncl = len(xo) - 1
+    max_modes = int(max_modes or n)
+    p = make_params(h, kernel, "fp32", tol, max_iter, merge_radius, cover_radius, 1.0, n_initial, L,
+                    all_points=all_points, rng_seed=rng_seed)
+    modes = torch.empty((max_modes, d), dtype=torch.float32, device=X.device)
+    lab = torch.empty((n,), dtype=torch.int32, device=X.device) if labels else None
+    k_off = np.zeros(ncl + 1, np.int64)
+    rounds = ctypes.c_int32(0)
+    rc = lib().ms_fit_batched(ctypes.byref(p), Xp, xo.ctypes.data, ncl, d, ctypes.c_void_p(modes.data_ptr()),
+                              max_modes, k_off.ctypes.data,
+                              ctypes.c_void_p(lab.data_ptr()) if lab is not None else None,
+                              ctypes.byref(rounds), _stream_ptr(X))
+    _check(rc, int(k_off[-1]))
+    per = [modes[int(k_off[c]):int(k_off[c + 1])] for c in range(ncl)]
+    return per, lab, k_off, int(rounds.value)
 
 
 def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=4):

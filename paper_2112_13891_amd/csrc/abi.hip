@@ -986,6 +986,179 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     return MS_OK;
 }
 
+thread_local Pinned g_pin_bpos, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_blen;
+
+// The whole method (Algorithm 2 with the seed pool of Section II-D; with
+// all_points_as_seeds, Algorithm 1) for every cloud of a CSR batch, the
+// clouds' rounds advancing together: per round, the host draws each active
+// cloud's seeds from its pool (SplitMix64 state rng_seed + c for cloud c),
+// the device gathers them and runs the batched fused step for all clouds
+// until every seed of the round converged, failed or max_iter updates were
+// made; the host merges each cloud's converged seeds into that cloud's modes
+// in draw order (first mode within merge_radius h, else a new mode), the
+// device removes covered points from each pool and compacts the pools, and
+// the host applies each cloud's seed-count rule (stop when its pool is empty
+// or N >= L M, else N <- 2N).  Labels: nearest mode within the cloud.
+int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, int ncl, int d, float* modes,
+                     int64_t max_modes, int64_t* k_off, int32_t* labels, int32_t* rounds_out, hipStream_t s) {
+    const long long n = x_off[ncl];
+    const bool all = p->all_points_as_seeds != 0;
+    const float rm = p->merge_radius * p->h, rc = p->cover_radius * p->h;
+    const float r2m = rm * rm, r2c = rc * rc;
+    Workspace ws(s);
+    long long* xo_dev;
+    long long* so_dev;
+    int32_t *pool[2], *pos_dev, *plen_dev, *moff_dev, *it_dev;
+    uint8_t *removed, *conv_dev;
+    float *S_dev, *sh2_dev, *nm_dev;
+    FMS_CHECK(ws.alloc(&xo_dev, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&so_dev, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&pool[0], (size_t)n));
+    FMS_CHECK(ws.alloc(&pool[1], (size_t)n));
+    FMS_CHECK(ws.alloc(&pos_dev, (size_t)n));
+    FMS_CHECK(ws.alloc(&plen_dev, (size_t)ncl));
+    FMS_CHECK(ws.alloc(&moff_dev, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&removed, (size_t)n));
+    FMS_CHECK(ws.alloc(&conv_dev, (size_t)n));
+    FMS_CHECK(ws.alloc(&it_dev, (size_t)n));
+    FMS_CHECK(ws.alloc(&S_dev, (size_t)n * d));
+    FMS_CHECK(ws.alloc(&sh2_dev, (size_t)n));
+    FMS_CHECK(ws.alloc(&nm_dev, (size_t)n * d));
+    const size_t pos_bytes = ((size_t)n * 4 + 7) / 8 * 8;   // the seed offsets follow, 8-byte aligned
+    FMS_CHECK(g_pin_bpos.ensure(pos_bytes + (size_t)(ncl + 1) * 8));
+    FMS_CHECK(g_pin_bseeds.ensure((size_t)n * d * 4));
+    FMS_CHECK(g_pin_bconv.ensure((size_t)n));
+    FMS_CHECK(g_pin_bmodes.ensure((size_t)n * d * 4 + (size_t)(ncl + 1) * 4));
+    FMS_CHECK(g_pin_blen.ensure((size_t)ncl * 4));
+    int32_t* hpos = (int32_t*)g_pin_bpos.p;
+    int64_t* hso = (int64_t*)((char*)g_pin_bpos.p + pos_bytes);
+    float* hS = (float*)g_pin_bseeds.p;
+    uint8_t* hconv = (uint8_t*)g_pin_bconv.p;
+    float* hnm = (float*)g_pin_bmodes.p;
+    int32_t* hmoff = (int32_t*)(hnm + (size_t)n * d);
+    int32_t* hlen = (int32_t*)g_pin_blen.p;
+
+    std::vector<long long> xo(x_off, x_off + ncl + 1);
+    FMS_HIP(hipMemcpyAsync(xo_dev, xo.data(), (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
+    FMS_HIP(launch_bf_iota(xo_dev, ncl, pool[0], n, s));
+    FMS_HIP(launch_fill_u8(removed, (int)n, 0, s));
+    std::vector<uint64_t> rng(ncl);
+    std::vector<long long> N(ncl, p->n_initial);
+    std::vector<int32_t> plen(ncl);
+    std::vector<char> active(ncl);
+    std::vector<std::vector<float>> cm(ncl);   // modes of each cloud, in creation order
+    for (int c = 0; c < ncl; ++c) {
+        rng[c] = p->rng_seed + (uint64_t)c;
+        plen[c] = (int32_t)(x_off[c + 1] - x_off[c]);
+        active[c] = plen[c] > 0;
+        hlen[c] = plen[c];
+    }
+    FMS_HIP(hipMemcpyAsync(plen_dev, hlen, (size_t)ncl * 4, hipMemcpyHostToDevice, s));
+    ms_params q = *p;
+    q.graph = 0;
+    q.tile_R = 0;
+    constexpr int kChunk = 4;   // iterations between checks for a finished round
+    int cur = 0, rounds = 0;
+    for (;;) {
+        // draws
+        int64_t M = 0;
+        hso[0] = 0;
+        for (int c = 0; c < ncl; ++c) {
+            int32_t B = 0;
+            if (active[c]) {
+                B = all ? plen[c] : (int32_t)std::min<long long>(N[c], plen[c]);
+                if (all)
+                    for (int32_t t = 0; t < B; ++t) hpos[M + t] = t;
+                else
+                    draw_positions(&rng[c], plen[c], B, hpos + M);
+            }
+            M += B;
+            hso[c + 1] = M;
+        }
+        if (M == 0) break;
+        FMS_HIP(hipMemcpyAsync(pos_dev, hpos, (size_t)M * 4, hipMemcpyHostToDevice, s));
+        FMS_HIP(hipMemcpyAsync(so_dev, hso, (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
+        FMS_HIP(launch_bf_gather(X, d, xo_dev, so_dev, ncl, pos_dev, pool[cur], removed, S_dev, (int)M, s));
+        FMS_HIP(launch_fill_u8(conv_dev, (int)M, 0, s));
+        // iterations until the round is over for every seed
+        for (int done = 0; done < p->max_iter;) {
+            const int k = std::min(kChunk, p->max_iter - done);
+            FMS_CHECK(step_batched_impl(&q, X, x_off, S_dev, hso, ncl, d, k, conv_dev, it_dev, sh2_dev, s));
+            done += k;
+            FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
+            FMS_HIP(wait_stream(s));
+            bool open = false;
+            for (long long g = 0; g < M && !open; ++g) open = hconv[g] == ST_ACTIVE;
+            if (!open) break;
+        }
+        FMS_HIP(hipMemcpyAsync(hS, S_dev, (size_t)M * d * 4, hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
+        FMS_HIP(wait_stream(s));
+        rounds += 1;
+        // merge, cloud by cloud, in draw order
+        long long nm = 0;
+        hmoff[0] = 0;
+        for (int c = 0; c < ncl; ++c) {
+            const size_t K_old = cm[c].size() / d;
+            for (long long g = hso[c]; g < hso[c + 1]; ++g) {
+                if (hconv[g] != ST_CONVERGED) continue;
+                const float* sg = hS + (size_t)g * d;
+                bool joined = false;
+                for (size_t j = 0; j < cm[c].size() / d && !joined; ++j)
+                    joined = host_dist2(sg, cm[c].data() + j * d, d) <= r2m;
+                if (!joined) cm[c].insert(cm[c].end(), sg, sg + d);
+            }
+            const size_t K_new = cm[c].size() / d;
+            for (size_t j = K_old; j < K_new; ++j, ++nm)
+                std::memcpy(hnm + (size_t)nm * d, cm[c].data() + j * d, (size_t)d * 4);
+            hmoff[c + 1] = (int32_t)nm;
+        }
+        if (all) break;
+        // pools: coverage by the new modes, compaction, seed-count control
+        FMS_HIP(hipMemcpyAsync(nm_dev, hnm, (size_t)std::max(1LL, nm) * d * 4, hipMemcpyHostToDevice, s));
+        FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
+        FMS_HIP(launch_bf_cover(X, d, xo_dev, ncl, pool[cur], plen_dev, nm_dev, moff_dev, r2c, removed, n, s));
+        FMS_HIP(launch_bf_compact(xo_dev, ncl, pool[cur], removed, plen_dev, pool[cur ^ 1], s));
+        cur ^= 1;
+        FMS_HIP(hipMemcpyAsync(hlen, plen_dev, (size_t)ncl * 4, hipMemcpyDeviceToHost, s));
+        FMS_HIP(wait_stream(s));
+        bool any = false;
+        for (int c = 0; c < ncl; ++c) {
+            if (!active[c]) continue;
+            plen[c] = hlen[c];
+            const long long K = (long long)(cm[c].size() / d);
+            if (plen[c] == 0 || N[c] >= (long long)p->L * K) active[c] = 0;
+            else N[c] *= 2;
+            any = any || active[c];
+        }
+        if (!any) break;
+    }
+    if (rounds_out) *rounds_out = rounds;
+
+    // modes and labels
+    long long K = 0;
+    k_off[0] = 0;
+    for (int c = 0; c < ncl; ++c) {
+        K += (long long)(cm[c].size() / d);
+        k_off[c + 1] = K;
+    }
+    if (K > max_modes) return fail(MS_E_CAPACITY, "more modes than max_modes (k_off holds the required counts)");
+    for (int c = 0; c < ncl; ++c)
+        if (x_off[c + 1] > x_off[c] && cm[c].empty()) return fail(MS_E_NO_MODES, "a cloud has no converged seed");
+    for (int c = 0; c < ncl; ++c) {
+        std::memcpy(hnm + (size_t)k_off[c] * d, cm[c].data(), cm[c].size() * 4);
+        hmoff[c] = (int32_t)k_off[c];
+    }
+    hmoff[ncl] = (int32_t)K;
+    if (K > 0) FMS_HIP(hipMemcpyAsync(modes, hnm, (size_t)K * d * 4, hipMemcpyHostToDevice, s));
+    if (labels) {
+        FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
+        FMS_HIP(launch_bf_assign(X, d, xo_dev, ncl, modes, moff_dev, labels, n, s));
+    }
+    FMS_HIP(wait_stream(s));
+    return MS_OK;
+}
+
 // Times each candidate R on private copies of the seeds; records the fastest.
 int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,
                       const int64_t* s_off, int ncl, int d, int trials, int32_t* best_R,
@@ -1130,6 +1303,20 @@ int ms_step_batched(const ms_params* p, const float* X, const int64_t* x_off, fl
     if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
     return step_batched_impl(p, X, x_off, seeds, s_off, ncl, d, n_iter, converged, iters, shift2,
                              (hipStream_t)stream, p->tile_R);
+}
+
+int ms_fit_batched(const ms_params* p, const float* X, const int64_t* x_off, int32_t ncl, int32_t d,
+                   float* modes, int64_t max_modes, int64_t* k_off, int32_t* labels, int32_t* rounds,
+                   void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_params(p, true));
+    FMS_CHECK(check_batched_args(p, X, x_off, x_off, ncl, d));
+    if (p->gamma != 1.0f) return fail(MS_E_INVALID, "ms_fit_batched runs every round to convergence: gamma must be 1");
+    if (!k_off) return fail(MS_E_INVALID, "k_off is NULL");
+    if (!modes) return fail(MS_E_INVALID, "modes is NULL");
+    if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");
+    if (x_off[ncl] == 0) return fail(MS_E_INVALID, "no cloud has points");
+    return fit_batched_impl(p, X, x_off, ncl, d, modes, max_modes, k_off, labels, rounds, (hipStream_t)stream);
 }
 
 int ms_tune_batched(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,

@@ -165,6 +165,19 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);
+// ---- whole method for many clouds (k_fit_batched.hip) ---------------------
+hipError_t launch_bf_iota(const long long* x_off, int ncl, int32_t* pool, long long n, hipStream_t s);
+hipError_t launch_bf_gather(const float* X, int d, const long long* x_off, const long long* s_off, int ncl,
+                            const int32_t* pos, const int32_t* pool, uint8_t* removed, float* seeds, int M,
+                            hipStream_t s);
+hipError_t launch_bf_cover(const float* X, int d, const long long* x_off, int ncl, const int32_t* pool,
+                           const int32_t* pool_len, const float* nm, const int32_t* m_off, float r2,
+                           uint8_t* removed, long long n, hipStream_t s);
+hipError_t launch_bf_compact(const long long* x_off, int ncl, const int32_t* pool_in, uint8_t* removed,
+                             int32_t* pool_len, int32_t* pool_out, hipStream_t s);
+hipError_t launch_bf_assign(const float* X, int d, const long long* x_off, int ncl, const float* modes,
+                            const int32_t* m_off, int32_t* labels, long long n, hipStream_t s);
+
 hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
 // One merge decision pass over a batch of B seeds (the first pass also
 // settles seeds that did not converge and seeds that join an old mode).

@@ -134,6 +134,15 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, None, so, 2, 2, 4, ctypes.byref(best), None,
                              None) == -1
     assert "seeds is NULL" in api.last_error()
+    kf = (ctypes.c_int64 * 3)()
+    pg = api.make_params(1.0, gamma=0.5)
+    assert L.ms_fit_batched(ctypes.byref(pg), FAKE, xo, 2, 2, FAKE, 10, kf, None, None, None) == -1
+    assert "gamma must be 1" in api.last_error()
+    assert L.ms_fit_batched(ctypes.byref(p), FAKE, xo, 2, 2, FAKE, 10, None, None, None, None) == -1
+    assert "k_off" in api.last_error()
+    zo = (ctypes.c_int64 * 3)(0, 0, 0)
+    assert L.ms_fit_batched(ctypes.byref(p), FAKE, zo, 2, 2, FAKE, 10, kf, None, None, None) == -1
+    assert "no cloud has points" in api.last_error()
     p.precision = api.PRECISIONS["bf16"]
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
                              None) == -1

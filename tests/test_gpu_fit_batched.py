@@ -1,0 +1,79 @@
+"""GPU parity of ms_fit_batched -- the whole method on many clouds at once
+-- against the FP64 oracle's fit of each cloud alone (cloud c draws with the
+SplitMix64 state rng_seed + c): the same mode count, the same modes in the
+same order, the same labels except at near-ties."""
+import sys
+
+import numpy as np
+import pytest
+
+from parity import MARGIN_TOL, MODE_TOL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2112_13891_amd import api, workloads  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _clouds(seed, sizes, d):
+    rng = np.random.default_rng(seed)
+    Xs = [workloads.cloud16(rng, n, d)[0] if n else np.zeros((0, d), np.float32) for n in sizes]
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    return Xs, xo
+
+
+def _compare(orc, Xs, xo, h, kernel, all_points, rng_seed, per, lab, k_off):
+    lab = lab.cpu().numpy() if lab is not None else None
+    for c, X in enumerate(Xs):
+        if len(X) == 0:
+            assert k_off[c + 1] == k_off[c]
+            continue
+        ref = orc.fit(X, h, kernel=kernel, all_points=all_points, rng_seed=rng_seed + c)
+        g = per[c].cpu().numpy().astype(np.float64)
+        assert len(g) == ref.k, (c, len(g), ref.k)
+        err = np.abs(g - ref.modes[:ref.k]).max()
+        assert err <= MODE_TOL * h, (c, err / h)
+        if lab is not None:
+            gl = lab[xo[c]:xo[c + 1]]
+            diff = np.nonzero(gl != ref.labels)[0]
+            assert (ref.margin[diff] < MARGIN_TOL * h).all(), (c, len(diff))
+
+
+@pytest.mark.parametrize("d", [2, 16])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_fit_batched_pool_matches_oracle_per_cloud(orc, d, kernel):
+    sizes = [300, 0, 2500, 1, 4100, 64, 1800]
+    Xs, xo = _clouds(10 * d + (kernel == "flat"), sizes, d)
+    say("fit_batched", d, kernel, sizes)
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0,
+                                              kernel=kernel, rng_seed=7)
+    torch.cuda.synchronize()
+    say("K per cloud", np.diff(k_off).tolist(), "rounds", rounds)
+    _compare(orc, Xs, xo, 1.0, kernel, False, 7, per, lab, k_off)
+
+
+def test_fit_batched_all_points_matches_oracle(orc):
+    sizes = [700, 5, 1500]
+    Xs, xo = _clouds(3, sizes, 3)
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0,
+                                              all_points=True)
+    torch.cuda.synchronize()
+    assert rounds == 1
+    _compare(orc, Xs, xo, 1.0, "gaussian", True, 0, per, lab, k_off)
+
+
+def test_fit_batched_capacity_reports_counts():
+    Xs, xo = _clouds(4, [400, 900], 2)
+    X = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    _, _, k_off, _ = api.fit_batched(X, xo, 1.0)
+    with pytest.raises(api.MeanShiftError) as e:
+        api.fit_batched(X, xo, 1.0, max_modes=1)
+    assert e.value.code == api.MS_E_CAPACITY and e.value.k == int(k_off[-1])
