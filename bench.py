@@ -236,6 +236,28 @@ def other_configs(api, torch, workloads):
         "pair_evals_per_iteration": pairs, "pair_evals_per_s": pairs / t_it,
         "per_cloud_calls_ms_per_iteration": t_pc * 1e3,
         "speedup_vs_per_cloud_calls": t_pc / t_it}
+    # the whole method on the 512 clouds in one call, beside one ms_fit per cloud
+    def fit_all():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per, lab, k_off, rounds = api.fit_batched(Xa, xo, 1.0)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, k_off, rounds
+
+    fit_all()
+    t_fb, k_off, rounds = min((fit_all() for _ in range(2)), key=lambda r: r[0])
+    Xc = [torch.from_numpy(x).cuda() for x in Xs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, x in enumerate(Xc):
+        api.fit(x, 1.0, rng_seed=c)
+    torch.cuda.synchronize()
+    t_pf = time.perf_counter() - t0
+    out["clouds16_fit_batched_fp32"] = {
+        "workload": "the 512 clouds above, whole method per cloud (pool seeding N0=128, L=8, merge/cover "
+                    "radius h, labels) in one ms_fit_batched call",
+        "ms_per_call": t_fb * 1e3, "rounds": rounds, "modes_total": int(k_off[-1]),
+        "per_cloud_fit_calls_ms": t_pf * 1e3, "speedup_vs_per_cloud_fits": t_pf / t_fb}
     # many small clouds, where the launches rather than the arithmetic set the
     # pace: whole-call time of 30 iterations launched eagerly and as one graph
     rng = np.random.default_rng(1)
