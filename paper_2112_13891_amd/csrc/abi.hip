@@ -897,10 +897,6 @@ TuneKey tune_key(int d, long long n, long long M, int ncl) {
     return TuneKey(step_shape(d).D, ilog2_ll(std::max(1LL, n / ncl)), ilog2_ll(std::max(1LL, M / ncl)));
 }
 
-// Batches of at least this many points (D = 16, 32) run the spatially
-// ordered, culled step.
-constexpr long long kBatchedSortMinPoints = 16384;
-
 // R_force = 0: the tuned shape for this kind of input, else seeds per lane
 // from the mean seeds per cloud (small clouds waste fewer lanes).  With
 // ev != NULL the iterations are bracketed by ev[0] and ev[1].
@@ -946,21 +942,6 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
     b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
-    if ((sh.D == 16 || sh.D == 32) && n >= kBatchedSortMinPoints) {
-        // every cloud's points in pivot order at the cloud's own rows, with
-        // block geometry: the step skips the blocks out of every seed's reach
-        float *Xs, *geom;
-        int32_t* perm;
-        char* sws;
-        FMS_CHECK(ws.alloc(&Xs, (size_t)n * sh.DP));
-        FMS_CHECK(ws.alloc(&perm, (size_t)n));
-        FMS_CHECK(ws.alloc(&geom, (size_t)((n + 255) / 256) * geom_stride(sh.D)));
-        FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n)));
-        FMS_HIP(launch_batched_sort(Xp, n, sh.DP, sh.D, xo_dev, ncl, Xs, perm, geom, sws, s));
-        b.Xs = Xs;
-        b.geom = geom;
-        b.shift = sort_frame_shift(sws);
-    }
     FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], M));
     FMS_CHECK(ws.alloc(&b.act[1], M));

@@ -165,10 +165,6 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);
-// Pivot order of the points of many clouds, each cloud at its own rows (D = 16, 32).
-hipError_t launch_batched_sort(const float* Xp, int n, int DP, int D, const long long* x_off_dev, int ncl,
-                               float* Xs, int* perm, float* geom, void* ws, hipStream_t s);
-
 // ---- whole method for many clouds (k_fit_batched.hip) ---------------------
 hipError_t launch_bf_iota(const long long* x_off, int ncl, int32_t* pool, long long n, hipStream_t s);
 hipError_t launch_bf_gather(const float* X, int d, const long long* x_off, const long long* s_off, int ncl,

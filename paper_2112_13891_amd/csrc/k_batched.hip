@@ -27,11 +27,6 @@ namespace fms {
 namespace {
 
 constexpr int kPlanThreads = 1024;
-// culling thresholds of the spatially ordered step, in packed units (as the
-// single-cloud culled step): exp2(-q) is exactly +0 in FP32 from q = 150 on;
-// the flat window ends at h^2 (a margin covers the bound's rounding)
-constexpr float kBatchedCullGauss = 160.0f;
-constexpr float kBatchedCullFlatMargin = 1.001f;
 constexpr int kChunkPoints = 1024;
 constexpr int kBStepGrid = 2048;
 
@@ -177,104 +172,6 @@ __global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs
     }
 }
 
-// The step over spatially ordered points (D = 16, 32; points of every cloud
-// at the cloud's own rows, in pivot order, shifted by the batch frame; the
-// seeds take the same shift).  A work item's chunk is the same row range as
-// bstep_kernel's; the 256-row blocks overlapping it whose rows all lie beyond
-// the weights' reach for every seed of the tile (bound |s - c| - R per seed,
-// as in the single-cloud culled step) are skipped -- their pairs add exact
-// zeros -- and each wave streams its 64 rows of a live block, clipped to the
-// chunk, through scalar loads.  The four wave sums are added in wave order.
-constexpr int kBCullBlk = 256;
-
-template <int D, int KERN>
-__global__ __launch_bounds__(kThreads) void bstep_cull_kernel(StepArgs a, BatchedArgs B, const float* __restrict__ geom,
-                                                             const float* __restrict__ shift, float qcull) {
-    constexpr int TS = 64;
-    constexpr int GS = D + 8;   // geometry row: centre[0..D), radius at [D]
-    const int total = B.item_pre[B.ncl];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    __shared__ float red[(kWaves - 1) * TS * (D + 1)];
-    const const_f32_ptr xq = wave_uniform_const(a.Xp);
-    const const_f32_ptr gq = wave_uniform_const(geom);
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
-        const int c = B.item_cloud[it];
-        const int local = it - B.item_pre[c];
-        const int tiles = B.tiles[c], chunks = B.chunks[c];
-        const int tile = local % tiles, chunk = local / tiles;
-        const long long x0 = B.x_off[c];
-        const long long n = B.x_off[c + 1] - x0;
-        const int m = B.slot_pre[c + 1] - B.slot_pre[c];
-        // the chunk's rows [lo, hi), uniform over the workgroup
-        const long long lo = wave_uniform(x0 + n * chunk / chunks);
-        const long long hi = wave_uniform(x0 + n * (chunk + 1) / chunks);
-        float s[D], acc[D + 1];
-        const int slot = tile * TS + lane;
-        const bool live = slot < m;
-        {
-            const int j = a.act_in[B.seg[c] + (live ? slot : tile * TS)];
-#pragma unroll
-            for (int k = 0; k < D; ++k) s[k] = a.S[(long long)j * D + k] * a.scale - shift[k];
-#pragma unroll
-            for (int k = 0; k <= D; ++k) acc[k] = 0.0f;
-        }
-        auto pair = [&](const float (&x)[D]) {
-            float dx[D];
-            float q = 0.0f;
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                dx[k] = x[k] - s[k];
-                q = fmaf(dx[k], dx[k], q);
-            }
-            float w;
-            if (KERN == MS_KERNEL_GAUSSIAN)
-                w = __builtin_amdgcn_exp2f(-q);
-            else
-                w = (q <= a.h2) ? 1.0f : 0.0f;
-            acc[D] += w;
-#pragma unroll
-            for (int k = 0; k < D; ++k) acc[k] = fmaf(w, dx[k], acc[k]);
-        };
-        if (hi > lo) {
-            const int b0 = (int)(lo / kBCullBlk), b1 = (int)((hi - 1) / kBCullBlk) + 1;
-            for (int blk = b0; blk < b1; ++blk) {
-                const const_f32_ptr gm = gq + (long long)blk * GS;
-                float d2 = 0.0f;
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const float u = s[k] - gm[k];
-                    d2 = fmaf(u, u, d2);
-                }
-                const float lb = sqrtf(d2) - gm[D];
-                const bool near = live && !(lb > 0.0f && lb * lb > qcull);
-                if (!__ballot(near)) continue;   // every wave holds the same seeds: uniform
-                const long long r0 = (long long)blk * kBCullBlk + wave * (kBCullBlk / kWaves);
-                const long long p0 = r0 > lo ? r0 : lo;
-                const long long r1 = r0 + kBCullBlk / kWaves;
-                const long long p1 = r1 < hi ? r1 : hi;
-                if (p1 > p0) stream_rows<D, D>(xq + p0 * D, (int)(p1 - p0), pair);
-            }
-        }
-        // the four wave sums added in wave order
-        if (wave > 0) {
-#pragma unroll
-            for (int k = 0; k <= D; ++k) red[(wave - 1) * TS * (D + 1) + k * TS + lane] = acc[k];
-        }
-        __syncthreads();
-        if (wave == 0) {
-#pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                float v = acc[k];
-#pragma unroll
-                for (int w2 = 1; w2 < kWaves; ++w2) v += red[(w2 - 1) * TS * (D + 1) + k * TS + lane];
-                a.part[((long long)it * TS + lane) * (D + 1) + k] = v;
-            }
-        }
-        __syncthreads();
-    }
-}
-
 template <int D, int DP, int R>
 __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, BatchedArgs B, int t) {
     constexpr int TS = 64 * R;
@@ -350,22 +247,6 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     // no more workgroups than the first iteration has work items (seeds only
     // ever leave the active lists)
     const int grid = std::max(1, std::min(kBStepGrid, b.grid));
-    if constexpr (D == 16 || D == 32) {
-        if (b.geom) {   // spatially ordered points: the culled step
-            static_assert(R == 1 && DP == D, "the culled batched step holds one seed per lane");
-            a.Xp = b.Xs;
-            if (b.kernel == MS_KERNEL_GAUSSIAN)
-                hipLaunchKernelGGL((bstep_cull_kernel<D, MS_KERNEL_GAUSSIAN>), dim3(grid), dim3(kThreads), 0, s,
-                                   a, B, b.geom, b.shift, kBatchedCullGauss);
-            else
-                hipLaunchKernelGGL((bstep_cull_kernel<D, MS_KERNEL_FLAT>), dim3(grid), dim3(kThreads), 0, s, a,
-                                   B, b.geom, b.shift, a.h2 * kBatchedCullFlatMargin);
-            int fb = (b.n_seeds + kFinThreads - 1) / kFinThreads;
-            fb = fb < 1 ? 1 : (fb > 1024 ? 1024 : fb);
-            hipLaunchKernelGGL((bfinal_kernel<D, DP, R>), dim3(fb), dim3(kFinThreads), 0, s, a, B, t);
-            return hipGetLastError();
-        }
-    }
     if (b.kernel == MS_KERNEL_GAUSSIAN)
         hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(grid), dim3(kThreads),
                            0, s, a, B);

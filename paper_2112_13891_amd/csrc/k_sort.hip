@@ -558,48 +558,6 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
     return hipGetLastError();
 }
 
-// Batched clouds (cloud c = rows x_off[c] .. x_off[c+1]): the cloud index
-// goes above the nearest-pivot key, keys[i] = c << 19 | pivot << 9 | the top
-// 9 distance bits, so that the sort keeps every cloud at its own rows and
-// orders each cloud by the pivots of the whole batch.
-__global__ void cloud_key_kernel(const long long* __restrict__ x_off, int ncl, int n, unsigned* keys) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int lo = 0, hi = ncl;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (x_off[mid] <= i) lo = mid;
-        else hi = mid;
-    }
-    keys[i] = ((unsigned)lo << 19) | ((keys[i] >> 5) & 0x7FFFFu);
-}
-
-// Spatial order of the points of many clouds (D = 8, 16, 32): as
-// launch_spatial_sort's pivot order, each cloud's points staying at the rows
-// of that cloud (x_off_dev on the device, ncl <= 8192).  Blocks of 256 rows
-// may straddle two clouds; their geometry covers all their rows.
-hipError_t launch_batched_sort(const float* Xp, int n, int DP, int D, const long long* x_off_dev, int ncl,
-                               float* Xs, int* perm, float* geom, void* ws, hipStream_t s) {
-    const SortWs w = carve(ws, n);
-    const int bblocks = 256;
-    hipLaunchKernelGGL(bounds_kernel, dim3(bblocks), dim3(256), 0, s, Xp, n, DP, D, w.bnd);
-    hipLaunchKernelGGL(bounds_final_kernel, dim3(1), dim3(256), 0, s, w.bnd, D, bblocks);
-    float* sh = w.bnd + kShiftOff;
-    hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(64), 0, s, w.bnd, D, sh);
-    const int P = pivot_count(n);
-    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
-                                            s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, w.k0, w.v0));
-    hipLaunchKernelGGL(cloud_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, x_off_dev, ncl, n, w.k0);
-    const int* sorted = radix_sort_pairs(w, n, s, 4);
-    hipError_t e = hipMemcpyAsync(perm, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),
-                       0, s, Xp, DP, D, perm, n, sh, Xs);
-    hipLaunchKernelGGL(block_geom_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xs, n, DP, D,
-                       geom_stride(D), geom);
-    return hipGetLastError();
-}
-
 const float* sort_frame_shift(const void* ws) {
     return (const float*)ws + kShiftOff;
 }

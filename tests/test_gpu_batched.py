@@ -207,26 +207,3 @@ def test_batched_full_size_sampled(orc):
         ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), 1.0, "gaussian", tol=1e-3, n_iter=3)
         say("cloud", c, "n", len(Xs[c]))
         ragged_check(Xs[c], Ss[c], 1.0, "gaussian", 3, S[a:b], it[a:b], ref, oit)
-
-
-@pytest.mark.parametrize("d", [16, 32])
-@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
-def test_batched_sorted_culled_step(orc, d, kernel):
-    """From 16,384 points on (D = 16, 32) the batched step orders every
-    cloud's points by the batch's pivots, at the cloud's own rows, and skips
-    the 256-row blocks out of every seed's reach; ragged clouds (1 point,
-    empty, not multiples of 256) share blocks.  Each cloud against the oracle."""
-    sizes = [5000, 1, 0, 2047, 7000, 300, 4100, 2500]
-    Xs, Ss, xo, so = _batch(60 + d + (kernel == "flat"), sizes, d, max_seeds=200)
-    assert xo[-1] >= 16384
-    h = 1.0
-    for n_iter in (1, 4):
-        S, conv, it, sh = _run(Xs, Ss, xo, so, h, kernel, n_iter)
-        torch.cuda.synchronize()
-        S, it = S.cpu().numpy(), it.cpu().numpy()
-        for c in range(len(Xs)):
-            a, b = so[c], so[c + 1]
-            if a == b:
-                continue
-            ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
-            ragged_check(Xs[c], Ss[c], h, kernel, n_iter, S[a:b], it[a:b], ref, oit)
