@@ -103,8 +103,8 @@ typedef struct {
                                  ignore it */
     int32_t tile_R;           /* ms_step_batched: seeds per lane of a seed
                                  tile (1, 2 or 4, as the padded dimension
-                                 allows: D <= 4 any, D = 8 1 or 2, D >= 16
-                                 1); 0 = the shape ms_tune_batched chose for
+                                 allows: D <= 4 any, D = 8 or 16 1 or 2,
+                                 D >= 32 1); 0 = the shape ms_tune_batched chose for
                                  inputs of this kind, else a default.  The
                                  results do not depend on it */
     int32_t plain;            /* ms_fit, ms_step with MS_PREC_FP32: 1 = the

@@ -873,7 +873,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
 // Seeds per lane that the batched step is built for, by padded dimension.
 bool batched_R_ok(int D, int R) {
     if (R == 1) return true;
-    if (R == 2) return D <= 8;
+    if (R == 2) return D <= 16;
     if (R == 4) return D <= 4;
     return false;
 }

@@ -306,7 +306,7 @@ hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, 
     FMS_BCASE(3, 4, 1) FMS_BCASE(3, 4, 2) FMS_BCASE(3, 4, 4)
     FMS_BCASE(4, 4, 1) FMS_BCASE(4, 4, 2) FMS_BCASE(4, 4, 4)
     FMS_BCASE(8, 8, 1) FMS_BCASE(8, 8, 2)
-    FMS_BCASE(16, 16, 1) FMS_BCASE(32, 32, 1) FMS_BCASE(64, 64, 1)
+    FMS_BCASE(16, 16, 1) FMS_BCASE(16, 16, 2) FMS_BCASE(32, 32, 1) FMS_BCASE(64, 64, 1)
 #undef FMS_BCASE
     return hipErrorInvalidValue;
 }

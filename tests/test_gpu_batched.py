@@ -151,7 +151,7 @@ def test_batched_graph_matches_eager_launches():
             del junk
 
 
-@pytest.mark.parametrize("d,Rs", [(2, (1, 2, 4)), (8, (1, 2)), (16, (1,))])
+@pytest.mark.parametrize("d,Rs", [(2, (1, 2, 4)), (8, (1, 2)), (16, (1, 2)), (32, (1,))])
 def test_batched_tile_shapes_give_identical_results(d, Rs):
     """The seeds per lane change how seeds share a workgroup, never the order
     in which a seed's sums are formed: every shape gives the same bits."""
