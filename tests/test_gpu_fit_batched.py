@@ -77,3 +77,18 @@ def test_fit_batched_capacity_reports_counts():
     with pytest.raises(api.MeanShiftError) as e:
         api.fit_batched(X, xo, 1.0, max_modes=1)
     assert e.value.code == api.MS_E_CAPACITY and e.value.k == int(k_off[-1])
+
+
+def test_fit_batched_wide_rows_match_oracle(orc):
+    sizes = [900, 2200, 40]
+    Xs, xo = _clouds(21, sizes, 32)
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0, rng_seed=3)
+    torch.cuda.synchronize()
+    _compare(orc, Xs, xo, 1.0, "gaussian", False, 3, per, lab, k_off)
+
+
+def test_fit_batched_no_converged_seed_is_an_error():
+    Xs, xo = _clouds(5, [500, 700], 2)
+    with pytest.raises(api.MeanShiftError) as e:
+        api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0, max_iter=1, tol=1e-9)
+    assert e.value.code == api.MS_E_NO_MODES
