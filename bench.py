@@ -340,7 +340,7 @@ def main():
                          "fits per precision; both for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is described, not built)"}))
         sys.exit(2)
 

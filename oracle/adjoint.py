@@ -5,7 +5,7 @@ float64, autograd for the derivative; nothing here is shared with the HIP
 library.
 
 One Gaussian update of every seed over all points (Section II-B, the batched
-update; Gaussian profile exp(-q / (2 h^2)) as read for this build):
+update; Gaussian profile exp(-q / (2 h^2)), the reading of the kernel used throughout):
     m(s_j) = sum_i w_ij x_i / sum_i w_ij,   w_ij = exp(-|s_j - x_i|^2 / (2 h^2)).
 The unrolled form starts from S_0 = X and applies T updates; the loss of the
 differentiable benchmark is sum_p |S_T[p] - c_{y_p}|^2 (each shifted point

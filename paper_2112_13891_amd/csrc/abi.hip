@@ -470,6 +470,20 @@ float bf16_e_thr(const ms_params* p, int D) {
     return -(float)(rr * rr);
 }
 
+// Distance (original units) within which the BF16 form computes every pair
+// exactly in FP32: its refine threshold.  Directions are at most a chord of 2
+// apart, so for the cosine metric a reach of 2 or more means every pair is
+// computed exactly -- the plain FP32 step, which then runs in its place.
+double bf16_exact_reach(const ms_params* p, int D) {
+    const double e = -(double)bf16_e_thr(p, D);
+    return std::sqrt(std::max(0.0, e)) / (double)packed_scale(p);
+}
+
+bool bf16_form(const ms_params* p, int d) {
+    if (p->precision != MS_PREC_BF16_REFINE) return false;
+    return !(p->metric == MS_METRIC_COSINE && bf16_exact_reach(p, step_shape(d).D) >= 2.0);
+}
+
 struct SortedPoints {
     float* Xs = nullptr;
     int32_t* perm = nullptr;
@@ -481,7 +495,7 @@ struct SortedPoints {
 void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_params* p,
                 float scale, const float* Xp, Ctl* ctl, const SortedPoints* sp = nullptr) {
     const float tolh = p->tol * p->h;
-    b.prec = p->precision;
+    b.prec = bf16_form(p, d) ? MS_PREC_BF16_REFINE : MS_PREC_FP32;   // the form that runs
     b.Xs = sp ? sp->Xs : nullptr;
     b.geom = sp ? sp->geom : nullptr;
     b.pf = sp ? sp->feat : nullptr;
@@ -550,7 +564,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     float* Xp;
     FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_HIP(launch_pack_points(X, n, d, DP, scale, Xp, s));
-    const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
+    const bool bf16 = bf16_form(p, d);
     // FP32 on enough points: spatially ordered points and block culling
     // (directions are at most 2 apart: nothing to cull when the reach is 2)
     const bool cull = !bf16 && !p->plain && cull_supported(d, n) &&
@@ -817,7 +831,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
               uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
-    const bool bf16 = p->precision == MS_PREC_BF16_REFINE;
+    const bool bf16 = bf16_form(p, d);
     const bool cull = !bf16 && !p->plain && cull_supported(d, n) &&
                       !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
     const bool sorted = bf16 || cull;
@@ -1274,7 +1288,7 @@ int ms_fit(const ms_params* p, const float* X, int64_t n, int32_t d, float* mode
     if (!k_out) return fail(MS_E_INVALID, "k_out is NULL");
     if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32 in this build");
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32");
     *k_out = 0;
     return fit_impl(p, X, (int)n, d, modes, max_modes, k_out, labels, diag, (hipStream_t)stream);
 }
@@ -1289,7 +1303,7 @@ int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* see
     if (m == 0) return MS_OK;
     if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
-        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32 in this build");
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32");
     return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
 }
 
