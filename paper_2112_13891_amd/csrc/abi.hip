@@ -189,9 +189,11 @@ thread_local Pinned g_pin_ctl, g_pin_pos, g_pin_rb, g_pin_modes;
 
 
 int ensure_pool_release_threshold() {
+    static std::mutex mu;
     static bool done[64] = {};
     int dev = 0;
     FMS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
     if (dev >= 0 && dev < 64 && !done[dev]) {
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -1000,7 +1002,9 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     return MS_OK;
 }
 
-thread_local Pinned g_pin_bpos, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_blen;
+// Host staging of ms_fit_batched, sized by each round's seeds and modes
+// (grown on demand, kept for the thread).
+thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_bmoff, g_pin_blen;
 
 // The whole method (Algorithm 2 with the seed pool of Section II-D; with
 // all_points_as_seeds, Algorithm 1) for every cloud of a CSR batch, the
@@ -1038,18 +1042,11 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     FMS_CHECK(ws.alloc(&S_dev, (size_t)n * d));
     FMS_CHECK(ws.alloc(&sh2_dev, (size_t)n));
     FMS_CHECK(ws.alloc(&nm_dev, (size_t)n * d));
-    const size_t pos_bytes = ((size_t)n * 4 + 7) / 8 * 8;   // the seed offsets follow, 8-byte aligned
-    FMS_CHECK(g_pin_bpos.ensure(pos_bytes + (size_t)(ncl + 1) * 8));
-    FMS_CHECK(g_pin_bseeds.ensure((size_t)n * d * 4));
-    FMS_CHECK(g_pin_bconv.ensure((size_t)n));
-    FMS_CHECK(g_pin_bmodes.ensure((size_t)n * d * 4 + (size_t)(ncl + 1) * 4));
+    FMS_CHECK(g_pin_bso.ensure((size_t)(ncl + 1) * 8));
+    FMS_CHECK(g_pin_bmoff.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_blen.ensure((size_t)ncl * 4));
-    int32_t* hpos = (int32_t*)g_pin_bpos.p;
-    int64_t* hso = (int64_t*)((char*)g_pin_bpos.p + pos_bytes);
-    float* hS = (float*)g_pin_bseeds.p;
-    uint8_t* hconv = (uint8_t*)g_pin_bconv.p;
-    float* hnm = (float*)g_pin_bmodes.p;
-    int32_t* hmoff = (int32_t*)(hnm + (size_t)n * d);
+    int64_t* hso = (int64_t*)g_pin_bso.p;
+    int32_t* hmoff = (int32_t*)g_pin_bmoff.p;
     int32_t* hlen = (int32_t*)g_pin_blen.p;
 
     std::vector<long long> xo(x_off, x_off + ncl + 1);
@@ -1074,22 +1071,29 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     constexpr int kChunk = 4;   // iterations between checks for a finished round
     int cur = 0, rounds = 0;
     for (;;) {
-        // draws
+        // draws (the staging buffers hold no copy in flight: every round ends
+        // with a wait on the stream)
         int64_t M = 0;
         hso[0] = 0;
         for (int c = 0; c < ncl; ++c) {
-            int32_t B = 0;
-            if (active[c]) {
-                B = all ? plen[c] : (int32_t)std::min<long long>(N[c], plen[c]);
-                if (all)
-                    for (int32_t t = 0; t < B; ++t) hpos[M + t] = t;
-                else
-                    draw_positions(&rng[c], plen[c], B, hpos + M);
-            }
-            M += B;
+            if (active[c]) M += all ? plen[c] : (int32_t)std::min<long long>(N[c], plen[c]);
             hso[c + 1] = M;
         }
         if (M == 0) break;
+        FMS_CHECK(g_pin_bpos.ensure((size_t)M * 4));
+        FMS_CHECK(g_pin_bseeds.ensure((size_t)M * d * 4));
+        FMS_CHECK(g_pin_bconv.ensure((size_t)M));
+        int32_t* hpos = (int32_t*)g_pin_bpos.p;
+        float* hS = (float*)g_pin_bseeds.p;
+        uint8_t* hconv = (uint8_t*)g_pin_bconv.p;
+        for (int c = 0; c < ncl; ++c) {
+            const int32_t B = (int32_t)(hso[c + 1] - hso[c]);
+            if (B == 0) continue;
+            if (all)
+                for (int32_t t = 0; t < B; ++t) hpos[hso[c] + t] = t;
+            else
+                draw_positions(&rng[c], plen[c], B, hpos + hso[c]);
+        }
         FMS_HIP(hipMemcpyAsync(pos_dev, hpos, (size_t)M * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(hipMemcpyAsync(so_dev, hso, (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
         FMS_HIP(launch_bf_gather(X, d, xo_dev, so_dev, ncl, pos_dev, pool[cur], removed, S_dev, (int)M, s));
@@ -1112,8 +1116,9 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         // merge, cloud by cloud, in draw order
         long long nm = 0;
         hmoff[0] = 0;
+        std::vector<size_t> k_old(ncl);
         for (int c = 0; c < ncl; ++c) {
-            const size_t K_old = cm[c].size() / d;
+            k_old[c] = cm[c].size() / d;
             for (long long g = hso[c]; g < hso[c + 1]; ++g) {
                 if (hconv[g] != ST_CONVERGED) continue;
                 const float* sg = hS + (size_t)g * d;
@@ -1122,12 +1127,16 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
                     joined = host_dist2(sg, cm[c].data() + j * d, d) <= r2m;
                 if (!joined) cm[c].insert(cm[c].end(), sg, sg + d);
             }
-            const size_t K_new = cm[c].size() / d;
-            for (size_t j = K_old; j < K_new; ++j, ++nm)
-                std::memcpy(hnm + (size_t)nm * d, cm[c].data() + j * d, (size_t)d * 4);
+            nm += (long long)(cm[c].size() / d - k_old[c]);
             hmoff[c + 1] = (int32_t)nm;
         }
         if (all) break;
+        // the round's new modes, cloud after cloud
+        FMS_CHECK(g_pin_bmodes.ensure((size_t)std::max(1LL, nm) * d * 4));
+        float* hnm = (float*)g_pin_bmodes.p;
+        for (int c = 0; c < ncl; ++c)
+            std::memcpy(hnm + (size_t)hmoff[c] * d, cm[c].data() + k_old[c] * d,
+                        (cm[c].size() - k_old[c] * d) * 4);
         // pools: coverage by the new modes, compaction, seed-count control
         FMS_HIP(hipMemcpyAsync(nm_dev, hnm, (size_t)std::max(1LL, nm) * d * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
@@ -1159,6 +1168,8 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     if (K > max_modes) return fail(MS_E_CAPACITY, "more modes than max_modes (k_off holds the required counts)");
     for (int c = 0; c < ncl; ++c)
         if (x_off[c + 1] > x_off[c] && cm[c].empty()) return fail(MS_E_NO_MODES, "a cloud has no converged seed");
+    FMS_CHECK(g_pin_bmodes.ensure((size_t)std::max(1LL, K) * d * 4));
+    float* hnm = (float*)g_pin_bmodes.p;
     for (int c = 0; c < ncl; ++c) {
         std::memcpy(hnm + (size_t)k_off[c] * d, cm[c].data(), cm[c].size() * 4);
         hmoff[c] = (int32_t)k_off[c];

@@ -92,3 +92,21 @@ def test_fit_batched_no_converged_seed_is_an_error():
     with pytest.raises(api.MeanShiftError) as e:
         api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0, max_iter=1, tol=1e-9)
     assert e.value.code == api.MS_E_NO_MODES
+
+
+def test_fit_batched_repeated_calls_are_reproducible():
+    # a larger batch between two equal calls: the host staging grows, and the
+    # second small call must give bitwise the first one's result
+    small, xo_s = _clouds(6, [300, 800], 2)
+    big, xo_b = _clouds(7, [5000, 3000, 4000], 2)
+    Xs = torch.from_numpy(np.concatenate(small)).to(DEV)
+    Xb = torch.from_numpy(np.concatenate(big)).to(DEV)
+    first = api.fit_batched(Xs, xo_s, 1.0, rng_seed=5)
+    mid = api.fit_batched(Xb, xo_b, 1.0, rng_seed=5)
+    again = api.fit_batched(Xs, xo_s, 1.0, rng_seed=5)
+    torch.cuda.synchronize()
+    assert int(mid[2][-1]) > 0
+    assert np.array_equal(first[2], again[2]) and first[3] == again[3]
+    for a, b in zip(first[0], again[0]):
+        assert torch.equal(a, b)
+    assert torch.equal(first[1], again[1])
