@@ -924,6 +924,14 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     const int n = (int)x_off[ncl];
     const int M = (int)s_off[ncl];
     StepShape sh = step_shape_for(d, std::max(1, M / ncl));
+    // default: at most two seeds per lane up to D = 8 and one above (timed on
+    // 512 uneven clouds: more seeds per lane cost occupancy here, and the
+    // work queue already balances the items)
+    const int r_cap = sh.D <= 8 ? 2 : 1;
+    if (sh.R > r_cap) {
+        sh.R = r_cap;
+        sh.TS = 64 * r_cap;
+    }
     int R = R_force;
     if (R == 0) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -966,7 +974,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_CHECK(ws.alloc(&b.shift2, M));
     int32_t *cnt, *plan, *item_cloud, *slot_cloud;
     FMS_CHECK(ws.alloc(&cnt, (size_t)2 * ncl));
-    FMS_CHECK(ws.alloc(&plan, (size_t)4 * ncl + 2));
+    FMS_CHECK(ws.alloc(&plan, (size_t)4 * ncl + 3));   // + the work-item queue head
     FMS_CHECK(ws.alloc(&item_cloud, (size_t)std::max(1LL, max_items)));
     FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
     FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));

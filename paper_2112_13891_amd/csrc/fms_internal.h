@@ -146,6 +146,8 @@ int batched_max_clouds();
 long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS);
 hipError_t launch_batched_init(const float* seeds, const uint8_t* conv_in, int d, int M,
                                const int32_t* seg_dev, int ncl, int32_t* cnt, Batch& b, hipStream_t s);
+// plan: 4 ncl + 3 ints of device scratch (per-cloud tiles, chunks, item and
+// slot prefixes, the work-item queue head)
 hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, const int32_t* seg_dev,
                                     int ncl, int32_t* cnt, int32_t* plan, int32_t* item_cloud,
                                     int32_t* slot_cloud, int t, hipStream_t s);

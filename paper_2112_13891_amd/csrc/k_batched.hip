@@ -12,8 +12,10 @@
 //            the prefix of work items and of active slots, and for every
 //            work item and active slot its cloud;
 //   step     a persistent grid over the work items (cloud, seed tile, point
-//            chunk), the same pair loop as the single-cloud step, one
-//            (D+1)-vector partial per seed and item;
+//            chunk), taken from a queue (one atomic per item and workgroup,
+//            so that uneven items and late-starting workgroups balance), the
+//            same pair loop as the single-cloud step, one (D+1)-vector
+//            partial per seed and item;
 //   finalize one lane per active seed: its chunk partials added in chunk
 //            order, the update and convergence test, and the seed kept in
 //            its cloud's next active list (per-cloud counter).
@@ -41,6 +43,7 @@ struct BatchedArgs {
     int32_t* slot_pre;        // ncl + 1
     int32_t* item_cloud;      // cloud of each work item
     int32_t* slot_cloud;      // cloud of each active slot
+    int32_t* queue;           // next work item to take (zeroed by the plan)
 };
 
 __device__ __forceinline__ int upper_cloud(const int32_t* pre, int ncl, int v) {
@@ -133,6 +136,7 @@ __global__ __launch_bounds__(kPlanThreads) void bplan_kernel(BatchedArgs B, int 
     if (threadIdx.x == 0) {
         ipre[B.ncl] = icarry;
         spre[B.ncl] = scarry;
+        *B.queue = 0;
     }
     __syncthreads();
     for (int c = threadIdx.x; c <= B.ncl; c += kPlanThreads) {
@@ -150,7 +154,14 @@ __global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     __shared__ float red[(kWaves - 1) * TS * (D + 1)];
-    for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    __shared__ int next_item;
+    for (;;) {
+        // every thread has read the previous item (the pair loop below holds
+        // barriers) before thread 0 writes the next one
+        if (threadIdx.x == 0) next_item = atomicAdd(B.queue, 1);
+        __syncthreads();
+        const int it = next_item;
+        if (it >= total) break;
         const int c = B.item_cloud[it];
         const int local = it - B.item_pre[c];
         const int tiles = B.tiles[c], chunks = B.chunks[c];
@@ -186,7 +197,23 @@ __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, Batched
         float v[D + 1];
 #pragma unroll
         for (int k = 0; k <= D; ++k) v[k] = 0.0f;
-        for (int ch = 0; ch < chunks; ++ch) {
+        // chunk order; the loads of four chunks in flight together
+        constexpr int U = D <= 16 ? 4 : 1;
+        int ch = 0;
+        for (; ch + U <= chunks; ch += U) {
+            float tmp[U][D + 1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float* p = a.part + ((long long)(ib + (ch + u) * tiles + tile) * TS + pos) * (D + 1);
+#pragma unroll
+                for (int k = 0; k <= D; ++k) tmp[u][k] = p[k];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k <= D; ++k) v[k] += tmp[u][k];
+        }
+        for (; ch < chunks; ++ch) {
             const float* p = a.part + ((long long)(ib + ch * tiles + tile) * TS + pos) * (D + 1);
 #pragma unroll
             for (int k = 0; k <= D; ++k) v[k] += p[k];
@@ -298,6 +325,7 @@ hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, 
     B.slot_pre = plan + 3 * ncl + 1;
     B.item_cloud = item_cloud;
     B.slot_cloud = slot_cloud;
+    B.queue = plan + 4 * ncl + 2;
     const int D = b.sh.D, R = b.sh.R;
 #define FMS_BCASE(DD, DPP, RR) \
     if (D == DD && R == RR) return bstep_t<DD, DPP, RR>(b, B, t, s);
