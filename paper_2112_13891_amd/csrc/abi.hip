@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fms_internal.h"
@@ -1010,6 +1011,73 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     return MS_OK;
 }
 
+// Runs f(c) for every cloud c, on up to 16 host threads when the round has
+// enough work (clouds are taken from a shared counter; each cloud's work is
+// sequential, so the results do not depend on the thread count).  If a thread
+// cannot be started the ones running finish the clouds.
+template <class F>
+void for_each_cloud(int ncl, long long work, F&& f) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1u, 16u);
+    nt = std::min(nt, ncl);
+    if (work < (1LL << 14) || nt <= 1) {
+        for (int c = 0; c < ncl; ++c) f(c);
+        return;
+    }
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        for (int c = next.fetch_add(1); c < ncl; c = next.fetch_add(1)) f(c);
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; ++i) {
+        try {
+            th.emplace_back(worker);
+        } catch (...) {
+            break;
+        }
+    }
+    worker();
+    for (auto& t : th) t.join();
+}
+
+// Greedy merge of one cloud's seeds g0..g1 (draw order) into its modes: a
+// converged seed joins the first mode within r2m (squared), else it becomes
+// a new mode.  FP32 distances with fused multiply-adds, as on the device; the
+// FMA form is compiled for CPUs that have the instruction (the same results,
+// without a call per multiply-add).
+__attribute__((always_inline)) inline void merge_cloud_body(const float* hS, const uint8_t* hconv, long long g0,
+                                                             long long g1, int d, float r2m,
+                                                             std::vector<float>& modes) {
+    for (long long g = g0; g < g1; ++g) {
+        if (hconv[g] != ST_CONVERGED) continue;
+        const float* sg = hS + (size_t)g * d;
+        const size_t K = modes.size() / d;
+        bool joined = false;
+        for (size_t j = 0; j < K && !joined; ++j) {
+            const float* mj = modes.data() + j * d;
+            float q = 0.0f;
+            for (int k = 0; k < d; ++k) {
+                const float t = sg[k] - mj[k];
+                q = __builtin_fmaf(t, t, q);
+            }
+            joined = q <= r2m;
+        }
+        if (!joined) modes.insert(modes.end(), sg, sg + d);
+    }
+}
+
+__attribute__((target("fma"))) void merge_cloud_fma(const float* hS, const uint8_t* hconv, long long g0,
+                                                    long long g1, int d, float r2m, std::vector<float>& modes) {
+    merge_cloud_body(hS, hconv, g0, g1, d, r2m, modes);
+}
+
+void merge_cloud(const float* hS, const uint8_t* hconv, long long g0, long long g1, int d, float r2m,
+                 std::vector<float>& modes) {
+    static const bool fma = __builtin_cpu_supports("fma");
+    if (fma) merge_cloud_fma(hS, hconv, g0, g1, d, r2m, modes);
+    else merge_cloud_body(hS, hconv, g0, g1, d, r2m, modes);
+}
+
 // Host staging of ms_fit_batched, sized by each round's seeds and modes
 // (grown on demand, kept for the thread).
 thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_bmoff, g_pin_blen;
@@ -1094,14 +1162,14 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         int32_t* hpos = (int32_t*)g_pin_bpos.p;
         float* hS = (float*)g_pin_bseeds.p;
         uint8_t* hconv = (uint8_t*)g_pin_bconv.p;
-        for (int c = 0; c < ncl; ++c) {
+        for_each_cloud(ncl, M, [&](int c) {
             const int32_t B = (int32_t)(hso[c + 1] - hso[c]);
-            if (B == 0) continue;
+            if (B == 0) return;
             if (all)
                 for (int32_t t = 0; t < B; ++t) hpos[hso[c] + t] = t;
             else
                 draw_positions(&rng[c], plen[c], B, hpos + hso[c]);
-        }
+        });
         FMS_HIP(hipMemcpyAsync(pos_dev, hpos, (size_t)M * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(hipMemcpyAsync(so_dev, hso, (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
         FMS_HIP(launch_bf_gather(X, d, xo_dev, so_dev, ncl, pos_dev, pool[cur], removed, S_dev, (int)M, s));
@@ -1122,19 +1190,12 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         FMS_HIP(wait_stream(s));
         rounds += 1;
         // merge, cloud by cloud, in draw order
+        std::vector<size_t> k_old(ncl);
+        for (int c = 0; c < ncl; ++c) k_old[c] = cm[c].size() / d;
+        for_each_cloud(ncl, M, [&](int c) { merge_cloud(hS, hconv, hso[c], hso[c + 1], d, r2m, cm[c]); });
         long long nm = 0;
         hmoff[0] = 0;
-        std::vector<size_t> k_old(ncl);
         for (int c = 0; c < ncl; ++c) {
-            k_old[c] = cm[c].size() / d;
-            for (long long g = hso[c]; g < hso[c + 1]; ++g) {
-                if (hconv[g] != ST_CONVERGED) continue;
-                const float* sg = hS + (size_t)g * d;
-                bool joined = false;
-                for (size_t j = 0; j < cm[c].size() / d && !joined; ++j)
-                    joined = host_dist2(sg, cm[c].data() + j * d, d) <= r2m;
-                if (!joined) cm[c].insert(cm[c].end(), sg, sg + d);
-            }
             nm += (long long)(cm[c].size() / d - k_old[c]);
             hmoff[c + 1] = (int32_t)nm;
         }

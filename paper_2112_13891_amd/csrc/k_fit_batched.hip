@@ -19,6 +19,19 @@ namespace {
 
 constexpr int kT = 256;
 
+// Row widths with a register-resident form; other d take the generic loop (D = 0).
+#define FMS_DSWITCH_ROWS(d_, CALL) \
+    switch (d_) {                  \
+        case 1: CALL(1); break;    \
+        case 2: CALL(2); break;    \
+        case 3: CALL(3); break;    \
+        case 4: CALL(4); break;    \
+        case 8: CALL(8); break;    \
+        case 16: CALL(16); break;  \
+        case 32: CALL(32); break;  \
+        default: CALL(0); break;   \
+    }
+
 __device__ __forceinline__ int cloud_of(const long long* __restrict__ off, int ncl, long long v) {
     // the cloud c with off[c] <= v < off[c + 1] (off ascending; empty clouds skipped)
     int lo = 0, hi = ncl;
@@ -52,9 +65,39 @@ __global__ void bf_gather_kernel(const float* __restrict__ X, int d, const long 
     for (int k = 0; k < d; ++k) seeds[(long long)g * d + k] = X[row * d + k];
 }
 
+// Squared FP32 distance (direct differences, k ascending) of a point to row m:
+// D > 0 with the point in registers, D = 0 for any d.
+template <int D>
+__device__ __forceinline__ float row_dist2(const float* __restrict__ x, const float (&xr)[D > 0 ? D : 1],
+                                           const float* __restrict__ m, int d) {
+    float q = 0.0f;
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float t = xr[k] - m[k];
+            q = fmaf(t, t, q);
+        }
+    } else {
+        for (int k = 0; k < d; ++k) {
+            const float t = x[k] - m[k];
+            q = fmaf(t, t, q);
+        }
+    }
+    return q;
+}
+
+template <int D>
+__device__ __forceinline__ void load_point(const float* __restrict__ x, float (&xr)[D > 0 ? D : 1]) {
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xr[k] = x[k];
+    }
+}
+
 // Pool coverage: every pool entry of cloud c still in the pool and within
 // r2 (squared) of one of the cloud's new modes (rows m_off[c] .. m_off[c+1]
 // of nm) leaves the pool.  FP32 direct differences.
+template <int D>
 __global__ void bf_cover_kernel(const float* __restrict__ X, int d, const long long* __restrict__ x_off,
                                 int ncl, const int32_t* __restrict__ pool, const int32_t* __restrict__ pool_len,
                                 const float* __restrict__ nm, const int32_t* __restrict__ m_off, float r2,
@@ -64,14 +107,10 @@ __global__ void bf_cover_kernel(const float* __restrict__ X, int d, const long l
     const int c = cloud_of(x_off, ncl, e);
     if (e - x_off[c] >= pool_len[c] || removed[e]) return;
     const float* x = X + (x_off[c] + pool[e]) * d;
+    float xr[D > 0 ? D : 1];
+    load_point<D>(x, xr);
     for (int j = m_off[c]; j < m_off[c + 1]; ++j) {
-        const float* m = nm + (long long)j * d;
-        float q = 0.0f;
-        for (int k = 0; k < d; ++k) {
-            const float t = x[k] - m[k];
-            q = fmaf(t, t, q);
-        }
-        if (q <= r2) {
+        if (row_dist2<D>(x, xr, nm + (long long)j * d, d) <= r2) {
             removed[e] = 1;
             return;
         }
@@ -117,6 +156,7 @@ __global__ __launch_bounds__(kT) void bf_compact_kernel(const long long* __restr
 // Labels: point i of cloud c gets the index (within the cloud) of its nearest
 // mode among rows m_off[c] .. m_off[c+1] of modes, ties to the lowest index
 // (strict '<' in increasing order); FP32 direct differences.
+template <int D>
 __global__ void bf_assign_kernel(const float* __restrict__ X, int d, const long long* __restrict__ x_off,
                                  int ncl, const float* __restrict__ modes, const int32_t* __restrict__ m_off,
                                  int32_t* labels, long long n) {
@@ -124,15 +164,12 @@ __global__ void bf_assign_kernel(const float* __restrict__ X, int d, const long 
     if (i >= n) return;
     const int c = cloud_of(x_off, ncl, i);
     const float* x = X + i * d;
+    float xr[D > 0 ? D : 1];
+    load_point<D>(x, xr);
     float best = __builtin_inff();
     int arg = 0;
     for (int j = m_off[c]; j < m_off[c + 1]; ++j) {
-        const float* m = modes + (long long)j * d;
-        float q = 0.0f;
-        for (int k = 0; k < d; ++k) {
-            const float t = x[k] - m[k];
-            q = fmaf(t, t, q);
-        }
+        const float q = row_dist2<D>(x, xr, modes + (long long)j * d, d);
         if (q < best) {
             best = q;
             arg = j - m_off[c];
@@ -162,8 +199,11 @@ hipError_t launch_bf_cover(const float* X, int d, const long long* x_off, int nc
                            const int32_t* pool_len, const float* nm, const int32_t* m_off, float r2,
                            uint8_t* removed, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bf_cover_kernel, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, X, d, x_off, ncl,
-                       pool, pool_len, nm, m_off, r2, removed, n);
+#define FMS_COVER(DD)                                                                                  \
+    hipLaunchKernelGGL(bf_cover_kernel<DD>, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, X, d, x_off, \
+                       ncl, pool, pool_len, nm, m_off, r2, removed, n)
+    FMS_DSWITCH_ROWS(d, FMS_COVER);
+#undef FMS_COVER
     return hipGetLastError();
 }
 
@@ -176,8 +216,11 @@ hipError_t launch_bf_compact(const long long* x_off, int ncl, const int32_t* poo
 hipError_t launch_bf_assign(const float* X, int d, const long long* x_off, int ncl, const float* modes,
                             const int32_t* m_off, int32_t* labels, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(bf_assign_kernel, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, X, d, x_off, ncl,
-                       modes, m_off, labels, n);
+#define FMS_ASSIGN(DD)                                                                                 \
+    hipLaunchKernelGGL(bf_assign_kernel<DD>, dim3((unsigned)((n + kT - 1) / kT)), dim3(kT), 0, s, X, d, x_off, \
+                       ncl, modes, m_off, labels, n)
+    FMS_DSWITCH_ROWS(d, FMS_ASSIGN);
+#undef FMS_ASSIGN
     return hipGetLastError();
 }
 
