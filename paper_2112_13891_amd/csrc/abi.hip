@@ -917,10 +917,20 @@ TuneKey tune_key(int d, long long n, long long M, int ncl) {
 // R_force = 0: the tuned shape for this kind of input, else seeds per lane
 // from the mean seeds per cloud (small clouds waste fewer lanes).  With
 // ev != NULL the iterations are bracketed by ev[0] and ev[1].
+// Points of a batch already packed (DP columns, packed units of the call's
+// parameters) with the point and seed offsets on the device: a caller that
+// runs several step calls over the same clouds packs them once.
+struct BatchedPrepared {
+    const float* Xp;
+    int DP;
+    const long long* xo_dev;
+    const int32_t* so_dev;
+};
+
 int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
                       const int64_t* s_off, int ncl, int d, int n_iter, uint8_t* converged,
                       int32_t* iters, float* shift2, hipStream_t s, int R_force = 0,
-                      hipEvent_t* ev = nullptr) {
+                      hipEvent_t* ev = nullptr, const BatchedPrepared* pre = nullptr) {
     FMS_CHECK(ensure_pool_release_threshold());
     const int n = (int)x_off[ncl];
     const int M = (int)s_off[ncl];
@@ -954,16 +964,29 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     const long long max_items = batched_max_items(xo.data(), so.data(), ncl, sh.TS);
     if (max_items > INT_MAX / 2) return fail(MS_E_INVALID, "too many work items for one batch");
     Workspace ws(s);
-    float* Xp;
-    FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
-    FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
-    long long* xo_dev;
-    int32_t* so_dev;
-    FMS_CHECK(ws.alloc(&xo_dev, (size_t)ncl + 1));
-    FMS_CHECK(ws.alloc(&so_dev, (size_t)ncl + 1));
-    FMS_HIP(hipMemcpyAsync(xo_dev, xo.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
-    FMS_HIP(hipMemcpyAsync(so_dev, so.data(), (size_t)(ncl + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    FMS_HIP(hipStreamSynchronize(s));   // the host copies of the offsets go out of scope
+    const float* Xp;
+    const long long* xo_dev;
+    const int32_t* so_dev;
+    if (pre) {
+        if (pre->DP != sh.DP) return fail(MS_E_HIP, "prepared points have another row width");
+        Xp = pre->Xp;
+        xo_dev = pre->xo_dev;
+        so_dev = pre->so_dev;
+    } else {
+        float* xp;
+        long long* xod;
+        int32_t* sod;
+        FMS_CHECK(ws.alloc(&xp, (size_t)n * sh.DP));
+        FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, xp, s));
+        FMS_CHECK(ws.alloc(&xod, (size_t)ncl + 1));
+        FMS_CHECK(ws.alloc(&sod, (size_t)ncl + 1));
+        FMS_HIP(hipMemcpyAsync(xod, xo.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+        FMS_HIP(hipMemcpyAsync(sod, so.data(), (size_t)(ncl + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        FMS_HIP(hipStreamSynchronize(s));   // the host copies of the offsets go out of scope
+        Xp = xp;
+        xo_dev = xod;
+        so_dev = sod;
+    }
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
     b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
@@ -1080,7 +1103,8 @@ void merge_cloud(const float* hS, const uint8_t* hconv, long long g0, long long 
 
 // Host staging of ms_fit_batched, sized by each round's seeds and modes
 // (grown on demand, kept for the thread).
-thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_bmoff, g_pin_blen;
+thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_bmoff,
+    g_pin_blen;
 
 // The whole method (Algorithm 2 with the seed pool of Section II-D; with
 // all_points_as_seeds, Algorithm 1) for every cloud of a CSR batch, the
@@ -1119,14 +1143,27 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     FMS_CHECK(ws.alloc(&sh2_dev, (size_t)n));
     FMS_CHECK(ws.alloc(&nm_dev, (size_t)n * d));
     FMS_CHECK(g_pin_bso.ensure((size_t)(ncl + 1) * 8));
+    FMS_CHECK(g_pin_bso32.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_bmoff.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_blen.ensure((size_t)ncl * 4));
     int64_t* hso = (int64_t*)g_pin_bso.p;
+    int32_t* hso32 = (int32_t*)g_pin_bso32.p;
     int32_t* hmoff = (int32_t*)g_pin_bmoff.p;
     int32_t* hlen = (int32_t*)g_pin_blen.p;
 
     std::vector<long long> xo(x_off, x_off + ncl + 1);
     FMS_HIP(hipMemcpyAsync(xo_dev, xo.data(), (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
+    // the points packed once for every step call of the fit
+    ms_params q = *p;
+    q.graph = 0;
+    q.tile_R = 0;
+    const int DP = step_shape(d).DP;
+    float* Xp;
+    int32_t* so32_dev;
+    FMS_CHECK(ws.alloc(&Xp, (size_t)n * DP));
+    FMS_CHECK(ws.alloc(&so32_dev, (size_t)ncl + 1));
+    FMS_HIP(launch_pack_points(X, (int)n, d, DP, packed_scale(&q), Xp, s));
+    const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev};
     FMS_HIP(launch_bf_iota(xo_dev, ncl, pool[0], n, s));
     FMS_HIP(launch_fill_u8(removed, (int)n, 0, s));
     std::vector<uint64_t> rng(ncl);
@@ -1141,9 +1178,6 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         hlen[c] = plen[c];
     }
     FMS_HIP(hipMemcpyAsync(plen_dev, hlen, (size_t)ncl * 4, hipMemcpyHostToDevice, s));
-    ms_params q = *p;
-    q.graph = 0;
-    q.tile_R = 0;
     constexpr int kChunk = 4;   // iterations between checks for a finished round
     int cur = 0, rounds = 0;
     for (;;) {
@@ -1172,12 +1206,15 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         });
         FMS_HIP(hipMemcpyAsync(pos_dev, hpos, (size_t)M * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(hipMemcpyAsync(so_dev, hso, (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
+        for (int c = 0; c <= ncl; ++c) hso32[c] = (int32_t)hso[c];
+        FMS_HIP(hipMemcpyAsync(so32_dev, hso32, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(launch_bf_gather(X, d, xo_dev, so_dev, ncl, pos_dev, pool[cur], removed, S_dev, (int)M, s));
         FMS_HIP(launch_fill_u8(conv_dev, (int)M, 0, s));
         // iterations until the round is over for every seed
         for (int done = 0; done < p->max_iter;) {
             const int k = std::min(kChunk, p->max_iter - done);
-            FMS_CHECK(step_batched_impl(&q, X, x_off, S_dev, hso, ncl, d, k, conv_dev, it_dev, sh2_dev, s));
+            FMS_CHECK(step_batched_impl(&q, X, x_off, S_dev, hso, ncl, d, k, conv_dev, it_dev, sh2_dev, s, 0,
+                                        nullptr, &pre));
             done += k;
             FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
             FMS_HIP(wait_stream(s));
