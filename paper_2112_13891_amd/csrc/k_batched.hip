@@ -12,8 +12,9 @@
 //            the prefix of work items and of active slots, and for every
 //            work item and active slot its cloud;
 //   step     a persistent grid over the work items (cloud, seed tile, point
-//            chunk), taken from a queue (one atomic per item and workgroup,
-//            so that uneven items and late-starting workgroups balance), the
+//            chunk): with more items than workgroups every item comes from
+//            a queue (one atomic per item, so that uneven items and
+//            late-starting workgroups balance), else each its own; the
 //            same pair loop as the single-cloud step, one (D+1)-vector
 //            partial per seed and item;
 //   finalize one lane per active seed: its chunk partials added in chunk
@@ -155,13 +156,17 @@ __global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs
     const int wave = threadIdx.x >> 6;
     __shared__ float red[(kWaves - 1) * TS * (D + 1)];
     __shared__ int next_item;
-    for (;;) {
-        // every thread has read the previous item (the pair loop below holds
-        // barriers) before thread 0 writes the next one
+    // with no more items than workgroups each takes its own; otherwise every
+    // item comes from the queue (every thread has read the previous item --
+    // the pair loop holds barriers -- before thread 0 writes the next one)
+    const bool own = total <= (int)gridDim.x;
+    int it = blockIdx.x;
+    if (!own) {
         if (threadIdx.x == 0) next_item = atomicAdd(B.queue, 1);
         __syncthreads();
-        const int it = next_item;
-        if (it >= total) break;
+        it = next_item;
+    }
+    while (it < total) {
         const int c = B.item_cloud[it];
         const int local = it - B.item_pre[c];
         const int tiles = B.tiles[c], chunks = B.chunks[c];
@@ -180,6 +185,10 @@ __global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs
                 for (int k = 0; k <= D; ++k) dst[k] = acc[r][k];
             }
         }
+        if (own) break;
+        if (threadIdx.x == 0) next_item = atomicAdd(B.queue, 1);
+        __syncthreads();
+        it = next_item;
     }
 }
 
