@@ -334,10 +334,11 @@ def main():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the secondary workloads (2-D blobs, 32-D embedding, adjoint)")
     ap.add_argument("--kernel-iters", type=int, default=20)
-    ap.add_argument("--phase", default="all", choices=["all", "kernel", "fit"],
+    ap.add_argument("--phase", default="all", choices=["all", "kernel", "fit", "batched"],
                     help="kernel: only the dominant-kernel launch shape (both precisions) and a "
                          "256 MiB copy that calibrates the traffic counters; fit: only --steps "
-                         "fits per precision; both for profilers")
+                         "fits per precision; batched: only --steps whole-method calls on the "
+                         "512 uneven clouds (D = 16); all for profilers")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
@@ -351,6 +352,21 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     api.lib()
+    if args.phase == "batched":
+        clouds = workloads.clouds16(seed=0)
+        xo = np.concatenate([[0], np.cumsum([len(c[0]) for c in clouds])]).astype(np.int64)
+        Xa = torch.from_numpy(np.concatenate([c[0] for c in clouds])).cuda()
+        log(f"workload clouds16: {len(clouds)} clouds, {int(xo[-1])} points, D=16")
+        for _ in range(args.warmup):
+            api.fit_batched(Xa, xo, 1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, k_off, rounds = api.fit_batched(Xa, xo, 1.0)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase": "batched", "ms_per_call": (time.perf_counter() - t0) / args.steps * 1e3,
+                          "rounds": rounds, "modes_total": int(k_off[-1])}), flush=True)
+        return
     w = workloads.aniso3d(seed=0)
     X = torch.from_numpy(w.X).cuda()
     n, d = w.X.shape
