@@ -10,7 +10,8 @@
 //   plan     one workgroup: from the per-cloud active counts, each cloud's
 //            seed tiles (64R seeds) and point chunks (kChunkPoints points),
 //            the prefix of work items and of active slots, and for every
-//            work item and active slot its cloud;
+//            work item and active slot its cloud (one wave per cloud fills
+//            the cloud's ranges);
 //   step     a persistent grid over the work items (cloud, seed tile, point
 //            chunk): with more items than workgroups every item comes from
 //            a queue (one atomic per item, so that uneven items and
@@ -144,8 +145,13 @@ __global__ __launch_bounds__(kPlanThreads) void bplan_kernel(BatchedArgs B, int 
         B.item_pre[c] = ipre[c];
         B.slot_pre[c] = spre[c];
     }
-    for (int i = threadIdx.x; i < icarry; i += kPlanThreads) B.item_cloud[i] = upper_cloud(ipre, B.ncl, i);
-    for (int g = threadIdx.x; g < scarry; g += kPlanThreads) B.slot_cloud[g] = upper_cloud(spre, B.ncl, g);
+    // a cloud's work items and active slots are contiguous ranges: one wave
+    // per cloud writes them, 64 entries per store
+    const int lane = threadIdx.x & 63;
+    for (int c = threadIdx.x >> 6; c < B.ncl; c += kPlanThreads / 64) {
+        for (int i = ipre[c] + lane; i < ipre[c + 1]; i += 64) B.item_cloud[i] = c;
+        for (int g = spre[c] + lane; g < spre[c + 1]; g += 64) B.slot_cloud[g] = c;
+    }
 }
 
 template <int D, int DP, int R, int KERN>
