@@ -17,7 +17,9 @@
 //            a queue (one atomic per item, so that uneven items and
 //            late-starting workgroups balance), else each its own; the
 //            same pair loop as the single-cloud step, one (D+1)-vector
-//            partial per seed and item;
+//            partial per seed and item, stored component-major within the
+//            item (component k of the item's TS seeds contiguous) so that
+//            the stores and the finalize's loads are coalesced;
 //   finalize one lane per active seed: its chunk partials added in chunk
 //            order, the update and convergence test, and the seed kept in
 //            its cloud's next active list (per-cloud counter).
@@ -186,9 +188,9 @@ __global__ __launch_bounds__(kThreads) void bstep_kernel(StepArgs a, BatchedArgs
         if (wave == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float* dst = a.part + ((long long)it * TS + r * 64 + lane) * (D + 1);
+                float* dst = a.part + (long long)it * TS * (D + 1) + r * 64 + lane;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) dst[k] = acc[r][k];
+                for (int k = 0; k <= D; ++k) dst[k * TS] = acc[r][k];
             }
         }
         if (own) break;
@@ -219,9 +221,9 @@ __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, Batched
             float tmp[U][D + 1];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const float* p = a.part + ((long long)(ib + (ch + u) * tiles + tile) * TS + pos) * (D + 1);
+                const float* p = a.part + (long long)(ib + (ch + u) * tiles + tile) * TS * (D + 1) + pos;
 #pragma unroll
-                for (int k = 0; k <= D; ++k) tmp[u][k] = p[k];
+                for (int k = 0; k <= D; ++k) tmp[u][k] = p[k * TS];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -229,9 +231,9 @@ __global__ __launch_bounds__(kFinThreads) void bfinal_kernel(StepArgs a, Batched
                 for (int k = 0; k <= D; ++k) v[k] += tmp[u][k];
         }
         for (; ch < chunks; ++ch) {
-            const float* p = a.part + ((long long)(ib + ch * tiles + tile) * TS + pos) * (D + 1);
+            const float* p = a.part + (long long)(ib + ch * tiles + tile) * TS * (D + 1) + pos;
 #pragma unroll
-            for (int k = 0; k <= D; ++k) v[k] += p[k];
+            for (int k = 0; k <= D; ++k) v[k] += p[k * TS];
         }
         const int j = a.act_in[B.seg[c] + q];
         const bool keep = update_seed_id<D, DP>(a, j, v) == 1;
