@@ -110,3 +110,17 @@ def test_fit_batched_repeated_calls_are_reproducible():
     for a, b in zip(first[0], again[0]):
         assert torch.equal(a, b)
     assert torch.equal(first[1], again[1])
+
+
+def test_fit_batched_many_clouds_host_threads_match_oracle(orc):
+    # enough seeds in a round (>= 16,384) that the draws and merges run on
+    # several host threads
+    rng = np.random.default_rng(11)
+    sizes = [int(v) for v in rng.integers(400, 900, 160)]
+    Xs, xo = _clouds(12, sizes, 2)
+    assert sum(min(n, 128) for n in sizes) >= 16384
+    say("fit_batched threaded", len(sizes), int(xo[-1]))
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0,
+                                              rng_seed=9)
+    torch.cuda.synchronize()
+    _compare(orc, Xs, xo, 1.0, "gaussian", False, 9, per, lab, k_off)
