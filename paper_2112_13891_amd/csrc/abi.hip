@@ -1178,7 +1178,9 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         hlen[c] = plen[c];
     }
     FMS_HIP(hipMemcpyAsync(plen_dev, hlen, (size_t)ncl * 4, hipMemcpyHostToDevice, s));
-    constexpr int kChunk = 4;   // iterations between checks for a finished round
+    // iterations between checks for a finished round (an iteration with no
+    // active seed is a few microseconds of empty launches)
+    constexpr int kChunk = 8;
     int cur = 0, rounds = 0;
     for (;;) {
         // draws (the staging buffers hold no copy in flight: every round ends

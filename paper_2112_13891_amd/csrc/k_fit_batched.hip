@@ -117,19 +117,21 @@ __global__ void bf_cover_kernel(const float* __restrict__ X, int d, const long l
     }
 }
 
-// Stable compaction of each cloud's pool slice, one workgroup per cloud:
-// entries not removed keep their order (the pool stays ascending); the
-// removed flags of the slice are cleared for the next round.
-__global__ __launch_bounds__(kT) void bf_compact_kernel(const long long* __restrict__ x_off,
+// Stable compaction of each cloud's pool slice, one workgroup of kCT
+// threads per cloud: entries not removed keep their order (the pool stays
+// ascending); the removed flags of the slice are cleared for the next round.
+constexpr int kCT = 1024;
+
+__global__ __launch_bounds__(kCT) void bf_compact_kernel(const long long* __restrict__ x_off,
                                                         const int32_t* __restrict__ pool_in, uint8_t* removed,
                                                         int32_t* pool_len, int32_t* pool_out) {
-    __shared__ int wsum[kT / 64];
+    __shared__ int wsum[kCT / 64];
     const int c = blockIdx.x;
     const long long base = x_off[c];
     const int len = pool_len[c];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int carry = 0;
-    for (int e0 = 0; e0 < len; e0 += kT) {
+    for (int e0 = 0; e0 < len; e0 += kCT) {
         const int e = e0 + threadIdx.x;
         bool keep = false;
         int32_t v = 0;
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(kT) void bf_compact_kernel(const long long* __restr
         if (lane == 0) wsum[wave] = __popcll(bal);
         __syncthreads();
         int before = carry, total = 0;
-        for (int w = 0; w < kT / 64; ++w) {
+        for (int w = 0; w < kCT / 64; ++w) {
             if (w < wave) before += wsum[w];
             total += wsum[w];
         }
@@ -209,7 +211,7 @@ hipError_t launch_bf_cover(const float* X, int d, const long long* x_off, int nc
 
 hipError_t launch_bf_compact(const long long* x_off, int ncl, const int32_t* pool_in, uint8_t* removed,
                              int32_t* pool_len, int32_t* pool_out, hipStream_t s) {
-    hipLaunchKernelGGL(bf_compact_kernel, dim3(ncl), dim3(kT), 0, s, x_off, pool_in, removed, pool_len, pool_out);
+    hipLaunchKernelGGL(bf_compact_kernel, dim3(ncl), dim3(kCT), 0, s, x_off, pool_in, removed, pool_len, pool_out);
     return hipGetLastError();
 }
 
