@@ -267,14 +267,20 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             }
             const float rr = gm[4] + sqrtf(ns);
             const float eps = A.kappa * rr * rr;
+            // whether this seed's pairs of the block are computed exactly: its
+            // own bound admits a pair within the refine radius.  The choice is
+            // per seed, so a seed's result never depends on its wave mates
+            // (whose grouping follows the order of the active list)
+            bool may;
             {
-                // some seed of the group may have a pair of this block within
-                // the refine radius: the wave's half block is computed exactly
-                // in FP32 (points from LDS), every pair, as the FP32 step does
-                // it; otherwise the bf16 products alone (no pair can need the
-                // recompute)
+                // a seed that may have a pair of this block within the refine
+                // radius gets every pair of the wave's half block exactly in
+                // FP32 (points from LDS), as the FP32 step computes it; a seed
+                // that cannot gets the bf16 products (no pair of it can need
+                // the recompute).  A wave whose seeds differ runs both paths,
+                // each seed keeping the one its own bound chose
                 const float lbk = sqrtf(ns) - gm[4];
-                const bool may = live[0] && !(lbk > 0.0f && lbk * lbk > -A.e_thr + 2.0f * eps);
+                may = live[0] && !(lbk > 0.0f && lbk * lbk > -A.e_thr + 2.0f * eps);
                 if (__ballot(may)) {
                     const long long pb = (long long)blk * kBlk + half * kPtsPerWave;
                     unsigned long long nex = 0;
@@ -297,17 +303,21 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                                     q2 = fmaf(dx[k], dx[k], q2);
                                 }
                                 float we = kGauss ? __builtin_amdgcn_exp2f(-q2) : (q2 <= a.h2 ? 1.0f : 0.0f);
-                                we = valid ? we : 0.0f;
+                                we = (valid && may) ? we : 0.0f;
                                 wex += we;
 #pragma unroll
                                 for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
-                                nex += __popcll(__ballot(valid) & lmask);
+                                nex += __popcll(__ballot(valid && may) & lmask);
                             }
                         }
                     }
                     refined += nex;
-                    blk = nxt;
-                    continue;
+                    // seeds whose own bound rules out the refine radius take
+                    // the products below, whatever their wave mates needed
+                    if (!__ballot(live[0] && !may)) {
+                        blk = nxt;
+                        continue;
+                    }
                 }
             }
             const bf16x8 sfrag = seed_frag<D>(st, ns, hf);
@@ -327,6 +337,10 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                     x1 = *reinterpret_cast<const bf16x8*>(xvb + tt * 512 + 2 * 16 * 8);
                 }
                 f32x16 E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag, f32x16{}, 0, 0, 0);
+                if (may) {   // this seed's pairs of the block were computed exactly above
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) E[v] = -__builtin_inff();
+                }
                 // tree of maxima (depth 3 instead of a chain of 8)
                 const float m0 = fmaxf(fmaxf(E[0], E[1]), E[2]);
                 const float m1 = fmaxf(fmaxf(E[3], E[4]), E[5]);
