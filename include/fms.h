@@ -17,7 +17,9 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     ms_step and ms_assign are stream-ordered and asynchronous; ms_fit
  *     returns only once K is known on the host.
- *   - 1 <= d <= 64; 1 <= n <= 2^31 - 1.
+ *   - 1 <= n <= 2^31 - 1.  1 <= d <= 256 for ms_fit, ms_step and
+ *     ms_assign (the BF16 form: d <= 32); 1 <= d <= 64 for the batched calls
+ *     and the differentiable form.
  *   - Return value: MS_OK (0) or a negative ms_status.  No exception crosses
  *     the ABI.  ms_last_error() gives a thread-local message for the last
  *     failure on the calling thread.
@@ -255,7 +257,12 @@ int ms_forward_update(const void *X, int32_t nbatch, int64_t n, const void *S_in
  *     dL/dx_i = sum_j [ (w_ij / W_j) g_j + beta_ij (s_j - x_i) ]
  * are ADDED to dS (nbatch x m x d) and dX (nbatch x n x d).  The weights
  * are recomputed, never stored.  Same layout and dtype rules as
- * ms_forward_update.  Device pointers; stream-ordered and asynchronous.
+ * ms_forward_update.  dS may be the same array as dX when m == n: in the
+ * first step of the unrolled form S_0 = X, so dL/dS_0 belongs to dX, and
+ * passing dX as both adds the seed term and the point term there (the
+ * passes that read X, S and G never read dS or dX, which are only added
+ * into, one after the other).  G must not overlap dS or dX.  Device pointers;
+ * stream-ordered and asynchronous.
  */
 int ms_step_adjoint(const void *X, int32_t nbatch, int64_t n, const void *S,
                     int64_t m, int32_t d, double h, const void *G, void *dS,
@@ -344,6 +351,19 @@ int ms_tune_batched(const ms_params *p, const float *X, const int64_t *x_off,
  * Host only; no GPU needed.
  */
 int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t *n_next);
+
+/*
+ * ms_release_workspace -- frees the device workspace and pinned host staging
+ * that ms_fit and ms_fit_batched keep for the calling thread between calls
+ * (grown on demand for reuse by the next call on the same thread and
+ * device), and whatever host threads that have exited left behind.  A thread
+ * that exits hands its caches to the library, which frees them in the next
+ * ms_fit or ms_fit_batched call on any thread, or here; so memory held for
+ * exited threads never outlives the next call.  Those calls are
+ * host-synchronous, so nothing is in flight on the released memory when they
+ * have returned.  The next call allocates again.  Always returns MS_OK.
+ */
+int ms_release_workspace(void);
 
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char *ms_last_error(void);

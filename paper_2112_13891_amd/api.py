@@ -81,7 +81,7 @@ class Diag(ctypes.Structure):
 EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_tune_batched", "ms_fit_batched",
            "ms_assign",
            "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
-           "ms_last_error", "ms_version")
+           "ms_release_workspace", "ms_last_error", "ms_version")
 
 _lib = None
 
@@ -118,6 +118,8 @@ def lib():
     L.ms_seed_draw.restype = ctypes.c_int
     L.ms_seed_count_next.argtypes = [i32, i32, i32, P]
     L.ms_seed_count_next.restype = ctypes.c_int
+    L.ms_release_workspace.argtypes = []
+    L.ms_release_workspace.restype = ctypes.c_int
     L.ms_last_error.argtypes = []
     L.ms_last_error.restype = ctypes.c_char_p
     L.ms_version.argtypes = []
@@ -438,6 +440,31 @@ def step_adjoint(X, S, h, G):
     return (dS[0], dX[0]) if squeeze else (dS, dX)
 
 
+def step_adjoint_accumulate(X, S, h, G, dS, dX):
+    """ms_step_adjoint adding into caller arrays: dS += dL/dS and dX += dL/dX
+    of one Gaussian update for the upstream gradient G.  dS may be dX itself
+    when S is X (the first step of the unrolled form, S_0 = X)."""
+    torch = _torch()
+    squeeze = X.dim() == 2
+    Xb = X.unsqueeze(0) if squeeze else X
+    nb, n, d = Xb.shape
+    m = S.shape[-2]
+    for name, t, rows in (("S", S, m), ("G", G, m), ("dS", dS, m), ("dX", dX, n)):
+        _dev(t, X.dtype, X.dim(), name)
+        if t.shape[-2:] != (rows, d) or (not squeeze and t.shape[0] != nb):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}")
+    _dev(X, X.dtype, None, "X")
+    if G.data_ptr() in (dS.data_ptr(), dX.data_ptr()):
+        raise ValueError("G must not share memory with dS or dX")
+    if dS.data_ptr() == dX.data_ptr() and m != n:
+        raise ValueError("dS may be dX only when S has as many rows as X")
+    rc = lib().ms_step_adjoint(ctypes.c_void_p(X.data_ptr()), nb, n, ctypes.c_void_p(S.data_ptr()),
+                               m, d, float(h), ctypes.c_void_p(G.data_ptr()),
+                               ctypes.c_void_p(dS.data_ptr()), ctypes.c_void_p(dX.data_ptr()),
+                               X.element_size(), _stream_ptr(X))
+    _check(rc)
+
+
 def seed_draw(rng_state: int, pool, count: int):
     """The library's seed draw on host memory.  Returns (ids, new_state)."""
     pool = np.ascontiguousarray(pool, dtype=np.int32)
@@ -447,6 +474,12 @@ def seed_draw(rng_state: int, pool, count: int):
                             int(count), out.ctypes.data_as(ctypes.c_void_p))
     _check(rc)
     return out, int(st.value)
+
+
+def release_workspace():
+    """Free the device workspace and pinned staging the library keeps for
+    the calling thread between ms_fit / ms_fit_batched calls."""
+    _check(lib().ms_release_workspace())
 
 
 def seed_count_next(n_last: int, modes: int, H: int = 32) -> int:

@@ -4,8 +4,9 @@ MeanShiftT.apply(X, h, T) returns S_T, where S_0 = X and S_{t+1} = m(S_t) is
 the Gaussian batched update of every point over all points (Section II-B).
 Forward: T launches of ms_forward_update.  Backward: for t = T-1 .. 0 one
 ms_step_adjoint launch recomputes the weights of step t from the stored S_t
-(no n x n matrix is stored) and returns dL/dS_t and the point term of dL/dX;
-S_0 = X adds the last seed gradient to dX.
+(no n x n matrix is stored), adds dL/dS_t into a fresh array and the point
+term of step t into dX; for t = 0, where S_0 = X, the library adds dL/dS_0
+into dX as well, so this module does no arithmetic of its own.
 
 Checkpointing: with ``every = k`` only S_0, S_k, S_2k, ... are stored and the
 states in between are recomputed by forward launches during backward.
@@ -44,6 +45,10 @@ class MeanShiftT(torch.autograd.Function):
         h, T, every = ctx.h, ctx.T, ctx.every
         saved = ctx.saved_states
         G = G.contiguous().to(X.dtype)
+        if T == 0:   # S_T = S_0 = X
+            return G, None, None, None
+        # ms_step_adjoint adds dL/dS_t into a fresh array and the point term of
+        # step t into dX; at t = 0, where S_0 = X, dL/dS_0 is added into dX too
         dX = torch.zeros_like(X)
         cache = {}
         for t in range(T - 1, -1, -1):
@@ -60,10 +65,9 @@ class MeanShiftT(torch.autograd.Function):
                     if u + 1 < t:
                         cache[u + 1] = S
                 S_t = S
-            dS, dX_t = api.step_adjoint(X, S_t, h, G)
-            dX += dX_t
+            dS = dX if t == 0 else torch.zeros_like(S_t)
+            api.step_adjoint_accumulate(X, S_t, h, G, dS, dX)
             G = dS
-        dX += G   # S_0 = X
         return dX, None, None, None
 
 

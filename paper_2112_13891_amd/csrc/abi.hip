@@ -13,7 +13,10 @@
 #include <atomic>
 #include <immintrin.h>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <sys/syscall.h>
+#include <unistd.h>
 #include <tuple>
 #include <chrono>
 #include <climits>
@@ -171,10 +174,50 @@ class Workspace {
     long long bytes_ = 0, peak_ = 0;
 };
 
-// Pinned host staging, per thread, grown on demand and kept for reuse.
+// True on the process's initial thread.  Its thread-local caches are left to
+// the end of the process (the HIP runtime may already be shutting down when
+// they are destroyed).
+bool on_initial_thread() { return (pid_t)syscall(SYS_gettid) == getpid(); }
+
+// Buffers of host threads that have exited.  A thread's caches cannot be
+// freed from its own exit (measured: hipFree / hipHostFree called from a
+// thread-local destructor returned only part of the memory), so the exiting
+// thread hands them here, and the next ms_fit or ms_fit_batched call on any
+// thread, or ms_release_workspace, frees them: memory held for exited
+// threads never outlives the next call.
+std::mutex g_orphan_mu;
+std::vector<void*> g_orphan_dev, g_orphan_host;
+
+void free_orphans() {
+    std::vector<void*> dev, host;
+    {
+        std::lock_guard<std::mutex> lock(g_orphan_mu);
+        dev.swap(g_orphan_dev);
+        host.swap(g_orphan_host);
+    }
+    for (void* q : dev) (void)hipFree(q);
+    for (void* q : host) (void)hipHostFree(q);
+}
+
+// Pinned host staging, per thread, grown on demand and kept for reuse; handed
+// to the orphan list when the thread exits, freed by ms_release_workspace.
 struct Pinned {
     void* p = nullptr;
     size_t cap = 0;
+    Pinned() = default;
+    Pinned(const Pinned&) = delete;
+    Pinned& operator=(const Pinned&) = delete;
+    ~Pinned() {
+        if (p && !on_initial_thread()) {
+            std::lock_guard<std::mutex> lock(g_orphan_mu);
+            g_orphan_host.push_back(p);
+        }
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
     int ensure(size_t bytes) {
         if (bytes <= cap) return MS_OK;
         if (p) (void)hipHostFree(p);
@@ -213,7 +256,7 @@ bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
 int check_common(const float* X, int64_t n, int32_t d) {
     if (!X) return fail(MS_E_INVALID, "X is NULL");
     if (n < 1 || n > INT_MAX) return fail(MS_E_INVALID, "n must be in [1, 2^31-1]");
-    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (d < 1 || d > 256) return fail(MS_E_INVALID, "d must be in [1, 256]");
     if ((long long)n * step_shape(d).DP > (1LL << 40))
         return fail(MS_E_INVALID, "n*d too large");
     return MS_OK;
@@ -267,20 +310,39 @@ enum Slot {
     SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN, SL_COUNT
 };
 
+// Handed to the orphan list when the thread exits (freed by the next call on
+// any thread), freed by ms_release_workspace.
 struct DevCache {
     int dev = -1;
     void* p[SL_COUNT] = {};
     size_t cap[SL_COUNT] = {};
     long long held = 0;
+    DevCache() = default;
+    DevCache(const DevCache&) = delete;
+    DevCache& operator=(const DevCache&) = delete;
+    ~DevCache() {
+        if (on_initial_thread()) return;
+        std::lock_guard<std::mutex> lock(g_orphan_mu);
+        for (int i = 0; i < SL_COUNT; ++i)
+            if (p[i]) g_orphan_dev.push_back(p[i]);
+    }
+    void release() {
+        for (int i = 0; i < SL_COUNT; ++i) {
+            if (p[i]) (void)hipFree(p[i]);
+            p[i] = nullptr;
+            cap[i] = 0;
+        }
+        held = 0;
+    }
 };
-thread_local std::vector<DevCache> g_cache;
+thread_local std::vector<std::unique_ptr<DevCache>> g_cache;
 
 DevCache& cache_for_device(int dev) {
     for (auto& c : g_cache)
-        if (c.dev == dev) return c;
-    g_cache.emplace_back();
-    g_cache.back().dev = dev;
-    return g_cache.back();
+        if (c->dev == dev) return *c;
+    g_cache.emplace_back(new DevCache());
+    g_cache.back()->dev = dev;
+    return *g_cache.back();
 }
 
 template <typename T>
@@ -524,6 +586,7 @@ void fill_batch(Batch& b, int n, int d, int B, const StepShape& sh, const ms_par
 int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int32_t max_modes,
              int32_t* k_out, int32_t* labels, ms_diag* diag, hipStream_t s) {
     const auto t_start = std::chrono::steady_clock::now();
+    free_orphans();
     const bool trace = log_enabled();
     int dev = 0;
     FMS_HIP(hipGetDevice(&dev));
@@ -830,10 +893,15 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     return MS_OK;
 }
 
-int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, int m, int n_iter,
-              uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
-    FMS_CHECK(ensure_pool_release_threshold());
-    Workspace ws(s);
+// The body of ms_step over device buffers taken from `ws` (a Workspace).  With run = false only the buffers are requested (nothing is
+// launched): the dry run that sizes an Arena.
+template <class A>
+int step_core(A& ws, bool run, const ms_params* p, const float* X, int n, int d, float* seeds, int m,
+              int n_iter, uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
+#define FMS_RUN(expr)                   \
+    do {                                \
+        if (run) FMS_HIP(expr);         \
+    } while (0)
     const bool bf16 = bf16_form(p, d);
     const bool cull = !bf16 && !p->plain && cull_supported(d, n) &&
                       !(p->metric == MS_METRIC_COSINE && cull_reach(p->kernel, p->h) >= 2.0);
@@ -846,12 +914,12 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
         // and every seed that sees it fails)
         float* Xn;
         FMS_CHECK(ws.alloc(&Xn, (size_t)n * d));
-        FMS_HIP(launch_normalize_rows(X, n, d, Xn, nullptr, s));
+        FMS_RUN(launch_normalize_rows(X, n, d, Xn, nullptr, s));
         X = Xn;
     }
     float* Xp;
     FMS_CHECK(ws.alloc(&Xp, (size_t)n * sh.DP));
-    FMS_HIP(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
+    FMS_RUN(launch_pack_points(X, n, d, sh.DP, scale, Xp, s));
     SortedPoints sp;
     if (sorted) {
         char* sws;
@@ -860,12 +928,12 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
         FMS_CHECK(ws.alloc(&sp.geom, (size_t)((n + 255) / 256) * geom_stride(sh.D)));
         FMS_CHECK(ws.alloc(&sws, sort_workspace_bytes(n > m ? n : m)));
         sp.sws = sws;
-        FMS_HIP(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
+        FMS_RUN(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
     }
     if (bf16) {
         FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n) : bf16w_feature_bytes(n, sh.D)));
-        if (sh.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
-        else FMS_HIP(launch_bf16w_features(sp.Xs, n, sh.D, sp.geom, sp.feat, s));
+        if (sh.D <= 4) FMS_RUN(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
+        else FMS_RUN(launch_bf16w_features(sp.Xs, n, sh.D, sp.geom, sp.feat, s));
     }
     Ctl* ctl;
     FMS_CHECK(ws.alloc(&ctl, 1));
@@ -878,6 +946,7 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     FMS_CHECK(ws.alloc(&b.iters, m));
     FMS_CHECK(ws.alloc(&b.shift2, m));
     FMS_CHECK(ws.alloc(&b.part, (size_t)step_part_floats(sh, m, b.grid)));
+    if (!run) return MS_OK;
     FMS_HIP(launch_ctl_reset(ctl, 0, INT_MAX, n_iter, s));
     FMS_HIP(launch_seed_init_from_array(seeds, converged, d, m, b, s));
     if (sorted)   // seeds that are close in space share waves (refine work, culled blocks)
@@ -885,6 +954,14 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
     for (int t = 0; t < n_iter; ++t) FMS_HIP(launch_iteration(b, t, s));
     FMS_HIP(launch_seed_export(b, m, seeds, converged, iters, shift2, s));
     return MS_OK;
+#undef FMS_RUN
+}
+
+int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, int m, int n_iter,
+              uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
+    FMS_CHECK(ensure_pool_release_threshold());
+    Workspace ws(s);
+    return step_core(ws, true, p, X, n, d, seeds, m, n_iter, converged, iters, shift2, s);
 }
 
 // Seeds per lane that the batched step is built for, by padded dimension.
@@ -1119,6 +1196,7 @@ thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bseeds, g_pin_bcon
 // or N >= L M, else N <- 2N).  Labels: nearest mode within the cloud.
 int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, int ncl, int d, float* modes,
                      int64_t max_modes, int64_t* k_off, int32_t* labels, int32_t* rounds_out, hipStream_t s) {
+    free_orphans();
     const long long n = x_off[ncl];
     const bool all = p->all_points_as_seeds != 0;
     const float rm = p->merge_radius * p->h, rc = p->cover_radius * p->h;
@@ -1361,7 +1439,7 @@ int check_batched_args(const ms_params* p, const float* X, const int64_t* x_off,
         return fail(MS_E_INVALID, "ms_step_batched computes the Euclidean metric only");
     if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
     if (ncl < 1 || ncl > batched_max_clouds()) return fail(MS_E_INVALID, "ncl must be in [1, 8192]");
-    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "the batched calls take d in [1, 64]");
     if (x_off[0] != 0 || s_off[0] != 0) return fail(MS_E_INVALID, "offsets must start at 0");
     for (int c = 0; c < ncl; ++c) {
         if (x_off[c + 1] < x_off[c] || s_off[c + 1] < s_off[c])
@@ -1481,7 +1559,7 @@ static int check_diff(const void* X, int32_t nbatch, int64_t n, const void* S, i
     if (bytes != 4 && bytes != 8) return fail(MS_E_INVALID, "dtype_bytes must be 4 or 8");
     if (nbatch < 1 || nbatch > 65535) return fail(MS_E_INVALID, "nbatch must be in [1, 65535]");
     if (n < 1 || m < 1 || n > INT_MAX / 2 || m > INT_MAX / 2) return fail(MS_E_INVALID, "bad n or m");
-    if (d < 1 || d > 64) return fail(MS_E_INVALID, "d must be in [1, 64]");
+    if (d < 1 || d > 64) return fail(MS_E_INVALID, "the differentiable calls take d in [1, 64]");
     if (!(std::isfinite(h) && h > 0.0)) return fail(MS_E_INVALID, "h must be finite and > 0");
     return MS_OK;
 }
@@ -1533,6 +1611,17 @@ int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t* n_next
     long long next = n_last;
     if ((long long)n_last > (long long)H * modes) next = (long long)n_last - modes;
     *n_next = (int32_t)std::max(1LL, next);
+    return MS_OK;
+}
+
+int ms_release_workspace(void) {
+    g_err.clear();
+    free_orphans();
+    for (auto& c : g_cache) c->release();
+    g_cache.clear();
+    for (Pinned* q : {&g_pin_ctl, &g_pin_pos, &g_pin_rb, &g_pin_modes, &g_pin_bpos, &g_pin_bso, &g_pin_bso32,
+                      &g_pin_bseeds, &g_pin_bconv, &g_pin_bmodes, &g_pin_bmoff, &g_pin_blen})
+        q->release();
     return MS_OK;
 }
 

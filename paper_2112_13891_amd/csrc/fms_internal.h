@@ -119,6 +119,9 @@ hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv
                               int32_t* iters, float* shift2, hipStream_t s);
 int step_grid(const StepShape& sh, int B, int n);
 
+// ---- launchers (k_step_wide.hip): FP32 step for padded D = 128, 256 --------
+hipError_t launch_iteration_wide(Batch& b, int t, hipStream_t s);
+
 // ---- launchers (k_step_cull.hip): FP32 step over Morton-ordered points, d <= 4 --
 bool cull_supported(int d, int n);
 // Distance beyond which the culled step may skip pairs (original units).

@@ -88,6 +88,8 @@ hipError_t launch_assign(const float* X, int n, int d, const float* modes, int k
         FMS_CASE(16)
         FMS_CASE(32)
         FMS_CASE(64)
+        FMS_CASE(128)
+        FMS_CASE(256)
 #undef FMS_CASE
         default:
             return hipErrorInvalidValue;

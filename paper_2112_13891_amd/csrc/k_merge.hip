@@ -116,6 +116,9 @@ __global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S,
 // first-hit rule, and a state staged before another workgroup settles it can
 // only read as undecided, which postpones a decision.
 constexpr int kDecideRows = 64;
+// rows staged per tile: 64, fewer for rows wider than 64 floats (16 KB of LDS)
+template <int D>
+constexpr int decide_rows() { return D <= 64 ? kDecideRows : (kDecideRows * 64) / D; }
 constexpr int kDecideTiledMinBatch = 16384;
 
 template <int D, bool kFirst>
@@ -123,8 +126,9 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
                                                           const uint8_t* __restrict__ status, int B,
                                                           const float* __restrict__ modes, int K_old,
                                                           float r2, int32_t* state, int32_t* und_counter) {
-    __shared__ float rows[kDecideRows][D];
-    __shared__ int32_t rst[kDecideRows];
+    constexpr int kRows = decide_rows<D>();
+    __shared__ float rows[kRows][D];
+    __shared__ int32_t rst[kRows];
     const int i0 = blockIdx.x * kT;
     const int i = i0 + threadIdx.x;
     bool todo = false;   // this lane decides seed i in this pass
@@ -138,9 +142,9 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
     for (int k = 0; k < D; ++k) si[k] = todo ? S[(long long)i * DP + k] : 0.0f;
     int result = MG_FOUNDER;   // unless an old mode or an earlier founder / undecided seed is within r
     if (kFirst) {
-        for (int base = 0; base < K_old; base += kDecideRows) {
+        for (int base = 0; base < K_old; base += kRows) {
             if (!__syncthreads_or(todo)) break;
-            const int cnt = min(kDecideRows, K_old - base);
+            const int cnt = min(kRows, K_old - base);
             for (int e = threadIdx.x; e < cnt * D; e += kT)
                 rows[e / D][e % D] = modes[(long long)(base + e / D) * DP + e % D];
             __syncthreads();
@@ -156,9 +160,9 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
         }
     }
     const int ilast = min(i0 + kT, B) - 1;   // the workgroup's last seed: candidates j < ilast
-    for (int base = 0; base < ilast; base += kDecideRows) {
+    for (int base = 0; base < ilast; base += kRows) {
         if (!__syncthreads_or(todo)) break;
-        const int cnt = min(kDecideRows, ilast - base);
+        const int cnt = min(kRows, ilast - base);
         for (int e = threadIdx.x; e < cnt * D; e += kT)
             rows[e / D][e % D] = S[(long long)(base + e / D) * DP + e % D];
         if (threadIdx.x < cnt) rst[threadIdx.x] = __atomic_load_n(&state[base + threadIdx.x], __ATOMIC_RELAXED);
@@ -240,33 +244,43 @@ __global__ __launch_bounds__(kCompactBlock) void cover_kernel(
     const float* __restrict__ X, int d, const int32_t* __restrict__ pool, int len,
     const float* __restrict__ modes, int DP, int k0, int k1, const Ctl* ctl, float r2,
     uint8_t* removed, int32_t* block_cnt) {
-    __shared__ float tileM[kModeTile * D];
+    constexpr int kTile = D <= 64 ? kModeTile : (kModeTile * 64) / D;   // at most 64 KB of LDS
+    // rows up to 64 floats stay in registers; wider ones are read from memory
+    // at each distance (1,024 threads leave 128 registers per lane)
+    constexpr int RD = D <= 64 ? D : 1;
+    __shared__ float tileM[kTile * D];
     __shared__ int wsum[kCompactBlock / 64];
     if (ctl) k1 = ctl->k_new;
     const int e = blockIdx.x * kCompactBlock + threadIdx.x;
     bool todo = e < len && !removed[e];
-    float x[D];
-    if (todo) {
-        const long long id = pool[e];
+    const long long id = todo ? pool[e] : 0;
+    float x[RD];
 #pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = (k < d) ? X[id * d + k] : 0.0f;
-    } else {
-#pragma unroll
-        for (int k = 0; k < D; ++k) x[k] = 0.0f;
-    }
+    for (int k = 0; k < RD; ++k) x[k] = (todo && k < d) ? X[id * d + k] : 0.0f;
     bool hit = false;
-    for (int base = k0; base < k1; base += kModeTile) {
+    for (int base = k0; base < k1; base += kTile) {
         if (__syncthreads_and(!todo || hit)) break;
-        const int cnt = min(kModeTile, k1 - base);
+        const int cnt = min(kTile, k1 - base);
         for (int q = threadIdx.x; q < cnt * D; q += kCompactBlock)
             tileM[q] = modes[(long long)(base + q / D) * DP + q % D];
         __syncthreads();
         if (todo && !hit) {
-            for (int j = 0; j < cnt; ++j)
-                if (dist2<D>(x, tileM + j * D) <= r2) {
+            for (int j = 0; j < cnt; ++j) {
+                float q2;
+                if constexpr (D <= 64) {
+                    q2 = dist2<D>(x, tileM + j * D);
+                } else {
+                    q2 = 0.0f;   // padded coordinates of the modes are zero
+                    for (int k = 0; k < D; ++k) {
+                        const float t = (k < d ? X[id * d + k] : 0.0f) - tileM[j * D + k];
+                        q2 = fmaf(t, t, q2);
+                    }
+                }
+                if (q2 <= r2) {
                     hit = true;
                     break;
                 }
+            }
         }
     }
     if (todo && hit) removed[e] = 1;
@@ -355,6 +369,8 @@ hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
         case 16: { constexpr int DD = 16; CALL; } break;      \
         case 32: { constexpr int DD = 32; CALL; } break;      \
         case 64: { constexpr int DD = 64; CALL; } break;      \
+        case 128: { constexpr int DD = 128; CALL; } break;    \
+        case 256: { constexpr int DD = 256; CALL; } break;    \
         default: return hipErrorInvalidValue;                 \
     }
 

@@ -248,7 +248,9 @@ StepShape step_shape(int d) {
     else if (d <= 8) sh.D = 8;
     else if (d <= 16) sh.D = 16;
     else if (d <= 32) sh.D = 32;
-    else sh.D = 64;
+    else if (d <= 64) sh.D = 64;
+    else if (d <= 128) sh.D = 128;
+    else sh.D = 256;
     sh.DP = sh.D < 4 ? 4 : sh.D;
     sh.R = sh.D <= 4 ? 4 : (sh.D <= 8 ? 2 : 1);
     sh.TS = 64 * sh.R;
@@ -334,6 +336,7 @@ hipError_t launch_seed_export(const Batch& b, int m, float* seeds, uint8_t* conv
 hipError_t launch_iteration(Batch& b, int t, hipStream_t s) {
     if (b.prec == MS_PREC_BF16_REFINE) return launch_iteration_bf16(b, t, s);
     if (b.Xs && b.geom) return launch_iteration_cull(b, t, s);
+    if (b.sh.D > 64) return launch_iteration_wide(b, t, s);
     const int D = b.sh.D, R = b.sh.R;
 #define FMS_CASE(DD, DPP, RR) \
     if (D == DD && R == RR) return launch_step_t<DD, DPP, RR>(b, t, s);
