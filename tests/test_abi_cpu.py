@@ -81,7 +81,7 @@ def test_fit_rejects_bad_params(api, field, value, msg):
     assert rc == api.MS_E_INVALID and msg in api.last_error()
 
 
-@pytest.mark.parametrize("n,d,msg", [(0, 2, "n must"), (10, 0, "d must"), (10, 65, "d must"),
+@pytest.mark.parametrize("n,d,msg", [(0, 2, "n must"), (10, 0, "d must"), (10, 257, "d must"),
                                      (2 ** 31, 2, "n must")])
 def test_fit_rejects_bad_shapes(api, n, d, msg):
     p = api.make_params(1.0)
@@ -192,7 +192,7 @@ def test_step_batched_rejects_bad_arguments(api):
         (dict(xo=(1, 5, 9, 12), so=good_s), "start at 0"),
         (dict(xo=(0, 5, 4, 12), so=good_s), "nondecreasing"),
         (dict(xo=(0, 5, 5, 12), so=(0, 2, 3, 4)), "no points"),
-        (dict(xo=good_x, so=good_s, d=65), "d must"),
+        (dict(xo=good_x, so=good_s, d=65), "take d in [1, 64]"),
         (dict(xo=good_x, so=good_s, n_iter=5000), "n_iter"),
     ]
     for kw, msg in cases:

@@ -57,14 +57,14 @@ def test_batched_fixed_iterations(orc, d, kernel):
     for n_iter in (1, 3):
         S, conv, it, sh = _run(Xs, Ss, xo, so, h, kernel, n_iter)
         torch.cuda.synchronize()
-        S, it = S.cpu().numpy(), it.cpu().numpy()
+        S, it, conv = S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy()
         for c in range(len(Xs)):
             a, b = so[c], so[c + 1]
             if a == b:
                 continue
             ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), h, kernel, tol=1e-3,
                                           n_iter=n_iter)
-            ties = ragged_check(Xs[c], Ss[c], h, kernel, n_iter, S[a:b], it[a:b], ref, oit)
+            ties = ragged_check(orc, Xs[c], Ss[c], h, kernel, n_iter, S[a:b], it[a:b], conv[a:b], ref, oit, ost)
             if ties:
                 say("cloud", c, "flat boundary ties", ties)
 
@@ -200,10 +200,10 @@ def test_batched_full_size_sampled(orc):
     say("full-size batched", len(Xs), "clouds", int(xo[-1]), "points")
     S, conv, it, sh = _run(Xs, Ss, xo, so, 1.0, "gaussian", 3)
     torch.cuda.synchronize()
-    S, it = S.cpu().numpy(), it.cpu().numpy()
+    S, it, conv = S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy()
     sizes = np.array([len(x) for x in Xs])
     for c in sorted({int(sizes.argmin()), int(sizes.argmax()), 100, 400}):
         a, b = so[c], so[c + 1]
         ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), 1.0, "gaussian", tol=1e-3, n_iter=3)
         say("cloud", c, "n", len(Xs[c]))
-        ragged_check(Xs[c], Ss[c], 1.0, "gaussian", 3, S[a:b], it[a:b], ref, oit)
+        ragged_check(orc, Xs[c], Ss[c], 1.0, "gaussian", 3, S[a:b], it[a:b], conv[a:b], ref, oit, ost)

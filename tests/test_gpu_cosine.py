@@ -61,8 +61,9 @@ def test_cosine_step_ragged(orc, n, d, kernel):
             ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter,
                                           metric="cosine")
             # ragged_check works in the units of X: compare on the directions
-            ties = ragged_check(_unit(X).astype(np.float32), _unit(S0).astype(np.float32), h, kernel, n_iter,
-                                S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+            ties = ragged_check(orc, _unit(X).astype(np.float32), _unit(S0).astype(np.float32), h, kernel,
+                                n_iter, S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(), ref, oit,
+                                ost, metric="cosine")
             if ties:
                 say("flat boundary ties", ties)
 

@@ -51,7 +51,8 @@ def test_culled_step_ragged(orc, n, d, kernel, precision):
         S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, precision=precision, n_iter=n_iter)
         torch.cuda.synchronize()
         ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
-        ties = ragged_check(X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        ties = ragged_check(orc, X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                            conv.cpu().numpy(), ref, oit, ost)
         if ties:
             say("flat boundary ties", ties)
 
@@ -68,7 +69,8 @@ def test_culled_step_seed_counts(orc, m):
         S, conv, it, sh = api.step(_gpu(X), _gpu(S0), 1.5, precision=precision, n_iter=2)
         torch.cuda.synchronize()
         ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), 1.5, "gaussian", tol=1e-3, n_iter=2)
-        ragged_check(X, S0, 1.5, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        ragged_check(orc, X, S0, 1.5, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(),
+                     ref, oit, ost)
 
 
 @pytest.mark.parametrize("kernel", ["gaussian", "flat"])
@@ -107,7 +109,7 @@ def test_plain_fp32_form_matches_oracle_and_culled_form(orc, d, kernel):
     Sc, cc, ic, _ = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=3)
     torch.cuda.synchronize()
     ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=3)
-    ragged_check(X, S0, h, kernel, 3, Sp.cpu().numpy(), ip.cpu().numpy(), ref, oit)
+    ragged_check(orc, X, S0, h, kernel, 3, Sp.cpu().numpy(), ip.cpu().numpy(), cp.cpu().numpy(), ref, oit, ost)
     assert np.abs(Sp.cpu().numpy() - Sc.cpu().numpy()).max() <= 1e-4 * h
     rp = api.fit(_gpu(X), h, kernel=kernel, plain=True)
     rc = api.fit(_gpu(X), h, kernel=kernel)
@@ -130,4 +132,5 @@ def test_reduce_paths_at_many_chunks(orc, plain, m):
     S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, n_iter=2, plain=plain)
     torch.cuda.synchronize()
     ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, "gaussian", tol=1e-3, n_iter=2)
-    ragged_check(X, S0, h, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+    ragged_check(orc, X, S0, h, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(),
+                 ref, oit, ost)

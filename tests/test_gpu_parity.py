@@ -103,9 +103,50 @@ def test_step_ragged_shapes(orc, n, d, kernel):
         S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=n_iter)
         torch.cuda.synchronize()
         ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
-        ties = ragged_check(X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        ties = ragged_check(orc, X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                            conv.cpu().numpy(), ref, oit, ost)
         if ties:
             say("flat boundary ties", ties)
+
+
+@pytest.mark.parametrize("n,d", [(300, 65), (1031, 100), (513, 128), (200, 129), (777, 200),
+                                 (300, 256), (70, 256)])
+@pytest.mark.parametrize("kernel", ["gaussian", "flat"])
+def test_step_wide_rows(orc, n, d, kernel):
+    """Rows of 65..256 coordinates (padded to 128 or 256): the four waves of a
+    workgroup split the coordinates, one wave per seed finalizes."""
+    say("step wide", n, d, kernel)
+    rng = np.random.default_rng(n * 1000 + d)
+    C = 4.0 * rng.standard_normal((5, d))
+    X = (C[rng.integers(0, 5, n)] + 0.5 * rng.standard_normal((n, d))).astype(np.float32)
+    m = min(n, 150)
+    S0 = X[rng.choice(n, m, replace=False)]
+    h = 0.5 * np.sqrt(d) * (1.0 if kernel == "gaussian" else 1.6)
+    for n_iter in (1, 4):
+        S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=n_iter)
+        torch.cuda.synchronize()
+        ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
+        ties = ragged_check(orc, X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                            conv.cpu().numpy(), ref, oit, ost)
+        if ties:
+            say("ties", ties)
+    S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, kernel=kernel, n_iter=100)
+    torch.cuda.synchronize()
+    say(step_parity(orc, X, S0, h, kernel, 1e-3, S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy()))
+
+
+@pytest.mark.parametrize("d", [65, 128, 256])
+@pytest.mark.parametrize("all_points", [False, True])
+def test_fit_wide_rows(orc, d, all_points):
+    rng = np.random.default_rng(d)
+    C = 4.0 * rng.standard_normal((6, d))
+    n = 2500
+    X = (C[rng.integers(0, 6, n)] + 0.5 * rng.standard_normal((n, d))).astype(np.float32)
+    h = 0.5 * np.sqrt(d)
+    g = api.fit(_gpu(X), h, all_points=all_points, trace=True)
+    ref = orc.fit(X, h, all_points=all_points)
+    rep = fit_parity(g, ref, X, h, orc=orc)
+    say("fit wide", d, all_points, rep, "K", g.k)
 
 
 def test_step_respects_converged_flags(orc, blobs):
@@ -214,7 +255,8 @@ def test_fit_single_point_and_tiny():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,d,k", [(200_000, 3, 50), (5000, 32, 300), (1001, 2, 1),
-                                   (3000, 64, 1500), (70_000, 16, 37)])
+                                   (3000, 64, 1500), (70_000, 16, 37), (4000, 65, 70),
+                                   (3001, 128, 257), (2000, 256, 40)])
 def test_assign_parity(orc, n, d, k):
     rng = np.random.default_rng(n + d + k)
     X = (rng.standard_normal((n, d)) * 10).astype(np.float32)
@@ -277,7 +319,8 @@ def test_bf16_step_ragged_shapes(orc, n, d, kernel):
                                    n_iter=n_iter)
         torch.cuda.synchronize()
         ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
-        ties = ragged_check(X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        ties = ragged_check(orc, X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                            conv.cpu().numpy(), ref, oit, ost)
         if ties:
             say("flat boundary ties", ties)
 
@@ -372,7 +415,8 @@ def test_bf16_step_ragged_wide(orc, n, d, kernel, layout):
                                    n_iter=n_iter)
         torch.cuda.synchronize()
         ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, kernel, tol=1e-3, n_iter=n_iter)
-        ties = ragged_check(X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(), ref, oit)
+        ties = ragged_check(orc, X, S0, h, kernel, n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                            conv.cpu().numpy(), ref, oit, ost)
         if ties:
             say("flat boundary ties", ties)
 
