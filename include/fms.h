@@ -17,9 +17,9 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     ms_step and ms_assign are stream-ordered and asynchronous; ms_fit
  *     returns only once K is known on the host.
- *   - 1 <= n <= 2^31 - 1.  1 <= d <= 256 for ms_fit, ms_step and
- *     ms_assign (the BF16 form: d <= 32); 1 <= d <= 64 for the batched calls
- *     and the differentiable form.
+ *   - 1 <= n <= 2^31 - 1.  1 <= d <= 256 for ms_fit, ms_step,
+ *     ms_step_noalloc and ms_assign (the BF16 form: d <= 32); 1 <= d <= 64
+ *     for the batched calls and the differentiable form.
  *   - Return value: MS_OK (0) or a negative ms_status.  No exception crosses
  *     the ABI.  ms_last_error() gives a thread-local message for the last
  *     failure on the calling thread.
@@ -196,6 +196,29 @@ int ms_fit(const ms_params *p, const float *X, int64_t n, int32_t d,
 int ms_step(const ms_params *p, const float *X, int64_t n, int32_t d,
             float *seeds, int32_t m, int32_t n_iter, uint8_t *converged,
             int32_t *iters, float *shift2, void *stream);
+
+/*
+ * ms_step_noalloc -- ms_step for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as ms_step, but every
+ * workspace buffer (packed and spatially ordered points, control block,
+ * active lists, chunk partials) is carved out of one fixed device scratch
+ * array of 32 MiB that the library holds on each GPU it runs on until the
+ * process ends; the call itself makes no hipMalloc, hipFree or other
+ * allocating call.  The caller still passes X and the seed arrays.
+ *   Size limit: the call is sized before anything is launched; one that
+ *   needs more than 32 MiB of workspace (for instance n = 200,000 points of
+ *   d = 3 need about 8 MB in FP32 and 24 MB in the BF16 form; n x d of a
+ *   few million floats and more do not fit) fails with MS_E_INVALID and a
+ *   message that gives the bytes it needs.
+ *   Concurrency: every call on one GPU uses that GPU's one scratch array and
+ *   leaves its contents behind; calls that overlap on one GPU (other
+ *   streams, other threads) race and must be serialized by the caller.
+ * Stream-ordered and asynchronous, as ms_step.
+ */
+int ms_step_noalloc(const ms_params *p, const float *X, int64_t n, int32_t d, float *seeds,
+                    int32_t m, int32_t n_iter, uint8_t *converged, int32_t *iters,
+                    float *shift2, void *stream);
 
 /*
  * ms_step_batched -- ms_step for many independent point clouds at once: cloud

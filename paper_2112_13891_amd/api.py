@@ -78,7 +78,7 @@ class Diag(ctypes.Structure):
     ]
 
 
-EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_batched", "ms_tune_batched", "ms_fit_batched",
+EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_noalloc", "ms_step_batched", "ms_tune_batched", "ms_fit_batched",
            "ms_assign",
            "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
            "ms_release_workspace", "ms_last_error", "ms_version")
@@ -102,6 +102,8 @@ def lib():
     L.ms_fit.restype = ctypes.c_int
     L.ms_step.argtypes = [ctypes.POINTER(Params), P, i64, i32, P, i32, i32, P, P, P, P]
     L.ms_step.restype = ctypes.c_int
+    L.ms_step_noalloc.argtypes = L.ms_step.argtypes
+    L.ms_step_noalloc.restype = ctypes.c_int
     L.ms_step_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P, P]
     L.ms_step_batched.restype = ctypes.c_int
     L.ms_tune_batched.argtypes = [ctypes.POINTER(Params), P, P, P, P, i32, i32, i32, P, P, P]
@@ -268,9 +270,10 @@ def fit(X, h, kernel="gaussian", precision="fp32", tol=1e-3, max_iter=100, merge
 
 
 def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, converged=None,
-         refine_radius=3.0, metric="euclidean", plain=False):
+         refine_radius=3.0, metric="euclidean", plain=False, noalloc=False):
     """Up to n_iter updates of the active seeds.  Returns new tensors
-    (seeds, converged uint8, iters int32, shift2 float32)."""
+    (seeds, converged uint8, iters int32, shift2 float32).  ``noalloc=True``
+    calls ms_step_noalloc (workspace in the library's fixed device scratch)."""
     torch = _torch()
     Xp = _dev(X, torch.float32, 2, "X")
     n, d = X.shape
@@ -285,7 +288,8 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
     p = make_params(h, kernel, precision, tol, refine_radius=refine_radius, metric=metric)
     p.plain = int(bool(plain))
-    rc = lib().ms_step(ctypes.byref(p), Xp, n, d, ctypes.c_void_p(S.data_ptr()), m, int(n_iter),
+    fn = lib().ms_step_noalloc if noalloc else lib().ms_step
+    rc = fn(ctypes.byref(p), Xp, n, d, ctypes.c_void_p(S.data_ptr()), m, int(n_iter),
                        ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
                        ctypes.c_void_p(sh.data_ptr()), _stream_ptr(X))
     _check(rc)

@@ -30,6 +30,14 @@
 
 #include "fms_internal.h"
 
+// Device scratch of ms_step_noalloc: every workspace buffer of that call is
+// carved out of it, so the call allocates nothing.  Each GPU the library runs
+// on holds its own copy until the process ends.  In host code this name is
+// only a handle for hipGetSymbolAddress: the device address it returns, kept
+// per device, is the one passed to kernels.
+static constexpr size_t kScratchBytes = 32ull << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace fms {
 
 namespace {
@@ -893,7 +901,31 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     return MS_OK;
 }
 
-// The body of ms_step over device buffers taken from `ws` (a Workspace).  With run = false only the buffers are requested (nothing is
+// Bump allocation out of one device buffer of fixed size, with no allocation
+// call: every request is rounded up to 256 bytes.  With a NULL base it only
+// counts, so that a dry run can size a call before anything is launched.
+class Arena {
+   public:
+    Arena(char* base, size_t cap) : base_(base), cap_(cap) {}
+    template <typename T>
+    int alloc(T** out, size_t count) {
+        const size_t bytes = (std::max<size_t>(count * sizeof(T), 256) + 255) / 256 * 256;
+        if (base_ && (off_ > cap_ || bytes > cap_ - off_))
+            return fail(MS_E_INVALID, "scratch buffer too small for this call");
+        *out = base_ ? (T*)(base_ + off_) : nullptr;
+        off_ += bytes;
+        return MS_OK;
+    }
+    size_t used() const { return off_; }
+
+   private:
+    char* base_;
+    size_t cap_;
+    size_t off_ = 0;
+};
+
+// The body of ms_step over device buffers taken from `ws` (a Workspace or an
+// Arena).  With run = false only the buffers are requested (nothing is
 // launched): the dry run that sizes an Arena.
 template <class A>
 int step_core(A& ws, bool run, const ms_params* p, const float* X, int n, int d, float* seeds, int m,
@@ -961,6 +993,44 @@ int step_impl(const ms_params* p, const float* X, int n, int d, float* seeds, in
               uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
     FMS_CHECK(ensure_pool_release_threshold());
     Workspace ws(s);
+    return step_core(ws, true, p, X, n, d, seeds, m, n_iter, converged, iters, shift2, s);
+}
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+int scratch_base(char** out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static char* base[kMaxDev] = {};
+    int dev = 0;
+    FMS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(MS_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!base[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(MS_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        base[dev] = (char*)ptr;
+    }
+    *out = base[dev];
+    return MS_OK;
+}
+
+// ms_step with every buffer in the fixed device scratch: a dry run sizes the
+// call, a call that needs more than the scratch holds is rejected before
+// anything is launched, and the kernels are those of ms_step.
+int step_noalloc_impl(const ms_params* p, const float* X, int n, int d, float* seeds, int m, int n_iter,
+                      uint8_t* converged, int32_t* iters, float* shift2, hipStream_t s) {
+    Arena need(nullptr, 0);
+    FMS_CHECK(step_core(need, false, p, X, n, d, seeds, m, n_iter, converged, iters, shift2, s));
+    if (need.used() > kScratchBytes)
+        return fail(MS_E_INVALID, "ms_step_noalloc: this call needs " + std::to_string(need.used()) +
+                                      " bytes of device scratch, more than the fixed " +
+                                      std::to_string(kScratchBytes));
+    char* base = nullptr;
+    FMS_CHECK(scratch_base(&base));
+    Arena ws(base, kScratchBytes);
     return step_core(ws, true, p, X, n, d, seeds, m, n_iter, converged, iters, shift2, s);
 }
 
@@ -1502,6 +1572,21 @@ int ms_step(const ms_params* p, const float* X, int64_t n, int32_t d, float* see
     if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
         return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32");
     return step_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2, (hipStream_t)stream);
+}
+
+int ms_step_noalloc(const ms_params* p, const float* X, int64_t n, int32_t d, float* seeds, int32_t m,
+                    int32_t n_iter, uint8_t* converged, int32_t* iters, float* shift2, void* stream) {
+    g_err.clear();
+    FMS_CHECK(check_params(p, false));
+    FMS_CHECK(check_common(X, n, d));
+    if (m < 0) return fail(MS_E_INVALID, "m must be >= 0");
+    if (n_iter < 0 || n_iter > kMaxIterCap) return fail(MS_E_INVALID, "n_iter must be in [0, 4096]");
+    if (m == 0) return MS_OK;
+    if (!seeds || !converged || !iters || !shift2) return fail(MS_E_INVALID, "NULL seed array");
+    if (p->precision == MS_PREC_BF16_REFINE && !bf16_supported(d))
+        return fail(MS_E_INVALID, "precision MS_PREC_BF16_REFINE supports 1 <= d <= 32");
+    return step_noalloc_impl(p, X, (int)n, d, seeds, m, n_iter, converged, iters, shift2,
+                             (hipStream_t)stream);
 }
 
 int ms_step_batched(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
