@@ -1,7 +1,7 @@
 """Host-side checks of bench.py's contract: one GPU only (a request for more
-exits with a JSON message), the flop count per pair, the algorithmic bytes of
-the timed launch, and the source hash that ties the committed counter figures
-to the sources they were measured on."""
+exits with a JSON message), the flop counts per pair, the algorithmic bytes of
+the timed launch, the roofline entry, and the source hash that ties the
+committed counter figures to the sources they were measured on."""
 import json
 import os
 import subprocess
@@ -29,13 +29,26 @@ def test_flops_per_pair_counts_distance_weight_and_accumulation():
 
 
 def test_algorithmic_bytes_of_the_timed_launch():
-    # 512 seeds = 8 tiles of 64; 200,000 points = 391 chunks of 512 points,
-    # at most 2048 items: 256 chunks per tile
-    m, n = 512, 200_000
-    assert bench.algorithmic_bytes("fp32", m, n) == 8 * n * 16 + 2 * m * 256 * 16
-    assert bench.algorithmic_bytes("bf16", m, n) == 8 * n * 80 + 2 * m * 256 * 16
-    # one tile: every chunk of 512 points is an item
-    assert bench.algorithmic_bytes("fp32", 64, 4096) == 4096 * 16 + 2 * 64 * 8 * 16
+    # every seed tile streams the n x D points once, 4 bytes per coordinate:
+    # 512 seeds = 8 tiles of 64 over 200,000 x 3 points
+    assert bench.algorithmic_bytes(512, 200_000, 3) == 8 * 200_000 * 3 * 4
+    assert bench.algorithmic_bytes(65, 1000, 2) == 2 * 1000 * 2 * 4
+    # the wide BF16 form's tiles hold 128 seeds
+    assert bench.algorithmic_bytes(8192, 262_144, 32, 128) == 64 * 262_144 * 32 * 4
+
+
+def test_adjoint_flops_per_pair():
+    # forward 4D+6, recomputed forward 4D+6, dS pass 6D+8, dX pass 8D+8
+    for d in (1, 4, 16):
+        assert bench.adjoint_flops_per_pair(d) == 22 * d + 28
+
+
+def test_roofline_entry_fields():
+    e = bench.roofline_entry(512 * 200_000, 3, 0.030, 512, 200_000, "bf16", "launch", "kernel")
+    assert e["bound"] == "alu" and e["unit"] == "TFLOP/s" and e["peak"] == bench.FP32_VEC_PEAK_TFLOPS
+    assert abs(e["achieved"] - 512 * 200_000 * 18 / 0.030e-3 / 1e12) < 1e-9
+    assert abs(e["frac"] - e["achieved"] / e["peak"]) < 1e-12
+    assert e["contraction_frac_of_bf16_mfma_peak"] > 0 and e["traffic"] is None
 
 
 def test_source_digest_is_stable_and_covers_the_kernel_sources():
