@@ -267,21 +267,19 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             }
             const float rr = gm[4] + sqrtf(ns);
             const float eps = A.kappa * rr * rr;
-            // whether this seed's pairs of the block are computed exactly: its
-            // own bound admits a pair within the refine radius.  The choice is
-            // per seed, so a seed's result never depends on its wave mates
-            // (whose grouping follows the order of the active list)
-            bool may;
             {
-                // a seed that may have a pair of this block within the refine
-                // radius gets every pair of the wave's half block exactly in
-                // FP32 (points from LDS), as the FP32 step computes it; a seed
-                // that cannot gets the bf16 products (no pair of it can need
-                // the recompute).  A wave whose seeds differ runs both paths,
-                // each seed keeping the one its own bound chose
-                const float lbk = sqrtf(ns) - gm[4];
-                may = live[0] && !(lbk > 0.0f && lbk * lbk > -A.e_thr + 2.0f * eps);
-                if (__ballot(may)) {
+                // every live seed of the wave has the whole block within the
+                // refine radius, by a bound: (|s~| + R)^2 <= -e_thr, so
+                // E + eps >= -|x - s|^2 >= e_thr for every pair and the bf16
+                // path below would recompute every pair exactly too.  The wave
+                // then computes its half block exactly in FP32 (points from
+                // LDS) with no products; the arithmetic and its order are
+                // those of the recompute below, so a seed's result is the
+                // same either way and never depends on its wave mates (whose
+                // grouping follows the order of the active list)
+                const float ub = (sqrtf(ns) + gm[4]) * (1.0f + 1e-5f);
+                const bool inside = ub * ub <= -A.e_thr;
+                if (!__ballot(live[0] && !inside)) {
                     const long long pb = (long long)blk * kBlk + half * kPtsPerWave;
                     unsigned long long nex = 0;
 #pragma unroll 1
@@ -303,21 +301,17 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                                     q2 = fmaf(dx[k], dx[k], q2);
                                 }
                                 float we = kGauss ? __builtin_amdgcn_exp2f(-q2) : (q2 <= a.h2 ? 1.0f : 0.0f);
-                                we = (valid && may) ? we : 0.0f;
+                                we = valid ? we : 0.0f;
                                 wex += we;
 #pragma unroll
                                 for (int k = 0; k < D; ++k) aex[k] = fmaf(we, dx[k], aex[k]);
-                                nex += __popcll(__ballot(valid && may) & lmask);
+                                nex += __popcll(__ballot(valid) & lmask);
                             }
                         }
                     }
                     refined += nex;
-                    // seeds whose own bound rules out the refine radius take
-                    // the products below, whatever their wave mates needed
-                    if (!__ballot(live[0] && !may)) {
-                        blk = nxt;
-                        continue;
-                    }
+                    blk = nxt;
+                    continue;
                 }
             }
             const bf16x8 sfrag = seed_frag<D>(st, ns, hf);
@@ -337,10 +331,6 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
                     x1 = *reinterpret_cast<const bf16x8*>(xvb + tt * 512 + 2 * 16 * 8);
                 }
                 f32x16 E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afrag, sfrag, f32x16{}, 0, 0, 0);
-                if (may) {   // this seed's pairs of the block were computed exactly above
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) E[v] = -__builtin_inff();
-                }
                 // tree of maxima (depth 3 instead of a chain of 8)
                 const float m0 = fmaxf(fmaxf(E[0], E[1]), E[2]);
                 const float m1 = fmaxf(fmaxf(E[3], E[4]), E[5]);
