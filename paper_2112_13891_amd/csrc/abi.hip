@@ -654,9 +654,10 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
     }
     if (bf16) {
         FMS_CHECK(cache_get(C, budget, SL_FEAT, base.D <= 4 ? bf16_feature_bytes(n)
-                                                           : bf16w_feature_bytes(n, base.D), &sp.feat));
+                                                           : bf16_wide_feature_bytes(n, base.D, p->kernel),
+                            &sp.feat));
         if (base.D <= 4) FMS_HIP(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
-        else FMS_HIP(launch_bf16w_features(sp.Xs, n, base.D, sp.geom, sp.feat, s));
+        else FMS_HIP(launch_bf16_wide_features(sp.Xs, n, base.D, sp.geom, sp.feat, p->kernel, s));
     }
 
     int32_t* pool[2] = {nullptr, nullptr};
@@ -963,9 +964,10 @@ int step_core(A& ws, bool run, const ms_params* p, const float* X, int n, int d,
         FMS_RUN(launch_spatial_sort(Xp, n, sh.DP, sh.D, sp.Xs, sp.perm, sp.geom, sws, s));
     }
     if (bf16) {
-        FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n) : bf16w_feature_bytes(n, sh.D)));
+        FMS_CHECK(ws.alloc(&sp.feat, sh.D <= 4 ? bf16_feature_bytes(n)
+                                               : bf16_wide_feature_bytes(n, sh.D, p->kernel)));
         if (sh.D <= 4) FMS_RUN(launch_bf16_features(sp.Xs, n, d, sp.geom, sp.feat, s));
-        else FMS_RUN(launch_bf16w_features(sp.Xs, n, sh.D, sp.geom, sp.feat, s));
+        else FMS_RUN(launch_bf16_wide_features(sp.Xs, n, sh.D, sp.geom, sp.feat, p->kernel, s));
     }
     Ctl* ctl;
     FMS_CHECK(ws.alloc(&ctl, 1));

@@ -144,6 +144,21 @@ size_t bf16w_feature_bytes(int n, int D);
 hipError_t launch_bf16w_features(const float* Xs, int n, int D, const float* geom, void* feat,
                                  hipStream_t s);
 
+// ---- launchers (k_step_bf16f.hip): BF16 form, Gaussian, D in {8, 16, 32} --------
+hipError_t launch_iteration_bf16f(Batch& b, int t, hipStream_t s);
+size_t bf16f_feature_bytes(int n, int D);
+hipError_t launch_bf16f_features(const float* Xs, int n, int D, const float* geom, void* feat, hipStream_t s);
+// Feature bytes and builder of the BF16 form for D > 4 (the Gaussian kernel's
+// compensated form or the flat window's screen form).
+inline size_t bf16_wide_feature_bytes(int n, int D, int kernel) {
+    return kernel == MS_KERNEL_GAUSSIAN ? bf16f_feature_bytes(n, D) : bf16w_feature_bytes(n, D);
+}
+inline hipError_t launch_bf16_wide_features(const float* Xs, int n, int D, const float* geom, void* feat,
+                                            int kernel, hipStream_t s) {
+    return kernel == MS_KERNEL_GAUSSIAN ? launch_bf16f_features(Xs, n, D, geom, feat, s)
+                                        : launch_bf16w_features(Xs, n, D, geom, feat, s);
+}
+
 // ---- launchers (k_batched.hip): FP32 step over many clouds ---------------------
 int batched_max_clouds();
 long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS);

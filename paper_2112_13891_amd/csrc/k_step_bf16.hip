@@ -536,7 +536,8 @@ StepShape step_shape_bf16(int d, int B) {
 bool bf16_supported(int d) { return d >= 1 && (d <= 4 || (d <= 32 && bf16w_dims(step_shape(d).D))); }
 
 hipError_t launch_iteration_bf16(Batch& b, int t, hipStream_t s) {
-    if (b.sh.D > 4) return launch_iteration_bf16w(b, t, s);
+    if (b.sh.D > 4)
+        return b.kernel == MS_KERNEL_GAUSSIAN ? launch_iteration_bf16f(b, t, s) : launch_iteration_bf16w(b, t, s);
     switch (b.sh.D) {
         case 1: return launch_bf16_t<1, 1>(b, t, s);
         case 2: return launch_bf16_t<2, 1>(b, t, s);

@@ -1,0 +1,604 @@
+// k_step_bf16f.hip -- the fused mean-shift iteration in the BF16 form for the
+// Gaussian kernel at 8 <= D <= 32 (gfx950), in the style of flash attention:
+// the seed-point products on MFMA in bf16 with FP32 accumulation, the
+// weights made in registers, and W.X accumulated on MFMA in FP32.
+//
+// Points are sorted by nearest pivot and shifted by the bounding-box
+// midpoint.  Each block of 256 of them is centred on c, the coordinate-wise
+// median of its points (robust to the few far points that end a pivot run),
+// and for a seed s (packed units, where w = exp2(-|x - s|^2)) both sides are
+// taken relative to it: x~ = x - c, s~ = s - c, and
+//     E = 2 x~.s~ - |x~|^2 - |s~|^2  (= -|x - s|^2),
+// each operand split into three bf16 parts (x~ = hi + mid + lo leaves a
+// relative error of u^3, u = 2^-8), with K slots
+// [x~ | -|x~|^2 hi, mid, lo | 0..] against [2 s~ | 1 | 1 | 1 | 0..] and
+// -|s~|^2 (FP32) as the accumulator's start value.  The error of E for a
+// pair grows with (|x~| + |s~|)^2, so a point farther than kInlierR from its
+// block's centre is an outlier of the block (a bit per point); R is the
+// radius of all the block's points, Rin that of the others.  Per block:
+//   1. cull: a seed whose distance bound |s~| - R puts every pair of the
+//      block beyond the FP32 underflow of the weight (2^-127) has nothing
+//      there; the workgroup skips a block no seed of it can see;
+//   2. screen: one product of the hi parts, whose error is at most
+//      eps = 2 (2u + u^2) R |s~| + 2^-14 (R + |s~|)^2 (Cauchy-Schwarz on the
+//      rounded products, plus the rounding of the norm and of the FP32
+//      accumulation); a 32 x 32 tile whose every E + eps < -127 has weights
+//      exactly 0 in FP32 and is skipped;
+//   3. a live tile completes E with the products hi.mid, mid.hi, hi.lo,
+//      lo.hi and mid.mid, whose remaining error is of order u^3 R |s~| plus
+//      the FP32 accumulation of terms of size (R + |s~|)^2;
+//   4. pairs for which that is not accurate enough are computed in FP32 by
+//      direct differences (distance, weight and w (x - s), as the FP32 step
+//      does): an outlier point whose compensated E, with its own small bound,
+//      can still give a nonzero weight; and every point of the block for a
+//      seed with (Rin + |s~|)^2 > 64 that can still have a weight of 2^-9 or
+//      more there.  (The MFMA aligns the products of an output to its
+//      largest term and truncates a few bits below that term's ulp: an
+//      outlier's large x~ in W.X~, or |E|-sized partial sums, would swamp
+//      the small products; the compensation products and each tile's W.X~
+//      therefore start from a zero accumulator and are added in FP32);
+//   5. the other weights w = exp2(E) are made in registers, split into three
+//      bf16 parts, and W.X~ accumulates as the six products of order up to
+//      u^2 on MFMA, the weight sum alongside in FP32;
+//   6. the block centre comes back per block: sum w (x - s) =
+//      sum w x~ - (s - c) sum w.
+// Every decision is per pair or per seed, or skips pairs whose weight is
+// exactly 0, so a seed's result never depends on the other seeds of its wave.
+// MFMA layouts (v_mfma_f32_32x32x16_bf16): A lane l holds row l%32 and
+// k = 8 (l/32) .. + 8; B lane l holds k = 8 (l/32) .. + 8 and column l%32; the
+// accumulator lane l holds column l%32 and rows 8 (v/4) + 4 (l/32) + v%4.
+// For W.X the weights of a lane (its column's seed, its 16 rows) are the A
+// operand as they stand; the point order of K follows that register order.
+
+#include "step_common.h"
+
+namespace fms {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kFThreads = 256;   // 4 waves x 32 seeds
+constexpr int kFSeeds = 128;     // seeds per tile
+constexpr int kFBlk = 256;       // points per block
+constexpr float kPadNorm = -1e30f;   // padding points: finite, weight 0
+// Points farther than this (packed units) from their block's centre are the
+// block's outliers: their pairs are recomputed exactly when they can matter.
+constexpr float kInlierR = 4.0f;
+// (Rin + |s~|)^2 above which a seed's distances to a block are recomputed in
+// FP32 (packed units), unless every weight it can have there is below
+// 2^-(3^2): the expanded form's terms are then too large for its FP32
+// accumulation
+constexpr float kExpandedMax = 64.0f;
+constexpr float kFarLower = 3.0f;
+
+template <int D>
+struct FShape {
+    static constexpr int KBH = (D + 3 + 15) / 16;   // K steps of the hi operand (with the norm)
+    static constexpr int KBL = (D + 15) / 16;       // K steps of the mid and lo operands
+    static constexpr int HI_BYTES = (kFBlk / 32) * KBH * 512 * 2;   // per block
+    static constexpr int LO_BYTES = (kFBlk / 32) * KBL * 512 * 2;   // each of mid and lo
+    static constexpr int STAGE = HI_BYTES + 2 * LO_BYTES;
+    static constexpr int FIN = (D + 1) * kFSeeds * 4;
+    static constexpr int TR = 4 * 32 * 33 * 4;
+    static constexpr int SMEM = STAGE > FIN ? (STAGE > TR ? STAGE : TR) : (FIN > TR ? FIN : TR);
+    // per-block row of the centring: centre[D], R, Rin, 6 unused, then the
+    // outlier bits of the 8 tiles (a uint32 each, bit p = point p of the tile)
+    static constexpr int INFO = D + 16;
+    static_assert(STAGE % (16 * kFThreads) == 0, "stage layout");
+};
+
+struct Bf16fArgs {
+    StepArgs base;
+    const float* info;     // per block: centre[D], R, Rin, .., outlier bits (FShape::INFO floats)
+    const __bf16* fhi;     // [tile][kb][half][point][8]: x~hi | -|x~|^2 hi, mid, lo
+    const __bf16* fmid;    // [tile][kb][half][point][8]: x~mid
+    const __bf16* flo;     // [tile][kb][half][point][8]: x~lo
+    const float* Xs;       // sorted, shifted points (n x D, packed units)
+    const float* shift;    // frame shift (D floats)
+};
+
+__device__ __forceinline__ float bfr(float x) { return (float)(__bf16)x; }
+
+// Centring and operands of the points, built once per fit from the sorted
+// points, one workgroup per block: the block's median centre (per
+// coordinate, the live point of rank (nl - 1) / 2, ties broken by index),
+// its radii, the outlier bits and the three bf16 parts.
+template <int D>
+__global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __restrict__ Xs, int n,
+                                                               __bf16* fhi, __bf16* fmid, __bf16* flo,
+                                                               float* info) {
+    using Sh = FShape<D>;
+    __shared__ __attribute__((aligned(16))) float vals[kFBlk];
+    __shared__ float ctr[D];
+    __shared__ float rmax[2][kFBlk / 64];
+    const int tid = threadIdx.x;
+    const int blk = blockIdx.x;
+    const int i = blk * kFBlk + tid;
+    const int nl = min(kFBlk, n - blk * kFBlk);   // live points of the block (>= 1)
+    const bool live = tid < nl;
+    const int mid = (nl - 1) / 2;
+    float x[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = live ? Xs[(long long)i * D + k] : 0.0f;
+    if (tid < D) ctr[tid] = Xs[(long long)blk * kFBlk * D + tid];   // stands in if ranks tie oddly (NaN)
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+        const float xv = x[k];
+        vals[tid] = live ? xv : __builtin_inff();
+        __syncthreads();
+        int rank = 0;
+        const float4* v4 = reinterpret_cast<const float4*>(vals);
+#pragma unroll 4
+        for (int j4 = 0; j4 < kFBlk / 4; ++j4) {
+            const float4 u = v4[j4];
+            const int j = 4 * j4;
+            rank += (u.x < xv) || (u.x == xv && j < tid);
+            rank += (u.y < xv) || (u.y == xv && j + 1 < tid);
+            rank += (u.z < xv) || (u.z == xv && j + 2 < tid);
+            rank += (u.w < xv) || (u.w == xv && j + 3 < tid);
+        }
+        if (live && rank == mid) ctr[k] = xv;
+        __syncthreads();   // vals is rewritten for the next coordinate
+    }
+    float xt[D];
+    float nx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        xt[k] = live ? x[k] - ctr[k] : 0.0f;
+        nx = fmaf(xt[k], xt[k], nx);
+    }
+    const bool outl = live && nx > kInlierR * kInlierR;
+    float ra = live ? nx : 0.0f, ri = (live && !outl) ? nx : 0.0f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        ra = fmaxf(ra, __shfl_xor(ra, off));
+        ri = fmaxf(ri, __shfl_xor(ri, off));
+    }
+    const unsigned long long om = __ballot(outl);
+    const int wave = tid >> 6;
+    float* g = info + (long long)blk * Sh::INFO;
+    if ((tid & 63) == 0) {
+        rmax[0][wave] = ra;
+        rmax[1][wave] = ri;
+        // tile 2 wave + h holds points 64 wave + 32 h ..: the ballot's halves
+        unsigned* bits = reinterpret_cast<unsigned*>(g + D + 8);
+        bits[2 * wave] = (unsigned)om;
+        bits[2 * wave + 1] = (unsigned)(om >> 32);
+    }
+    __syncthreads();
+    if (tid < D) g[tid] = ctr[tid];
+    if (tid == 0) {
+        float a = 0.0f, b = 0.0f;
+        for (int w = 0; w < kFBlk / 64; ++w) {
+            a = fmaxf(a, rmax[0][w]);
+            b = fmaxf(b, rmax[1][w]);
+        }
+        // rounded up slightly, so that they bound the FP32 distances
+        g[D] = sqrtf(a) * 1.0001f + 1e-30f;
+        g[D + 1] = sqrtf(b) * 1.0001f + 1e-30f;
+    }
+    const float ph = live ? bfr(-nx) : kPadNorm;
+    const float pm = live ? bfr(-nx - ph) : 0.0f;
+    const float pl = live ? bfr((-nx - ph) - pm) : 0.0f;
+    __bf16* oh = fhi + (long long)(i >> 5) * (Sh::KBH * 512) + (i & 31) * 8;
+#pragma unroll
+    for (int s = 0; s < Sh::KBH * 16; ++s) {
+        float v = 0.0f;
+        if (s < D) v = bfr(xt[s]);
+        else if (s == D) v = ph;
+        else if (s == D + 1) v = pm;
+        else if (s == D + 2) v = pl;
+        oh[(s >> 4) * 512 + ((s >> 3) & 1) * 256 + (s & 7)] = (__bf16)v;
+    }
+    __bf16* om2 = fmid + (long long)(i >> 5) * (Sh::KBL * 512) + (i & 31) * 8;
+    __bf16* ol = flo + (long long)(i >> 5) * (Sh::KBL * 512) + (i & 31) * 8;
+#pragma unroll
+    for (int s = 0; s < Sh::KBL * 16; ++s) {
+        float vm = 0.0f, vl = 0.0f;
+        if (s < D) {
+            const float h = bfr(xt[s]);
+            vm = bfr(xt[s] - h);
+            vl = bfr((xt[s] - h) - vm);
+        }
+        const int o = (s >> 4) * 512 + ((s >> 3) & 1) * 256 + (s & 7);
+        om2[o] = (__bf16)vm;
+        ol[o] = (__bf16)vl;
+    }
+}
+
+// One bf16 of coordinate c of staged point p (tile tt) from an operand stored
+// [tile][kb][half][point][8] with `kbs` K steps per tile.
+__device__ __forceinline__ __bf16 staged_coord(const __bf16* base, int kbs, int tt, int p, int c) {
+    return base[((tt * kbs + (c >> 4)) * 2 + ((c >> 3) & 1)) * 256 + p * 8 + (c & 7)];
+}
+
+template <int D>
+__global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, int t) {
+    using Sh = FShape<D>;
+    constexpr int TS = kFSeeds;
+    constexpr int KBH = Sh::KBH, KBL = Sh::KBL;
+    const StepArgs& a = A.base;
+    Ctl* ctl = a.ctl;
+    const int n = a.n;
+    const int m = active_count(ctl, t);
+    step_prologue(a, t, m);
+    if (m == 0) return;
+    const int G = gridDim.x;
+    const int tiles = (m + TS - 1) / TS;
+    const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
+    const int nblk = (n + kFBlk - 1) / kFBlk;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 31, hf = lane >> 5;
+
+    __shared__ __attribute__((aligned(16))) char smem[Sh::SMEM];
+    const __bf16* shi = reinterpret_cast<const __bf16*>(smem);
+    const __bf16* smid = reinterpret_cast<const __bf16*>(smem + Sh::HI_BYTES);
+    const __bf16* slo = reinterpret_cast<const __bf16*>(smem + Sh::HI_BYTES + Sh::LO_BYTES);
+    unsigned long long live_pairs = 0;   // wave-uniform: pairs of the live tiles
+
+    const const_f32_ptr gq = wave_uniform_const(A.info);   // block centring: scalar loads
+    for (int item = blockIdx.x; item < tiles * chunks; item += G) {
+        const int tile = item % tiles;
+        const int chunk = item / tiles;
+        const int b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
+        const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
+        const int slot = tile * TS + wave * 32 + col;
+        const bool live = slot < m;
+        const unsigned long long lmask = __ballot(live);   // lanes holding a seed
+        const int j = a.act_in[live ? slot : 0];
+        float shat[D], aex[D];
+        float wsum = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            shat[k] = a.S[(long long)j * D + k] * a.scale - A.shift[k];
+            aex[k] = 0.0f;
+        }
+        f32x16 acc = f32x16{};   // sum of w x~ over the chunk: column = coordinate, rows = seeds
+
+        for (int blk = b0; blk < b1; ++blk) {
+            const const_f32_ptr gm = gq + (long long)blk * Sh::INFO;
+            const float R = gm[D];
+            const float Rin = gm[D + 1];
+            float st[D];
+            float ns = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                st[k] = shat[k] - gm[k];
+                ns = fmaf(st[k], st[k], ns);
+            }
+            const float dist = sqrtf(ns);
+            const float eps = 0.016f * R * dist + (1.0f / 16384.0f) * (R + dist) * (R + dist);
+            // 1. no pair of the block can reach the screen: E + eps >= -127
+            //    needs |x - s|^2 <= 127 + 2 eps, and |x - s| >= |s~| - R
+            const float lower = dist * (1.0f - 1e-5f) - R;
+            const bool maybe = live && !(lower > 0.0f && lower * lower > (127.0f + 2.0f * eps) * 1.001f + 1e-6f);
+            if (!__syncthreads_or(maybe)) continue;   // (also: the previous block's stage is free)
+            {
+                const uint4* gh = reinterpret_cast<const uint4*>(A.fhi + (long long)blk * (Sh::HI_BYTES / 2));
+                const uint4* gm2 = reinterpret_cast<const uint4*>(A.fmid + (long long)blk * (Sh::LO_BYTES / 2));
+                const uint4* gl = reinterpret_cast<const uint4*>(A.flo + (long long)blk * (Sh::LO_BYTES / 2));
+                uint4* sm = reinterpret_cast<uint4*>(smem);
+                constexpr int NH = Sh::HI_BYTES / 16, NL = Sh::LO_BYTES / 16;
+                // in two passes (the hi operand, then mid and lo), so that
+                // fewer registers hold vectors in flight
+                {
+                    uint4 v[NH / kFThreads];
+#pragma unroll
+                    for (int q = 0; q < NH / kFThreads; ++q) v[q] = gh[q * kFThreads + threadIdx.x];
+#pragma unroll
+                    for (int q = 0; q < NH / kFThreads; ++q) sm[q * kFThreads + threadIdx.x] = v[q];
+                }
+                {
+                    uint4 v[2 * NL / kFThreads];
+#pragma unroll
+                    for (int q = 0; q < 2 * NL / kFThreads; ++q) {
+                        const int f = q * kFThreads + threadIdx.x;
+                        v[q] = f < NL ? gm2[f] : gl[f - NL];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 2 * NL / kFThreads; ++q) sm[NH + q * kFThreads + threadIdx.x] = v[q];
+                }
+            }
+            __syncthreads();
+            if (__ballot(maybe)) {
+                // seed operands of this block: [2 s~hi | 1 | 1 | 1 | 0..], [2 s~mid | 0..], [2 s~lo | 0..]
+                bf16x8 bh[KBH], bm[KBL], bl[KBL];
+#pragma unroll
+                for (int kb = 0; kb < KBH; ++kb) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        // the slot for hf = 0 is s0, for hf = 1 it is s0 + 8
+                        const int s0 = kb * 16 + e, s1 = s0 + 8;
+                        const float c0 = s0 < D ? 2.0f * st[s0 < D ? s0 : 0] : 0.0f;
+                        const float c1 = s1 < D ? 2.0f * st[s1 < D ? s1 : 0] : 0.0f;
+                        const float one0 = (s0 >= D && s0 <= D + 2) ? 1.0f : 0.0f;
+                        const float one1 = (s1 >= D && s1 <= D + 2) ? 1.0f : 0.0f;
+                        const float c = hf ? c1 : c0;
+                        const float vh = bfr(c);
+                        const float vm = bfr(c - vh);
+                        bh[kb][e] = (__bf16)(vh + (hf ? one1 : one0));
+                        if (kb < KBL) {
+                            bm[kb][e] = (__bf16)vm;
+                            bl[kb][e] = (__bf16)bfr((c - vh) - vm);
+                        }
+                    }
+                }
+                // the expanded form's terms are too large for its FP32
+                // accumulation and the weights can be sizeable: this seed's
+                // distances to the block are recomputed exactly
+                const bool exact_seed = live && (Rin + dist) * (Rin + dist) > kExpandedMax &&
+                                        dist * (1.0f - 1e-5f) - Rin < kFarLower;
+                // the compensated E's bound for the outliers (R their radius)
+                const float eps3 = 1.2e-6f * R * dist + 1e-6f * (R + dist) * (R + dist);
+                float wb = 0.0f;   // this lane's weight sum over the block
+                unsigned long long nlive = 0;
+#pragma unroll 1
+                for (int tt = 0; tt < kFBlk / 32; ++tt) {
+                    // the hi products (the screen), from -|s~|^2
+                    f32x16 E;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) E[v] = -ns;
+#pragma unroll
+                    for (int kb = 0; kb < KBH; ++kb) {
+                        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(shi + (tt * KBH + kb) * 512 + hf * 256 + col * 8);
+                        E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[kb], E, 0, 0, 0);
+                    }
+                    const float m0 = fmaxf(fmaxf(E[0], E[1]), E[2]);
+                    const float m1 = fmaxf(fmaxf(E[3], E[4]), E[5]);
+                    const float m2 = fmaxf(fmaxf(E[6], E[7]), E[8]);
+                    const float m3 = fmaxf(fmaxf(E[9], E[10]), E[11]);
+                    const float m4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
+                    const float emax = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[15]));
+                    // 2. every weight of the tile is exactly 0 in FP32
+                    if (!__ballot(live && emax + eps >= -127.0f)) continue;
+                    nlive += (unsigned long long)__popcll(lmask) * 16;
+                    // 3. the compensated products, in an accumulator of their
+                    //    own (their sizes are u and u^2 of the hi products)
+                    {
+                        f32x16 Ec = f32x16{};
+#pragma unroll
+                        for (int kb = 0; kb < KBL; ++kb) {
+                            const int o = (tt * KBL + kb) * 512 + hf * 256 + col * 8;
+                            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(shi + (tt * KBH + kb) * 512 + hf * 256 + col * 8);
+                            const bf16x8 am = *reinterpret_cast<const bf16x8*>(smid + o);
+                            const bf16x8 al = *reinterpret_cast<const bf16x8*>(slo + o);
+                            Ec = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bm[kb], Ec, 0, 0, 0);
+                            Ec = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bh[kb], Ec, 0, 0, 0);
+                            Ec = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[kb], Ec, 0, 0, 0);
+                            Ec = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[kb], Ec, 0, 0, 0);
+                            Ec = __builtin_amdgcn_mfma_f32_32x32x16_bf16(am, bm[kb], Ec, 0, 0, 0);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) E[v] += Ec[v];
+                    }
+                    // 4. the pairs that are computed in FP32 by direct
+                    //    differences, as the FP32 step does: distance, weight,
+                    //    and w (x - s) into the seed's own sums; the MFMA sees
+                    //    weight 0 for them (its products would be truncated
+                    //    against the large x~ of an outlier)
+                    const unsigned obits = __float_as_uint(gm[D + 8 + tt]);
+                    if (obits != 0u || __ballot(exact_seed)) {
+                        const long long r0 = (long long)blk * kFBlk + tt * 32;
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int p = 8 * (v >> 2) + 4 * hf + (v & 3);
+                            const long long r = r0 + p;
+                            const bool need = exact_seed || (live && ((obits >> p) & 1u) && E[v] + eps3 >= -127.0f);
+                            if (__ballot(need)) {
+                                if (need && r < n) {
+                                    const float4* xr = reinterpret_cast<const float4*>(A.Xs + r * D);
+                                    float q2 = 0.0f;
+#pragma unroll
+                                    for (int k4 = 0; k4 < D; k4 += 4) {
+                                        const float4 x4 = xr[k4 / 4];
+                                        const float d0 = x4.x - shat[k4], d1 = x4.y - shat[k4 + 1];
+                                        const float d2 = x4.z - shat[k4 + 2], d3 = x4.w - shat[k4 + 3];
+                                        q2 = fmaf(d0, d0, q2);
+                                        q2 = fmaf(d1, d1, q2);
+                                        q2 = fmaf(d2, d2, q2);
+                                        q2 = fmaf(d3, d3, q2);
+                                    }
+                                    const float we = __builtin_amdgcn_exp2f(-q2);
+                                    wsum += we;
+#pragma unroll
+                                    for (int k4 = 0; k4 < D; k4 += 4) {
+                                        const float4 x4 = xr[k4 / 4];
+                                        aex[k4] = fmaf(we, x4.x - shat[k4], aex[k4]);
+                                        aex[k4 + 1] = fmaf(we, x4.y - shat[k4 + 1], aex[k4 + 1]);
+                                        aex[k4 + 2] = fmaf(we, x4.z - shat[k4 + 2], aex[k4 + 2]);
+                                        aex[k4 + 3] = fmaf(we, x4.w - shat[k4 + 3], aex[k4 + 3]);
+                                    }
+                                }
+                                if (need) E[v] = kPadNorm;
+                            }
+                        }
+                    }
+                    // 5. weights and W.X~
+                    bf16x8 wh[2], wm[2], wl[2];
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const float w = live ? __builtin_amdgcn_exp2f(E[v]) : 0.0f;
+                        const float h = bfr(w);
+                        const float mm = bfr(w - h);
+                        const float l = bfr((w - h) - mm);
+                        wb += w;
+                        wh[v >> 3][v & 7] = (__bf16)h;
+                        wm[v >> 3][v & 7] = (__bf16)mm;
+                        wl[v >> 3][v & 7] = (__bf16)l;
+                    }
+                    // the tile's W.X~ in a fresh accumulator, added to the
+                    // chunk's sums in FP32 (the MFMA would truncate the
+                    // tile's products against the running sums)
+                    f32x16 tw = f32x16{};
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks) {
+                        // this lane's column c = col of X~: the 8 points of K step ks
+                        // w x~ = (wh + wm + wl)(xh + xm + xl) to a relative
+                        // u^3: the six products of order up to u^2
+                        bf16x8 xh, xm, xl;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int p = 16 * ks + 8 * (e >> 2) + 4 * hf + (e & 3);
+                            xh[e] = col < D ? staged_coord(shi, KBH, tt, p, col) : (__bf16)0.0f;
+                            xm[e] = col < D ? staged_coord(smid, KBL, tt, p, col) : (__bf16)0.0f;
+                            xl[e] = col < D ? staged_coord(slo, KBL, tt, p, col) : (__bf16)0.0f;
+                        }
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[ks], xh, tw, 0, 0, 0);
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[ks], xm, tw, 0, 0, 0);
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wm[ks], xh, tw, 0, 0, 0);
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wh[ks], xl, tw, 0, 0, 0);
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wl[ks], xh, tw, 0, 0, 0);
+                        tw = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wm[ks], xm, tw, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc[v] += tw[v];
+                }
+                // 6. sum w (x - s) = sum w x~ - (s - c) sum w, this block's part
+                // (s~ recomputed from the scalar geometry row: not kept live
+                // through the tiles)
+#pragma unroll
+                for (int k = 0; k < D; ++k) aex[k] = fmaf(-wb, shat[k] - gm[k], aex[k]);
+                wsum += wb;
+                live_pairs += nlive;
+            }
+        }
+
+        // the chunk's sum w x~ (column = coordinate, rows = seeds) into the
+        // seed lanes through LDS; the two lane halves saw different points
+        __syncthreads();   // the stage is free
+        float* tr = reinterpret_cast<float*>(smem) + wave * 32 * 33;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tr[(8 * (v >> 2) + 4 * hf + (v & 3)) * 33 + col] = acc[v];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < D; ++k) aex[k] += __shfl_xor(aex[k], 32);
+        wsum += __shfl_xor(wsum, 32);
+#pragma unroll
+        for (int k = 0; k < D; ++k) aex[k] += tr[col * 33 + k];
+        __syncthreads();   // tr is read before smem is reused
+        const int pos = wave * 32 + col;
+        if (chunks == 1) {
+            float* fin = reinterpret_cast<float*>(smem);
+            if (hf == 0) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) fin[k * TS + pos] = aex[k];
+                fin[D * TS + pos] = wsum;
+            }
+            __syncthreads();
+            finalize_tile<D, D, 2>(a, t, m, tile, fin);
+            __syncthreads();
+        } else if (hf == 0) {
+            float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
+#pragma unroll
+            for (int k = 0; k < D; ++k) dst[k] = aex[k];
+            dst[D] = wsum;
+        }
+    }
+    // pairs of the live tiles: wave counts summed per workgroup, one atomic
+    // per workgroup on one of the spread counters
+    __shared__ unsigned long long wref[kWaves];
+    if (lane == 0) wref[threadIdx.x >> 6] = live_pairs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0;
+        for (int w = 0; w < kWaves; ++w) r += wref[w];
+        if (r) atomicAdd((unsigned long long*)&ctl->refined[(blockIdx.x % kRefinedSlots) * kRefinedStride], r);
+    }
+}
+
+template <int D>
+hipError_t launch_bf16f_t(Batch& b, int t, hipStream_t s) {
+    using Sh = FShape<D>;
+    Bf16fArgs A;
+    StepArgs& a = A.base;
+    a.Xp = b.Xp;
+    a.n = b.n;
+    a.d = b.d;
+    a.min_chunk = b.sh.MC;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.red = b.part + step_red_offset(b.sh, b.n_seeds, b.grid);
+    a.prog = b.prog;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    a.metric = b.metric;
+    const int npad = (b.n + kFBlk - 1) / kFBlk * kFBlk;
+    A.fhi = (const __bf16*)b.pf;
+    A.fmid = A.fhi + (size_t)npad / 32 * Sh::KBH * 512;
+    A.flo = A.fmid + (size_t)npad / 32 * Sh::KBL * 512;
+    A.info = reinterpret_cast<const float*>(A.flo + (size_t)npad / 32 * Sh::KBL * 512);
+    A.Xs = b.Xs;
+    A.shift = b.shift;
+    hipLaunchKernelGGL((step_bf16f_kernel<D>), dim3(b.grid), dim3(kFThreads), 0, s, A, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_finalize<D, D, 2>(a, t, b.grid, b.n_seeds, s);
+}
+
+template <int D>
+size_t bf16f_bytes_t(int n) {
+    using Sh = FShape<D>;
+    const size_t blocks = (size_t)((n + kFBlk - 1) / kFBlk);
+    return blocks * (kFBlk / 32) * (Sh::KBH + 2 * Sh::KBL) * 512 * 2 + blocks * Sh::INFO * 4;
+}
+
+}  // namespace
+
+hipError_t launch_iteration_bf16f(Batch& b, int t, hipStream_t s) {
+    switch (b.sh.D) {
+        case 8: return launch_bf16f_t<8>(b, t, s);
+        case 16: return launch_bf16f_t<16>(b, t, s);
+        case 32: return launch_bf16f_t<32>(b, t, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t bf16f_feature_bytes(int n, int D) {
+    switch (D) {
+        case 8: return bf16f_bytes_t<8>(n);
+        case 16: return bf16f_bytes_t<16>(n);
+        case 32: return bf16f_bytes_t<32>(n);
+        default: return 0;
+    }
+}
+
+// (geom, the shared block geometry, is not used: this form centres its blocks
+// itself)
+hipError_t launch_bf16f_features(const float* Xs, int n, int D, const float* /*geom*/, void* feat,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nblk = (n + kFBlk - 1) / kFBlk;
+    const int npad = nblk * kFBlk;
+    __bf16* fhi = (__bf16*)feat;
+#define FMS_FEAT(DD)                                                                                      \
+    case DD: {                                                                                            \
+        __bf16* fmid = fhi + (size_t)npad / 32 * FShape<DD>::KBH * 512;                                   \
+        __bf16* flo = fmid + (size_t)npad / 32 * FShape<DD>::KBL * 512;                                   \
+        float* info = reinterpret_cast<float*>(flo + (size_t)npad / 32 * FShape<DD>::KBL * 512);          \
+        hipLaunchKernelGGL(bf16f_features_kernel<DD>, dim3(nblk), dim3(kFBlk), 0, s, Xs, n, fhi, fmid,   \
+                           flo, info);                                                                    \
+        break;                                                                                            \
+    }
+    switch (D) {
+        FMS_FEAT(8)
+        FMS_FEAT(16)
+        FMS_FEAT(32)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef FMS_FEAT
+    return hipGetLastError();
+}
+
+}  // namespace fms
