@@ -5,7 +5,10 @@
 // in space.  For D <= 4 points are ordered by the Morton code of their
 // quantized coordinates; for larger D (where a Morton code has too few bits
 // per axis) by their nearest pivot, pivots being a fixed sample of the points
-// (one per 1,024).  Both use a stable LSD radix sort, deterministic (no
+// (one per 256, at most 1,024, taken in the order of a greedy
+// nearest-neighbour chain), and within a pivot's run by distance; points far from
+// every pivot follow all the runs, so that they do not widen the runs' last
+// blocks.  Both use a stable LSD radix sort, deterministic (no
 // floating-point atomics; ranks inside a block come from wave ballots in wave
 // order).  The order only changes which points share a block: the update sums
 // over all points whatever their order.
@@ -317,19 +320,26 @@ __global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift)
     if (k < D) shift[k] = 0.5f * (bnd[2 * k] + bnd[2 * k + 1]);
 }
 
+// Distance (packed units) from the nearest pivot beyond which a point or seed
+// is sorted into the far region, after every pivot run.
+constexpr float kFarPivot = 8.0f;
+
 // Nearest pivot (ties to the lowest index) of each row r of `rows` (stride
 // DPr, times `scale`), pivots being the points Xp[j * n / P], j < P.  Key =
-// pivot index << 14 | the top 14 bits of the squared distance's FP32 pattern
-// (monotone in the distance), so that a pivot's rows run from near to far and
-// its few distant rows (outliers) share the last blocks instead of widening
-// every block of the pivot.  Rows whose status is not active (when status is
-// given) get bit 30, so that they sort last.
+// the pivot's rank in the chain order << 14 | the top 14 bits of the squared
+// distance's FP32 pattern (monotone in the distance), so that a pivot's rows
+// run from near to far and runs of nearby pivots are adjacent;
+// rows farther than kFarPivot from every pivot get bit 24, so that they
+// follow all the runs instead of widening the runs' last blocks.  Rows whose
+// status is not active (when status is given) get bit 30, so that they sort
+// last.
 template <int D>
 __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict__ rows, int m, int DPr,
                                                         float scale, const float* __restrict__ Xp,
                                                         int n, int DP, int P,
                                                         const uint8_t* __restrict__ status,
-                                                        unsigned* keys, int* vals) {
+                                                        const int* __restrict__ prank, unsigned* keys,
+                                                        int* vals) {
     constexpr int kTile = 128;
     constexpr int kPer = kTile * D / 256;   // pivot coordinates each thread stages per tile
     static_assert(D % 4 == 0 && (kTile * D) % 256 == 0, "pivot tile layout");
@@ -381,10 +391,64 @@ __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict_
         }
     }
     if (r >= m) return;
-    unsigned key = ((unsigned)bi << 14) | (__float_as_uint(best) >> 17);
+    unsigned key = ((unsigned)prank[bi] << 14) | (__float_as_uint(best) >> 17);
+    // far from every pivot: after all the pivot runs, so that a run's last
+    // block is not widened by scattered points
+    if (best > kFarPivot * kFarPivot) key |= 1u << 24;
     if (status && status[r] != ST_ACTIVE) key |= 1u << 30;
     keys[r] = key;
     vals[r] = r;
+}
+
+// Order of the pivots along a greedy nearest-neighbour chain: from pivot 0,
+// each next pivot is the nearest one not yet taken (ties to the lowest
+// index), so that the pivots of one cluster follow each other.  One
+// workgroup, a pivot per thread (its coordinates in registers); prank[j] =
+// the chain position of pivot j.
+template <int D>
+__global__ __launch_bounds__(1024) void pivot_chain_kernel(const float* __restrict__ Xp, int n, int DP, int P,
+                                                          int* prank) {
+    __shared__ float cur[D];
+    __shared__ unsigned long long wbest[16];
+    __shared__ int next;
+    const int j = threadIdx.x;
+    const bool mine = j < P;
+    float x[D];
+    const long long row = mine ? (long long)j * n / P : 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) x[k] = Xp[row * DP + k];
+    bool taken = j == 0;
+    if (j == 0) prank[0] = 0;
+    if (j < D) cur[j] = Xp[(long long)j];   // pivot 0 is point 0
+    __syncthreads();
+    for (int step = 1; step < P; ++step) {
+        float q = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float t = x[k] - cur[k];
+            q = fmaf(t, t, q);
+        }
+        // (distance bits, index): the minimum is the nearest, lowest index
+        unsigned long long key = (mine && !taken) ? ((unsigned long long)__float_as_uint(q) << 32) | (unsigned)j : ~0ull;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(key, off);
+            key = o < key ? o : key;
+        }
+        if ((j & 63) == 0) wbest[j >> 6] = key;
+        __syncthreads();
+        if (j == 0) {
+            unsigned long long b = wbest[0];
+            for (int w = 1; w < 16; ++w) b = wbest[w] < b ? wbest[w] : b;
+            next = (int)(unsigned)b;
+            prank[next] = step;
+        }
+        __syncthreads();
+        const int nx = next;
+        if (j == nx) taken = true;
+        if (j < D) cur[j] = Xp[((long long)nx * n / P) * DP + j];
+        __syncthreads();
+    }
 }
 
 // Per 256-point block of the sorted points: centre = midpoint of the bounding
@@ -466,7 +530,8 @@ struct SortWs {
 // bounds: 2D final + 2D per bounds block (256 blocks), D <= 32; then the
 // frame shift (32 floats)
 constexpr size_t kShiftOff = 2 * 32 + 2 * 32 * 256;
-constexpr size_t kBndFloats = kShiftOff + 64;
+constexpr size_t kRankOff = kShiftOff + 64;        // chain rank of each pivot (1024 ints)
+constexpr size_t kBndFloats = kRankOff + 1024;
 
 SortWs carve(void* ws, int count) {
     SortWs w;
@@ -524,7 +589,7 @@ size_t sort_workspace_bytes(int count) {
     }
 
 int pivot_count(int n) {
-    int P = n / 1024;
+    int P = n / 256;
     return P < 1 ? 1 : (P > 1024 ? 1024 : P);
 }
 
@@ -543,12 +608,15 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         hipLaunchKernelGGL(shift_kernel, dim3(1), dim3(64), 0, s, w.bnd, D, sh);
         shift = sh;
         const int P = pivot_count(n);
+        int* prank = reinterpret_cast<int*>(w.bnd + kRankOff);
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(1), dim3(1024), 0, s, Xp, n, DP,
+                                                P, prank));
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
-                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, w.k0, w.v0));
+                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, prank, w.k0, w.v0));
     }
-    // point keys: 24-bit Morton codes (D <= 4) or pivot index and distance
-    // (10 + 14 bits)
-    const int* sorted = radix_sort_pairs(w, n, s, 3);
+    // point keys: 24-bit Morton codes (D <= 4) or a far bit, pivot index and
+    // distance (1 + 10 + 14 bits)
+    const int* sorted = radix_sort_pairs(w, n, s, D <= 4 ? 3 : 4);
     hipError_t e = hipMemcpyAsync(perm, sorted, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * DP + 255) / 256)), dim3(256),
@@ -574,8 +642,9 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
     const SortWs w = carve(ws, m);
     if (D > 4) {
         const int P = pivot_count(n);
+        const int* prank = reinterpret_cast<const int*>(w.bnd + kRankOff);   // from launch_spatial_sort
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((m + 255) / 256), dim3(256), 0,
-                                                s, S, m, DP, scale, Xp, n, DP, P, status, w.k0, w.v0));
+                                                s, S, m, DP, scale, Xp, n, DP, P, status, prank, w.k0, w.v0));
     }
     if (m <= kSeedSortMax) {
         hipLaunchKernelGGL(seed_order_small_kernel, dim3(1), dim3(1024), 0, s, S, DP, D, m, scale,

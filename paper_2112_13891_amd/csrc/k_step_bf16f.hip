@@ -83,15 +83,16 @@ struct FShape {
     static constexpr int FIN = (D + 1) * kFSeeds * 4;
     static constexpr int TR = 4 * 32 * 33 * 4;
     static constexpr int SMEM = STAGE > FIN ? (STAGE > TR ? STAGE : TR) : (FIN > TR ? FIN : TR);
-    // per-block row of the centring: centre[D], R, Rin, 6 unused, then the
-    // outlier bits of the 8 tiles (a uint32 each, bit p = point p of the tile)
-    static constexpr int INFO = D + 16;
+    // per-block row of the centring: centre[D], R, Rin, Ro, 5 unused, the
+    // outlier bits of the 8 tiles (a uint32 each, bit p = point p of the
+    // tile), then the outliers' own centre[D] (Ro < 0: no outliers)
+    static constexpr int INFO = 2 * D + 16;
     static_assert(STAGE % (16 * kFThreads) == 0, "stage layout");
 };
 
 struct Bf16fArgs {
     StepArgs base;
-    const float* info;     // per block: centre[D], R, Rin, .., outlier bits (FShape::INFO floats)
+    const float* info;     // per block: centre, R, Rin, Ro, outlier bits, outlier centre (FShape::INFO floats)
     const __bf16* fhi;     // [tile][kb][half][point][8]: x~hi | -|x~|^2 hi, mid, lo
     const __bf16* fmid;    // [tile][kb][half][point][8]: x~mid
     const __bf16* flo;     // [tile][kb][half][point][8]: x~lo
@@ -104,7 +105,9 @@ __device__ __forceinline__ float bfr(float x) { return (float)(__bf16)x; }
 // Centring and operands of the points, built once per fit from the sorted
 // points, one workgroup per block: the block's median centre (per
 // coordinate, the live point of rank (nl - 1) / 2, ties broken by index),
-// its radii, the outlier bits and the three bf16 parts.
+// its radii, the outlier bits, the outliers' own ball (bounding-box
+// midpoint and radius: where two pivot runs meet, the block's other run) and
+// the three bf16 parts.
 template <int D>
 __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __restrict__ Xs, int n,
                                                                __bf16* fhi, __bf16* fmid, __bf16* flo,
@@ -112,7 +115,8 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
     using Sh = FShape<D>;
     __shared__ __attribute__((aligned(16))) float vals[kFBlk];
     __shared__ float ctr[D];
-    __shared__ float rmax[2][kFBlk / 64];
+    __shared__ float rmax[3][kFBlk / 64];
+    __shared__ float omin[kFBlk / 64][D], omax[kFBlk / 64][D], oc[D];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
     const int i = blk * kFBlk + tid;
@@ -158,26 +162,67 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
     }
     const unsigned long long om = __ballot(outl);
     const int wave = tid >> 6;
+    // the outliers' bounding box, per wave, then over the waves
+#pragma unroll 1
+    for (int k = 0; k < D; ++k) {
+        float lo = outl ? x[k] : __builtin_inff(), hi = outl ? x[k] : -__builtin_inff();
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo = fminf(lo, __shfl_xor(lo, off));
+            hi = fmaxf(hi, __shfl_xor(hi, off));
+        }
+        if ((tid & 63) == 0) {
+            omin[wave][k] = lo;
+            omax[wave][k] = hi;
+        }
+    }
+    __syncthreads();
+    if (tid < D) {
+        float lo = omin[0][tid], hi = omax[0][tid];
+        for (int w = 1; w < kFBlk / 64; ++w) {
+            lo = fminf(lo, omin[w][tid]);
+            hi = fmaxf(hi, omax[w][tid]);
+        }
+        oc[tid] = lo <= hi ? 0.5f * (lo + hi) : 0.0f;
+    }
+    __syncthreads();
+    float ro = -1.0f;
+    if (outl) {
+        ro = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const float t = x[k] - oc[k];
+            ro = fmaf(t, t, ro);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) ro = fmaxf(ro, __shfl_xor(ro, off));
     float* g = info + (long long)blk * Sh::INFO;
     if ((tid & 63) == 0) {
         rmax[0][wave] = ra;
         rmax[1][wave] = ri;
+        rmax[2][wave] = ro;
         // tile 2 wave + h holds points 64 wave + 32 h ..: the ballot's halves
         unsigned* bits = reinterpret_cast<unsigned*>(g + D + 8);
         bits[2 * wave] = (unsigned)om;
         bits[2 * wave + 1] = (unsigned)(om >> 32);
     }
     __syncthreads();
-    if (tid < D) g[tid] = ctr[tid];
+    if (tid < D) {
+        g[tid] = ctr[tid];
+        g[D + 16 + tid] = oc[tid];
+    }
     if (tid == 0) {
-        float a = 0.0f, b = 0.0f;
+        float a = 0.0f, b = 0.0f, c = -1.0f;
         for (int w = 0; w < kFBlk / 64; ++w) {
             a = fmaxf(a, rmax[0][w]);
             b = fmaxf(b, rmax[1][w]);
+            c = fmaxf(c, rmax[2][w]);
         }
         // rounded up slightly, so that they bound the FP32 distances
         g[D] = sqrtf(a) * 1.0001f + 1e-30f;
         g[D + 1] = sqrtf(b) * 1.0001f + 1e-30f;
+        g[D + 2] = c < 0.0f ? -1.0f : sqrtf(c) * 1.0001f + 1e-30f;
     }
     const float ph = live ? bfr(-nx) : kPadNorm;
     const float pm = live ? bfr(-nx - ph) : 0.0f;
@@ -272,9 +317,23 @@ __global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, i
             const float dist = sqrtf(ns);
             const float eps = 0.016f * R * dist + (1.0f / 16384.0f) * (R + dist) * (R + dist);
             // 1. no pair of the block can reach the screen: E + eps >= -127
-            //    needs |x - s|^2 <= 127 + 2 eps, and |x - s| >= |s~| - R
-            const float lower = dist * (1.0f - 1e-5f) - R;
-            const bool maybe = live && !(lower > 0.0f && lower * lower > (127.0f + 2.0f * eps) * 1.001f + 1e-6f);
+            //    needs |x - s|^2 <= 127 + 2 eps, and |x - s| >= |s~| - Rin for
+            //    the inliers, |s - co| - Ro for the outliers
+            const float reach = (127.0f + 2.0f * eps) * 1.001f + 1e-6f;
+            const float li = dist * (1.0f - 1e-5f) - Rin;
+            bool maybe = !(li > 0.0f && li * li > reach);
+            const float Ro = gm[D + 2];
+            if (!maybe && Ro >= 0.0f) {
+                float no = 0.0f;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const float u = shat[k] - gm[D + 16 + k];
+                    no = fmaf(u, u, no);
+                }
+                const float lo = sqrtf(no) * (1.0f - 1e-5f) - Ro;
+                maybe = !(lo > 0.0f && lo * lo > reach);
+            }
+            maybe = maybe && live;
             if (!__syncthreads_or(maybe)) continue;   // (also: the previous block's stage is free)
             {
                 const uint4* gh = reinterpret_cast<const uint4*>(A.fhi + (long long)blk * (Sh::HI_BYTES / 2));
