@@ -320,81 +320,86 @@ __global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift)
     if (k < D) shift[k] = 0.5f * (bnd[2 * k] + bnd[2 * k + 1]);
 }
 
-// Distance (packed units) from the nearest pivot beyond which a point or seed
-// is sorted into the far region, after every pivot run.
-constexpr float kFarPivot = 8.0f;
+// Nearest pivot of each row r of `rows` (stride DPr, times `scale`), pivots
+// being the points Xp[j * n / P], j < P, in two launches: pivot_near_kernel
+// takes a tile of rows against a chunk of kPivChunk pivots (so that few rows
+// still fill the machine) and folds its result into best[r] = (squared
+// distance bits << 32 | pivot index) with a 64-bit atomic minimum (the
+// nearest pivot, ties to the lowest index, whatever the order of the
+// chunks); pivot_key_kernel turns it into the sort key.
+constexpr int kPivChunk = 64;
 
-// Nearest pivot (ties to the lowest index) of each row r of `rows` (stride
-// DPr, times `scale`), pivots being the points Xp[j * n / P], j < P.  Key =
-// the pivot's rank in the chain order << 14 | the top 14 bits of the squared
-// distance's FP32 pattern (monotone in the distance), so that a pivot's rows
-// run from near to far and runs of nearby pivots are adjacent;
-// rows farther than kFarPivot from every pivot get bit 24, so that they
-// follow all the runs instead of widening the runs' last blocks.  Rows whose
-// status is not active (when status is given) get bit 30, so that they sort
-// last.
 template <int D>
-__global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict__ rows, int m, int DPr,
-                                                        float scale, const float* __restrict__ Xp,
-                                                        int n, int DP, int P,
-                                                        const uint8_t* __restrict__ status,
-                                                        const int* __restrict__ prank, unsigned* keys,
-                                                        int* vals) {
-    constexpr int kTile = 128;
-    constexpr int kPer = kTile * D / 256;   // pivot coordinates each thread stages per tile
-    static_assert(D % 4 == 0 && (kTile * D) % 256 == 0, "pivot tile layout");
-    __shared__ __attribute__((aligned(16))) float piv[kTile][D];
-    __shared__ long long prow[kTile];
+__global__ __launch_bounds__(256) void pivot_near_kernel(const float* __restrict__ rows, int m, int DPr,
+                                                         float scale, const float* __restrict__ Xp, int n,
+                                                         int DP, int P, unsigned long long* best) {
+    static_assert(D % 4 == 0 && (kPivChunk * D) % 256 == 0, "pivot chunk layout");
+    constexpr int kPer = kPivChunk * D / 256;   // pivot coordinates each thread stages
+    __shared__ __attribute__((aligned(16))) float piv[kPivChunk][D];
     const int r = blockIdx.x * 256 + threadIdx.x;
-    // rows past m load a valid row (their key is never written)
+    const int j0 = blockIdx.y * kPivChunk;
+    const int cnt = min(kPivChunk, P - j0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = u * 256 + threadIdx.x;
+        const int j = e / D, k = e % D;
+        piv[j][k] = j < cnt ? Xp[((long long)(j0 + j) * n / P) * DP + k] : 0.0f;
+    }
+    // rows past m load a valid row (nothing is written for them)
     const long long rr = r < m ? r : m - 1;
     float x[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = rows[rr * DPr + k] * scale;
-    float best = __builtin_inff();
+    __syncthreads();
+    float bq = __builtin_inff();
     int bi = 0;
-    for (int j0 = 0; j0 < P; j0 += kTile) {
-        const int cnt = min(kTile, P - j0);
-        __syncthreads();   // the previous tile is no longer read
-        if (threadIdx.x < cnt) prow[threadIdx.x] = (long long)(j0 + threadIdx.x) * n / P;
-        __syncthreads();
-        float v[kPer];
+    for (int j = 0; j < cnt; ++j) {
+        const float4* pj = reinterpret_cast<const float4*>(piv[j]);   // broadcast reads
+        float q = 0.0f;
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {   // all loads first, then the stores
-            const int e = u * 256 + threadIdx.x;
-            const int j = e / D, k = e % D;
-            v[u] = j < cnt ? Xp[prow[j] * DP + k] : 0.0f;
+        for (int k4 = 0; k4 < D / 4; ++k4) {
+            const float4 pv = pj[k4];
+            const float t0 = x[4 * k4] - pv.x, t1 = x[4 * k4 + 1] - pv.y;
+            const float t2 = x[4 * k4 + 2] - pv.z, t3 = x[4 * k4 + 3] - pv.w;
+            q = fmaf(t0, t0, q);
+            q = fmaf(t1, t1, q);
+            q = fmaf(t2, t2, q);
+            q = fmaf(t3, t3, q);
         }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int e = u * 256 + threadIdx.x;
-            piv[e / D][e % D] = v[u];
-        }
-        __syncthreads();
-        for (int j = 0; j < cnt; ++j) {
-            const float4* pj = reinterpret_cast<const float4*>(piv[j]);   // broadcast reads
-            float q = 0.0f;
-#pragma unroll
-            for (int k4 = 0; k4 < D / 4; ++k4) {
-                const float4 pv = pj[k4];
-                const float t0 = x[4 * k4] - pv.x, t1 = x[4 * k4 + 1] - pv.y;
-                const float t2 = x[4 * k4 + 2] - pv.z, t3 = x[4 * k4 + 3] - pv.w;
-                q = fmaf(t0, t0, q);
-                q = fmaf(t1, t1, q);
-                q = fmaf(t2, t2, q);
-                q = fmaf(t3, t3, q);
-            }
-            if (q < best) {
-                best = q;
-                bi = j0 + j;
-            }
+        if (q < bq) {
+            bq = q;
+            bi = j0 + j;
         }
     }
+    if (r < m) atomicMin(&best[r], ((unsigned long long)__float_as_uint(bq) << 32) | (unsigned)bi);
+}
+
+__global__ void fill_u64_kernel(unsigned long long* a, int count, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = v;
+}
+
+// Distance (packed units) from the nearest pivot beyond which a point or seed
+// is sorted into the far region, after every pivot run.
+constexpr float kFarPivot = 8.0f;
+
+// Sort key of row r from its nearest pivot: the pivot's rank in the chain
+// order << 14 | the top 14 bits of the squared distance's FP32 pattern
+// (monotone in the distance), so that a pivot's rows run from near to far and
+// runs of nearby pivots are adjacent; rows farther than kFarPivot from every
+// pivot get bit 24, so that they follow all the runs instead of widening the
+// runs' last blocks.  Rows whose status is not active (when status is given)
+// get bit 30, so that they sort last.
+__global__ void pivot_key_kernel(const unsigned long long* __restrict__ best, int m,
+                                 const uint8_t* __restrict__ status, const int* __restrict__ prank,
+                                 unsigned* keys, int* vals) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= m) return;
-    unsigned key = ((unsigned)prank[bi] << 14) | (__float_as_uint(best) >> 17);
-    // far from every pivot: after all the pivot runs, so that a run's last
-    // block is not widened by scattered points
-    if (best > kFarPivot * kFarPivot) key |= 1u << 24;
+    const unsigned long long b = best[r];
+    const unsigned qbits = (unsigned)(b >> 32);
+    const int bi = (int)(unsigned)b;
+    unsigned key = ((unsigned)prank[bi] << 14) | (qbits >> 17);
+    if (__uint_as_float(qbits) > kFarPivot * kFarPivot) key |= 1u << 24;
     if (status && status[r] != ST_ACTIVE) key |= 1u << 30;
     keys[r] = key;
     vals[r] = r;
@@ -402,53 +407,191 @@ __global__ __launch_bounds__(256) void pivot_key_kernel(const float* __restrict_
 
 // Order of the pivots along a greedy nearest-neighbour chain: from pivot 0,
 // each next pivot is the nearest one not yet taken (ties to the lowest
-// index), so that the pivots of one cluster follow each other.  One
-// workgroup, a pivot per thread (its coordinates in registers); prank[j] =
-// the chain position of pivot j.
+// index), so that the pivots of one cluster follow each other.  Two
+// launches: pivot_knn_kernel lists each pivot's kKnn nearest other pivots in
+// (distance, index) order; pivot_chain_kernel walks the chain in one thread,
+// whose next pivot is the first untaken one of the current pivot's list
+// (exactly the nearest untaken pivot), and only when every listed pivot is
+// taken does the whole workgroup search all pivots.  prank[j] = the chain
+// position of pivot j.
+constexpr int kKnn = 8;
+
+// One workgroup per 64 pivots; wave q of the sixteen scans the candidates
+// i = q (mod 16), and the sixteen lists of a pivot are merged through LDS.
 template <int D>
-__global__ __launch_bounds__(1024) void pivot_chain_kernel(const float* __restrict__ Xp, int n, int DP, int P,
-                                                          int* prank) {
-    __shared__ float cur[D];
-    __shared__ unsigned long long wbest[16];
-    __shared__ int next;
-    const int j = threadIdx.x;
-    const bool mine = j < P;
+__global__ __launch_bounds__(1024) void pivot_knn_kernel(const float* __restrict__ Xp, int n, int DP, int P,
+                                                         int* knn) {
+    constexpr int kW = 16;                     // waves
+    constexpr int kCand = 256;                 // candidates staged per pass
+    constexpr int kPer = kCand * D / 1024;
+    __shared__ __attribute__((aligned(16))) float cand[kCand][D];
+    __shared__ unsigned long long lists[kW][64][kKnn];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
+    const long long row = j < P ? (long long)j * n / P : 0;
     float x[D];
-    const long long row = mine ? (long long)j * n / P : 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = Xp[row * DP + k];
-    bool taken = j == 0;
-    if (j == 0) prank[0] = 0;
-    if (j < D) cur[j] = Xp[(long long)j];   // pivot 0 is point 0
+    unsigned long long best[kKnn];
+#pragma unroll
+    for (int t = 0; t < kKnn; ++t) best[t] = ~0ull;
+    for (int i0 = 0; i0 < P; i0 += kCand) {
+        const int cnt = min(kCand, P - i0);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int e = u * 1024 + threadIdx.x;
+            const int c = e / D, k = e % D;
+            cand[c][k] = c < cnt ? Xp[((long long)(i0 + c) * n / P) * DP + k] : 0.0f;
+        }
+        __syncthreads();
+        for (int c = q; c < cnt; c += kW) {
+            const int i = i0 + c;
+            const float4* pc = reinterpret_cast<const float4*>(cand[c]);
+            float d2 = 0.0f;
+#pragma unroll
+            for (int k4 = 0; k4 < D / 4; ++k4) {
+                const float4 v = pc[k4];
+                const float t0 = x[4 * k4] - v.x, t1 = x[4 * k4 + 1] - v.y;
+                const float t2 = x[4 * k4 + 2] - v.z, t3 = x[4 * k4 + 3] - v.w;
+                d2 = fmaf(t0, t0, d2);
+                d2 = fmaf(t1, t1, d2);
+                d2 = fmaf(t2, t2, d2);
+                d2 = fmaf(t3, t3, d2);
+            }
+            unsigned long long key = i == j ? ~0ull : ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)i;
+            // insertion into the sorted list (registers: a fixed compare-swap chain)
+#pragma unroll
+            for (int t = 0; t < kKnn; ++t) {
+                const unsigned long long lo = key < best[t] ? key : best[t];
+                const unsigned long long hi = key < best[t] ? best[t] : key;
+                best[t] = lo;
+                key = hi;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kKnn; ++t) lists[q][lane][t] = best[t];
     __syncthreads();
-    for (int step = 1; step < P; ++step) {
+    if (q == 0 && j < P) {
+        // merge the sixteen sorted lists: the kKnn smallest keys
+        int h[kW];
+#pragma unroll
+        for (int r = 0; r < kW; ++r) h[r] = 0;
+        for (int t = 0; t < kKnn; ++t) {
+            int wq = 0;
+            unsigned long long m = lists[0][lane][h[0]];
+#pragma unroll
+            for (int r = 1; r < kW; ++r) {
+                const unsigned long long v = lists[r][lane][h[r]];
+                if (v < m) {
+                    m = v;
+                    wq = r;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kW; ++r) h[r] += r == wq;
+            knn[j * kKnn + t] = m == ~0ull ? -1 : (int)(unsigned)m;
+        }
+    }
+}
+
+// The walk.  Wave 0 walks while the other waves wait at a barrier: lanes
+// 0..7 each read one entry of the current pivot's list and its taken flag,
+// and a ballot picks the first untaken entry (two LDS round trips a step).
+// When every listed pivot is taken, the whole workgroup searches all pivots
+// (a pivot per thread, its coordinates in registers; the current pivot's
+// coordinates from LDS) and wave 0 goes on from the nearest untaken one.
+// The taken flags and the ranks stay in LDS; the ranks go out at the end.
+template <int D>
+__global__ __launch_bounds__(1024) void pivot_chain_kernel(const float* __restrict__ Xp, int n, int DP, int P,
+                                                          const int* __restrict__ knn, int* prank) {
+    __shared__ __attribute__((aligned(16))) float4 pc[D / 4][1024];
+    __shared__ short lst[1024 * kKnn];
+    __shared__ unsigned char taken[1024];
+    __shared__ int rk[1024];
+    __shared__ unsigned long long wbest[16];
+    __shared__ int s_cur, s_step;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool mine = tid < P;
+    float x[D];
+    const long long row = mine ? (long long)tid * n / P : 0;
+#pragma unroll
+    for (int k4 = 0; k4 < D / 4; ++k4) {
+        const float4 v = *reinterpret_cast<const float4*>(Xp + row * DP + 4 * k4);
+        pc[k4][tid] = v;
+        x[4 * k4] = v.x;
+        x[4 * k4 + 1] = v.y;
+        x[4 * k4 + 2] = v.z;
+        x[4 * k4 + 3] = v.w;
+    }
+#pragma unroll
+    for (int t = 0; t < kKnn; ++t) lst[t * 1024 + tid] = mine ? (short)knn[tid * kKnn + t] : (short)-1;
+    taken[tid] = tid == 0 ? 1 : 0;
+    if (tid == 0) {
+        rk[0] = 0;
+        s_cur = 0;
+        s_step = 1;
+    }
+    __syncthreads();
+    int cur = 0, step = 1;   // wave 0's walk state
+    for (;;) {
+        if (wave == 0) {
+            while (step < P) {
+                const int c = lane < kKnn ? lst[lane * 1024 + cur] : -1;
+                const bool fr = c >= 0 && !taken[c < 0 ? 0 : c];
+                const unsigned long long bal = __ballot(fr);
+                if (!bal) break;
+                const int nx = __builtin_amdgcn_readlane(c, __builtin_ctzll(bal));
+                if (lane == 0) {
+                    taken[nx] = 1;
+                    rk[nx] = step;
+                }
+                cur = nx;
+                ++step;
+            }
+            if (lane == 0) {
+                s_cur = cur;
+                s_step = step;
+            }
+        }
+        __syncthreads();
+        const int c0 = s_cur, st = s_step;
+        if (st >= P) break;
+        // every listed pivot is taken: the nearest untaken one over all
         float q = 0.0f;
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-            const float t = x[k] - cur[k];
-            q = fmaf(t, t, q);
+        for (int k4 = 0; k4 < D / 4; ++k4) {
+            const float4 v = pc[k4][c0];
+            const float t0 = x[4 * k4] - v.x, t1 = x[4 * k4 + 1] - v.y;
+            const float t2 = x[4 * k4 + 2] - v.z, t3 = x[4 * k4 + 3] - v.w;
+            q = fmaf(t0, t0, q);
+            q = fmaf(t1, t1, q);
+            q = fmaf(t2, t2, q);
+            q = fmaf(t3, t3, q);
         }
-        // (distance bits, index): the minimum is the nearest, lowest index
-        unsigned long long key = (mine && !taken) ? ((unsigned long long)__float_as_uint(q) << 32) | (unsigned)j : ~0ull;
+        unsigned long long key = (mine && !taken[tid]) ? ((unsigned long long)__float_as_uint(q) << 32) | (unsigned)tid : ~0ull;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const unsigned long long o = __shfl_xor(key, off);
             key = o < key ? o : key;
         }
-        if ((j & 63) == 0) wbest[j >> 6] = key;
+        if (lane == 0) wbest[wave] = key;
         __syncthreads();
-        if (j == 0) {
+        if (wave == 0) {
             unsigned long long b = wbest[0];
+#pragma unroll
             for (int w = 1; w < 16; ++w) b = wbest[w] < b ? wbest[w] : b;
-            next = (int)(unsigned)b;
-            prank[next] = step;
+            const int nx = (int)(unsigned)b;
+            if (lane == 0) {
+                taken[nx] = 1;
+                rk[nx] = st;
+            }
+            cur = nx;
+            step = st + 1;
         }
-        __syncthreads();
-        const int nx = next;
-        if (j == nx) taken = true;
-        if (j < D) cur[j] = Xp[((long long)nx * n / P) * DP + j];
-        __syncthreads();
     }
+    if (mine) prank[tid] = rk[tid];
 }
 
 // Per 256-point block of the sorted points: centre = midpoint of the bounding
@@ -524,6 +667,7 @@ struct SortWs {
     unsigned* k1;
     int* v0;
     int* v1;
+    unsigned long long* best;   // nearest pivot per row (count)
     int* hist;
 };
 
@@ -532,6 +676,13 @@ struct SortWs {
 constexpr size_t kShiftOff = 2 * 32 + 2 * 32 * 256;
 constexpr size_t kRankOff = kShiftOff + 64;        // chain rank of each pivot (1024 ints)
 constexpr size_t kBndFloats = kRankOff + 1024;
+
+// the nearest-pivot keys (8 bytes per row), first used for the pivots'
+// neighbour lists (kKnn ints per pivot, at most 1,024 pivots)
+size_t best_bytes(int count) {
+    const size_t a = (size_t)count * 8, b = (size_t)1024 * kKnn * 4;
+    return a > b ? a : b;
+}
 
 SortWs carve(void* ws, int count) {
     SortWs w;
@@ -542,6 +693,7 @@ SortWs carve(void* ws, int count) {
     w.k1 = (unsigned*)p; p += (size_t)count * 4;
     w.v0 = (int*)p; p += (size_t)count * 4;
     w.v1 = (int*)p; p += (size_t)count * 4;
+    w.best = (unsigned long long*)p; p += best_bytes(count);
     w.hist = (int*)p;
     return w;
 }
@@ -574,7 +726,7 @@ int* radix_sort_pairs(const SortWs& w, int n, hipStream_t s, int passes = 4) {
 
 size_t sort_workspace_bytes(int count) {
     const size_t nblocks = (count + kSortThreads - 1) / kSortThreads;
-    return kBndFloats * 4 + 4 * 256 * 4 + (size_t)count * 4 * 4 + nblocks * 256 * 4 + 256;
+    return kBndFloats * 4 + 4 * 256 * 4 + (size_t)count * 4 * 4 + best_bytes(count) + nblocks * 256 * 4 + 256;
 }
 
 // Packed points Xp (n x DP) -> sorted copy Xs, permutation perm (Xs[i] =
@@ -609,10 +761,17 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         shift = sh;
         const int P = pivot_count(n);
         int* prank = reinterpret_cast<int*>(w.bnd + kRankOff);
+        int* knn = reinterpret_cast<int*>(w.best);   // free until the nearest-pivot search
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_knn_kernel<DD>), dim3((P + 63) / 64), dim3(1024), 0, s,
+                                                Xp, n, DP, P, knn));
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(1), dim3(1024), 0, s, Xp, n, DP,
-                                                P, prank));
-        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((n + 255) / 256), dim3(256), 0,
-                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, nullptr, prank, w.k0, w.v0));
+                                                P, knn, prank));
+        hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, ~0ull);
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>),
+                                                dim3((n + 255) / 256, (P + kPivChunk - 1) / kPivChunk), dim3(256), 0,
+                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, w.best));
+        hipLaunchKernelGGL(pivot_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, nullptr, prank,
+                           w.k0, w.v0);
     }
     // point keys: 24-bit Morton codes (D <= 4) or a far bit, pivot index and
     // distance (1 + 10 + 14 bits)
@@ -643,8 +802,12 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
     if (D > 4) {
         const int P = pivot_count(n);
         const int* prank = reinterpret_cast<const int*>(w.bnd + kRankOff);   // from launch_spatial_sort
-        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_key_kernel<DD>), dim3((m + 255) / 256), dim3(256), 0,
-                                                s, S, m, DP, scale, Xp, n, DP, P, status, prank, w.k0, w.v0));
+        hipLaunchKernelGGL(fill_u64_kernel, dim3((m + 255) / 256), dim3(256), 0, s, w.best, m, ~0ull);
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>),
+                                                dim3((m + 255) / 256, (P + kPivChunk - 1) / kPivChunk), dim3(256), 0,
+                                                s, S, m, DP, scale, Xp, n, DP, P, w.best));
+        hipLaunchKernelGGL(pivot_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, w.best, m, status, prank,
+                           w.k0, w.v0);
     }
     if (m <= kSeedSortMax) {
         hipLaunchKernelGGL(seed_order_small_kernel, dim3(1), dim3(1024), 0, s, S, DP, D, m, scale,
