@@ -27,7 +27,6 @@ Printed (one JSON line):
                    that oracle.
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -61,12 +60,20 @@ COUNTERS = {
 }
 
 
-def source_digest():
-    """Digest of the HIP sources, recorded next to the counter figures so that
-    stale figures are never reported."""
+# The sources each counted launch runs (its step kernels, their reduction and
+# finalize, and the spatial order that decides which blocks they skip).
+COUNTER_SOURCES = {
+    "c2": ["k_step.hip", "k_step_cull.hip", "k_step_bf16.hip", "k_sort.hip", "step_common.h"],
+    "c3": ["k_step_cull.hip", "k_step_bf16f.hip", "k_sort.hip", "step_common.h"],
+}
+
+
+def source_digest(which):
+    """Digest of the HIP sources of one counted launch, recorded next to its
+    counter figures so that stale figures are never reported."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2112_13891_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in COUNTER_SOURCES[which]:
+        with open(os.path.join(ROOT, "paper_2112_13891_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -75,8 +82,8 @@ def counter_figures(which, prec):
     """Figures of one fused-step iteration read from a committed counter
     summary ("- key: value" lines): HBM bytes (FETCH_SIZE and WRITE_SIZE,
     scaled by a copy kernel of known size), the executed MFMA flops and the
-    fraction of pairs the kernels evaluated.  Empty when the HIP sources
-    changed since the counters were taken."""
+    fraction of pairs the kernels evaluated.  Empty when the launch's HIP
+    sources changed since the counters were taken."""
     try:
         text = open(COUNTERS[which]).read()
     except OSError:
@@ -86,7 +93,7 @@ def counter_figures(which, prec):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_digest") != source_digest():
+    if vals.get("source_digest") != source_digest(which):
         return {}
     out = {}
     for key in ("traffic_bytes_per_iteration", "mfma_flops_per_iteration", "evaluated_pair_fraction"):
@@ -229,8 +236,8 @@ def config_c3(api, torch, workloads, gpu_fits, iters):
     seeds = torch.from_numpy(w.X[rng.choice(w.n, m, replace=False)]).cuda()
     for prec in ("fp32", "bf16"):
         t = time_kernel(api, torch, X, seeds, w.h, w.kernel, prec, iters)
-        name = ("step_cull_kernel<32, 1, 1> + finalize_kernel" if prec == "fp32"
-                else "step_bf16w_kernel<32, 1> + finalize_kernel")
+        name = ("step_cull_kernel<32, 1, 1> + reduce_kernel + finalize_kernel" if prec == "fp32"
+                else "step_bf16f_kernel<32> + reduce_kernel + finalize_kernel")
         out[prec]["roofline"] = roofline_entry(m * w.n, w.d, t, m, w.n, prec, f"{m} seeds x {w.n} points",
                                                name, counter_figures("c3", prec))
     out["bf16_kernel_speedup_vs_fp32"] = out["fp32"]["roofline"]["avg_ms"] / out["bf16"]["roofline"]["avg_ms"]

@@ -52,6 +52,13 @@ def test_roofline_entry_fields():
 
 
 def test_source_digest_is_stable_and_covers_the_kernel_sources():
-    a = bench.source_digest()
-    assert a == bench.source_digest()
-    assert len(a) == 16 and int(a, 16) >= 0
+    for which in ("c2", "c3"):
+        a = bench.source_digest(which)
+        assert a == bench.source_digest(which)
+        assert len(a) == 16 and int(a, 16) >= 0
+        for f in bench.COUNTER_SOURCES[which]:
+            assert os.path.exists(os.path.join(bench.ROOT, "paper_2112_13891_amd", "csrc", f)), f
+    # each launch's own step kernels are covered
+    assert "k_step_bf16.hip" in bench.COUNTER_SOURCES["c2"]
+    assert "k_step_bf16f.hip" in bench.COUNTER_SOURCES["c3"]
+    assert bench.source_digest("c2") != bench.source_digest("c3")
