@@ -226,11 +226,16 @@ __global__ __launch_bounds__(kWThreads) void step_bf16w_kernel(Bf16wArgs A, int 
                 const float m3 = fmaxf(fmaxf(E[9], E[10]), E[11]);
                 const float m4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
                 const float emax = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[15]));
-                if (!__ballot(emax + eps >= A.e_thr)) continue;
+                // only lanes holding a seed: the FP32 points of this block
+                // are in LDS only if one of them may need them (a lane past
+                // the active count would read what an earlier block or
+                // kernel left there, and even at weight 0 a NaN there
+                // spreads into the sums)
+                if (!__ballot(live && emax + eps >= A.e_thr)) continue;
                 unsigned long long nref = 0;
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    const bool need = E[v] + eps >= A.e_thr;
+                    const bool need = live && E[v] + eps >= A.e_thr;
                     const float* xr = sxs + (tt * 32 + 8 * (v >> 2) + 4 * hf + (v & 3)) * D;
                     // differences computed twice (distance, then accumulation)
                     // rather than held: the registers matter more than the

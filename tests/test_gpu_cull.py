@@ -134,3 +134,26 @@ def test_reduce_paths_at_many_chunks(orc, plain, m):
     ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, "gaussian", tol=1e-3, n_iter=2)
     ragged_check(orc, X, S0, h, "gaussian", 2, S.cpu().numpy(), it.cpu().numpy(), conv.cpu().numpy(),
                  ref, oit, ost)
+
+
+def test_bf16_flat_step_repeatable():
+    # a tile of the flat BF16 form is processed only for lanes holding a seed:
+    # a lane past the active count once forced tiles whose points were not in
+    # LDS, and a NaN left there by an earlier kernel spread into live seeds'
+    # sums (even at weight 0), now and then
+    n, d, h = 65537, 6, 1.5
+    X = clustered(n * 10 + d, n, d)
+    rng = np.random.default_rng(n + d)
+    S0 = X[rng.choice(n, 300, replace=False)]
+    Xg, Sg = _gpu(X), _gpu(S0)
+    first = None
+    for rep in range(16):
+        S, conv, it, sh = api.step(Xg, Sg, h, kernel="flat", precision="bf16", n_iter=2)
+        torch.cuda.synchronize()
+        out = (S.cpu().numpy(), conv.cpu().numpy(), it.cpu().numpy())
+        assert np.isfinite(out[0]).all() and (out[1] != 2).all(), rep
+        if first is None:
+            first = out
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(first, out)), rep
+
