@@ -315,7 +315,8 @@ float packed_scale(const ms_params* p) {
 // and device (grown on demand, never shrunk).
 enum Slot {
     SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
-    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN, SL_COUNT
+    SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN,
+    SL_JPTS, SL_JSEEDS, SL_JMODES, SL_COVERED, SL_CAND, SL_COUNT
 };
 
 // Handed to the orphan list when the thread exits (freed by the next call on
@@ -673,11 +674,27 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         FMS_HIP(launch_fill_u8(removed, n, 0, s));   // kept clear by each compaction
     }
 
+    // block join (spatially ordered sides) for the round epilogue and the
+    // labels once the modes are many; the points are indexed when first needed
+    const bool join_ok = join_shape_ok(base.D);
+    JoinIndex jpts{};
+    bool have_jpts = false;
+    auto points_index = [&]() -> int {
+        if (have_jpts) return MS_OK;
+        char* w;
+        FMS_CHECK(cache_get(C, budget, SL_JPTS, join_layout(n, DP, base.D).total, &w));
+        FMS_HIP(launch_join_index(X, n, d, d, DP, base.D, scale, w, &jpts, s));
+        have_jpts = true;
+        return MS_OK;
+    };
+
     // device mode store (DP stride), grown on demand
     int Kcap = std::min(n, 1024);
     float* modes_ws;
     FMS_CHECK(cache_get(C, budget, SL_MODES, (size_t)Kcap * DP, &modes_ws));
     std::vector<int32_t> counts;
+    // the mode each drawn point's seed ended in: a start for the labels' join
+    std::vector<int32_t> cand;
 
     FMS_CHECK(g_pin_ctl.ensure(2 * sizeof(Ctl)));
     Ctl* mirror = (Ctl*)g_pin_ctl.p;
@@ -751,15 +768,50 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
             Kcap = newcap;
         }
         const int kPasses = 3;
-        for (int q = 0; q < kPasses; ++q)
-            FMS_HIP(launch_merge_decide_pass(b.S, DP, d, b.status, B, modes_ws, K_old, r2m, bstate,
-                                             &ctl->und[q], q == 0, s));
+        // many seeds: their final positions are indexed once, for the merge
+        // (against the old modes, then the decision passes among the seeds)
+        // and, as the new modes, for the pool coverage
+        const bool join_merge = join_ok && B >= kJoinMin;
+        const bool join_cover = join_ok && !all && B >= kJoinMin && n >= kJoinMin;
+        JoinIndex jseeds{};
+        if (join_merge || join_cover) {
+            char* w;
+            FMS_CHECK(cache_get(C, budget, SL_JSEEDS, join_layout(B, DP, base.D).total, &w));
+            FMS_HIP(launch_join_index(b.S, B, DP, d, DP, base.D, scale, w, &jseeds, s));
+        }
+        if (join_merge) {
+            if (K_old > 0) {
+                char* w;
+                JoinIndex jmodes{};
+                FMS_CHECK(cache_get(C, budget, SL_JMODES, join_layout(K_old, DP, base.D).total, &w));
+                FMS_HIP(launch_join_index(modes_ws, K_old, DP, d, DP, base.D, scale, w, &jmodes, s));
+                FMS_HIP(launch_join(JOIN_FIRST, jseeds, jmodes, DP, base.D, r2m, nullptr, nullptr, b.status, bstate,
+                                    nullptr, nullptr, 0, nullptr, s));
+            }
+            for (int q = 0; q < kPasses; ++q)
+                FMS_HIP(launch_join(JOIN_DECIDE, jseeds, jseeds, DP, base.D, r2m, nullptr, nullptr, b.status,
+                                    bstate, nullptr, nullptr, 0, nullptr, s, K_old, q == 0, &ctl->und[q]));
+        } else {
+            for (int q = 0; q < kPasses; ++q)
+                FMS_HIP(launch_merge_decide_pass(b.S, DP, d, b.status, B, modes_ws, K_old, K_old, r2m, bstate,
+                                                 &ctl->und[q], q == 0, s));
+        }
         FMS_HIP(launch_merge_founders(b.S, DP, B, K_old, bstate, modes_ws, ctl, kPasses - 1, s));
         if (!all) {
             // seed pool: drop the drawn seeds and the points the new modes
             // cover, keep the rest in ascending order
-            FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, 0, ctl, r2c, removed,
-                                 block_tmp, s));
+            if (join_cover) {
+                uint8_t* covered;
+                FMS_CHECK(points_index());
+                FMS_CHECK(cache_get(C, budget, SL_COVERED, n, &covered));
+                FMS_HIP(launch_fill_u8(covered, n, 0, s));
+                FMS_HIP(launch_join(JOIN_ANY, jpts, jseeds, DP, base.D, r2c, nullptr, nullptr, nullptr, nullptr,
+                                    bstate, ctl, kPasses - 1, covered, s));
+                FMS_HIP(launch_pool_mark(pool[cur], pool_len, covered, removed, block_tmp, s));
+            } else {
+                FMS_HIP(launch_cover(X, d, pool[cur], pool_len, modes_ws, K_old, 0, ctl, r2c, removed,
+                                     block_tmp, s));
+            }
             FMS_HIP(launch_pool_compact(pool[cur], removed, pool_len, pool[cur ^ 1], block_tmp, ctl, s));
         }
 
@@ -817,6 +869,11 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         }
         if (!host_merge && K != cs.k_new)
             return fail(MS_E_HIP, "merge: device and host founder counts differ");
+        if (join_ok && n >= kJoinMin) {
+            if (cand.empty()) cand.assign(n, -1);
+            for (int i = 0; i < B; ++i)
+                if (mode_of[i] >= 0) cand[h_ids[i]] = mode_of[i];
+        }
         if (host_merge && K > K_old) {
             FMS_CHECK(g_pin_modes.ensure((size_t)(K - K_old) * DP * 4));
             float* hm = (float*)g_pin_modes.p;
@@ -887,7 +944,26 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
                              hipMemcpyDeviceToDevice, s));
     if (labels) {
         FMS_HIP(hipEventRecord(ev[2], s));
-        FMS_HIP(launch_assign(X, n, d, modes, K, labels, nullptr, s));
+        if (join_ok && K >= kJoinMin && n >= kJoinMin) {
+            // many modes: nearest mode by the block join (the same distances
+            // and ties as the brute-force labelling)
+            char* w;
+            JoinIndex jm{};
+            FMS_CHECK(points_index());
+            FMS_CHECK(cache_get(C, budget, SL_JMODES, join_layout(K, DP, base.D).total, &w));
+            FMS_HIP(launch_join_index(modes_ws, K, DP, d, DP, base.D, scale, w, &jm, s));
+            int32_t* dcand = nullptr;
+            if (!cand.empty()) {
+                FMS_CHECK(cache_get(C, budget, SL_CAND, n, &dcand));
+                FMS_CHECK(g_pin_pos.ensure((size_t)n * sizeof(int32_t)));
+                std::memcpy(g_pin_pos.p, cand.data(), (size_t)n * sizeof(int32_t));
+                FMS_HIP(hipMemcpyAsync(dcand, g_pin_pos.p, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            }
+            FMS_HIP(launch_join(JOIN_NEAREST, jpts, jm, DP, base.D, 0.0f, labels, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, 0, nullptr, s, 0, false, nullptr, dcand, modes_ws));
+        } else {
+            FMS_HIP(launch_assign(X, n, d, modes, K, labels, nullptr, s));
+        }
         FMS_HIP(hipEventRecord(ev[3], s));
     }
     FMS_HIP(wait_stream(s));

@@ -199,10 +199,13 @@ hipError_t launch_bf_assign(const float* X, int d, const long long* x_off, int n
                             const int32_t* m_off, int32_t* labels, long long n, hipStream_t s);
 
 hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
+constexpr int kCompactBlock = 1024;   // pool entries per compaction block
 // One merge decision pass over a batch of B seeds (the first pass also
-// settles seeds that did not converge and seeds that join an old mode).
+// settles seeds that did not converge and seeds that join one of the first
+// k_scan old modes: K_old, or 0 when the block join matched them already).
+// A seed joining batch seed j is recorded as K_old + j.
 hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t* status, int B,
-                                    const float* modes, int K_old, float r2, int32_t* state,
+                                    const float* modes, int K_old, int k_scan, float r2, int32_t* state,
                                     int32_t* und_counter, bool first, hipStream_t s);
 hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
                                  float* modes, Ctl* ctl, int und_slot, hipStream_t s);
@@ -219,6 +222,51 @@ hipError_t launch_pool_compact(const int32_t* pool_in, uint8_t* removed, int len
                                int32_t* pool_out, int32_t* block_tmp, Ctl* ctl,
                                hipStream_t s);
 int pool_compact_blocks(int len);
+
+// ---- block join of two large row sets (k_join.hip) ------------------------
+// Used when both sides have at least kJoinMin rows and the padded D is one of
+// 1..4, 8, 16, 32.
+constexpr int kJoinMin = 4096;
+enum : int { JOIN_NEAREST = 0, JOIN_FIRST = 1, JOIN_ANY = 2, JOIN_DECIDE = 3 };
+// Rows in spatial order (unchanged values, stride DP, zero beyond d), their
+// original indices, a ball (centre[D], radius; stride D + 4) per block of 256
+// rows, and each row's distance to its block's centre.
+struct JoinIndex {
+    const float* rows;
+    const int32_t* idx;
+    const float* ball;
+    const float* rho;
+    int count;
+};
+struct JoinLayout {
+    size_t packed, sorted_tmp, perm, geom_tmp, sort_ws, rows, ball, rho, total;
+};
+bool join_shape_ok(int D);
+JoinLayout join_layout(int count, int DP, int D);
+// Index of count rows of src (stride ld, d coordinates); `scale` only sets
+// the units of the spatial sort.  ws: join_layout(count, DP, D).total bytes,
+// which the index points into.
+hipError_t launch_join_index(const float* src, int count, int ld, int d, int DP, int D, float scale, void* ws,
+                             JoinIndex* out, hipStream_t s);
+// nearest: labels[q] = the nearest row's index (ties to the lowest), margin
+//   (optional) = sqrt(second) - sqrt(best); cand (optional, with rows_orig:
+//   the unsorted rows) gives per query a row to start from, or -1;
+// first: for converged queries whose state is MG_UNDECIDED, state[q] = the
+//   lowest row index within r2, if any;
+// any: covered[q] = 1 if a row whose rstate is MG_FOUNDER lies within r2
+//   (nothing while ctl->und[und_slot] > 0);
+// decide: one merge decision pass of a batch against itself (q and r index
+//   the batch seeds): seeds it leaves undecided are counted in und_counter;
+//   the first pass also settles the seeds that did not converge.
+hipError_t launch_join(int op, const JoinIndex& q, const JoinIndex& r, int DP, int D, float r2, int32_t* labels,
+                       float* margin, const uint8_t* status, int32_t* state, const int32_t* rstate, const Ctl* ctl,
+                       int und_slot, uint8_t* covered, hipStream_t s, int K_old = 0, bool first_pass = false,
+                       int32_t* und_counter = nullptr, const int32_t* cand = nullptr,
+                       const float* rows_orig = nullptr);
+// Pool entries whose point is covered leave the pool; writes the block counts
+// launch_pool_compact consumes.
+hipError_t launch_pool_mark(const int32_t* pool, int len, const uint8_t* covered, uint8_t* removed,
+                            int32_t* block_cnt, hipStream_t s);
 
 // ---- launchers (k_assign.hip) --------------------------------------------
 hipError_t launch_assign(const float* X, int n, int d, const float* modes, int k,

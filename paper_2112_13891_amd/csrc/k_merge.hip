@@ -55,7 +55,7 @@ constexpr int kWavesT = kT / 64;
 template <int D, bool kFirst>
 __global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S, int DP,
                                                     const uint8_t* __restrict__ status, int B,
-                                                    const float* __restrict__ modes, int K_old,
+                                                    const float* __restrict__ modes, int K_old, int k_scan,
                                                     float r2, int32_t* state, int32_t* und_counter) {
     const int i = blockIdx.x * kWavesT + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -64,15 +64,16 @@ __global__ __launch_bounds__(kT) void decide_kernel(const float* __restrict__ S,
         if (lane == 0) __atomic_store_n(&state[i], (int32_t)MG_SKIP, __ATOMIC_RELAXED);
         return;
     }
-    if (!kFirst && __atomic_load_n(&state[i], __ATOMIC_RELAXED) != MG_UNDECIDED) return;
+    // (a seed the block join matched to an old mode is decided already)
+    if (__atomic_load_n(&state[i], __ATOMIC_RELAXED) != MG_UNDECIDED) return;
     float si[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) si[k] = S[(long long)i * DP + k];
     if (kFirst) {
-        for (int base = 0; base < K_old; base += 64) {
+        for (int base = 0; base < k_scan; base += 64) {
             const int j = base + lane;
             bool hit = false;
-            if (j < K_old) hit = dist2<D>(si, modes + (long long)j * DP) <= r2;
+            if (j < k_scan) hit = dist2<D>(si, modes + (long long)j * DP) <= r2;
             const unsigned long long bal = __ballot(hit);
             if (bal) {
                 if (lane == 0)
@@ -125,7 +126,8 @@ template <int D, bool kFirst>
 __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restrict__ S, int DP,
                                                           const uint8_t* __restrict__ status, int B,
                                                           const float* __restrict__ modes, int K_old,
-                                                          float r2, int32_t* state, int32_t* und_counter) {
+                                                          int k_scan, float r2, int32_t* state,
+                                                          int32_t* und_counter) {
     constexpr int kRows = decide_rows<D>();
     __shared__ float rows[kRows][D];
     __shared__ int32_t rst[kRows];
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
     bool todo = false;   // this lane decides seed i in this pass
     if (i < B) {
         if (kFirst && status[i] != ST_CONVERGED) __atomic_store_n(&state[i], (int32_t)MG_SKIP, __ATOMIC_RELAXED);
-        else todo = kFirst || __atomic_load_n(&state[i], __ATOMIC_RELAXED) == MG_UNDECIDED;
+        else todo = __atomic_load_n(&state[i], __ATOMIC_RELAXED) == MG_UNDECIDED;
     }
     const bool owner = todo;
     float si[D];
@@ -142,9 +144,9 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
     for (int k = 0; k < D; ++k) si[k] = todo ? S[(long long)i * DP + k] : 0.0f;
     int result = MG_FOUNDER;   // unless an old mode or an earlier founder / undecided seed is within r
     if (kFirst) {
-        for (int base = 0; base < K_old; base += kRows) {
+        for (int base = 0; base < k_scan; base += kRows) {
             if (!__syncthreads_or(todo)) break;
-            const int cnt = min(kRows, K_old - base);
+            const int cnt = min(kRows, k_scan - base);
             for (int e = threadIdx.x; e < cnt * D; e += kT)
                 rows[e / D][e % D] = modes[(long long)(base + e / D) * DP + e % D];
             __syncthreads();
@@ -232,7 +234,6 @@ __global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __
     }
 }
 
-constexpr int kCompactBlock = 1024;
 constexpr int kModeTile = 256;
 
 // Pool coverage: entries of the pool list within r of a new mode [k0, k1)
@@ -375,7 +376,7 @@ hipError_t launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
     }
 
 hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t* status, int B,
-                                    const float* modes, int K_old, float r2, int32_t* state,
+                                    const float* modes, int K_old, int k_scan, float r2, int32_t* state,
                                     int32_t* und_counter, bool first, hipStream_t s) {
     const int D = step_shape(d).D;
     if (B <= 0) return hipSuccess;
@@ -383,20 +384,20 @@ hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t
         const dim3 tgrid((B + kT - 1) / kT);
         if (first) {
             FMS_DSWITCH(D, hipLaunchKernelGGL((decide_tiled_kernel<DD, true>), tgrid, dim3(kT), 0, s, S, DP,
-                                              status, B, modes, K_old, r2, state, und_counter));
+                                              status, B, modes, K_old, k_scan, r2, state, und_counter));
         } else {
             FMS_DSWITCH(D, hipLaunchKernelGGL((decide_tiled_kernel<DD, false>), tgrid, dim3(kT), 0, s, S, DP,
-                                              status, B, modes, K_old, r2, state, und_counter));
+                                              status, B, modes, K_old, k_scan, r2, state, und_counter));
         }
         return hipGetLastError();
     }
     const dim3 grid((B + kWavesT - 1) / kWavesT);
     if (first) {
         FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD, true>), grid, dim3(kT), 0, s, S, DP,
-                                          status, B, modes, K_old, r2, state, und_counter));
+                                          status, B, modes, K_old, k_scan, r2, state, und_counter));
     } else {
         FMS_DSWITCH(D, hipLaunchKernelGGL((decide_kernel<DD, false>), grid, dim3(kT), 0, s, S, DP,
-                                          status, B, modes, K_old, r2, state, und_counter));
+                                          status, B, modes, K_old, k_scan, r2, state, und_counter));
     }
     return hipGetLastError();
 }
