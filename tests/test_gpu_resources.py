@@ -71,25 +71,31 @@ def test_exited_threads_leave_no_device_memory():
             t.join()
         assert not errors, errors
 
-    # a first round brings up whatever the runtime keeps per process
+    # a first generation brings up whatever the runtime keeps per process
     round_of_threads()
     api.release_workspace()
     base = _free_bytes()
     # threads exit holding their caches; the next call on any thread frees
-    # them, so generations of threads do not add up
-    held.clear()
-    round_of_threads()
-    after1 = _free_bytes()
-    round_of_threads()
-    after2 = _free_bytes()
-    say("device workspace held per thread", held, "free at baseline", base, "after one round", after1,
-        "after two", after2)
-    assert sum(held) > 4 * SLACK   # enough held that a leak would show
-    assert after1 - after2 <= SLACK, (after1 - after2)
+    # them, so generations of threads do not add up: a leak would take a
+    # whole generation's caches more each time.  (The HIP runtime itself
+    # keeps a few tens of MiB per exited host thread for a while, more or
+    # less from one generation to the next; half a generation's caches
+    # bounds that noise.)
+    free = []
+    for g in range(4):
+        held.clear()
+        round_of_threads()
+        free.append(_free_bytes())
+    generation = sum(held)
+    growth = max(free[0] - f for f in free[1:])
+    say("device workspace held by one generation", held, "free at baseline", base, "after each generation",
+        free, "largest growth", growth)
+    assert generation > 4 * SLACK   # enough held that a leak would show
+    assert growth <= generation // 2, (growth, generation)
     # and nothing stays once the exited threads' caches are released
     api.release_workspace()
     after = _free_bytes()
-    assert base - after <= SLACK, (base - after)
+    assert base - after <= generation // 2, (base - after, generation)
 
 
 def test_release_workspace_frees_calling_thread_cache():
