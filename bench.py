@@ -410,13 +410,13 @@ def other_configs(api, torch, workloads):
     batched(2, True)
     t_e = min(batched(30) for _ in range(5))
     t_g = min(batched(30, True) for _ in range(5))
-    best_R, ms_R = api.tune_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, trials=8)
+    best_R, ms_R, best_chunk, best_grid = api.tune_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, trials=8)
     t_t = min(batched(30) for _ in range(5))   # the tuned shape from here on
     out["small_clouds2_batched_fp32"] = {
         "workload": "256 clouds of 200..2000 points (%d points), D=2, 32 seeds each, Gaussian h=1, "
                     "30 iterations per call" % int(xo[-1]),
         "ms_per_call_eager": t_e * 1e3, "ms_per_call_graph": t_g * 1e3,
-        "graph_speedup": t_e / t_g, "tuned_R": best_R,
+        "graph_speedup": t_e / t_g, "tuned_R": best_R, "tuned_chunk": best_chunk, "tuned_grid": best_grid,
         "tuner_ms_per_iteration_by_R": {str(r): v for r, v in ms_R.items()},
         "ms_per_call_tuned": t_t * 1e3}
     return out

@@ -101,6 +101,9 @@ typedef struct {
     int32_t graph;            /* ms_step_batched: 1 = capture the n_iter
                                  iterations in one HIP graph and launch it
                                  once (the call then returns when it is done);
+                                 the executable graph is kept per host thread
+                                 and updated in place by later calls of the
+                                 same topology (instantiated once per shape);
                                  0 = launch kernel by kernel.  Other calls
                                  ignore it */
     int32_t tile_R;           /* ms_step_batched: seeds per lane of a seed
@@ -115,6 +118,16 @@ typedef struct {
                                  the skipped blocks contribute exact zeros,
                                  so only the summation order differs); for
                                  comparison.  Ignored by the BF16 form */
+    int32_t tile_chunk;       /* ms_step_batched, ms_fit_batched: points per
+                                 point chunk of a cloud, 64..65536; 0 = the
+                                 size ms_tune_batched chose for inputs of this
+                                 kind, else 1024.  It sets how each seed's sums
+                                 are grouped (the rounding of the results,
+                                 not their parity) */
+    int32_t tile_grid;        /* ms_step_batched, ms_fit_batched: most
+                                 workgroups of the step launch, 1..65536; 0 =
+                                 the tuned value, else 2048.  The results do
+                                 not depend on it */
     int32_t reserved[1];      /* must be 0 */
 } ms_params;
 
@@ -337,29 +350,37 @@ int ms_fit_batched(const ms_params *p, const float *X, const int64_t *x_off, int
                    void *stream);
 
 /*
- * ms_tune_batched -- tile-shape tuning for ms_step_batched.
+ * ms_tune_batched -- launch-shape tuning for ms_step_batched and
+ * ms_fit_batched.
  *
- * Times `trials` iterations (every seed active) of each seed tile shape that
- * the padded dimension allows (the seeds per lane R, see ms_params.tile_R) on
- * this input, keeps the fastest, and records it for the rest of the process
- * under the input's kind: padded dimension, floor(log2) of the mean points
- * per cloud and floor(log2) of the mean seeds per cloud.  Later
- * ms_step_batched calls with tile_R = 0 on inputs of that kind use it.  The
- * iterations run on private copies of the seeds: nothing the caller passed is
- * written, and since the results of ms_step_batched do not depend on R,
- * tuning never changes them.
- *   p, X, x_off, seeds, s_off, ncl, d: as ms_step_batched (p->tile_R and
- *              p->graph are ignored); at least one cloud must have seeds.
+ * Times `trials` iterations (every seed active) of each launch shape on this
+ * input -- the seeds per lane R that the padded dimension allows (see
+ * ms_params.tile_R), times the points per chunk 512, 1024, 2048, 4096 (see
+ * tile_chunk), times the step grids of 1024, 2048 and 4096 workgroups (see
+ * tile_grid) -- keeps the fastest, and records it for the rest of the
+ * process under the input's kind: padded dimension, floor(log2) of the mean
+ * points per cloud and floor(log2) of the mean seeds per cloud.  Later calls
+ * with tile_R, tile_chunk or tile_grid = 0 on inputs of that kind use it.
+ * The iterations run on private copies of the seeds: nothing the caller
+ * passed is written.  R and the grid never change the results; the chunk
+ * size groups each seed's sums differently, so a tuned chunk size changes
+ * their rounding (within the same parity with the oracle).
+ *   p, X, x_off, seeds, s_off, ncl, d: as ms_step_batched (p->tile_R,
+ *              tile_chunk, tile_grid and graph are ignored); at least one
+ *              cloud must have seeds.
  *   trials     1..64 iterations per candidate.
  *   best_R     host, may be NULL: the chosen R.
- *   ms_per_iter host, may be NULL: 3 entries, the measured milliseconds per
- *              iteration for R = 1, 2, 4 (-1 where R is not a candidate).
+ *   ms_per_iter host, may be NULL: 3 entries, the fastest milliseconds per
+ *              iteration measured with R = 1, 2, 4 (over the chunk sizes and
+ *              grids; -1 where R is not a candidate).
+ *   best_chunk, best_grid  host, may be NULL: the chosen chunk size and grid.
  * Synchronous (returns once the candidates are timed).  Allocates device
  * workspace on `stream`.
  */
 int ms_tune_batched(const ms_params *p, const float *X, const int64_t *x_off,
                     const float *seeds, const int64_t *s_off, int32_t ncl, int32_t d,
-                    int32_t trials, int32_t *best_R, float *ms_per_iter, void *stream);
+                    int32_t trials, int32_t *best_R, float *ms_per_iter, int32_t *best_chunk,
+                    int32_t *best_grid, void *stream);
 
 /*
  * ms_seed_count_next -- seed-count adaptation across the frames of a
@@ -384,9 +405,21 @@ int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t *n_next
  * ms_fit or ms_fit_batched call on any thread, or here; so memory held for
  * exited threads never outlives the next call.  Those calls are
  * host-synchronous, so nothing is in flight on the released memory when they
- * have returned.  The next call allocates again.  Always returns MS_OK.
+ * have returned.  It also drops the calling thread's kept executable graph
+ * of ms_step_batched (ms_params.graph = 1).  The next call allocates again.
+ * Always returns MS_OK.
  */
 int ms_release_workspace(void);
+
+/*
+ * ms_graph_stats -- how ms_step_batched's graph launches (ms_params.graph = 1)
+ * on the calling thread came to be: graphs instantiated, and launches that
+ * reused the kept executable graph, updated in place because the call
+ * captured the same topology (same cloud count, iteration count and tile
+ * shape).  Counts since the thread's first graph launch; either pointer
+ * (host) may be NULL.  Always MS_OK.  Host only.
+ */
+int ms_graph_stats(int64_t *instantiations, int64_t *updates);
 
 /* Thread-local message for the last failure on this thread ("" if none). */
 const char *ms_last_error(void);

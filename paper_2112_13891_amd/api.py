@@ -51,6 +51,8 @@ class Params(ctypes.Structure):
         ("graph", ctypes.c_int32),
         ("tile_R", ctypes.c_int32),
         ("plain", ctypes.c_int32),
+        ("tile_chunk", ctypes.c_int32),
+        ("tile_grid", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 1),
     ]
 
@@ -81,7 +83,7 @@ class Diag(ctypes.Structure):
 EXPORTS = ("ms_default_params", "ms_fit", "ms_step", "ms_step_noalloc", "ms_step_batched", "ms_tune_batched", "ms_fit_batched",
            "ms_assign",
            "ms_forward_update", "ms_step_adjoint", "ms_seed_draw", "ms_seed_count_next",
-           "ms_release_workspace", "ms_last_error", "ms_version")
+           "ms_release_workspace", "ms_graph_stats", "ms_last_error", "ms_version")
 
 _lib = None
 
@@ -297,11 +299,12 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
 
 
 def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=1,
-                 converged=None, graph=False, tile_R=0):
+                 converged=None, graph=False, tile_R=0, tile_chunk=0, tile_grid=0):
     """ms_step over many clouds: cloud c owns X[x_off[c]:x_off[c+1]] and
     seeds[s_off[c]:s_off[c+1]].  Offsets are host sequences of ncl + 1 ints.
-    graph=True runs the n_iter iterations as one captured HIP graph; tile_R
-    forces the seeds per lane (0: tuned or default shape).
+    graph=True runs the n_iter iterations as one captured HIP graph; tile_R,
+    tile_chunk and tile_grid force the seeds per lane, points per chunk and
+    step grid (0: tuned or default shape).
     Returns new tensors (seeds, converged uint8, iters int32, shift2 float32)."""
     import numpy as np
     torch = _torch()
@@ -323,6 +326,8 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
     p = make_params(h, kernel, "fp32", tol)
     p.graph = 1 if graph else 0
     p.tile_R = int(tile_R)
+    p.tile_chunk = int(tile_chunk)
+    p.tile_grid = int(tile_grid)
     rc = lib().ms_step_batched(ctypes.byref(p), Xp, xo.ctypes.data, ctypes.c_void_p(S.data_ptr()),
                                so.ctypes.data, int(len(xo) - 1), d, int(n_iter),
                                ctypes.c_void_p(conv.data_ptr()), ctypes.c_void_p(iters.data_ptr()),
@@ -363,9 +368,10 @@ def fit_batched(X, x_off, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_ra
 
 
 def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=4):
-    """ms_tune_batched: time each seeds-per-lane shape on this input and keep
-    the fastest for later step_batched calls on inputs of the same kind.
-    Returns (best R, {R: ms per iteration})."""
+    """ms_tune_batched: time each launch shape (seeds per lane, points per
+    chunk, step grid) on this input and keep the fastest for later
+    step_batched / fit_batched calls on inputs of the same kind.
+    Returns (best R, {R: ms per iteration}, best chunk, best grid)."""
     import numpy as np
     torch = _torch()
     Xp = _dev(X, torch.float32, 2, "X")
@@ -376,12 +382,14 @@ def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=
         raise ValueError("x_off and s_off must both have ncl + 1 entries")
     p = make_params(h, kernel, "fp32", tol)
     best = ctypes.c_int32(0)
+    chunk = ctypes.c_int32(0)
+    grid = ctypes.c_int32(0)
     ms = (ctypes.c_float * 3)()
     rc = lib().ms_tune_batched(ctypes.byref(p), Xp, xo.ctypes.data, Sp, so.ctypes.data,
                                int(len(xo) - 1), X.shape[1], int(trials), ctypes.byref(best), ms,
-                               _stream_ptr(X))
+                               ctypes.byref(chunk), ctypes.byref(grid), _stream_ptr(X))
     _check(rc)
-    return best.value, {r: ms[c] for c, r in enumerate((1, 2, 4)) if ms[c] >= 0}
+    return best.value, {r: ms[c] for c, r in enumerate((1, 2, 4)) if ms[c] >= 0}, chunk.value, grid.value
 
 
 def assign(X, modes, margin=False):
@@ -478,6 +486,14 @@ def seed_draw(rng_state: int, pool, count: int):
                             int(count), out.ctypes.data_as(ctypes.c_void_p))
     _check(rc)
     return out, int(st.value)
+
+
+def graph_stats():
+    """(instantiations, in-place updates) of ms_step_batched's graph launches
+    on the calling thread."""
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().ms_graph_stats(ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
 
 
 def release_workspace():

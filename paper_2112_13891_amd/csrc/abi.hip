@@ -288,6 +288,9 @@ int check_params(const ms_params* p, bool for_fit) {
     if (p->tile_R != 0 && p->tile_R != 1 && p->tile_R != 2 && p->tile_R != 4)
         return fail(MS_E_INVALID, "tile_R must be 0, 1, 2 or 4");
     if (p->plain != 0 && p->plain != 1) return fail(MS_E_INVALID, "plain must be 0 or 1");
+    if (p->tile_chunk != 0 && (p->tile_chunk < 64 || p->tile_chunk > 65536))
+        return fail(MS_E_INVALID, "tile_chunk must be 0 or in [64, 65536]");
+    if (p->tile_grid < 0 || p->tile_grid > 65536) return fail(MS_E_INVALID, "tile_grid must be in [0, 65536]");
     if (p->reserved[0] != 0) return fail(MS_E_INVALID, "reserved fields must be 0");
     if (!for_fit) return MS_OK;
     if (p->max_iter < 1 || p->max_iter > kMaxIterCap)
@@ -495,6 +498,25 @@ int iterate_batch(Batch& b, int max_iter, hipStream_t s, Ctl* mirror) {
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
+
+// The executable graph of ms_step_batched's iterations and its capture
+// stream, per host thread (released by ms_release_workspace; a thread that
+// exits keeps its handles, a few kilobytes of host state, to the end of the
+// process).
+struct GraphCache {
+    int dev = -1;
+    hipStream_t cs = nullptr;
+    hipGraphExec_t ge = nullptr;
+    long long instantiations = 0, updates = 0;
+    void clear() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (cs) (void)hipStreamDestroy(cs);
+        ge = nullptr;
+        cs = nullptr;
+        dev = -1;
+    }
+};
+thread_local GraphCache g_graph;
 
 struct Events {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -1120,11 +1142,17 @@ bool batched_R_ok(int D, int R) {
     return false;
 }
 
-// Tuned seeds per lane, by input kind (padded dimension, floor(log2) of the
-// mean points and of the mean seeds per cloud), for the whole process.
+// Tuned launch shape (seeds per lane, points per chunk, step grid), by input
+// kind (padded dimension, floor(log2) of the mean points and of the mean
+// seeds per cloud), for the whole process.
 using TuneKey = std::tuple<int, int, int>;
+struct TuneShape {
+    int R, chunk, grid;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneShape> g_tune;
+constexpr int kBatchedChunk = 1024;   // points per chunk unless set or tuned
+constexpr int kBatchedGrid = 2048;    // workgroups of the step unless set or tuned
 
 int ilog2_ll(long long v) {
     int r = 0;
@@ -1169,11 +1197,18 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         sh.TS = 64 * r_cap;
     }
     int R = R_force;
-    if (R == 0) {
+    int chunk = p->tile_chunk, grid_cap = p->tile_grid;
+    if (R == 0 || chunk == 0 || grid_cap == 0) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         const auto it = g_tune.find(tune_key(d, n, M, ncl));
-        if (it != g_tune.end()) R = it->second;
+        if (it != g_tune.end()) {
+            if (R == 0) R = it->second.R;
+            if (chunk == 0) chunk = it->second.chunk;
+            if (grid_cap == 0) grid_cap = it->second.grid;
+        }
     }
+    if (chunk == 0) chunk = kBatchedChunk;
+    if (grid_cap == 0) grid_cap = kBatchedGrid;
     if (R != 0) {
         if (!batched_R_ok(sh.D, R)) return fail(MS_E_INVALID, "tile_R is not built for this dimension");
         sh.R = R;
@@ -1186,7 +1221,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         xo[c] = x_off[c];
         so[c] = (int32_t)s_off[c];
     }
-    const long long max_items = batched_max_items(xo.data(), so.data(), ncl, sh.TS);
+    const long long max_items = batched_max_items(xo.data(), so.data(), ncl, sh.TS, chunk);
     if (max_items > INT_MAX / 2) return fail(MS_E_INVALID, "too many work items for one batch");
     Workspace ws(s);
     const float* Xp;
@@ -1215,6 +1250,8 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
     b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
+    b.chunk_points = chunk;
+    b.grid_cap = grid_cap;
     FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], M));
     FMS_CHECK(ws.alloc(&b.act[1], M));
@@ -1231,24 +1268,44 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     if (ev) FMS_HIP(hipEventRecord(ev[0], s));
     if (p->graph && n_iter > 0) {
         // every iteration captured on a private stream (capture is not allowed
-        // on the null stream), then one graph launch on the caller's stream
-        hipStream_t cs = nullptr;
+        // on the null stream), then one graph launch on the caller's stream.
+        // The executable graph is kept (per host thread and device) and
+        // updated in place when a later call captures the same topology, so
+        // that it is instantiated once per shape.
+        int dev = 0;
+        FMS_HIP(hipGetDevice(&dev));
+        GraphCache& gc = g_graph;
+        if (gc.dev != dev) gc.clear();
+        gc.dev = dev;
+        if (!gc.cs) FMS_HIP(hipStreamCreateWithFlags(&gc.cs, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
-        hipGraphExec_t ge = nullptr;
-        FMS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        hipError_t e = hipStreamBeginCapture(gc.cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             for (int t = 0; t < n_iter && e == hipSuccess; ++t)
-                e = launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, cs);
-            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+                e = launch_batched_iteration(b, xo_dev, so_dev, ncl, cnt, plan, item_cloud, slot_cloud, t, gc.cs);
+            const hipError_t e2 = hipStreamEndCapture(gc.cs, &g);
             if (e == hipSuccess) e = e2;
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(ge, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the graph is done before it is destroyed
-        if (ge) (void)hipGraphExecDestroy(ge);
+        if (e == hipSuccess && gc.ge) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            const hipError_t eu = hipGraphExecUpdate(gc.ge, g, &bad, &res);
+            if (eu != hipSuccess || res != hipGraphExecUpdateSuccess) {
+                (void)hipGetLastError();   // another topology: instantiate anew
+                (void)hipGraphExecDestroy(gc.ge);
+                gc.ge = nullptr;
+            } else {
+                gc.updates += 1;
+            }
+        }
+        if (e == hipSuccess && !gc.ge) {
+            e = hipGraphInstantiate(&gc.ge, g, nullptr, nullptr, 0);
+            if (e == hipSuccess) gc.instantiations += 1;
+            else gc.ge = nullptr;
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(gc.ge, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // the workspace outlives the launch
         if (g) (void)hipGraphDestroy(g);
-        (void)hipStreamDestroy(cs);
         if (e != hipSuccess) return hip_fail(e, "batched iterations as a graph");
     } else {
         for (int t = 0; t < n_iter; ++t)
@@ -1521,7 +1578,7 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
 // Times each candidate R on private copies of the seeds; records the fastest.
 int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,
                       const int64_t* s_off, int ncl, int d, int trials, int32_t* best_R,
-                      float* ms_per_iter, hipStream_t s) {
+                      float* ms_per_iter, int32_t* best_chunk, int32_t* best_grid, hipStream_t s) {
     const long long n = x_off[ncl], M = s_off[ncl];
     const int D = step_shape(d).D;
     Workspace ws(s);
@@ -1538,35 +1595,44 @@ int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     ms_params q = *p;
     q.graph = 0;
     q.tile_R = 0;
-    const int cand[3] = {1, 2, 4};
-    int best = 0;
+    const int candR[3] = {1, 2, 4};
+    const int candC[4] = {512, 1024, 2048, 4096};
+    const int candG[3] = {1024, 2048, 4096};
+    TuneShape best{0, kBatchedChunk, kBatchedGrid};
     float best_ms = 0.0f;
     for (int c = 0; c < 3; ++c) {
         if (ms_per_iter) ms_per_iter[c] = -1.0f;
-        if (!batched_R_ok(D, cand[c])) continue;
-        float ms = 0.0f;
-        // one untimed pass (first launch of the shape), then the timed one
-        for (int pass = 0; pass < 2; ++pass) {
-            FMS_HIP(hipMemcpyAsync(S, seeds, (size_t)M * d * 4, hipMemcpyDeviceToDevice, s));
-            FMS_HIP(launch_fill_u8(conv, (int)M, 0, s));
-            FMS_CHECK(step_batched_impl(&q, X, x_off, S, s_off, ncl, d, pass ? trials : 1, conv, it, sh2, s,
-                                        cand[c], pass ? ev : nullptr));
-        }
-        FMS_HIP(hipEventSynchronize(ev[1]));
-        FMS_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        ms /= (float)trials;
-        if (ms_per_iter) ms_per_iter[c] = ms;
-        if (best == 0 || ms < best_ms) {
-            best = cand[c];
-            best_ms = ms;
-        }
+        if (!batched_R_ok(D, candR[c])) continue;
+        for (int ci = 0; ci < 4; ++ci)
+            for (int gi = 0; gi < 3; ++gi) {
+                q.tile_chunk = candC[ci];
+                q.tile_grid = candG[gi];
+                float ms = 0.0f;
+                // one untimed pass (first launch of the shape), then the timed one
+                for (int pass = 0; pass < 2; ++pass) {
+                    FMS_HIP(hipMemcpyAsync(S, seeds, (size_t)M * d * 4, hipMemcpyDeviceToDevice, s));
+                    FMS_HIP(launch_fill_u8(conv, (int)M, 0, s));
+                    FMS_CHECK(step_batched_impl(&q, X, x_off, S, s_off, ncl, d, pass ? trials : 1, conv, it, sh2,
+                                                s, candR[c], pass ? ev : nullptr));
+                }
+                FMS_HIP(hipEventSynchronize(ev[1]));
+                FMS_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+                ms /= (float)trials;
+                if (ms_per_iter && (ms_per_iter[c] < 0.0f || ms < ms_per_iter[c])) ms_per_iter[c] = ms;
+                if (best.R == 0 || ms < best_ms) {
+                    best = TuneShape{candR[c], candC[ci], candG[gi]};
+                    best_ms = ms;
+                }
+            }
     }
     FMS_HIP(hipStreamSynchronize(s));
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune[tune_key(d, n, M, ncl)] = best;
     }
-    if (best_R) *best_R = best;
+    if (best_R) *best_R = best.R;
+    if (best_chunk) *best_chunk = best.chunk;
+    if (best_grid) *best_grid = best.grid;
     return MS_OK;
 }
 
@@ -1695,14 +1761,14 @@ int ms_fit_batched(const ms_params* p, const float* X, const int64_t* x_off, int
 
 int ms_tune_batched(const ms_params* p, const float* X, const int64_t* x_off, const float* seeds,
                     const int64_t* s_off, int32_t ncl, int32_t d, int32_t trials, int32_t* best_R,
-                    float* ms_per_iter, void* stream) {
+                    float* ms_per_iter, int32_t* best_chunk, int32_t* best_grid, void* stream) {
     g_err.clear();
     FMS_CHECK(check_batched_args(p, X, x_off, s_off, ncl, d));
     if (trials < 1 || trials > 64) return fail(MS_E_INVALID, "trials must be in [1, 64]");
     if (s_off[ncl] == 0) return fail(MS_E_INVALID, "no cloud has seeds");
     if (!seeds) return fail(MS_E_INVALID, "seeds is NULL");
-    return tune_batched_impl(p, X, x_off, seeds, s_off, ncl, d, trials, best_R, ms_per_iter,
-                             (hipStream_t)stream);
+    return tune_batched_impl(p, X, x_off, seeds, s_off, ncl, d, trials, best_R, ms_per_iter, best_chunk,
+                             best_grid, (hipStream_t)stream);
 }
 
 int ms_assign(const float* X, int64_t n, int32_t d, const float* modes, int32_t k, int32_t* labels,
@@ -1780,11 +1846,18 @@ int ms_seed_count_next(int32_t n_last, int32_t modes, int32_t H, int32_t* n_next
 int ms_release_workspace(void) {
     g_err.clear();
     free_orphans();
+    g_graph.clear();
     for (auto& c : g_cache) c->release();
     g_cache.clear();
     for (Pinned* q : {&g_pin_ctl, &g_pin_pos, &g_pin_rb, &g_pin_modes, &g_pin_bpos, &g_pin_bso, &g_pin_bso32,
                       &g_pin_bseeds, &g_pin_bconv, &g_pin_bmodes, &g_pin_bmoff, &g_pin_blen})
         q->release();
+    return MS_OK;
+}
+
+int ms_graph_stats(int64_t* instantiations, int64_t* updates) {
+    if (instantiations) *instantiations = g_graph.instantiations;
+    if (updates) *updates = g_graph.updates;
     return MS_OK;
 }
 

@@ -84,6 +84,8 @@ struct Batch {
     float* shift2;         // cap
     float* part;           // chunk partials, one (D+1)-vector per seed and chunk
     int grid;              // workgroups of the fused step
+    int chunk_points = 1024;   // batched step: points per point chunk
+    int grid_cap = 2048;       // batched step: most workgroups of the step launch
     int prec;              // ms_precision
     const float* Xs;       // BF16 and culled FP32 forms: points in spatial order (n x DP)
     const float* geom;     // BF16 and culled FP32 forms: per 256-point block centre and radius
@@ -161,7 +163,7 @@ inline hipError_t launch_bf16_wide_features(const float* Xs, int n, int D, const
 
 // ---- launchers (k_batched.hip): FP32 step over many clouds ---------------------
 int batched_max_clouds();
-long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS);
+long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS, int chunk_points);
 hipError_t launch_batched_init(const float* seeds, const uint8_t* conv_in, int d, int M,
                                const int32_t* seg_dev, int ncl, int32_t* cnt, Batch& b, hipStream_t s);
 // plan: 4 ncl + 3 ints of device scratch (per-cloud tiles, chunks, item and

@@ -8,7 +8,8 @@
 //
 // One iteration is three launches:
 //   plan     one workgroup: from the per-cloud active counts, each cloud's
-//            seed tiles (64R seeds) and point chunks (kChunkPoints points),
+//            seed tiles (64R seeds) and point chunks (chunk_points points,
+//            1024 unless the call or the tuner sets another),
 //            the prefix of work items and of active slots, and for every
 //            work item and active slot its cloud (one wave per cloud fills
 //            the cloud's ranges);
@@ -33,8 +34,6 @@ namespace fms {
 namespace {
 
 constexpr int kPlanThreads = 1024;
-constexpr int kChunkPoints = 1024;
-constexpr int kBStepGrid = 2048;
 
 struct BatchedArgs {
     int ncl;
@@ -48,6 +47,8 @@ struct BatchedArgs {
     int32_t* item_cloud;      // cloud of each work item
     int32_t* slot_cloud;      // cloud of each active slot
     int32_t* queue;           // next work item to take (zeroed by the plan)
+    int chunk_points;         // points per point chunk
+    int grid_cap;             // most workgroups of the step
 };
 
 __device__ __forceinline__ int upper_cloud(const int32_t* pre, int ncl, int v) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kPlanThreads) void bplan_kernel(BatchedArgs B, int 
             m = cin[c];
             const long long n = B.x_off[c + 1] - B.x_off[c];
             const int tl = (m + TS - 1) / TS;
-            const int ch = m > 0 ? (int)((n + kChunkPoints - 1) / kChunkPoints) : 0;
+            const int ch = m > 0 ? (int)((n + B.chunk_points - 1) / B.chunk_points) : 0;
             B.tiles[c] = tl;
             B.chunks[c] = ch;
             items = tl * ch;
@@ -273,7 +274,7 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     a.Xp = b.Xp;
     a.n = b.n;
     a.d = b.d;
-    a.min_chunk = kChunkPoints;
+    a.min_chunk = B.chunk_points;
     a.S = b.S;
     a.act_in = b.act[t & 1];
     a.act_out = b.act[(t + 1) & 1];
@@ -290,7 +291,7 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, 64 * R);
     // no more workgroups than the first iteration has work items (seeds only
     // ever leave the active lists)
-    const int grid = std::max(1, std::min(kBStepGrid, b.grid));
+    const int grid = std::max(1, std::min(B.grid_cap, b.grid));
     if (b.kernel == MS_KERNEL_GAUSSIAN)
         hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_GAUSSIAN>), dim3(grid), dim3(kThreads),
                            0, s, a, B);
@@ -309,12 +310,12 @@ int batched_max_clouds() { return kMaxClouds; }
 
 // Work items of the first iteration (every seed active): the size of the
 // partials and of the item map.
-long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS) {
+long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS, int chunk_points) {
     long long items = 0;
     for (int c = 0; c < ncl; ++c) {
         const long long m = seg[c + 1] - seg[c];
         const long long n = x_off[c + 1] - x_off[c];
-        if (m > 0) items += ((m + TS - 1) / TS) * ((n + kChunkPoints - 1) / kChunkPoints);
+        if (m > 0) items += ((m + TS - 1) / TS) * ((n + chunk_points - 1) / chunk_points);
     }
     return items;
 }
@@ -343,6 +344,8 @@ hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, 
     B.item_cloud = item_cloud;
     B.slot_cloud = slot_cloud;
     B.queue = plan + 4 * ncl + 2;
+    B.chunk_points = b.chunk_points;
+    B.grid_cap = b.grid_cap;
     const int D = b.sh.D, R = b.sh.R;
 #define FMS_BCASE(DD, DPP, RR) \
     if (D == DD && R == RR) return bstep_t<DD, DPP, RR>(b, B, t, s);

@@ -125,14 +125,14 @@ def test_null_pointers_and_reserved(api):
     so = (ctypes.c_int64 * 3)(0, 0, 0)
     best = ctypes.c_int32(0)
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
-                             None) == -1
+                             None, None, None) == -1
     assert "no cloud has seeds" in api.last_error()
     so = (ctypes.c_int64 * 3)(0, 2, 4)
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 0, ctypes.byref(best), None,
-                             None) == -1
+                             None, None, None) == -1
     assert "trials" in api.last_error()
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, None, so, 2, 2, 4, ctypes.byref(best), None,
-                             None) == -1
+                             None, None, None) == -1
     assert "seeds is NULL" in api.last_error()
     kf = (ctypes.c_int64 * 3)()
     pg = api.make_params(1.0, gamma=0.5)
@@ -145,7 +145,7 @@ def test_null_pointers_and_reserved(api):
     assert "no cloud has points" in api.last_error()
     p.precision = api.PRECISIONS["bf16"]
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
-                             None) == -1
+                             None, None, None) == -1
     assert "FP32 form only" in api.last_error()
 
 

@@ -151,6 +151,32 @@ def test_batched_graph_matches_eager_launches():
             del junk
 
 
+def test_batched_graph_reused_across_calls():
+    """The executable graph is kept per thread and updated in place by a later
+    call of the same topology (other clouds, other buffers), so it is
+    instantiated once per shape; every launch gives bitwise the outputs of the
+    kernel-by-kernel launches of the same call."""
+    api.release_workspace()   # no kept graph on this thread
+    i0, u0 = api.graph_stats()
+
+    def run(seed, n_iter):
+        Xs, Ss, xo, so = _batch(seed, SIZES[:8], 3)
+        Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+        Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+        ref = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=n_iter, tile_R=1)]
+        got = api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=n_iter, tile_R=1, graph=True)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, got):
+            torch.testing.assert_close(b.cpu(), a, rtol=0, atol=0, equal_nan=True)
+        return api.graph_stats()
+
+    assert run(61, 5) == (i0 + 1, u0)       # instantiated
+    assert run(62, 5) == (i0 + 1, u0 + 1)   # same topology, other data: updated in place
+    assert run(63, 5) == (i0 + 1, u0 + 2)
+    assert run(64, 6) == (i0 + 2, u0 + 2)   # one more iteration: another graph
+    say("graph instantiations and updates", api.graph_stats())
+
+
 @pytest.mark.parametrize("d,Rs", [(2, (1, 2, 4)), (8, (1, 2)), (16, (1, 2)), (32, (1,))])
 def test_batched_tile_shapes_give_identical_results(d, Rs):
     """The seeds per lane change how seeds share a workgroup, never the order
@@ -171,19 +197,42 @@ def test_batched_tile_shapes_give_identical_results(d, Rs):
             api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=1, tile_R=4)
 
 
-def test_batched_tuner_picks_a_built_shape_and_keeps_results():
+def test_batched_tuner_picks_a_built_shape():
+    """The tuner searches seeds per lane, points per chunk and the step grid;
+    later calls on inputs of the same kind take its shape, the grid never
+    changes a bit of the results, and the caller's seeds are not written."""
     Xs, Ss, xo, so = _batch(50, SIZES, 3, max_seeds=300)
     Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
     Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
-    ref = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5, tile_R=1)]
     S_before = Sa.cpu().clone()
-    best, ms = api.tune_batched(Xa, xo, Sa, so, 1.0, trials=3)
-    say("tuned R", best, ms)
+    best, ms, chunk, grid = api.tune_batched(Xa, xo, Sa, so, 1.0, trials=3)
+    say("tuned R", best, ms, "chunk", chunk, "grid", grid)
     assert best in (1, 2, 4) and set(ms) == {1, 2, 4} and all(v > 0 for v in ms.values())
+    assert chunk in (512, 1024, 2048, 4096) and grid in (1024, 2048, 4096)
     assert torch.equal(Sa.cpu(), S_before)   # the caller's seeds are not written
     got = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5)]
-    for a, b in zip(ref, got):
+    explicit = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5, tile_R=best,
+                                                  tile_chunk=chunk, tile_grid=grid)]
+    other_grid = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5, tile_R=best,
+                                                    tile_chunk=chunk, tile_grid=7 if grid != 7 else 9)]
+    for a, b, c in zip(explicit, got, other_grid):
         torch.testing.assert_close(b, a, rtol=0, atol=0, equal_nan=True)
+        torch.testing.assert_close(c, a, rtol=0, atol=0, equal_nan=True)
+
+
+@pytest.mark.parametrize("chunk", [64, 512, 4096, 65536])
+def test_batched_chunk_size_changes_rounding_only(chunk):
+    """The points per chunk group each seed's sums differently: after a few
+    iterations (no convergence decisions: tol 1e-30) the seeds agree with the
+    default chunking to within the FP32 rounding of the sums."""
+    Xs, Ss, xo, so = _batch(70, SIZES, 8, max_seeds=200)
+    Xa = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    Sa = torch.from_numpy(np.concatenate(Ss)).to(DEV)
+    ref = api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=3, tile_chunk=1024)[0].cpu().numpy()
+    got = api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=3, tile_chunk=chunk)[0].cpu().numpy()
+    err = float(np.abs(got.astype(np.float64) - ref).max())
+    say("chunk", chunk, "largest difference to 1024-point chunks", err)
+    assert err <= 1e-4 * 1.0
 
 
 def test_batched_full_size_sampled(orc):
