@@ -531,10 +531,11 @@ def main():
                     help="skip the secondary shapes (flat window, cosine metric, images, frames, small clouds)")
     ap.add_argument("--kernel-iters", type=int, default=20)
     ap.add_argument("--phase", default="all",
-                    choices=["all", "kernel", "fit", "c3", "c3kernel", "batched", "c5"],
+                    choices=["all", "kernel", "fit", "c3", "c3flat", "c3kernel", "batched", "c5"],
                     help="kernel: the 200K mixture's largest launch (both precisions) and a 256 MiB copy "
                          "that calibrates the traffic counters; fit: --steps fits per precision of the 200K "
-                         "mixture; c3: --steps fits per precision of the 32-D embeddings; c3kernel: their "
+                         "mixture; c3: --steps fits per precision of the 32-D embeddings; c3flat: the same "
+                         "with the flat window (every window a singleton); c3kernel: their "
                          "largest launch (8,192 seeds) and the copy; batched: --steps whole-method calls on "
                          "the 512 uneven clouds; c5: --steps steps of the differentiable form; all: the "
                          "benchmark")
@@ -580,13 +581,14 @@ def main():
         out["phase"] = "c5"
         print(json.dumps(out, default=_plain), flush=True)
         return
-    if args.phase in ("c3", "c3kernel"):
+    if args.phase in ("c3", "c3flat", "c3kernel"):
         w = workloads.embed32(seed=0)
         X = torch.from_numpy(w.X).cuda()
         out = {"phase": args.phase}
-        if args.phase == "c3":
+        if args.phase in ("c3", "c3flat"):
+            kern = "flat" if args.phase == "c3flat" else w.kernel
             for prec in ("fp32", "bf16"):
-                dt, r = fit_timing(api, torch, X, w.h, w.kernel, args.steps, precision=prec)
+                dt, r = fit_timing(api, torch, X, w.h, kern, args.steps, precision=prec)
                 out[prec] = fit_summary(dt, r)
                 out[prec]["breakdown_ms"] = {"iterate": r.iterate_ms, "merge_and_pool": r.merge_ms,
                                              "assign": r.assign_ms, "host_total": r.total_ms}
