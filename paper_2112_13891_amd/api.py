@@ -299,12 +299,13 @@ def step(X, seeds, h, kernel="gaussian", precision="fp32", tol=1e-3, n_iter=1, c
 
 
 def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=1,
-                 converged=None, graph=False, tile_R=0, tile_chunk=0, tile_grid=0):
+                 converged=None, graph=False, tile_R=0, tile_chunk=0, tile_grid=0, precision="fp32"):
     """ms_step over many clouds: cloud c owns X[x_off[c]:x_off[c+1]] and
     seeds[s_off[c]:s_off[c+1]].  Offsets are host sequences of ncl + 1 ints.
     graph=True runs the n_iter iterations as one captured HIP graph; tile_R,
     tile_chunk and tile_grid force the seeds per lane, points per chunk and
-    step grid (0: tuned or default shape).
+    step grid (0: tuned or default shape).  precision="bf16" takes the BF16
+    form (Gaussian kernel, 5 <= d <= 32; tile_R does not apply).
     Returns new tensors (seeds, converged uint8, iters int32, shift2 float32)."""
     import numpy as np
     torch = _torch()
@@ -323,7 +324,7 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
             else converged.detach().clone().to(torch.uint8).contiguous())
     iters = torch.zeros(m, dtype=torch.int32, device=X.device)
     sh = torch.full((m,), float("nan"), dtype=torch.float32, device=X.device)
-    p = make_params(h, kernel, "fp32", tol)
+    p = make_params(h, kernel, precision, tol)
     p.graph = 1 if graph else 0
     p.tile_R = int(tile_R)
     p.tile_chunk = int(tile_chunk)
@@ -367,10 +368,11 @@ def fit_batched(X, x_off, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_ra
     return per, lab, k_off, int(rounds.value)
 
 
-def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=4):
+def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=4, precision="fp32"):
     """ms_tune_batched: time each launch shape (seeds per lane, points per
     chunk, step grid) on this input and keep the fastest for later
-    step_batched / fit_batched calls on inputs of the same kind.
+    step_batched / fit_batched calls on inputs of the same kind and
+    precision (the BF16 form: seed tiles of 128, R = 2, only).
     Returns (best R, {R: ms per iteration}, best chunk, best grid)."""
     import numpy as np
     torch = _torch()
@@ -380,7 +382,7 @@ def tune_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, trials=
     so = np.ascontiguousarray(np.asarray(s_off, dtype=np.int64))
     if xo.shape != so.shape or xo.ndim != 1:
         raise ValueError("x_off and s_off must both have ncl + 1 entries")
-    p = make_params(h, kernel, "fp32", tol)
+    p = make_params(h, kernel, precision, tol)
     best = ctypes.c_int32(0)
     chunk = ctypes.c_int32(0)
     grid = ctypes.c_int32(0)

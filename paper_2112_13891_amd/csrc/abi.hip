@@ -1145,7 +1145,7 @@ bool batched_R_ok(int D, int R) {
 // Tuned launch shape (seeds per lane, points per chunk, step grid), by input
 // kind (padded dimension, floor(log2) of the mean points and of the mean
 // seeds per cloud), for the whole process.
-using TuneKey = std::tuple<int, int, int>;
+using TuneKey = std::tuple<int, int, int, int>;
 struct TuneShape {
     int R, chunk, grid;
 };
@@ -1163,8 +1163,8 @@ int ilog2_ll(long long v) {
     return r;
 }
 
-TuneKey tune_key(int d, long long n, long long M, int ncl) {
-    return TuneKey(step_shape(d).D, ilog2_ll(std::max(1LL, n / ncl)), ilog2_ll(std::max(1LL, M / ncl)));
+TuneKey tune_key(int d, long long n, long long M, int ncl, int precision) {
+    return TuneKey(step_shape(d).D, ilog2_ll(std::max(1LL, n / ncl)), ilog2_ll(std::max(1LL, M / ncl)), precision);
 }
 
 // R_force = 0: the tuned shape for this kind of input, else seeds per lane
@@ -1180,6 +1180,69 @@ struct BatchedPrepared {
     const int32_t* so_dev;
 };
 
+// The BF16 form over many clouds (Gaussian, padded D in {8, 16, 32}): each
+// cloud's points in the spatial order of the one-cloud form (its own pivots),
+// their block features, and the per-cloud offsets the kernels use.
+struct BatchedBf16 {
+    float* Xs = nullptr;
+    void* feat = nullptr;
+    void* sws = nullptr;
+    int32_t* poff = nullptr;     // pivots before each cloud
+    int32_t* boff = nullptr;     // 256-point blocks before each cloud
+    int32_t* stpre = nullptr;    // 256-seed tiles before each cloud
+    long long* soff = nullptr;   // seed offsets (64-bit, for the seed order)
+    float* zero = nullptr;       // frame of the sorted points (no shift)
+    int ptot = 0, nblk = 0, stiles = 0, count = 0;
+};
+
+bool batched_bf16_ok(const ms_params* p, int d) {
+    const int D = step_shape(d).D;
+    return p->kernel == MS_KERNEL_GAUSSIAN && (D == 8 || D == 16 || D == 32);
+}
+
+// Sorts the packed points Xp of the clouds and builds their features (the
+// workspace comes from ws); the offsets are xo / so (host) and xo_dev.
+int prepare_batched_bf16(Workspace& ws, const float* Xp, int n, int D, const std::vector<long long>& xo,
+                         const std::vector<int32_t>& so, const long long* xo_dev, int ncl, int M, BatchedBf16& bb,
+                         hipStream_t s) {
+    std::vector<int32_t> poff(ncl + 1, 0), boff(ncl + 1, 0), stpre(ncl + 1, 0);
+    std::vector<long long> soff(ncl + 1, 0);
+    for (int c = 0; c < ncl; ++c) {
+        const long long nc = xo[c + 1] - xo[c];
+        poff[c + 1] = poff[c] + batched_pivot_count(nc);
+        boff[c + 1] = boff[c] + (int)((nc + 255) / 256);
+        stpre[c + 1] = stpre[c] + (so[c + 1] - so[c] + 255) / 256;
+        soff[c + 1] = so[c + 1];
+    }
+    bb.ptot = poff[ncl];
+    bb.nblk = boff[ncl];
+    bb.stiles = stpre[ncl];
+    bb.count = std::max(std::max(n, M), 1);
+    FMS_CHECK(ws.alloc(&bb.poff, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&bb.boff, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&bb.stpre, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&bb.soff, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&bb.zero, (size_t)D));
+    FMS_CHECK(ws.alloc(&bb.Xs, (size_t)std::max(n, 1) * D));
+    char* feat;
+    FMS_CHECK(ws.alloc(&feat, bf16f_feature_bytes_blocks(std::max(bb.nblk, 1), D)));
+    bb.feat = feat;
+    char* sws;
+    FMS_CHECK(ws.alloc(&sws, batched_sort_workspace_bytes(bb.count, bb.ptot)));
+    bb.sws = sws;
+    const size_t ob = (size_t)(ncl + 1) * sizeof(int32_t);
+    FMS_HIP(hipMemcpyAsync(bb.poff, poff.data(), ob, hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemcpyAsync(bb.boff, boff.data(), ob, hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemcpyAsync(bb.stpre, stpre.data(), ob, hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemcpyAsync(bb.soff, soff.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemsetAsync(bb.zero, 0, (size_t)D * 4, s));
+    FMS_HIP(hipStreamSynchronize(s));   // the host copies go out of scope
+    const CloudRows pts{ncl, xo_dev, bb.boff, bb.nblk};
+    FMS_HIP(launch_batched_sort(Xp, n, D, pts, bb.poff, bb.ptot, bb.Xs, bb.sws, bb.count, s));
+    FMS_HIP(launch_bf16f_features_batched(bb.Xs, D, xo_dev, bb.boff, ncl, bb.nblk, bb.feat, s));
+    return MS_OK;
+}
+
 int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, float* seeds,
                       const int64_t* s_off, int ncl, int d, int n_iter, uint8_t* converged,
                       int32_t* iters, float* shift2, hipStream_t s, int R_force = 0,
@@ -1187,6 +1250,10 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_CHECK(ensure_pool_release_threshold());
     const int n = (int)x_off[ncl];
     const int M = (int)s_off[ncl];
+    const bool bf = p->precision == MS_PREC_BF16_REFINE;
+    if (bf && !batched_bf16_ok(p, d))
+        return fail(MS_E_INVALID, "the batched BF16 form is built for the Gaussian kernel at 5 <= d <= 32");
+    if (bf && pre) return fail(MS_E_INVALID, "the batched BF16 form takes unprepared points");
     StepShape sh = step_shape_for(d, std::max(1, M / ncl));
     // default: at most two seeds per lane up to D = 8 and one above (timed on
     // 512 uneven clouds: more seeds per lane cost occupancy here, and the
@@ -1200,7 +1267,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     int chunk = p->tile_chunk, grid_cap = p->tile_grid;
     if (R == 0 || chunk == 0 || grid_cap == 0) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        const auto it = g_tune.find(tune_key(d, n, M, ncl));
+        const auto it = g_tune.find(tune_key(d, n, M, ncl, p->precision));
         if (it != g_tune.end()) {
             if (R == 0) R = it->second.R;
             if (chunk == 0) chunk = it->second.chunk;
@@ -1209,7 +1276,13 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     }
     if (chunk == 0) chunk = kBatchedChunk;
     if (grid_cap == 0) grid_cap = kBatchedGrid;
-    if (R != 0) {
+    if (bf) {
+        // seed tiles of 128 (the finalize's two slots per lane), chunks of
+        // whole 256-point blocks
+        sh.R = 2;
+        sh.TS = kBf16fTile;
+        chunk = (chunk + 255) / 256 * 256;
+    } else if (R != 0) {
         if (!batched_R_ok(sh.D, R)) return fail(MS_E_INVALID, "tile_R is not built for this dimension");
         sh.R = R;
         sh.TS = 64 * R;
@@ -1247,11 +1320,20 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         xo_dev = xod;
         so_dev = sod;
     }
+    BatchedBf16 bb;
+    if (bf) FMS_CHECK(prepare_batched_bf16(ws, Xp, n, sh.D, xo, so, xo_dev, ncl, M, bb, s));
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
     b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
     b.chunk_points = chunk;
     b.grid_cap = grid_cap;
+    if (bf) {
+        b.Xs = bb.Xs;
+        b.pf = bb.feat;
+        b.feat_blocks = bb.nblk;
+        b.boff = bb.boff;
+        b.shift = bb.zero;
+    }
     FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
     FMS_CHECK(ws.alloc(&b.act[0], M));
     FMS_CHECK(ws.alloc(&b.act[1], M));
@@ -1265,6 +1347,13 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
     FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));
     FMS_HIP(launch_batched_init(seeds, converged, d, M, so_dev, ncl, cnt, b, s));
+    if (bf) {
+        // each cloud's active list in the spatial order of its seeds
+        const CloudRows pts{ncl, xo_dev, bb.boff, bb.nblk};
+        const CloudRows sds{ncl, bb.soff, bb.stpre, bb.stiles};
+        FMS_HIP(launch_batched_seed_order(b.S, sh.DP, sh.D, M, scale, b.status, sds, Xp, pts, bb.poff, bb.sws,
+                                          bb.count, bb.ptot, b.act[0], s));
+    }
     if (ev) FMS_HIP(hipEventRecord(ev[0], s));
     if (p->graph && n_iter > 0) {
         // every iteration captured on a private stream (capture is not allowed
@@ -1603,6 +1692,7 @@ int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     for (int c = 0; c < 3; ++c) {
         if (ms_per_iter) ms_per_iter[c] = -1.0f;
         if (!batched_R_ok(D, candR[c])) continue;
+        if (p->precision == MS_PREC_BF16_REFINE && candR[c] != 2) continue;   // tiles of 128 only
         for (int ci = 0; ci < 4; ++ci)
             for (int gi = 0; gi < 3; ++gi) {
                 q.tile_chunk = candC[ci];
@@ -1628,7 +1718,7 @@ int tune_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     FMS_HIP(hipStreamSynchronize(s));
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_tune[tune_key(d, n, M, ncl)] = best;
+        g_tune[tune_key(d, n, M, ncl, p->precision)] = best;
     }
     if (best_R) *best_R = best.R;
     if (best_chunk) *best_chunk = best.chunk;
@@ -1647,8 +1737,10 @@ namespace {
 int check_batched_args(const ms_params* p, const float* X, const int64_t* x_off, const int64_t* s_off,
                        int32_t ncl, int32_t d) {
     FMS_CHECK(check_params(p, false));
-    if (p->precision != MS_PREC_FP32)
-        return fail(MS_E_INVALID, "ms_step_batched computes the FP32 form only");
+    if (p->precision != MS_PREC_FP32 && p->precision != MS_PREC_BF16_REFINE)
+        return fail(MS_E_INVALID, "unknown precision");
+    if (p->precision == MS_PREC_BF16_REFINE && !batched_bf16_ok(p, d))
+        return fail(MS_E_INVALID, "the batched BF16 form is built for the Gaussian kernel at 5 <= d <= 32");
     if (p->metric != MS_METRIC_EUCLIDEAN)
         return fail(MS_E_INVALID, "ms_step_batched computes the Euclidean metric only");
     if (!x_off || !s_off) return fail(MS_E_INVALID, "offsets are NULL");
@@ -1752,6 +1844,7 @@ int ms_fit_batched(const ms_params* p, const float* X, const int64_t* x_off, int
     FMS_CHECK(check_params(p, true));
     FMS_CHECK(check_batched_args(p, X, x_off, x_off, ncl, d));
     if (p->gamma != 1.0f) return fail(MS_E_INVALID, "ms_fit_batched runs every round to convergence: gamma must be 1");
+    if (p->precision != MS_PREC_FP32) return fail(MS_E_INVALID, "ms_fit_batched computes the FP32 form only");
     if (!k_off) return fail(MS_E_INVALID, "k_off is NULL");
     if (!modes) return fail(MS_E_INVALID, "modes is NULL");
     if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");

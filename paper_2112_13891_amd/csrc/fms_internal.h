@@ -94,6 +94,8 @@ struct Batch {
     float e_thr;           // BF16 form: refine threshold (packed units)
     float kappa;           // BF16 form: error bound coefficient
     const float* shift = nullptr;   // BF16 form, D > 4: frame of the sorted points
+    int feat_blocks = 0;   // BF16 form over many clouds: 256-point blocks of the features (0: from n)
+    const int32_t* boff = nullptr;   // BF16 form over many clouds: blocks before each cloud
     unsigned long long* prog = nullptr;   // host-mapped progress word (t << 32 | m), or NULL
     int metric = MS_METRIC_EUCLIDEAN;     // cosine: seeds are renormalized after each update
     Ctl* ctl;
@@ -131,6 +133,39 @@ double cull_reach(int kernel, double h);
 StepShape step_shape_cull(int d, int B, int n);
 hipError_t launch_iteration_cull(Batch& b, int t, hipStream_t s);
 
+// ---- many clouds ---------------------------------------------------------------
+// The cloud c with pre[c] <= v < pre[c + 1] (pre ascending over ncl + 1
+// entries; empty clouds, whose range is empty, are never returned).
+template <class T>
+__device__ __forceinline__ int upper_cloud(const T* pre, int ncl, long long v) {
+    int lo = 0, hi = ncl;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((long long)pre[mid] <= v) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Device plan of one batched iteration (k_batched.hip fills it; the step
+// kernels read it).
+struct BatchedArgs {
+    int ncl;
+    const long long* x_off;   // ncl + 1 point offsets
+    const int32_t* seg;       // ncl + 1 seed offsets
+    int32_t* cnt;             // 2 x ncl active counts, by iteration t % 2
+    int32_t* tiles;           // ncl
+    int32_t* chunks;          // ncl
+    int32_t* item_pre;        // ncl + 1
+    int32_t* slot_pre;        // ncl + 1
+    int32_t* item_cloud;      // cloud of each work item
+    int32_t* slot_cloud;      // cloud of each active slot
+    int32_t* queue;           // next work item to take (zeroed by the plan)
+    int chunk_points;         // points per point chunk (BF16 form: a multiple of 256)
+    int grid_cap;             // most workgroups of the step
+    const int32_t* boff;      // BF16 form: 256-point blocks before cloud c (ncl + 1), else NULL
+};
+
 // ---- launchers (k_step_bf16.hip) -----------------------------------------
 StepShape step_shape_bf16(int d, int B);
 bool bf16_supported(int d);
@@ -150,6 +185,15 @@ hipError_t launch_bf16w_features(const float* Xs, int n, int D, const float* geo
 hipError_t launch_iteration_bf16f(Batch& b, int t, hipStream_t s);
 size_t bf16f_feature_bytes(int n, int D);
 hipError_t launch_bf16f_features(const float* Xs, int n, int D, const float* geom, void* feat, hipStream_t s);
+// Many clouds: the features of nblk blocks, block b of cloud c holding the
+// sorted rows x_off[c] + 256 (b - boff[c]) .. (at most 256, within the cloud).
+size_t bf16f_feature_bytes_blocks(long long nblk, int D);
+hipError_t launch_bf16f_features_batched(const float* Xs, int D, const long long* x_off, const int32_t* boff,
+                                         int ncl, int nblk, void* feat, hipStream_t s);
+// The step of one batched iteration in this form (one partial per seed and
+// work item, as the FP32 batched step stores them; seed tiles of 128).
+hipError_t launch_bstep_bf16f(const Batch& b, const BatchedArgs& B, int t, int grid, hipStream_t s);
+constexpr int kBf16fTile = 128;
 // Feature bytes and builder of the BF16 form for D > 4 (the Gaussian kernel's
 // compensated form or the flat window's screen form).
 inline size_t bf16_wide_feature_bytes(int n, int D, int kernel) {
@@ -161,7 +205,7 @@ inline hipError_t launch_bf16_wide_features(const float* Xs, int n, int D, const
                                         : launch_bf16w_features(Xs, n, D, geom, feat, s);
 }
 
-// ---- launchers (k_batched.hip): FP32 step over many clouds ---------------------
+// ---- launchers (k_batched.hip): the step over many clouds ----------------------
 int batched_max_clouds();
 long long batched_max_items(const long long* x_off, const int32_t* seg, int ncl, int TS, int chunk_points);
 hipError_t launch_batched_init(const float* seeds, const uint8_t* conv_in, int d, int M,
@@ -184,6 +228,30 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
 hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
                              const uint8_t* status, void* ws, int32_t* act0, const float* Xp, int n,
                              hipStream_t s);
+// Many clouds (D in {8, 16, 32}): every cloud's points ordered as the D > 4
+// sort orders one cloud's, within the cloud's own rows and against its own
+// pivots (batched_pivot_count of them, poff their prefix).  The workspace
+// keeps the pivots' chain ranks for launch_batched_seed_order.
+int batched_pivot_count(long long n_cloud);
+size_t batched_sort_workspace_bytes(int count, int ptot);
+struct CloudRows {
+    int ncl;
+    const long long* roff;   // device, ncl + 1 row offsets of the clouds
+    const int32_t* tpre;     // device, ncl + 1: 256-row tiles before each cloud
+    int tiles;               // tpre[ncl]
+};
+// ws: batched_sort_workspace_bytes(count, ptot) bytes, count >= the points
+// and the seeds to be ordered (the same count for both calls).
+hipError_t launch_batched_sort(const float* Xp, int n, int D, const CloudRows& pts, const int32_t* poff, int ptot,
+                               float* Xs, void* ws, int count, hipStream_t s);
+// Active lists of a batch of seeds (S in original units, `scale` to packed
+// units) in the order of their positions within each cloud, the active seeds
+// of a cloud first: act0[seg[c] ..] holds cloud c's seeds.  count: as for
+// launch_batched_sort (>= M).
+hipError_t launch_batched_seed_order(const float* S, int DP, int D, int M, float scale, const uint8_t* status,
+                                     const CloudRows& seeds, const float* Xp, const CloudRows& pts,
+                                     const int32_t* poff, void* ws, int count, int ptot, int32_t* act0,
+                                     hipStream_t s);
 
 // ---- launchers (k_merge.hip) ---------------------------------------------
 hipError_t launch_iota(int32_t* a, int n, hipStream_t s);

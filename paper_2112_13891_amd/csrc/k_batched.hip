@@ -35,33 +35,6 @@ namespace {
 
 constexpr int kPlanThreads = 1024;
 
-struct BatchedArgs {
-    int ncl;
-    const long long* x_off;   // ncl + 1 point offsets
-    const int32_t* seg;       // ncl + 1 seed offsets
-    int32_t* cnt;             // 2 x ncl active counts, by iteration t % 2
-    int32_t* tiles;           // ncl
-    int32_t* chunks;          // ncl
-    int32_t* item_pre;        // ncl + 1
-    int32_t* slot_pre;        // ncl + 1
-    int32_t* item_cloud;      // cloud of each work item
-    int32_t* slot_cloud;      // cloud of each active slot
-    int32_t* queue;           // next work item to take (zeroed by the plan)
-    int chunk_points;         // points per point chunk
-    int grid_cap;             // most workgroups of the step
-};
-
-__device__ __forceinline__ int upper_cloud(const int32_t* pre, int ncl, int v) {
-    // the cloud c with pre[c] <= v < pre[c + 1] (pre ascending, empty clouds skipped)
-    int lo = 0, hi = ncl;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= v) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // Appends seed j to the active list of its cloud c (slots seg[c] + cnt[c]++)
 // for every lane with keep set: the wave's seeds one cloud at a time, one
 // atomic per cloud and wave, slots in lane order.  Every active lane of the
@@ -268,8 +241,7 @@ __global__ void bzero_kernel(int32_t* a, int count) {
     if (i < count) a[i] = 0;
 }
 
-template <int D, int DP, int R>
-hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
+StepArgs batched_step_args(const Batch& b, const BatchedArgs& B, int t) {
     StepArgs a = {};
     a.Xp = b.Xp;
     a.n = b.n;
@@ -288,6 +260,17 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
     a.metric = b.metric;
+    return a;
+}
+
+int batched_finalize_blocks(const Batch& b) {
+    const int fblocks = (b.n_seeds + kFinThreads - 1) / kFinThreads;
+    return fblocks < 1 ? 1 : (fblocks > 1024 ? 1024 : fblocks);
+}
+
+template <int D, int DP, int R>
+hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
+    const StepArgs a = batched_step_args(b, B, t);
     hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, 64 * R);
     // no more workgroups than the first iteration has work items (seeds only
     // ever leave the active lists)
@@ -298,9 +281,25 @@ hipError_t bstep_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
     else
         hipLaunchKernelGGL((bstep_kernel<D, DP, R, MS_KERNEL_FLAT>), dim3(grid), dim3(kThreads), 0,
                            s, a, B);
-    int fblocks = (b.n_seeds + kFinThreads - 1) / kFinThreads;
-    fblocks = fblocks < 1 ? 1 : (fblocks > 1024 ? 1024 : fblocks);
-    hipLaunchKernelGGL((bfinal_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a, B, t);
+    hipLaunchKernelGGL((bfinal_kernel<D, DP, R>), dim3(batched_finalize_blocks(b)), dim3(kFinThreads), 0, s, a, B,
+                       t);
+    return hipGetLastError();
+}
+
+// The BF16 form (Gaussian, D in {8, 16, 32}): the same plan over seed tiles
+// of 128 and chunks of whole 256-point blocks of each cloud's sorted points,
+// the compensated step per work item, the same finalize (two seeds' slots per
+// lane: tiles of 128).
+template <int D>
+hipError_t bstep_bf16_t(const Batch& b, const BatchedArgs& B, int t, hipStream_t s) {
+    static_assert(kBf16fTile == 128, "the finalize's tile");
+    const StepArgs a = batched_step_args(b, B, t);
+    hipLaunchKernelGGL(bplan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, t, kBf16fTile);
+    const int grid = std::max(1, std::min(B.grid_cap, b.grid));
+    hipError_t e = launch_bstep_bf16f(b, B, t, grid, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bfinal_kernel<D, D, 2>), dim3(batched_finalize_blocks(b)), dim3(kFinThreads), 0, s, a, B,
+                       t);
     return hipGetLastError();
 }
 
@@ -346,7 +345,17 @@ hipError_t launch_batched_iteration(const Batch& b, const long long* x_off_dev, 
     B.queue = plan + 4 * ncl + 2;
     B.chunk_points = b.chunk_points;
     B.grid_cap = b.grid_cap;
+    B.boff = b.boff;
     const int D = b.sh.D, R = b.sh.R;
+    if (b.prec == MS_PREC_BF16_REFINE) {
+        if (!b.boff || b.chunk_points % 256 != 0) return hipErrorInvalidValue;
+        switch (D) {
+            case 8: return bstep_bf16_t<8>(b, B, t, s);
+            case 16: return bstep_bf16_t<16>(b, B, t, s);
+            case 32: return bstep_bf16_t<32>(b, B, t, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
 #define FMS_BCASE(DD, DPP, RR) \
     if (D == DD && R == RR) return bstep_t<DD, DPP, RR>(b, B, t, s);
     FMS_BCASE(1, 4, 1) FMS_BCASE(1, 4, 2) FMS_BCASE(1, 4, 4)

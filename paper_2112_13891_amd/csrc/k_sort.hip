@@ -329,15 +329,29 @@ __global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift)
 // chunks); pivot_key_kernel turns it into the sort key.
 constexpr int kPivChunk = 64;
 
+// Many clouds (rc.roff set): blockIdx.x is a 256-row tile of one cloud's
+// rows, whose pivots are the cloud's own (points Xp[xoff[c] ..], poff).
 template <int D>
-__global__ __launch_bounds__(256) void pivot_near_kernel(const float* __restrict__ rows, int m, int DPr,
+__global__ __launch_bounds__(256) void pivot_near_kernel(const float* __restrict__ rows, long long m, int DPr,
                                                          float scale, const float* __restrict__ Xp, int n,
-                                                         int DP, int P, unsigned long long* best) {
+                                                         int DP, int P, unsigned long long* best,
+                                                         CloudRows rc, const long long* __restrict__ xoff,
+                                                         const int32_t* __restrict__ poff) {
     static_assert(D % 4 == 0 && (kPivChunk * D) % 256 == 0, "pivot chunk layout");
     constexpr int kPer = kPivChunk * D / 256;   // pivot coordinates each thread stages
     __shared__ __attribute__((aligned(16))) float piv[kPivChunk][D];
-    const int r = blockIdx.x * 256 + threadIdx.x;
+    long long r = (long long)blockIdx.x * 256 + threadIdx.x;
     const int j0 = blockIdx.y * kPivChunk;
+    if (rc.roff) {
+        const int c = upper_cloud(rc.tpre, rc.ncl, blockIdx.x);
+        r = rc.roff[c] + (long long)(blockIdx.x - rc.tpre[c]) * 256 + threadIdx.x;
+        m = rc.roff[c + 1];
+        const long long x0 = xoff[c];
+        n = (int)(xoff[c + 1] - x0);
+        P = poff[c + 1] - poff[c];
+        Xp += x0 * DP;
+        if (j0 >= P) return;   // the whole workgroup
+    }
     const int cnt = min(kPivChunk, P - j0);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -405,6 +419,27 @@ __global__ void pivot_key_kernel(const unsigned long long* __restrict__ best, in
     vals[r] = r;
 }
 
+// Many clouds: the sort key of row r of cloud c (the cloud found from the
+// row offsets) keeps the clouds apart and each cloud's rows in the order of
+// the one-cloud key: c << 19 | inactive << 18 | far << 17 | the pivot's chain
+// rank within the cloud (< 256) << 9 | the top 9 bits of the squared distance.
+__global__ void bpivot_key_kernel(const unsigned long long* __restrict__ best, long long m,
+                                  const uint8_t* __restrict__ status, const long long* __restrict__ roff, int ncl,
+                                  const int32_t* __restrict__ poff, const int* __restrict__ prank, unsigned* keys,
+                                  int* vals) {
+    const long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= m) return;
+    const int c = upper_cloud(roff, ncl, r);
+    const unsigned long long b = best[r];
+    const unsigned qbits = (unsigned)(b >> 32);
+    const int bi = (int)(unsigned)b;
+    unsigned key = ((unsigned)c << 19) | ((unsigned)prank[poff[c] + bi] << 9) | (qbits >> 22);
+    if (__uint_as_float(qbits) > kFarPivot * kFarPivot) key |= 1u << 17;
+    if (status && status[r] != ST_ACTIVE) key |= 1u << 18;
+    keys[r] = key;
+    vals[r] = (int)r;
+}
+
 // Order of the pivots along a greedy nearest-neighbour chain: from pivot 0,
 // each next pivot is the nearest one not yet taken (ties to the lowest
 // index), so that the pivots of one cluster follow each other.  Two
@@ -415,17 +450,30 @@ __global__ void pivot_key_kernel(const unsigned long long* __restrict__ best, in
 // taken does the whole workgroup search all pivots.  prank[j] = the chain
 // position of pivot j.
 constexpr int kKnn = 8;
+constexpr int kBatchedPivotMax = 256;   // pivots of one cloud in a batched sort
 
 // One workgroup per 64 pivots; wave q of the sixteen scans the candidates
 // i = q (mod 16), and the sixteen lists of a pivot are merged through LDS.
+// Many clouds (xoff set): blockIdx.y is the cloud, whose pivots and lists
+// are its own (indices within the cloud).
 template <int D>
 __global__ __launch_bounds__(1024) void pivot_knn_kernel(const float* __restrict__ Xp, int n, int DP, int P,
-                                                         int* knn) {
+                                                         int* knn, const long long* __restrict__ xoff,
+                                                         const int32_t* __restrict__ poff) {
     constexpr int kW = 16;                     // waves
     constexpr int kCand = 256;                 // candidates staged per pass
     constexpr int kPer = kCand * D / 1024;
     __shared__ __attribute__((aligned(16))) float cand[kCand][D];
     __shared__ unsigned long long lists[kW][64][kKnn];
+    if (xoff) {
+        const int c = blockIdx.y;
+        const long long x0 = xoff[c];
+        n = (int)(xoff[c + 1] - x0);
+        P = poff[c + 1] - poff[c];
+        Xp += x0 * DP;
+        knn += (long long)poff[c] * kKnn;
+        if ((int)blockIdx.x * 64 >= P) return;   // the whole workgroup
+    }
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + lane;
     const long long row = j < P ? (long long)j * n / P : 0;
@@ -503,15 +551,29 @@ __global__ __launch_bounds__(1024) void pivot_knn_kernel(const float* __restrict
 // (a pivot per thread, its coordinates in registers; the current pivot's
 // coordinates from LDS) and wave 0 goes on from the nearest untaken one.
 // The taken flags and the ranks stay in LDS; the ranks go out at the end.
+// Many clouds (xoff set): one workgroup per cloud (blockIdx.x), ranks within
+// the cloud.
 template <int D>
 __global__ __launch_bounds__(1024) void pivot_chain_kernel(const float* __restrict__ Xp, int n, int DP, int P,
-                                                          const int* __restrict__ knn, int* prank) {
+                                                          const int* __restrict__ knn, int* prank,
+                                                          const long long* __restrict__ xoff,
+                                                          const int32_t* __restrict__ poff) {
     __shared__ __attribute__((aligned(16))) float4 pc[D / 4][1024];
     __shared__ short lst[1024 * kKnn];
     __shared__ unsigned char taken[1024];
     __shared__ int rk[1024];
     __shared__ unsigned long long wbest[16];
     __shared__ int s_cur, s_step;
+    if (xoff) {
+        const int c = blockIdx.x;
+        const long long x0 = xoff[c];
+        n = (int)(xoff[c + 1] - x0);
+        P = poff[c + 1] - poff[c];
+        Xp += x0 * DP;
+        knn += (long long)poff[c] * kKnn;
+        prank += poff[c];
+        if (P == 0) return;   // the whole workgroup
+    }
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool mine = tid < P;
     float x[D];
@@ -763,13 +825,14 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         int* prank = reinterpret_cast<int*>(w.bnd + kRankOff);
         int* knn = reinterpret_cast<int*>(w.best);   // free until the nearest-pivot search
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_knn_kernel<DD>), dim3((P + 63) / 64), dim3(1024), 0, s,
-                                                Xp, n, DP, P, knn));
+                                                Xp, n, DP, P, knn, nullptr, nullptr));
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(1), dim3(1024), 0, s, Xp, n, DP,
-                                                P, knn, prank));
+                                                P, knn, prank, nullptr, nullptr));
         hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, ~0ull);
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>),
                                                 dim3((n + 255) / 256, (P + kPivChunk - 1) / kPivChunk), dim3(256), 0,
-                                                s, Xp, n, DP, 1.0f, Xp, n, DP, P, w.best));
+                                                s, Xp, (long long)n, DP, 1.0f, Xp, n, DP, P, w.best, CloudRows{},
+                                                nullptr, nullptr));
         hipLaunchKernelGGL(pivot_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, nullptr, prank,
                            w.k0, w.v0);
     }
@@ -782,6 +845,92 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
                        0, s, Xp, DP, D, perm, n, shift, Xs);
     hipLaunchKernelGGL(block_geom_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Xs, n, DP, D,
                        geom_stride(D), geom);
+    return hipGetLastError();
+}
+
+// ---- many clouds -------------------------------------------------------------
+
+int batched_pivot_count(long long n_cloud) {
+    if (n_cloud <= 0) return 0;
+    const long long P = n_cloud / 256;
+    return (int)(P < 1 ? 1 : (P > kBatchedPivotMax ? kBatchedPivotMax : P));
+}
+
+namespace {
+
+// Batched sort workspace: the sort's (as for `count` rows), then the pivots'
+// neighbour lists and chain ranks.
+size_t bws_sort_bytes(int count) {
+    const size_t nblocks = (count + kSortThreads - 1) / kSortThreads;
+    return kBndFloats * 4 + 4 * 256 * 4 + (size_t)count * 4 * 4 + (size_t)count * 8 + nblocks * 256 * 4 + 256;
+}
+
+SortWs carve_batched(void* ws, int count, int ptot, int** knn, int** prank) {
+    SortWs w;
+    char* p = (char*)ws;
+    w.bnd = (float*)p; p += kBndFloats * 4;
+    w.dtot = (int*)p; p += 4 * 256 * 4;
+    w.k0 = (unsigned*)p; p += (size_t)count * 4;
+    w.k1 = (unsigned*)p; p += (size_t)count * 4;
+    w.v0 = (int*)p; p += (size_t)count * 4;
+    w.v1 = (int*)p; p += (size_t)count * 4;
+    w.best = (unsigned long long*)p; p += (size_t)count * 8;
+    w.hist = (int*)p;
+    p = (char*)ws + bws_sort_bytes(count);
+    *knn = (int*)p; p += (size_t)ptot * kKnn * 4;
+    *prank = (int*)p;
+    return w;
+}
+
+}  // namespace
+
+size_t batched_sort_workspace_bytes(int count, int ptot) {
+    return bws_sort_bytes(count) + (size_t)ptot * (kKnn + 1) * 4 + 256;
+}
+
+hipError_t launch_batched_sort(const float* Xp, int n, int D, const CloudRows& pts, const int32_t* poff, int ptot,
+                               float* Xs, void* ws, int count, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n > count) return hipErrorInvalidValue;
+    int *knn, *prank;
+    const SortWs w = carve_batched(ws, count, ptot, &knn, &prank);
+    const int ncl = pts.ncl;
+    const dim3 pgroups((kBatchedPivotMax + 63) / 64, ncl);
+    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_knn_kernel<DD>), pgroups, dim3(1024), 0, s, Xp, 0, D, 0, knn,
+                                            pts.roff, poff));
+    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(ncl), dim3(1024), 0, s, Xp, 0, D, 0,
+                                            knn, prank, pts.roff, poff));
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, ~0ull);
+    const dim3 ngrid(pts.tiles, (kBatchedPivotMax + kPivChunk - 1) / kPivChunk);
+    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>), ngrid, dim3(256), 0, s, Xp, (long long)n, D,
+                                            1.0f, Xp, 0, D, 0, w.best, pts, pts.roff, poff));
+    hipLaunchKernelGGL(bpivot_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, (long long)n, nullptr,
+                       pts.roff, ncl, poff, prank, w.k0, w.v0);
+    const int* sorted = radix_sort_pairs(w, n, s, 4);
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)(((long long)n * D + 255) / 256)), dim3(256), 0, s, Xp,
+                       D, D, sorted, n, nullptr, Xs);
+    return hipGetLastError();
+}
+
+hipError_t launch_batched_seed_order(const float* S, int DP, int D, int M, float scale, const uint8_t* status,
+                                     const CloudRows& seeds, const float* Xp, const CloudRows& pts,
+                                     const int32_t* poff, void* ws, int count, int ptot, int32_t* act0,
+                                     hipStream_t s) {
+    if (M <= 0) return hipSuccess;
+    if (M > count) return hipErrorInvalidValue;
+    int *knn, *prank;
+    // the ranks the point sort left (sized for `count` rows there too)
+    SortWs w = carve_batched(ws, count, ptot, &knn, &prank);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((M + 255) / 256), dim3(256), 0, s, w.best, M, ~0ull);
+    const dim3 ngrid(seeds.tiles, (kBatchedPivotMax + kPivChunk - 1) / kPivChunk);
+    if (seeds.tiles > 0)
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>), ngrid, dim3(256), 0, s, S, (long long)M,
+                                                DP, scale, Xp, 0, D, 0, w.best, seeds, pts.roff, poff));
+    hipLaunchKernelGGL(bpivot_key_kernel, dim3((M + 255) / 256), dim3(256), 0, s, w.best, (long long)M, status,
+                       seeds.roff, seeds.ncl, poff, prank, w.k0, w.v0);
+    const int* sorted = radix_sort_pairs(w, M, s, 4);
+    hipError_t e = hipMemcpyAsync(act0, sorted, (size_t)M * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -805,7 +954,8 @@ hipError_t launch_seed_order(const float* S, int DP, int D, int m, float scale,
         hipLaunchKernelGGL(fill_u64_kernel, dim3((m + 255) / 256), dim3(256), 0, s, w.best, m, ~0ull);
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>),
                                                 dim3((m + 255) / 256, (P + kPivChunk - 1) / kPivChunk), dim3(256), 0,
-                                                s, S, m, DP, scale, Xp, n, DP, P, w.best));
+                                                s, S, (long long)m, DP, scale, Xp, n, DP, P, w.best, CloudRows{},
+                                                nullptr, nullptr));
         hipLaunchKernelGGL(pivot_key_kernel, dim3((m + 255) / 256), dim3(256), 0, s, w.best, m, status, prank,
                            w.k0, w.v0);
     }

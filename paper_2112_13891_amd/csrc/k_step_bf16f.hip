@@ -83,9 +83,10 @@ struct FShape {
     static constexpr int FIN = (D + 1) * kFSeeds * 4;
     static constexpr int TR = 4 * 32 * 33 * 4;
     static constexpr int SMEM = STAGE > FIN ? (STAGE > TR ? STAGE : TR) : (FIN > TR ? FIN : TR);
-    // per-block row of the centring: centre[D], R, Rin, Ro, 5 unused, the
-    // outlier bits of the 8 tiles (a uint32 each, bit p = point p of the
-    // tile), then the outliers' own centre[D] (Ro < 0: no outliers)
+    // per-block row of the centring: centre[D], R, Rin, Ro, the block's
+    // first row and live count (int32 bit patterns), 3 unused, the outlier
+    // bits of the 8 tiles (a uint32 each, bit p = point p of the tile), then
+    // the outliers' own centre[D] (Ro < 0: no outliers)
     static constexpr int INFO = 2 * D + 16;
     static_assert(STAGE % (16 * kFThreads) == 0, "stage layout");
 };
@@ -108,10 +109,15 @@ __device__ __forceinline__ float bfr(float x) { return (float)(__bf16)x; }
 // its radii, the outlier bits, the outliers' own ball (bounding-box
 // midpoint and radius: where two pivot runs meet, the block's other run) and
 // the three bf16 parts.
+// With boff set (many clouds), block b belongs to the cloud c with boff[c] <=
+// b < boff[c + 1] and holds the sorted rows x_off[c] + 256 (b - boff[c]) ..,
+// at most 256 and within the cloud; otherwise block b holds rows 256 b .. of
+// the n.  The first row and the live count go into the info row.
 template <int D>
 __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __restrict__ Xs, int n,
                                                                __bf16* fhi, __bf16* fmid, __bf16* flo,
-                                                               float* info) {
+                                                               float* info, const long long* __restrict__ x_off,
+                                                               const int32_t* __restrict__ boff, int ncl) {
     using Sh = FShape<D>;
     __shared__ __attribute__((aligned(16))) float vals[kFBlk];
     __shared__ float ctr[D];
@@ -119,14 +125,21 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
     __shared__ float omin[kFBlk / 64][D], omax[kFBlk / 64][D], oc[D];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
-    const int i = blk * kFBlk + tid;
-    const int nl = min(kFBlk, n - blk * kFBlk);   // live points of the block (>= 1)
+    long long row0 = (long long)blk * kFBlk, rend = n;
+    if (boff) {
+        const int c = upper_cloud(boff, ncl, blk);
+        row0 = x_off[c] + (long long)(blk - boff[c]) * kFBlk;
+        rend = x_off[c + 1];
+    }
+    const long long row = row0 + tid;                 // this thread's point
+    const long long i = (long long)blk * kFBlk + tid;   // its slot in the operands
+    const int nl = (int)min((long long)kFBlk, rend - row0);   // live points of the block (>= 1)
     const bool live = tid < nl;
     const int mid = (nl - 1) / 2;
     float x[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) x[k] = live ? Xs[(long long)i * D + k] : 0.0f;
-    if (tid < D) ctr[tid] = Xs[(long long)blk * kFBlk * D + tid];   // stands in if ranks tie oddly (NaN)
+    for (int k = 0; k < D; ++k) x[k] = live ? Xs[row * D + k] : 0.0f;
+    if (tid < D) ctr[tid] = Xs[row0 * D + tid];   // stands in if ranks tie oddly (NaN)
 #pragma unroll 1
     for (int k = 0; k < D; ++k) {
         const float xv = x[k];
@@ -213,6 +226,8 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
         g[D + 16 + tid] = oc[tid];
     }
     if (tid == 0) {
+        g[D + 3] = __int_as_float((int)row0);
+        g[D + 4] = __int_as_float(nl);
         float a = 0.0f, b = 0.0f, c = -1.0f;
         for (int w = 0; w < kFBlk / 64; ++w) {
             a = fmaxf(a, rmax[0][w]);
@@ -259,41 +274,84 @@ __device__ __forceinline__ __bf16 staged_coord(const __bf16* base, int kbs, int 
     return base[((tt * kbs + (c >> 4)) * 2 + ((c >> 3) & 1)) * 256 + p * 8 + (c & 7)];
 }
 
-template <int D>
-__global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, int t) {
+// The step kernel, in two launch forms.  One cloud (MANY = false): the work
+// items (seed tile of 128, chunk of the blocks) of the iteration's active
+// list, in a grid-stride loop, a chunk's partials finalized in place when the
+// tile has one chunk.  Many clouds (MANY = true): a persistent grid over the
+// work items (cloud, seed tile of 128, chunk of the cloud's blocks) of the
+// batched plan, taken as the FP32 batched step takes them (from the queue
+// when they outnumber the workgroups), each storing one partial per seed,
+// component-major within the item, for the batched finalize.  Either way a
+// lane holds one seed (the two halves of a wave the same 32 seeds, each half
+// its own points of every tile).
+template <int D, bool MANY>
+__global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, int t, BatchedArgs B) {
     using Sh = FShape<D>;
     constexpr int TS = kFSeeds;
     constexpr int KBH = Sh::KBH, KBL = Sh::KBL;
     const StepArgs& a = A.base;
     Ctl* ctl = a.ctl;
-    const int n = a.n;
-    const int m = active_count(ctl, t);
-    step_prologue(a, t, m);
-    if (m == 0) return;
-    const int G = gridDim.x;
-    const int tiles = (m + TS - 1) / TS;
-    const int chunks = chunks_for(m, TS, n, G, a.min_chunk);
-    const int nblk = (n + kFBlk - 1) / kFBlk;
+    int m = 0, tiles = 1, chunks = 1, nblk = 0, total = 0;
+    if constexpr (MANY) {
+        total = B.item_pre[B.ncl];
+    } else {
+        m = active_count(ctl, t);
+        step_prologue(a, t, m);
+        if (m == 0) return;
+        tiles = (m + TS - 1) / TS;
+        chunks = chunks_for(m, TS, a.n, gridDim.x, a.min_chunk);
+        nblk = (a.n + kFBlk - 1) / kFBlk;
+        total = tiles * chunks;
+    }
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int col = lane & 31, hf = lane >> 5;
 
     __shared__ __attribute__((aligned(16))) char smem[Sh::SMEM];
+    __shared__ int next_item;
     const __bf16* shi = reinterpret_cast<const __bf16*>(smem);
     const __bf16* smid = reinterpret_cast<const __bf16*>(smem + Sh::HI_BYTES);
     const __bf16* slo = reinterpret_cast<const __bf16*>(smem + Sh::HI_BYTES + Sh::LO_BYTES);
     unsigned long long live_pairs = 0;   // wave-uniform: pairs of the live tiles
 
+    // many clouds: with no more items than workgroups each takes its own;
+    // otherwise every item comes from the queue (every thread has read the
+    // previous item -- the transposition below holds barriers -- before
+    // thread 0 writes the next one)
+    const bool own = !MANY || total <= (int)gridDim.x;
+    int item = blockIdx.x;
+    if (!own) {
+        if (threadIdx.x == 0) next_item = atomicAdd(B.queue, 1);
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(next_item);
+    }
     const const_f32_ptr gq = wave_uniform_const(A.info);   // block centring: scalar loads
-    for (int item = blockIdx.x; item < tiles * chunks; item += G) {
-        const int tile = item % tiles;
-        const int chunk = item / tiles;
-        const int b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
-        const int b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
+    while (item < total) {
+        int tile, chunk, b0, b1, slot0;
+        if constexpr (MANY) {
+            const int c = __builtin_amdgcn_readfirstlane(B.item_cloud[item]);
+            const int local = item - B.item_pre[c];
+            tiles = B.tiles[c];
+            chunks = B.chunks[c];
+            tile = local % tiles;
+            chunk = local / tiles;
+            const int bc = B.boff[c];
+            const int nb = B.boff[c + 1] - bc;
+            b0 = __builtin_amdgcn_readfirstlane(bc + (int)((long long)nb * chunk / chunks));
+            b1 = __builtin_amdgcn_readfirstlane(bc + (int)((long long)nb * (chunk + 1) / chunks));
+            m = B.slot_pre[c + 1] - B.slot_pre[c];
+            slot0 = B.seg[c];
+        } else {
+            tile = item % tiles;
+            chunk = item / tiles;
+            b0 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * chunk / chunks));
+            b1 = __builtin_amdgcn_readfirstlane((int)((long long)nblk * (chunk + 1) / chunks));
+            slot0 = 0;
+        }
         const int slot = tile * TS + wave * 32 + col;
         const bool live = slot < m;
         const unsigned long long lmask = __ballot(live);   // lanes holding a seed
-        const int j = a.act_in[live ? slot : 0];
+        const int j = a.act_in[slot0 + (live ? slot : 0)];
         float shat[D], aex[D];
         float wsum = 0.0f;
 #pragma unroll
@@ -440,14 +498,16 @@ __global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, i
                     //    against the large x~ of an outlier)
                     const unsigned obits = __float_as_uint(gm[D + 8 + tt]);
                     if (obits != 0u || __ballot(exact_seed)) {
-                        const long long r0 = (long long)blk * kFBlk + tt * 32;
+                        // the block's first row and live count
+                        const long long r0 = (long long)__float_as_int(gm[D + 3]) + tt * 32;
+                        const int nl = __float_as_int(gm[D + 4]) - tt * 32;
 #pragma unroll
                         for (int v = 0; v < 16; ++v) {
                             const int p = 8 * (v >> 2) + 4 * hf + (v & 3);
                             const long long r = r0 + p;
                             const bool need = exact_seed || (live && ((obits >> p) & 1u) && E[v] + eps3 >= -127.0f);
                             if (__ballot(need)) {
-                                if (need && r < n) {
+                                if (need && p < nl) {
                                     const float4* xr = reinterpret_cast<const float4*>(A.Xs + r * D);
                                     float q2 = 0.0f;
 #pragma unroll
@@ -539,32 +599,48 @@ __global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, i
         for (int k = 0; k < D; ++k) aex[k] += tr[col * 33 + k];
         __syncthreads();   // tr is read before smem is reused
         const int pos = wave * 32 + col;
-        if (chunks == 1) {
-            float* fin = reinterpret_cast<float*>(smem);
+        if constexpr (MANY) {
             if (hf == 0) {
+                float* dst = a.part + (long long)item * TS * (D + 1) + pos;
 #pragma unroll
-                for (int k = 0; k < D; ++k) fin[k * TS + pos] = aex[k];
-                fin[D * TS + pos] = wsum;
+                for (int k = 0; k < D; ++k) dst[k * TS] = aex[k];
+                dst[D * TS] = wsum;
             }
+            if (own) break;
+            if (threadIdx.x == 0) next_item = atomicAdd(B.queue, 1);
             __syncthreads();
-            finalize_tile<D, D, 2>(a, t, m, tile, fin);
-            __syncthreads();
-        } else if (hf == 0) {
-            float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
+            item = __builtin_amdgcn_readfirstlane(next_item);
+        } else {
+            if (chunks == 1) {
+                float* fin = reinterpret_cast<float*>(smem);
+                if (hf == 0) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) dst[k] = aex[k];
-            dst[D] = wsum;
+                    for (int k = 0; k < D; ++k) fin[k * TS + pos] = aex[k];
+                    fin[D * TS + pos] = wsum;
+                }
+                __syncthreads();
+                finalize_tile<D, D, 2>(a, t, m, tile, fin);
+                __syncthreads();
+            } else if (hf == 0) {
+                float* dst = a.part + (((long long)tile * chunks + chunk) * TS + pos) * (D + 1);
+#pragma unroll
+                for (int k = 0; k < D; ++k) dst[k] = aex[k];
+                dst[D] = wsum;
+            }
+            item += gridDim.x;
         }
     }
-    // pairs of the live tiles: wave counts summed per workgroup, one atomic
-    // per workgroup on one of the spread counters
-    __shared__ unsigned long long wref[kWaves];
-    if (lane == 0) wref[threadIdx.x >> 6] = live_pairs;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long r = 0;
-        for (int w = 0; w < kWaves; ++w) r += wref[w];
-        if (r) atomicAdd((unsigned long long*)&ctl->refined[(blockIdx.x % kRefinedSlots) * kRefinedStride], r);
+    if constexpr (!MANY) {
+        // pairs of the live tiles: wave counts summed per workgroup, one
+        // atomic per workgroup on one of the spread counters
+        __shared__ unsigned long long wref[kWaves];
+        if (lane == 0) wref[threadIdx.x >> 6] = live_pairs;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long r = 0;
+            for (int w = 0; w < kWaves; ++w) r += wref[w];
+            if (r) atomicAdd((unsigned long long*)&ctl->refined[(blockIdx.x % kRefinedSlots) * kRefinedStride], r);
+        }
     }
 }
 
@@ -599,17 +675,58 @@ hipError_t launch_bf16f_t(Batch& b, int t, hipStream_t s) {
     A.info = reinterpret_cast<const float*>(A.flo + (size_t)npad / 32 * Sh::KBL * 512);
     A.Xs = b.Xs;
     A.shift = b.shift;
-    hipLaunchKernelGGL((step_bf16f_kernel<D>), dim3(b.grid), dim3(kFThreads), 0, s, A, t);
+    hipLaunchKernelGGL((step_bf16f_kernel<D, false>), dim3(b.grid), dim3(kFThreads), 0, s, A, t, BatchedArgs{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_finalize<D, D, 2>(a, t, b.grid, b.n_seeds, s);
 }
 
 template <int D>
-size_t bf16f_bytes_t(int n) {
+size_t bf16f_bytes_blocks_t(long long blocks) {
     using Sh = FShape<D>;
-    const size_t blocks = (size_t)((n + kFBlk - 1) / kFBlk);
-    return blocks * (kFBlk / 32) * (Sh::KBH + 2 * Sh::KBL) * 512 * 2 + blocks * Sh::INFO * 4;
+    return (size_t)blocks * (kFBlk / 32) * (Sh::KBH + 2 * Sh::KBL) * 512 * 2 + (size_t)blocks * Sh::INFO * 4;
+}
+
+template <int D>
+size_t bf16f_bytes_t(int n) {
+    return bf16f_bytes_blocks_t<D>((n + kFBlk - 1) / kFBlk);
+}
+
+template <int D>
+void bf16f_operands(Bf16fArgs& A, const void* feat, long long nblk) {
+    using Sh = FShape<D>;
+    const size_t npad = (size_t)nblk * kFBlk;
+    A.fhi = (const __bf16*)feat;
+    A.fmid = A.fhi + npad / 32 * Sh::KBH * 512;
+    A.flo = A.fmid + npad / 32 * Sh::KBL * 512;
+    A.info = reinterpret_cast<const float*>(A.flo + npad / 32 * Sh::KBL * 512);
+}
+
+template <int D>
+hipError_t launch_bstep_bf16f_t(const Batch& b, const BatchedArgs& B, int t, int grid, hipStream_t s) {
+    Bf16fArgs A = {};
+    StepArgs& a = A.base;
+    a.Xp = b.Xp;
+    a.n = b.n;
+    a.d = b.d;
+    a.S = b.S;
+    a.act_in = b.act[t & 1];
+    a.act_out = b.act[(t + 1) & 1];
+    a.status = b.status;
+    a.iters = b.iters;
+    a.shift2 = b.shift2;
+    a.part = b.part;
+    a.ctl = b.ctl;
+    a.h2 = b.h * b.h;
+    a.scale = b.scale;
+    a.inv_scale = b.inv_scale;
+    a.thr2 = b.thr2;
+    a.metric = b.metric;
+    bf16f_operands<D>(A, b.pf, b.feat_blocks);
+    A.Xs = b.Xs;
+    A.shift = b.shift;
+    hipLaunchKernelGGL((step_bf16f_kernel<D, true>), dim3(grid), dim3(kFThreads), 0, s, A, t, B);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -621,6 +738,47 @@ hipError_t launch_iteration_bf16f(Batch& b, int t, hipStream_t s) {
         case 32: return launch_bf16f_t<32>(b, t, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_bstep_bf16f(const Batch& b, const BatchedArgs& B, int t, int grid, hipStream_t s) {
+    switch (b.sh.D) {
+        case 8: return launch_bstep_bf16f_t<8>(b, B, t, grid, s);
+        case 16: return launch_bstep_bf16f_t<16>(b, B, t, grid, s);
+        case 32: return launch_bstep_bf16f_t<32>(b, B, t, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+size_t bf16f_feature_bytes_blocks(long long nblk, int D) {
+    switch (D) {
+        case 8: return bf16f_bytes_blocks_t<8>(nblk);
+        case 16: return bf16f_bytes_blocks_t<16>(nblk);
+        case 32: return bf16f_bytes_blocks_t<32>(nblk);
+        default: return 0;
+    }
+}
+
+hipError_t launch_bf16f_features_batched(const float* Xs, int D, const long long* x_off, const int32_t* boff,
+                                         int ncl, int nblk, void* feat, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    Bf16fArgs A = {};
+#define FMS_BFEAT(DD)                                                                                     \
+    case DD: {                                                                                            \
+        bf16f_operands<DD>(A, feat, nblk);                                                                \
+        hipLaunchKernelGGL(bf16f_features_kernel<DD>, dim3(nblk), dim3(kFBlk), 0, s, Xs, 0,              \
+                           (__bf16*)A.fhi, (__bf16*)A.fmid, (__bf16*)A.flo, (float*)A.info, x_off, boff,  \
+                           ncl);                                                                          \
+        break;                                                                                            \
+    }
+    switch (D) {
+        FMS_BFEAT(8)
+        FMS_BFEAT(16)
+        FMS_BFEAT(32)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef FMS_BFEAT
+    return hipGetLastError();
 }
 
 size_t bf16f_feature_bytes(int n, int D) {
@@ -646,7 +804,7 @@ hipError_t launch_bf16f_features(const float* Xs, int n, int D, const float* /*g
         __bf16* flo = fmid + (size_t)npad / 32 * FShape<DD>::KBL * 512;                                   \
         float* info = reinterpret_cast<float*>(flo + (size_t)npad / 32 * FShape<DD>::KBL * 512);          \
         hipLaunchKernelGGL(bf16f_features_kernel<DD>, dim3(nblk), dim3(kFBlk), 0, s, Xs, n, fhi, fmid,   \
-                           flo, info);                                                                    \
+                           flo, info, nullptr, nullptr, 0);                                               \
         break;                                                                                            \
     }
     switch (D) {

@@ -146,6 +146,8 @@ def test_null_pointers_and_reserved(api):
     p.precision = api.PRECISIONS["bf16"]
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
                              None, None, None) == -1
+    assert "Gaussian kernel at 5 <= d <= 32" in api.last_error()
+    assert L.ms_fit_batched(ctypes.byref(p), FAKE, xo, 2, 16, FAKE, 10, kf, None, None, None) == -1
     assert "FP32 form only" in api.last_error()
 
 
@@ -178,15 +180,17 @@ def test_step_batched_rejects_bad_arguments(api):
     L = api.lib()
     I64 = ctypes.c_int64 * 4
 
-    def call(xo, so, ncl=3, d=2, n_iter=1, prec="fp32"):
-        p = api.make_params(1.0, precision=prec)
+    def call(xo, so, ncl=3, d=2, n_iter=1, prec="fp32", kernel="gaussian"):
+        p = api.make_params(1.0, kernel=kernel, precision=prec)
         return L.ms_step_batched(ctypes.byref(p), FAKE, I64(*xo), FAKE, I64(*so), ncl, d, n_iter,
                                  FAKE, FAKE, FAKE, None)
 
     good_x, good_s = (0, 5, 9, 12), (0, 2, 2, 4)
     assert call((0, 5, 9, 12), (0, 0, 0, 0)) == 0     # no seeds: nothing to do
     cases = [
-        (dict(xo=good_x, so=good_s, prec="bf16"), "FP32 form only"),
+        (dict(xo=good_x, so=good_s, prec="bf16"), "Gaussian kernel at 5 <= d <= 32"),
+        (dict(xo=good_x, so=good_s, prec="bf16", d=33), "Gaussian kernel at 5 <= d <= 32"),
+        (dict(xo=good_x, so=good_s, prec="bf16", d=16, kernel="flat"), "Gaussian kernel at 5 <= d <= 32"),
         (dict(xo=good_x, so=good_s, ncl=0), "ncl must"),
         (dict(xo=good_x, so=good_s, ncl=9000), "ncl must"),
         (dict(xo=(1, 5, 9, 12), so=good_s), "start at 0"),
