@@ -259,17 +259,29 @@ def config_c4(api, torch, workloads):
     Sa = torch.from_numpy(np.concatenate(Ss)).cuda()
     pairs = sum(len(s) * len(x) for s, x in zip(Ss, Xs))
 
-    def batched(k, graph=False):
+    def batched(k, graph=False, precision="fp32"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=k, graph=graph)
+        api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=k, graph=graph, precision=precision)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
-    batched(2)
-    batched(2, True)
-    t_it = (min(batched(20) for _ in range(2)) - min(batched(10) for _ in range(2))) / 10
-    t_itg = (min(batched(20, True) for _ in range(2)) - min(batched(10, True) for _ in range(2))) / 10
+    def per_iteration(graph=False, precision="fp32"):
+        # the difference of 20 and 10 iterations: a call's set-up (the BF16
+        # form's per-cloud sort and block features) cancels
+        batched(2, graph, precision)
+        return (min(batched(20, graph, precision) for _ in range(2))
+                - min(batched(10, graph, precision) for _ in range(2))) / 10
+
+    t_it = per_iteration()
+    t_itg = per_iteration(graph=True)
+    t_bf = per_iteration(precision="bf16")
+    t_bfg = per_iteration(graph=True, precision="bf16")
+    t_bf_setup = min(batched(1, precision="bf16") for _ in range(2)) - t_bf
+    S32 = api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5)[0]
+    S16 = api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=5, precision="bf16")[0]
+    torch.cuda.synchronize()
+    bf_diff = float((S32 - S16).abs().max())
     Xc = [torch.from_numpy(x).cuda() for x in Xs]
     Sc = [torch.from_numpy(s).cuda() for s in Ss]
 
@@ -287,7 +299,11 @@ def config_c4(api, torch, workloads):
                        "each, Gaussian h=1, min(n, 256) seeds per cloud" % int(xo[-1]),
            "ms_per_iteration": t_it * 1e3, "ms_per_iteration_graph": t_itg * 1e3,
            "pair_evals_per_iteration": pairs, "pair_evals_per_s": pairs / t_it,
-           "per_cloud_calls_ms_per_iteration": t_pc * 1e3, "speedup_vs_per_cloud_calls": t_pc / t_it}
+           "per_cloud_calls_ms_per_iteration": t_pc * 1e3, "speedup_vs_per_cloud_calls": t_pc / t_it,
+           "bf16": {"ms_per_iteration": t_bf * 1e3, "ms_per_iteration_graph": t_bfg * 1e3,
+                    "pair_evals_per_s": pairs / t_bf, "speedup_vs_fp32": t_it / t_bf,
+                    "call_setup_ms": t_bf_setup * 1e3,
+                    "max_seed_difference_to_fp32_after_5_iterations_over_h": bf_diff}}
     e = roofline_entry(pairs, 16, t_it * 1e3, 0, 0, "fp32", "one batched iteration, every seed active",
                        "bstep_kernel<16, 16, 1> + bfinal_kernel + bplan_kernel")
     e["algorithmic_bytes"] = sum(-(-len(s) // 64) * len(x) * 16 * 4 for s, x in zip(Ss, Xs))

@@ -249,7 +249,18 @@ int ms_step_noalloc(const ms_params *p, const float *X, int64_t n, int32_t d, fl
  *              cloud with seeds must have points.
  *   ncl        1..8192 clouds.
  *   converged, iters, shift2: as ms_step, one entry per seed.
- * Uses p->h, kernel, tol, graph, tile_R; p->precision must be MS_PREC_FP32.
+ * Uses p->h, kernel, tol, precision, graph, tile_R, tile_chunk, tile_grid.
+ * MS_PREC_FP32: every pair in FP32 (the fused step of ms_step).
+ * MS_PREC_BF16_REFINE: the BF16 form of ms_step for D > 4, per cloud, for
+ * the Gaussian kernel at 5 <= d <= 32 (else MS_E_INVALID): each cloud's
+ * points are put in spatial order within the cloud's own rows (nearest of
+ * the cloud's own pivots, one per 256 points, at most 256), centred per
+ * 256-point block, and every seed's sums take the seed-point products and
+ * W.X on MFMA with three-part bf16 operands, the pairs whose weight the
+ * expanded form cannot resolve computed in FP32 by direct differences; the
+ * active seeds of a cloud are ordered by position; tiles of 128 seeds
+ * (tile_R does not apply), chunks of whole 256-point blocks (tile_chunk is
+ * rounded up to a multiple of 256).  Each call sorts the points again.
  * Stream-ordered; the call returns once the offsets are on the device (it
  * waits for the work already queued on the stream), the iterations
  * themselves run asynchronously -- with p->graph = 1 they are captured on a
@@ -355,11 +366,12 @@ int ms_fit_batched(const ms_params *p, const float *X, const int64_t *x_off, int
  *
  * Times `trials` iterations (every seed active) of each launch shape on this
  * input -- the seeds per lane R that the padded dimension allows (see
- * ms_params.tile_R), times the points per chunk 512, 1024, 2048, 4096 (see
- * tile_chunk), times the step grids of 1024, 2048 and 4096 workgroups (see
- * tile_grid) -- keeps the fastest, and records it for the rest of the
- * process under the input's kind: padded dimension, floor(log2) of the mean
- * points per cloud and floor(log2) of the mean seeds per cloud.  Later calls
+ * ms_params.tile_R; the BF16 form: R = 2 only), times the points per chunk
+ * 512, 1024, 2048, 4096 (see tile_chunk), times the step grids of 1024, 2048
+ * and 4096 workgroups (see tile_grid) -- keeps the fastest, and records it
+ * for the rest of the process under the input's kind: padded dimension,
+ * floor(log2) of the mean points per cloud, floor(log2) of the mean seeds
+ * per cloud and the precision.  Later calls
  * with tile_R, tile_chunk or tile_grid = 0 on inputs of that kind use it.
  * The iterations run on private copies of the seeds: nothing the caller
  * passed is written.  R and the grid never change the results; the chunk

@@ -818,7 +818,7 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
                 FMS_HIP(launch_merge_decide_pass(b.S, DP, d, b.status, B, modes_ws, K_old, K_old, r2m, bstate,
                                                  &ctl->und[q], q == 0, s));
         }
-        FMS_HIP(launch_merge_founders(b.S, DP, B, K_old, bstate, modes_ws, ctl, kPasses - 1, s));
+        FMS_HIP(launch_merge_founders(b.S, DP, B, K_old, bstate, modes_ws, ctl, kPasses - 1, block_tmp, s));
         if (!all) {
             // seed pool: drop the drawn seeds and the points the new modes
             // cover, keep the rest in ascending order

@@ -277,8 +277,9 @@ constexpr int kCompactBlock = 1024;   // pool entries per compaction block
 hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t* status, int B,
                                     const float* modes, int K_old, int k_scan, float r2, int32_t* state,
                                     int32_t* und_counter, bool first, hipStream_t s);
+// block_tmp: ceil(B / 1024) ints of device scratch (NULL: one workgroup).
 hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
-                                 float* modes, Ctl* ctl, int und_slot, hipStream_t s);
+                                 float* modes, Ctl* ctl, int und_slot, int32_t* block_tmp, hipStream_t s);
 // Pool coverage by the modes [k0, k1) (k1 read from ctl->k_new on the device
 // when ctl is not NULL); also writes the per-block counts that
 // launch_pool_compact consumes.

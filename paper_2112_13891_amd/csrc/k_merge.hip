@@ -192,6 +192,7 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
 // alone and flag the round for the host (k_new = K_old, merge_host = 1).
 // One workgroup; B may exceed its size.
 constexpr int kFoundThreads = 1024;
+constexpr int kFoundersOneGroup = 4;   // batches of up to 4,096 seeds: the one-workgroup form
 
 __global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __restrict__ S, int DP,
                                                                  int B, int K_old,
@@ -231,6 +232,95 @@ __global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __
     if (threadIdx.x == 0) {
         ctl->k_new = K_old + carry_s;
         ctl->merge_host = 0;
+    }
+}
+
+// Large batches: the same numbering over many workgroups of kFoundThreads
+// seeds -- each counts its founders, one workgroup turns the counts into
+// offsets (and the new mode count), and each copies its founders' rows to
+// their modes, the workgroup's rows contiguous (coalesced stores).
+__global__ __launch_bounds__(kFoundThreads) void founders_count_kernel(int B, const int32_t* __restrict__ state,
+                                                                       const Ctl* ctl, int und_slot, int32_t* cnt) {
+    __shared__ int wsum[kFoundThreads / 64];
+    if (ctl->und[und_slot] > 0) return;
+    const int i = blockIdx.x * kFoundThreads + threadIdx.x;
+    const unsigned long long bal = __ballot(i < B && state[i] == MG_FOUNDER);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kFoundThreads / 64; ++w) t += wsum[w];
+        cnt[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kFoundThreads) void founders_scan_kernel(int nb, int K_old, int32_t* cnt, Ctl* ctl,
+                                                                      int und_slot) {
+    __shared__ int wsum[kFoundThreads / 64];
+    __shared__ int carry_s;
+    if (ctl->und[und_slot] > 0) {
+        if (threadIdx.x == 0) {
+            ctl->k_new = K_old;
+            ctl->merge_host = 1;
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += kFoundThreads) {
+        const int i = base + threadIdx.x;
+        const int v = i < nb ? cnt[i] : 0;
+        int incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int u = __shfl_up(incl, off);
+            if (lane >= off) incl += u;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int before = carry_s, total = 0;
+        for (int w = 0; w < kFoundThreads / 64; ++w) {
+            if (w < wave) before += wsum[w];
+            total += wsum[w];
+        }
+        if (i < nb) cnt[i] = before + incl - v;   // exclusive offset
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->k_new = K_old + carry_s;
+        ctl->merge_host = 0;
+    }
+}
+
+__global__ __launch_bounds__(kFoundThreads) void founders_copy_kernel(const float* __restrict__ S, int DP, int B,
+                                                                      int K_old, const int32_t* __restrict__ state,
+                                                                      const int32_t* __restrict__ off, float* modes,
+                                                                      const Ctl* ctl, int und_slot) {
+    __shared__ int wsum[kFoundThreads / 64];
+    __shared__ int rows[kFoundThreads];   // the workgroup's founders, in seed order
+    if (ctl->und[und_slot] > 0) return;
+    const int i0 = blockIdx.x * kFoundThreads;
+    const int i = i0 + threadIdx.x;
+    const bool f = i < B && state[i] == MG_FOUNDER;
+    const unsigned long long bal = __ballot(f);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < kFoundThreads / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    if (f) rows[before + __popcll(bal & ((1ull << lane) - 1ull))] = i;
+    __syncthreads();
+    const long long q0 = (long long)K_old + off[blockIdx.x];
+    for (int e = threadIdx.x; e < total * DP; e += kFoundThreads) {
+        const int r = e / DP, k = e - r * DP;
+        modes[(q0 + r) * DP + k] = S[(long long)rows[r] * DP + k];
     }
 }
 
@@ -403,9 +493,19 @@ hipError_t launch_merge_decide_pass(const float* S, int DP, int d, const uint8_t
 }
 
 hipError_t launch_merge_founders(const float* S, int DP, int B, int K_old, const int32_t* state,
-                                 float* modes, Ctl* ctl, int und_slot, hipStream_t s) {
-    hipLaunchKernelGGL(founders_kernel, dim3(1), dim3(kFoundThreads), 0, s, S, DP, B, K_old, state,
-                       modes, ctl, und_slot);
+                                 float* modes, Ctl* ctl, int und_slot, int32_t* block_tmp, hipStream_t s) {
+    const int nb = (B + kFoundThreads - 1) / kFoundThreads;
+    if (nb <= kFoundersOneGroup || !block_tmp) {
+        hipLaunchKernelGGL(founders_kernel, dim3(1), dim3(kFoundThreads), 0, s, S, DP, B, K_old, state,
+                           modes, ctl, und_slot);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(founders_count_kernel, dim3(nb), dim3(kFoundThreads), 0, s, B, state, ctl, und_slot,
+                       block_tmp);
+    hipLaunchKernelGGL(founders_scan_kernel, dim3(1), dim3(kFoundThreads), 0, s, nb, K_old, block_tmp, ctl,
+                       und_slot);
+    hipLaunchKernelGGL(founders_copy_kernel, dim3(nb), dim3(kFoundThreads), 0, s, S, DP, B, K_old, state,
+                       block_tmp, modes, ctl, und_slot);
     return hipGetLastError();
 }
 

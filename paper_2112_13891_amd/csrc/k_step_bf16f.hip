@@ -501,37 +501,60 @@ __global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, i
                         // the block's first row and live count
                         const long long r0 = (long long)__float_as_int(gm[D + 3]) + tt * 32;
                         const int nl = __float_as_int(gm[D + 4]) - tt * 32;
-#pragma unroll
-                        for (int v = 0; v < 16; ++v) {
+                        // pair v of this lane in FP32 (every lane of the wave
+                        // calls it for the same v)
+                        auto exact_pair = [&](int v, bool need) {
                             const int p = 8 * (v >> 2) + 4 * hf + (v & 3);
-                            const long long r = r0 + p;
-                            const bool need = exact_seed || (live && ((obits >> p) & 1u) && E[v] + eps3 >= -127.0f);
-                            if (__ballot(need)) {
-                                if (need && p < nl) {
-                                    const float4* xr = reinterpret_cast<const float4*>(A.Xs + r * D);
-                                    float q2 = 0.0f;
+                            if (need && p < nl) {
+                                const float4* xr = reinterpret_cast<const float4*>(A.Xs + (r0 + p) * D);
+                                float q2 = 0.0f;
 #pragma unroll
-                                    for (int k4 = 0; k4 < D; k4 += 4) {
-                                        const float4 x4 = xr[k4 / 4];
-                                        const float d0 = x4.x - shat[k4], d1 = x4.y - shat[k4 + 1];
-                                        const float d2 = x4.z - shat[k4 + 2], d3 = x4.w - shat[k4 + 3];
-                                        q2 = fmaf(d0, d0, q2);
-                                        q2 = fmaf(d1, d1, q2);
-                                        q2 = fmaf(d2, d2, q2);
-                                        q2 = fmaf(d3, d3, q2);
-                                    }
-                                    const float we = __builtin_amdgcn_exp2f(-q2);
-                                    wsum += we;
-#pragma unroll
-                                    for (int k4 = 0; k4 < D; k4 += 4) {
-                                        const float4 x4 = xr[k4 / 4];
-                                        aex[k4] = fmaf(we, x4.x - shat[k4], aex[k4]);
-                                        aex[k4 + 1] = fmaf(we, x4.y - shat[k4 + 1], aex[k4 + 1]);
-                                        aex[k4 + 2] = fmaf(we, x4.z - shat[k4 + 2], aex[k4 + 2]);
-                                        aex[k4 + 3] = fmaf(we, x4.w - shat[k4 + 3], aex[k4 + 3]);
-                                    }
+                                for (int k4 = 0; k4 < D; k4 += 4) {
+                                    const float4 x4 = xr[k4 / 4];
+                                    const float d0 = x4.x - shat[k4], d1 = x4.y - shat[k4 + 1];
+                                    const float d2 = x4.z - shat[k4 + 2], d3 = x4.w - shat[k4 + 3];
+                                    q2 = fmaf(d0, d0, q2);
+                                    q2 = fmaf(d1, d1, q2);
+                                    q2 = fmaf(d2, d2, q2);
+                                    q2 = fmaf(d3, d3, q2);
                                 }
-                                if (need) E[v] = kPadNorm;
+                                const float we = __builtin_amdgcn_exp2f(-q2);
+                                wsum += we;
+#pragma unroll
+                                for (int k4 = 0; k4 < D; k4 += 4) {
+                                    const float4 x4 = xr[k4 / 4];
+                                    aex[k4] = fmaf(we, x4.x - shat[k4], aex[k4]);
+                                    aex[k4 + 1] = fmaf(we, x4.y - shat[k4 + 1], aex[k4 + 1]);
+                                    aex[k4 + 2] = fmaf(we, x4.z - shat[k4 + 2], aex[k4 + 2]);
+                                    aex[k4 + 3] = fmaf(we, x4.w - shat[k4 + 3], aex[k4 + 3]);
+                                }
+                            }
+                            if (need) E[v] = kPadNorm;
+                        };
+                        auto needs = [&](int v) {
+                            const int p = 8 * (v >> 2) + 4 * hf + (v & 3);
+                            return exact_seed || (live && ((obits >> p) & 1u) && E[v] + eps3 >= -127.0f);
+                        };
+                        if constexpr (D <= 16) {
+                            // this lane's pairs first, then one ballot for the
+                            // common case of none in the wave
+                            unsigned nm = 0u;
+#pragma unroll
+                            for (int v = 0; v < 16; ++v)
+                                if (needs(v)) nm |= 1u << v;
+                            if (__ballot(nm != 0u)) {
+#pragma unroll
+                                for (int v = 0; v < 16; ++v) {
+                                    const bool need = (nm >> v) & 1u;
+                                    if (__ballot(need)) exact_pair(v, need);
+                                }
+                            }
+                        } else {
+                            // (at D = 32 the mask costs more registers than it saves)
+#pragma unroll
+                            for (int v = 0; v < 16; ++v) {
+                                const bool need = needs(v);
+                                if (__ballot(need)) exact_pair(v, need);
                             }
                         }
                     }
