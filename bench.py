@@ -237,7 +237,7 @@ def config_c3(api, torch, workloads, gpu_fits, iters):
     for prec in ("fp32", "bf16"):
         t = time_kernel(api, torch, X, seeds, w.h, w.kernel, prec, iters)
         name = ("step_cull_kernel<32, 1, 1> + reduce_kernel + finalize_kernel" if prec == "fp32"
-                else "step_bf16f_kernel<32> + reduce_kernel + finalize_kernel")
+                else "step_bf16f_kernel<32, false> + reduce_kernel + finalize_kernel")
         out[prec]["roofline"] = roofline_entry(m * w.n, w.d, t, m, w.n, prec, f"{m} seeds x {w.n} points",
                                                name, counter_figures("c3", prec))
     out["bf16_kernel_speedup_vs_fp32"] = out["fp32"]["roofline"]["avg_ms"] / out["bf16"]["roofline"]["avg_ms"]
@@ -547,14 +547,15 @@ def main():
                     help="skip the secondary shapes (flat window, cosine metric, images, frames, small clouds)")
     ap.add_argument("--kernel-iters", type=int, default=20)
     ap.add_argument("--phase", default="all",
-                    choices=["all", "kernel", "fit", "c3", "c3flat", "c3kernel", "batched", "c5"],
+                    choices=["all", "kernel", "fit", "c3", "c3flat", "c3kernel", "batched", "c4kernel", "c5"],
                     help="kernel: the 200K mixture's largest launch (both precisions) and a 256 MiB copy "
                          "that calibrates the traffic counters; fit: --steps fits per precision of the 200K "
                          "mixture; c3: --steps fits per precision of the 32-D embeddings; c3flat: the same "
                          "with the flat window (every window a singleton); c3kernel: their "
                          "largest launch (8,192 seeds) and the copy; batched: --steps whole-method calls on "
-                         "the 512 uneven clouds; c5: --steps steps of the differentiable form; all: the "
-                         "benchmark")
+                         "the 512 uneven clouds; c4kernel: one batched-step call of --kernel-iters iterations "
+                         "per precision on those clouds (every seed active) and the copy; c5: --steps steps of "
+                         "the differentiable form; all: the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1 "
@@ -591,6 +592,26 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"phase": "batched", "ms_per_call": (time.perf_counter() - t0) / args.steps * 1e3,
                           "rounds": rounds, "modes_total": int(k_off[-1])}), flush=True)
+        return
+    if args.phase == "c4kernel":
+        clouds = workloads.clouds16(seed=0)
+        Xs = [c[0] for c in clouds]
+        rng = np.random.default_rng(0)
+        Ss = [X[rng.choice(len(X), min(len(X), 256), replace=False)] for X in Xs]
+        xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+        so = np.concatenate([[0], np.cumsum([len(s) for s in Ss])]).astype(np.int64)
+        Xa = torch.from_numpy(np.concatenate(Xs)).cuda()
+        Sa = torch.from_numpy(np.concatenate(Ss)).cuda()
+        out = {"phase": "c4kernel", "launch": f"{len(Xs)} clouds, {int(xo[-1])} points, {int(so[-1])} seeds"}
+        for prec in ("fp32", "bf16"):
+            api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=2, precision=prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            api.step_batched(Xa, xo, Sa, so, 1.0, tol=1e-30, n_iter=args.kernel_iters, precision=prec)
+            torch.cuda.synchronize()
+            out[prec + "_call_ms"] = (time.perf_counter() - t0) * 1e3
+        copy_calibration(out)
+        print(json.dumps(out, default=_plain), flush=True)
         return
     if args.phase == "c5":
         out = config_c5(api, torch, workloads)

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kT) void decide_tiled_kernel(const float* __restric
 // alone and flag the round for the host (k_new = K_old, merge_host = 1).
 // One workgroup; B may exceed its size.
 constexpr int kFoundThreads = 1024;
-constexpr int kFoundersOneGroup = 4;   // batches of up to 4,096 seeds: the one-workgroup form
+constexpr int kFoundersOneGroup = 1;   // batches of up to 1,024 seeds: the one-workgroup form
 
 __global__ __launch_bounds__(kFoundThreads) void founders_kernel(const float* __restrict__ S, int DP,
                                                                  int B, int K_old,
