@@ -319,7 +319,11 @@ float packed_scale(const ms_params* p) {
 enum Slot {
     SL_XP, SL_RB, SL_POOL0, SL_POOL1, SL_REMOVED, SL_BLOCKS, SL_MODES, SL_ACT0, SL_ACT1,
     SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN,
-    SL_JPTS, SL_JSEEDS, SL_JMODES, SL_COVERED, SL_CAND, SL_COUNT
+    SL_JPTS, SL_JSEEDS, SL_JMODES, SL_COVERED, SL_CAND,
+    // ms_fit_batched's rounds and the batched steps they run
+    SL_BCONV, SL_BITERS, SL_BS, SL_BSH2, SL_BNM, SL_BSTEP_S, SL_BSTEP_ACT0, SL_BSTEP_ACT1, SL_BSTEP_STATUS,
+    SL_BSTEP_ITERS, SL_BSTEP_SHIFT2, SL_BSTEP_CNT, SL_BSTEP_PLAN, SL_BSTEP_ITEMC, SL_BSTEP_SLOTC, SL_BSTEP_PART,
+    SL_COUNT
 };
 
 // Handed to the orphan list when the thread exits (freed by the next call on
@@ -1178,6 +1182,7 @@ struct BatchedPrepared {
     int DP;
     const long long* xo_dev;
     const int32_t* so_dev;
+    DevCache* cache;   // the calling fit's cache for the step's buffers (kept across calls), or NULL
 };
 
 // The BF16 form over many clouds (Gaussian, padded D in {8, 16, 32}): each
@@ -1334,18 +1339,25 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         b.boff = bb.boff;
         b.shift = bb.zero;
     }
-    FMS_CHECK(ws.alloc(&b.S, (size_t)M * sh.DP));
-    FMS_CHECK(ws.alloc(&b.act[0], M));
-    FMS_CHECK(ws.alloc(&b.act[1], M));
-    FMS_CHECK(ws.alloc(&b.status, M));
-    FMS_CHECK(ws.alloc(&b.iters, M));
-    FMS_CHECK(ws.alloc(&b.shift2, M));
+    // the step's buffers: from the calling fit's cache (kept from one step
+    // call of the fit to the next), else stream-ordered for this call
+    AllocBudget budget;
+    DevCache* cache = pre ? pre->cache : nullptr;
+    auto get = [&](auto** out, size_t count, Slot sl) {
+        return cache ? cache_get(*cache, budget, sl, count, out) : ws.alloc(out, count);
+    };
+    FMS_CHECK(get(&b.S, (size_t)M * sh.DP, SL_BSTEP_S));
+    FMS_CHECK(get(&b.act[0], (size_t)M, SL_BSTEP_ACT0));
+    FMS_CHECK(get(&b.act[1], (size_t)M, SL_BSTEP_ACT1));
+    FMS_CHECK(get(&b.status, (size_t)M, SL_BSTEP_STATUS));
+    FMS_CHECK(get(&b.iters, (size_t)M, SL_BSTEP_ITERS));
+    FMS_CHECK(get(&b.shift2, (size_t)M, SL_BSTEP_SHIFT2));
     int32_t *cnt, *plan, *item_cloud, *slot_cloud;
-    FMS_CHECK(ws.alloc(&cnt, (size_t)2 * ncl));
-    FMS_CHECK(ws.alloc(&plan, (size_t)4 * ncl + 3));   // + the work-item queue head
-    FMS_CHECK(ws.alloc(&item_cloud, (size_t)std::max(1LL, max_items)));
-    FMS_CHECK(ws.alloc(&slot_cloud, (size_t)M));
-    FMS_CHECK(ws.alloc(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1)));
+    FMS_CHECK(get(&cnt, (size_t)2 * ncl, SL_BSTEP_CNT));
+    FMS_CHECK(get(&plan, (size_t)4 * ncl + 3, SL_BSTEP_PLAN));   // + the work-item queue head
+    FMS_CHECK(get(&item_cloud, (size_t)std::max(1LL, max_items), SL_BSTEP_ITEMC));
+    FMS_CHECK(get(&slot_cloud, (size_t)M, SL_BSTEP_SLOTC));
+    FMS_CHECK(get(&b.part, (size_t)std::max(1LL, max_items) * sh.TS * (sh.D + 1), SL_BSTEP_PART));
     FMS_HIP(launch_batched_init(seeds, converged, d, M, so_dev, ncl, cnt, b, s));
     if (bf) {
         // each cloud's active list in the spatial order of its seeds
@@ -1490,7 +1502,9 @@ thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bseeds, g_pin_bcon
 // or N >= L M, else N <- 2N).  Labels: nearest mode within the cloud.
 int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, int ncl, int d, float* modes,
                      int64_t max_modes, int64_t* k_off, int32_t* labels, int32_t* rounds_out, hipStream_t s) {
+    const auto t_start = std::chrono::steady_clock::now();
     free_orphans();
+    FMS_CHECK(ensure_pool_release_threshold());
     const long long n = x_off[ncl];
     const bool all = p->all_points_as_seeds != 0;
     const float rm = p->merge_radius * p->h, rc = p->cover_radius * p->h;
@@ -1501,19 +1515,25 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     int32_t *pool[2], *pos_dev, *plen_dev, *moff_dev, *it_dev;
     uint8_t *removed, *conv_dev;
     float *S_dev, *sh2_dev, *nm_dev;
+    // the point-sized buffers come from this thread's cache (kept across
+    // calls); the small per-cloud ones are stream-ordered
+    int dev = 0;
+    FMS_HIP(hipGetDevice(&dev));
+    DevCache& C = cache_for_device(dev);
+    AllocBudget budget;
     FMS_CHECK(ws.alloc(&xo_dev, (size_t)ncl + 1));
     FMS_CHECK(ws.alloc(&so_dev, (size_t)ncl + 1));
-    FMS_CHECK(ws.alloc(&pool[0], (size_t)n));
-    FMS_CHECK(ws.alloc(&pool[1], (size_t)n));
-    FMS_CHECK(ws.alloc(&pos_dev, (size_t)n));
+    FMS_CHECK(cache_get(C, budget, SL_POOL0, (size_t)n, &pool[0]));
+    FMS_CHECK(cache_get(C, budget, SL_POOL1, (size_t)n, &pool[1]));
+    FMS_CHECK(cache_get(C, budget, SL_POS, (size_t)n, &pos_dev));
     FMS_CHECK(ws.alloc(&plen_dev, (size_t)ncl));
     FMS_CHECK(ws.alloc(&moff_dev, (size_t)ncl + 1));
-    FMS_CHECK(ws.alloc(&removed, (size_t)n));
-    FMS_CHECK(ws.alloc(&conv_dev, (size_t)n));
-    FMS_CHECK(ws.alloc(&it_dev, (size_t)n));
-    FMS_CHECK(ws.alloc(&S_dev, (size_t)n * d));
-    FMS_CHECK(ws.alloc(&sh2_dev, (size_t)n));
-    FMS_CHECK(ws.alloc(&nm_dev, (size_t)n * d));
+    FMS_CHECK(cache_get(C, budget, SL_REMOVED, (size_t)n, &removed));
+    FMS_CHECK(cache_get(C, budget, SL_BCONV, (size_t)n, &conv_dev));
+    FMS_CHECK(cache_get(C, budget, SL_BITERS, (size_t)n, &it_dev));
+    FMS_CHECK(cache_get(C, budget, SL_BS, (size_t)n * d, &S_dev));
+    FMS_CHECK(cache_get(C, budget, SL_BSH2, (size_t)n, &sh2_dev));
+    FMS_CHECK(cache_get(C, budget, SL_BNM, (size_t)n * d, &nm_dev));
     FMS_CHECK(g_pin_bso.ensure((size_t)(ncl + 1) * 8));
     FMS_CHECK(g_pin_bso32.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_bmoff.ensure((size_t)(ncl + 1) * 4));
@@ -1532,10 +1552,10 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     const int DP = step_shape(d).DP;
     float* Xp;
     int32_t* so32_dev;
-    FMS_CHECK(ws.alloc(&Xp, (size_t)n * DP));
+    FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_CHECK(ws.alloc(&so32_dev, (size_t)ncl + 1));
     FMS_HIP(launch_pack_points(X, (int)n, d, DP, packed_scale(&q), Xp, s));
-    const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev};
+    const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev, &C};
     FMS_HIP(launch_bf_iota(xo_dev, ncl, pool[0], n, s));
     FMS_HIP(launch_fill_u8(removed, (int)n, 0, s));
     std::vector<uint64_t> rng(ncl);
@@ -1554,7 +1574,15 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     // active seed is a few microseconds of empty launches)
     constexpr int kChunk = 8;
     int cur = 0, rounds = 0;
+    const bool trace = log_enabled();
+    if (trace) {
+        FMS_HIP(wait_stream(s));
+        std::fprintf(stderr, "[fms] fit_batched %d clouds, %lld points: setup %.3f ms\n", ncl, n, ms_since(t_start));
+    }
     for (;;) {
+        const auto t_round = std::chrono::steady_clock::now();
+        double t_draw = 0.0, t_iter = 0.0, t_merge = 0.0;
+        int iters_run = 0;
         // draws (the staging buffers hold no copy in flight: every round ends
         // with a wait on the stream)
         int64_t M = 0;
@@ -1584,18 +1612,21 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         FMS_HIP(hipMemcpyAsync(so32_dev, hso32, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
         FMS_HIP(launch_bf_gather(X, d, xo_dev, so_dev, ncl, pos_dev, pool[cur], removed, S_dev, (int)M, s));
         FMS_HIP(launch_fill_u8(conv_dev, (int)M, 0, s));
+        t_draw = ms_since(t_round);
         // iterations until the round is over for every seed
         for (int done = 0; done < p->max_iter;) {
             const int k = std::min(kChunk, p->max_iter - done);
             FMS_CHECK(step_batched_impl(&q, X, x_off, S_dev, hso, ncl, d, k, conv_dev, it_dev, sh2_dev, s, 0,
                                         nullptr, &pre));
             done += k;
+            iters_run = done;
             FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
             FMS_HIP(wait_stream(s));
             bool open = false;
             for (long long g = 0; g < M && !open; ++g) open = hconv[g] == ST_ACTIVE;
             if (!open) break;
         }
+        t_iter = ms_since(t_round) - t_draw;
         FMS_HIP(hipMemcpyAsync(hS, S_dev, (size_t)M * d * 4, hipMemcpyDeviceToHost, s));
         FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
         FMS_HIP(wait_stream(s));
@@ -1610,6 +1641,11 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
             nm += (long long)(cm[c].size() / d - k_old[c]);
             hmoff[c + 1] = (int32_t)nm;
         }
+        t_merge = ms_since(t_round) - t_draw - t_iter;
+        if (trace)
+            std::fprintf(stderr, "[fms] fit_batched round %d: %lld seeds, %lld new modes, %d iterations; draws %.3f, "
+                                 "iterations %.3f, read-back and merge %.3f ms\n",
+                         rounds, (long long)M, nm, iters_run, t_draw, t_iter, t_merge);
         if (all) break;
         // the round's new modes, cloud after cloud
         FMS_CHECK(g_pin_bmodes.ensure((size_t)std::max(1LL, nm) * d * 4));
@@ -1625,6 +1661,9 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         cur ^= 1;
         FMS_HIP(hipMemcpyAsync(hlen, plen_dev, (size_t)ncl * 4, hipMemcpyDeviceToHost, s));
         FMS_HIP(wait_stream(s));
+        if (trace)
+            std::fprintf(stderr, "[fms] fit_batched round %d: coverage and pools %.3f ms, round %.3f ms\n", rounds,
+                         ms_since(t_round) - t_draw - t_iter - t_merge, ms_since(t_round));
         bool any = false;
         for (int c = 0; c < ncl; ++c) {
             if (!active[c]) continue;
@@ -1661,6 +1700,7 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         FMS_HIP(launch_bf_assign(X, d, xo_dev, ncl, modes, moff_dev, labels, n, s));
     }
     FMS_HIP(wait_stream(s));
+    if (trace) std::fprintf(stderr, "[fms] fit_batched done: %lld modes, %.3f ms\n", K, ms_since(t_start));
     return MS_OK;
 }
 
