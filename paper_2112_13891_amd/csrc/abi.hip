@@ -321,7 +321,7 @@ enum Slot {
     SL_SHIFT2, SL_PART, SL_POS, SL_FLAG, SL_XS, SL_PERM, SL_GEOM, SL_SORTWS, SL_FEAT, SL_XN,
     SL_JPTS, SL_JSEEDS, SL_JMODES, SL_COVERED, SL_CAND,
     // ms_fit_batched's rounds and the batched steps they run
-    SL_BCONV, SL_BITERS, SL_BS, SL_BSH2, SL_BNM, SL_BSTEP_S, SL_BSTEP_ACT0, SL_BSTEP_ACT1, SL_BSTEP_STATUS,
+    SL_BCONV, SL_BITERS, SL_BS, SL_BSH2, SL_BNM, SL_BSTATE, SL_BSTEP_S, SL_BSTEP_ACT0, SL_BSTEP_ACT1, SL_BSTEP_STATUS,
     SL_BSTEP_ITERS, SL_BSTEP_SHIFT2, SL_BSTEP_CNT, SL_BSTEP_PLAN, SL_BSTEP_ITEMC, SL_BSTEP_SLOTC, SL_BSTEP_PART,
     SL_COUNT
 };
@@ -1446,48 +1446,9 @@ void for_each_cloud(int ncl, long long work, F&& f) {
     for (auto& t : th) t.join();
 }
 
-// Greedy merge of one cloud's seeds g0..g1 (draw order) into its modes: a
-// converged seed joins the first mode within r2m (squared), else it becomes
-// a new mode.  FP32 distances with fused multiply-adds, as on the device; the
-// FMA form is compiled for CPUs that have the instruction (the same results,
-// without a call per multiply-add).
-__attribute__((always_inline)) inline void merge_cloud_body(const float* hS, const uint8_t* hconv, long long g0,
-                                                             long long g1, int d, float r2m,
-                                                             std::vector<float>& modes) {
-    for (long long g = g0; g < g1; ++g) {
-        if (hconv[g] != ST_CONVERGED) continue;
-        const float* sg = hS + (size_t)g * d;
-        const size_t K = modes.size() / d;
-        bool joined = false;
-        for (size_t j = 0; j < K && !joined; ++j) {
-            const float* mj = modes.data() + j * d;
-            float q = 0.0f;
-            for (int k = 0; k < d; ++k) {
-                const float t = sg[k] - mj[k];
-                q = __builtin_fmaf(t, t, q);
-            }
-            joined = q <= r2m;
-        }
-        if (!joined) modes.insert(modes.end(), sg, sg + d);
-    }
-}
-
-__attribute__((target("fma"))) void merge_cloud_fma(const float* hS, const uint8_t* hconv, long long g0,
-                                                    long long g1, int d, float r2m, std::vector<float>& modes) {
-    merge_cloud_body(hS, hconv, g0, g1, d, r2m, modes);
-}
-
-void merge_cloud(const float* hS, const uint8_t* hconv, long long g0, long long g1, int d, float r2m,
-                 std::vector<float>& modes) {
-    static const bool fma = __builtin_cpu_supports("fma");
-    if (fma) merge_cloud_fma(hS, hconv, g0, g1, d, r2m, modes);
-    else merge_cloud_body(hS, hconv, g0, g1, d, r2m, modes);
-}
-
 // Host staging of ms_fit_batched, sized by each round's seeds and modes
 // (grown on demand, kept for the thread).
-thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bseeds, g_pin_bconv, g_pin_bmodes, g_pin_bmoff,
-    g_pin_blen;
+thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bconv, g_pin_bmoff, g_pin_blen, g_pin_bk;
 
 // The whole method (Algorithm 2 with the seed pool of Section II-D; with
 // all_points_as_seeds, Algorithm 1) for every cloud of a CSR batch, the
@@ -1495,11 +1456,13 @@ thread_local Pinned g_pin_bpos, g_pin_bso, g_pin_bso32, g_pin_bseeds, g_pin_bcon
 // cloud's seeds from its pool (SplitMix64 state rng_seed + c for cloud c),
 // the device gathers them and runs the batched fused step for all clouds
 // until every seed of the round converged, failed or max_iter updates were
-// made; the host merges each cloud's converged seeds into that cloud's modes
-// in draw order (first mode within merge_radius h, else a new mode), the
-// device removes covered points from each pool and compacts the pools, and
-// the host applies each cloud's seed-count rule (stop when its pool is empty
-// or N >= L M, else N <- 2N).  Labels: nearest mode within the cloud.
+// made; the device merges each cloud's converged seeds into that cloud's
+// modes in draw order (first mode within merge_radius h, else a new mode;
+// decision passes until none is undecided, the modes kept per cloud at the
+// cloud's own rows of a mode store), removes covered points from each pool
+// and compacts the pools, and the host applies each cloud's seed-count rule
+// (stop when its pool is empty or N >= L M, else N <- 2N) from the mode
+// counts it reads back.  Labels: nearest mode within the cloud.
 int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, int ncl, int d, float* modes,
                      int64_t max_modes, int64_t* k_off, int32_t* labels, int32_t* rounds_out, hipStream_t s) {
     const auto t_start = std::chrono::steady_clock::now();
@@ -1533,15 +1496,22 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     FMS_CHECK(cache_get(C, budget, SL_BITERS, (size_t)n, &it_dev));
     FMS_CHECK(cache_get(C, budget, SL_BS, (size_t)n * d, &S_dev));
     FMS_CHECK(cache_get(C, budget, SL_BSH2, (size_t)n, &sh2_dev));
-    FMS_CHECK(cache_get(C, budget, SL_BNM, (size_t)n * d, &nm_dev));
+    FMS_CHECK(cache_get(C, budget, SL_BNM, (size_t)n * d, &nm_dev));   // the mode store
+    int32_t *state_dev, *kcnt_dev, *kold_dev, *und_dev;
+    FMS_CHECK(cache_get(C, budget, SL_BSTATE, (size_t)n, &state_dev));
+    FMS_CHECK(ws.alloc(&kcnt_dev, (size_t)ncl));
+    FMS_CHECK(ws.alloc(&kold_dev, (size_t)ncl));
+    FMS_CHECK(ws.alloc(&und_dev, (size_t)1));
     FMS_CHECK(g_pin_bso.ensure((size_t)(ncl + 1) * 8));
     FMS_CHECK(g_pin_bso32.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_bmoff.ensure((size_t)(ncl + 1) * 4));
     FMS_CHECK(g_pin_blen.ensure((size_t)ncl * 4));
+    FMS_CHECK(g_pin_bk.ensure((size_t)(ncl + 1) * 4));
     int64_t* hso = (int64_t*)g_pin_bso.p;
     int32_t* hso32 = (int32_t*)g_pin_bso32.p;
     int32_t* hmoff = (int32_t*)g_pin_bmoff.p;
     int32_t* hlen = (int32_t*)g_pin_blen.p;
+    int32_t* hk = (int32_t*)g_pin_bk.p;   // [0, ncl): modes per cloud; [ncl]: undecided seeds
 
     std::vector<long long> xo(x_off, x_off + ncl + 1);
     FMS_HIP(hipMemcpyAsync(xo_dev, xo.data(), (size_t)(ncl + 1) * 8, hipMemcpyHostToDevice, s));
@@ -1557,12 +1527,12 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     FMS_HIP(launch_pack_points(X, (int)n, d, DP, packed_scale(&q), Xp, s));
     const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev, &C};
     FMS_HIP(launch_bf_iota(xo_dev, ncl, pool[0], n, s));
+    FMS_HIP(launch_bf_fill_i32(kcnt_dev, ncl, 0, s));
     FMS_HIP(launch_fill_u8(removed, (int)n, 0, s));
     std::vector<uint64_t> rng(ncl);
     std::vector<long long> N(ncl, p->n_initial);
     std::vector<int32_t> plen(ncl);
     std::vector<char> active(ncl);
-    std::vector<std::vector<float>> cm(ncl);   // modes of each cloud, in creation order
     for (int c = 0; c < ncl; ++c) {
         rng[c] = p->rng_seed + (uint64_t)c;
         plen[c] = (int32_t)(x_off[c + 1] - x_off[c]);
@@ -1593,10 +1563,8 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         }
         if (M == 0) break;
         FMS_CHECK(g_pin_bpos.ensure((size_t)M * 4));
-        FMS_CHECK(g_pin_bseeds.ensure((size_t)M * d * 4));
         FMS_CHECK(g_pin_bconv.ensure((size_t)M));
         int32_t* hpos = (int32_t*)g_pin_bpos.p;
-        float* hS = (float*)g_pin_bseeds.p;
         uint8_t* hconv = (uint8_t*)g_pin_bconv.p;
         for_each_cloud(ncl, M, [&](int c) {
             const int32_t B = (int32_t)(hso[c + 1] - hso[c]);
@@ -1627,39 +1595,38 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
             if (!open) break;
         }
         t_iter = ms_since(t_round) - t_draw;
-        FMS_HIP(hipMemcpyAsync(hS, S_dev, (size_t)M * d * 4, hipMemcpyDeviceToHost, s));
-        FMS_HIP(hipMemcpyAsync(hconv, conv_dev, (size_t)M, hipMemcpyDeviceToHost, s));
-        FMS_HIP(wait_stream(s));
         rounds += 1;
-        // merge, cloud by cloud, in draw order
-        std::vector<size_t> k_old(ncl);
-        for (int c = 0; c < ncl; ++c) k_old[c] = cm[c].size() / d;
-        for_each_cloud(ncl, M, [&](int c) { merge_cloud(hS, hconv, hso[c], hso[c + 1], d, r2m, cm[c]); });
-        long long nm = 0;
-        hmoff[0] = 0;
-        for (int c = 0; c < ncl; ++c) {
-            nm += (long long)(cm[c].size() / d - k_old[c]);
-            hmoff[c + 1] = (int32_t)nm;
+        // merge on the device, cloud by cloud in draw order: decision passes
+        // until no seed is undecided (each pass settles at least the first
+        // undecided seed of each cloud), then the founders become modes
+        FMS_HIP(launch_bf_merge_init(state_dev, (int)M, s));
+        int passes = 0;
+        for (;;) {
+            FMS_HIP(launch_bf_decide_pass(S_dev, d, conv_dev, so_dev, ncl, nm_dev, xo_dev, kcnt_dev, r2m, state_dev,
+                                          und_dev, (int)M, passes == 0, s));
+            ++passes;
+            FMS_HIP(hipMemcpyAsync(hk + ncl, und_dev, 4, hipMemcpyDeviceToHost, s));
+            FMS_HIP(wait_stream(s));
+            if (hk[ncl] == 0) break;
         }
+        FMS_HIP(launch_bf_founders(S_dev, d, so_dev, ncl, state_dev, xo_dev, nm_dev, kcnt_dev, kold_dev, s));
         t_merge = ms_since(t_round) - t_draw - t_iter;
         if (trace)
-            std::fprintf(stderr, "[fms] fit_batched round %d: %lld seeds, %lld new modes, %d iterations; draws %.3f, "
-                                 "iterations %.3f, read-back and merge %.3f ms\n",
-                         rounds, (long long)M, nm, iters_run, t_draw, t_iter, t_merge);
-        if (all) break;
-        // the round's new modes, cloud after cloud
-        FMS_CHECK(g_pin_bmodes.ensure((size_t)std::max(1LL, nm) * d * 4));
-        float* hnm = (float*)g_pin_bmodes.p;
-        for (int c = 0; c < ncl; ++c)
-            std::memcpy(hnm + (size_t)hmoff[c] * d, cm[c].data() + k_old[c] * d,
-                        (cm[c].size() - k_old[c] * d) * 4);
+            std::fprintf(stderr, "[fms] fit_batched round %d: %lld seeds, %d iterations, %d merge passes; draws "
+                                 "%.3f, iterations %.3f, merge %.3f ms\n",
+                         rounds, (long long)M, iters_run, passes, t_draw, t_iter, t_merge);
+        if (all) {
+            FMS_HIP(hipMemcpyAsync(hk, kcnt_dev, (size_t)ncl * 4, hipMemcpyDeviceToHost, s));
+            FMS_HIP(wait_stream(s));
+            break;
+        }
         // pools: coverage by the new modes, compaction, seed-count control
-        FMS_HIP(hipMemcpyAsync(nm_dev, hnm, (size_t)std::max(1LL, nm) * d * 4, hipMemcpyHostToDevice, s));
-        FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
-        FMS_HIP(launch_bf_cover(X, d, xo_dev, ncl, pool[cur], plen_dev, nm_dev, moff_dev, r2c, removed, n, s));
+        FMS_HIP(launch_bf_cover(X, d, xo_dev, ncl, pool[cur], plen_dev, nm_dev, kold_dev, kcnt_dev, r2c, removed, n,
+                                s));
         FMS_HIP(launch_bf_compact(xo_dev, ncl, pool[cur], removed, plen_dev, pool[cur ^ 1], s));
         cur ^= 1;
         FMS_HIP(hipMemcpyAsync(hlen, plen_dev, (size_t)ncl * 4, hipMemcpyDeviceToHost, s));
+        FMS_HIP(hipMemcpyAsync(hk, kcnt_dev, (size_t)ncl * 4, hipMemcpyDeviceToHost, s));
         FMS_HIP(wait_stream(s));
         if (trace)
             std::fprintf(stderr, "[fms] fit_batched round %d: coverage and pools %.3f ms, round %.3f ms\n", rounds,
@@ -1668,7 +1635,7 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
         for (int c = 0; c < ncl; ++c) {
             if (!active[c]) continue;
             plen[c] = hlen[c];
-            const long long K = (long long)(cm[c].size() / d);
+            const long long K = hk[c];
             if (plen[c] == 0 || N[c] >= (long long)p->L * K) active[c] = 0;
             else N[c] *= 2;
             any = any || active[c];
@@ -1681,24 +1648,16 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     long long K = 0;
     k_off[0] = 0;
     for (int c = 0; c < ncl; ++c) {
-        K += (long long)(cm[c].size() / d);
+        K += hk[c];
         k_off[c + 1] = K;
     }
     if (K > max_modes) return fail(MS_E_CAPACITY, "more modes than max_modes (k_off holds the required counts)");
     for (int c = 0; c < ncl; ++c)
-        if (x_off[c + 1] > x_off[c] && cm[c].empty()) return fail(MS_E_NO_MODES, "a cloud has no converged seed");
-    FMS_CHECK(g_pin_bmodes.ensure((size_t)std::max(1LL, K) * d * 4));
-    float* hnm = (float*)g_pin_bmodes.p;
-    for (int c = 0; c < ncl; ++c) {
-        std::memcpy(hnm + (size_t)k_off[c] * d, cm[c].data(), cm[c].size() * 4);
-        hmoff[c] = (int32_t)k_off[c];
-    }
-    hmoff[ncl] = (int32_t)K;
-    if (K > 0) FMS_HIP(hipMemcpyAsync(modes, hnm, (size_t)K * d * 4, hipMemcpyHostToDevice, s));
-    if (labels) {
-        FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
-        FMS_HIP(launch_bf_assign(X, d, xo_dev, ncl, modes, moff_dev, labels, n, s));
-    }
+        if (x_off[c + 1] > x_off[c] && hk[c] == 0) return fail(MS_E_NO_MODES, "a cloud has no converged seed");
+    for (int c = 0; c <= ncl; ++c) hmoff[c] = (int32_t)k_off[c];
+    FMS_HIP(hipMemcpyAsync(moff_dev, hmoff, (size_t)(ncl + 1) * 4, hipMemcpyHostToDevice, s));
+    if (K > 0) FMS_HIP(launch_bf_modes_out(nm_dev, d, xo_dev, ncl, moff_dev, modes, s));
+    if (labels) FMS_HIP(launch_bf_assign(X, d, xo_dev, ncl, modes, moff_dev, labels, n, s));
     FMS_HIP(wait_stream(s));
     if (trace) std::fprintf(stderr, "[fms] fit_batched done: %lld modes, %.3f ms\n", K, ms_since(t_start));
     return MS_OK;
@@ -1983,7 +1942,7 @@ int ms_release_workspace(void) {
     for (auto& c : g_cache) c->release();
     g_cache.clear();
     for (Pinned* q : {&g_pin_ctl, &g_pin_pos, &g_pin_rb, &g_pin_modes, &g_pin_bpos, &g_pin_bso, &g_pin_bso32,
-                      &g_pin_bseeds, &g_pin_bconv, &g_pin_bmodes, &g_pin_bmoff, &g_pin_blen})
+                      &g_pin_bconv, &g_pin_bmoff, &g_pin_blen, &g_pin_bk})
         q->release();
     return MS_OK;
 }

@@ -260,9 +260,21 @@ hipError_t launch_bf_iota(const long long* x_off, int ncl, int32_t* pool, long l
 hipError_t launch_bf_gather(const float* X, int d, const long long* x_off, const long long* s_off, int ncl,
                             const int32_t* pos, const int32_t* pool, uint8_t* removed, float* seeds, int M,
                             hipStream_t s);
+// mstore: the mode store, cloud c's modes at rows x_off[c] + k (n x d)
 hipError_t launch_bf_cover(const float* X, int d, const long long* x_off, int ncl, const int32_t* pool,
-                           const int32_t* pool_len, const float* nm, const int32_t* m_off, float r2,
-                           uint8_t* removed, long long n, hipStream_t s);
+                           const int32_t* pool_len, const float* mstore, const int32_t* k_old,
+                           const int32_t* k_new, float r2, uint8_t* removed, long long n, hipStream_t s);
+// The round's merge: state (M ints) to undecided, then decision passes until
+// *und (device) reads 0, then the founders appended to each cloud's modes.
+hipError_t launch_bf_merge_init(int32_t* state, int M, hipStream_t s);
+hipError_t launch_bf_decide_pass(const float* S, int d, const uint8_t* conv, const long long* s_off, int ncl,
+                                 const float* mstore, const long long* x_off, const int32_t* k_cnt, float r2,
+                                 int32_t* state, int32_t* und, int M, bool first, hipStream_t s);
+hipError_t launch_bf_founders(const float* S, int d, const long long* s_off, int ncl, const int32_t* state,
+                              const long long* x_off, float* mstore, int32_t* k_cnt, int32_t* k_old, hipStream_t s);
+hipError_t launch_bf_modes_out(const float* mstore, int d, const long long* x_off, int ncl, const int32_t* k_off,
+                               float* modes, hipStream_t s);
+hipError_t launch_bf_fill_i32(int32_t* a, long long count, int32_t v, hipStream_t s);
 hipError_t launch_bf_compact(const long long* x_off, int ncl, const int32_t* pool_in, uint8_t* removed,
                              int32_t* pool_len, int32_t* pool_out, hipStream_t s);
 hipError_t launch_bf_assign(const float* X, int d, const long long* x_off, int ncl, const float* modes,
