@@ -124,3 +124,32 @@ def test_fit_batched_many_clouds_host_threads_match_oracle(orc):
                                               rng_seed=9)
     torch.cuda.synchronize()
     _compare(orc, Xs, xo, 1.0, "gaussian", False, 9, per, lab, k_off)
+
+
+@pytest.mark.parametrize("all_points", [False, True])
+def test_fit_batched_merge_chains(orc, all_points):
+    """Isolated points on lines 5h apart with merge radius 6h: each seed stays
+    on its point, and every merge decision waits on the previous link of its
+    chain, so the device passes run as deep as the longest chain (each pass
+    settles the first undecided seed of every cloud); the greedy result must
+    be the sequential rule's, cloud by cloud."""
+    rng = np.random.default_rng(5)
+    Xs = []
+    for n in (300, 7, 120, 1, 260):
+        X = np.zeros((n, 2), np.float32)
+        X[:, 0] = 5.0 * np.arange(n, dtype=np.float32)
+        X[:, 1] = float(rng.integers(0, 100))
+        Xs.append(X[rng.permutation(n)] if n > 1 else X)
+    xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0,
+                                              kernel="flat", merge_radius=6.0, all_points=all_points, rng_seed=3)
+    torch.cuda.synchronize()
+    say("chains: K per cloud", np.diff(k_off).tolist(), "rounds", rounds)
+    lab = lab.cpu().numpy()
+    for c, X in enumerate(Xs):
+        ref = orc.fit(X, 1.0, kernel="flat", merge_radius=6.0, all_points=all_points, rng_seed=3 + c)
+        g = per[c].cpu().numpy().astype(np.float64)
+        assert len(g) == ref.k, (c, len(g), ref.k)
+        assert np.abs(g - ref.modes[:ref.k]).max() <= MODE_TOL, c
+        diff = np.nonzero(lab[xo[c]:xo[c + 1]] != ref.labels)[0]
+        assert (ref.margin[diff] < MARGIN_TOL).all(), (c, len(diff))
