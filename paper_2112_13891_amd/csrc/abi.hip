@@ -584,6 +584,17 @@ bool bf16_form(const ms_params* p, int d) {
     return !(p->metric == MS_METRIC_COSINE && bf16_exact_reach(p, step_shape(d).D) >= 2.0);
 }
 
+// Pairs from which the merge and the pool coverage take the block join
+// instead of the brute-force passes (MS_JOIN_PAIRS overrides both, e.g. 0 to
+// take the join whenever the sides are large enough).
+constexpr long long kJoinMergePairs = 1LL << 27;
+constexpr long long kJoinCoverPairs = 1LL << 28;
+long long join_pairs_min(long long dflt) {
+    const char* e = std::getenv("MS_JOIN_PAIRS");
+    if (e && *e) return std::atoll(e);
+    return dflt;
+}
+
 struct SortedPoints {
     float* Xs = nullptr;
     int32_t* perm = nullptr;
@@ -797,8 +808,17 @@ int fit_impl(const ms_params* p, const float* X, int n, int d, float* modes, int
         // many seeds: their final positions are indexed once, for the merge
         // (against the old modes, then the decision passes among the seeds)
         // and, as the new modes, for the pool coverage
-        const bool join_merge = join_ok && B >= kJoinMin;
-        const bool join_cover = join_ok && !all && B >= kJoinMin && n >= kJoinMin;
+        // (only when the brute-force passes would compare many pairs: the
+        // index builds cost about a millisecond, the brute-force decision and
+        // coverage passes run 1e8 pairs in a fraction of one).  The coverage
+        // compares the pool with the round's founders, estimated from the
+        // founders per drawn seed so far
+        const long long est_founders =
+            drawn_total > 0 ? ((long long)B * K_old + drawn_total - 1) / drawn_total : (long long)B;
+        const bool join_merge =
+            join_ok && B >= kJoinMin && (long long)B * ((long long)K_old + B) >= join_pairs_min(kJoinMergePairs);
+        const bool join_cover = join_ok && !all && B >= kJoinMin && n >= kJoinMin &&
+                                (long long)pool_len * est_founders >= join_pairs_min(kJoinCoverPairs);
         JoinIndex jseeds{};
         if (join_merge || join_cover) {
             char* w;

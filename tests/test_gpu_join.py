@@ -4,6 +4,7 @@ ordered points and modes, only nearby blocks compared): its labels equal the
 brute-force nearest-mode labelling of ms_assign on the same modes, element by
 element, and a fit that goes through every join matches the FP64 oracle
 (Algorithms 1-2: prune modes, cluster by distance to modes)."""
+import os
 import sys
 
 import numpy as np
@@ -20,6 +21,20 @@ from paper_2112_13891_amd import api  # noqa: E402
 
 DEV = "cuda:0"
 JOIN_MIN = 4096   # modes (and seeds) from which the fit takes the join
+
+
+@pytest.fixture(autouse=True)
+def join_always():
+    """These sizes are below the pair count from which the fit prefers the
+    join for the merge and the coverage: the override makes it take the join
+    wherever both sides have JOIN_MIN rows (the library reads it per call)."""
+    old = os.environ.get("MS_JOIN_PAIRS")
+    os.environ["MS_JOIN_PAIRS"] = "0"
+    yield
+    if old is None:
+        del os.environ["MS_JOIN_PAIRS"]
+    else:
+        os.environ["MS_JOIN_PAIRS"] = old
 
 
 def say(*a):
