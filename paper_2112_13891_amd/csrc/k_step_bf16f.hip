@@ -284,8 +284,14 @@ __device__ __forceinline__ __bf16 staged_coord(const __bf16* base, int kbs, int 
 // component-major within the item, for the batched finalize.  Either way a
 // lane holds one seed (the two halves of a wave the same 32 seeds, each half
 // its own points of every tile).
+// Many clouds at D <= 16: three waves per SIMD (168 VGPRs, some spilled):
+// the batched workload's clusters lie within the weights' reach, so about
+// half of the tiles pass the screen and the kernel waits on latency more
+// than it computes (2.43 -> 2.15 ms per iteration on 512 uneven clouds at
+// D = 16).  Four waves spill too much.
 template <int D, bool MANY>
-__global__ __launch_bounds__(kFThreads, 2) void step_bf16f_kernel(Bf16fArgs A, int t, BatchedArgs B) {
+__global__ __launch_bounds__(kFThreads, (MANY && D <= 16) ? 3 : 2) void step_bf16f_kernel(Bf16fArgs A, int t,
+                                                                                        BatchedArgs B) {
     using Sh = FShape<D>;
     constexpr int TS = kFSeeds;
     constexpr int KBH = Sh::KBH, KBL = Sh::KBL;

@@ -172,3 +172,22 @@ def test_bf16_batched_full_size_sampled(orc):
         ref, ost, oit, osh = orc.step(Xs[c], Ss[c].astype(np.float64), 1.0, "gaussian", tol=1e-3, n_iter=3)
         say("cloud", c, "n", len(Xs[c]))
         ragged_check(orc, Xs[c], Ss[c], 1.0, "gaussian", 3, S[a:b], it[a:b], conv[a:b], ref, oit, ost)
+
+
+def test_bf16_batched_tuner_keeps_tiles_of_128():
+    """The tuner searches the BF16 form's chunk sizes and grids with tiles of
+    128 seeds only, records the shape under the BF16 precision, and later
+    default calls take it: the same bits as the explicit shape."""
+    Xs, Ss, xo, so = _batch(52, SIZES, 16, max_seeds=300)
+    Xa, Sa = _tensors(Xs, Ss)
+    S_before = Sa.cpu().clone()
+    best, ms, chunk, grid = api.tune_batched(Xa, xo, Sa, so, 1.0, trials=2, precision="bf16")
+    say("bf16 tuned R", best, ms, "chunk", chunk, "grid", grid)
+    assert best == 2 and set(ms) == {2} and ms[2] > 0
+    assert chunk in (512, 1024, 2048, 4096) and grid in (1024, 2048, 4096)
+    assert torch.equal(Sa.cpu(), S_before)
+    got = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=4, precision="bf16")]
+    explicit = [t.cpu() for t in api.step_batched(Xa, xo, Sa, so, 1.0, n_iter=4, precision="bf16",
+                                                  tile_chunk=chunk, tile_grid=grid)]
+    for a, b in zip(explicit, got):
+        torch.testing.assert_close(b, a, rtol=0, atol=0, equal_nan=True)
