@@ -399,36 +399,22 @@ __global__ __launch_bounds__(kFThreads, (MANY && D <= 16) ? 3 : 2) void step_bf1
             }
             maybe = maybe && live;
             if (!__syncthreads_or(maybe)) continue;   // (also: the previous block's stage is free)
+            constexpr int NH = Sh::HI_BYTES / 16, NL = Sh::LO_BYTES / 16;
+            // the hi operand first: the screen needs nothing else
             {
                 const uint4* gh = reinterpret_cast<const uint4*>(A.fhi + (long long)blk * (Sh::HI_BYTES / 2));
-                const uint4* gm2 = reinterpret_cast<const uint4*>(A.fmid + (long long)blk * (Sh::LO_BYTES / 2));
-                const uint4* gl = reinterpret_cast<const uint4*>(A.flo + (long long)blk * (Sh::LO_BYTES / 2));
                 uint4* sm = reinterpret_cast<uint4*>(smem);
-                constexpr int NH = Sh::HI_BYTES / 16, NL = Sh::LO_BYTES / 16;
-                // in two passes (the hi operand, then mid and lo), so that
-                // fewer registers hold vectors in flight
-                {
-                    uint4 v[NH / kFThreads];
+                uint4 v[NH / kFThreads];
 #pragma unroll
-                    for (int q = 0; q < NH / kFThreads; ++q) v[q] = gh[q * kFThreads + threadIdx.x];
+                for (int q = 0; q < NH / kFThreads; ++q) v[q] = gh[q * kFThreads + threadIdx.x];
 #pragma unroll
-                    for (int q = 0; q < NH / kFThreads; ++q) sm[q * kFThreads + threadIdx.x] = v[q];
-                }
-                {
-                    uint4 v[2 * NL / kFThreads];
-#pragma unroll
-                    for (int q = 0; q < 2 * NL / kFThreads; ++q) {
-                        const int f = q * kFThreads + threadIdx.x;
-                        v[q] = f < NL ? gm2[f] : gl[f - NL];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 2 * NL / kFThreads; ++q) sm[NH + q * kFThreads + threadIdx.x] = v[q];
-                }
+                for (int q = 0; q < NH / kFThreads; ++q) sm[q * kFThreads + threadIdx.x] = v[q];
             }
             __syncthreads();
+            // seed operands of this block: [2 s~hi | 1 | 1 | 1 | 0..], [2 s~mid | 0..], [2 s~lo | 0..]
+            bf16x8 bh[KBH], bm[KBL], bl[KBL];
+            unsigned tmask = 0u;   // this wave's tiles that pass the screen
             if (__ballot(maybe)) {
-                // seed operands of this block: [2 s~hi | 1 | 1 | 1 | 0..], [2 s~mid | 0..], [2 s~lo | 0..]
-                bf16x8 bh[KBH], bm[KBL], bl[KBL];
 #pragma unroll
                 for (int kb = 0; kb < KBH; ++kb) {
 #pragma unroll
@@ -449,18 +435,10 @@ __global__ __launch_bounds__(kFThreads, (MANY && D <= 16) ? 3 : 2) void step_bf1
                         }
                     }
                 }
-                // the expanded form's terms are too large for its FP32
-                // accumulation and the weights can be sizeable: this seed's
-                // distances to the block are recomputed exactly
-                const bool exact_seed = live && (Rin + dist) * (Rin + dist) > kExpandedMax &&
-                                        dist * (1.0f - 1e-5f) - Rin < kFarLower;
-                // the compensated E's bound for the outliers (R their radius)
-                const float eps3 = 1.2e-6f * R * dist + 1e-6f * (R + dist) * (R + dist);
-                float wb = 0.0f;   // this lane's weight sum over the block
-                unsigned long long nlive = 0;
+                // 2. the screen, on the hi products alone: a 32 x 32 tile whose
+                //    every E + eps < -127 has weights exactly 0 in FP32
 #pragma unroll 1
                 for (int tt = 0; tt < kFBlk / 32; ++tt) {
-                    // the hi products (the screen), from -|s~|^2
                     f32x16 E;
 #pragma unroll
                     for (int v = 0; v < 16; ++v) E[v] = -ns;
@@ -475,8 +453,48 @@ __global__ __launch_bounds__(kFThreads, (MANY && D <= 16) ? 3 : 2) void step_bf1
                     const float m3 = fmaxf(fmaxf(E[9], E[10]), E[11]);
                     const float m4 = fmaxf(fmaxf(E[12], E[13]), E[14]);
                     const float emax = fmaxf(fmaxf(fmaxf(m0, m1), m2), fmaxf(fmaxf(m3, m4), E[15]));
-                    // 2. every weight of the tile is exactly 0 in FP32
-                    if (!__ballot(live && emax + eps >= -127.0f)) continue;
+                    if (__ballot(live && emax + eps >= -127.0f)) tmask |= 1u << tt;
+                }
+            }
+            // the mid and lo operands only for a block with a tile that passed
+            // (a block no wave needs further ends here: its weights are all 0)
+            if (!__syncthreads_or(tmask != 0u)) continue;
+            {
+                const uint4* gm2 = reinterpret_cast<const uint4*>(A.fmid + (long long)blk * (Sh::LO_BYTES / 2));
+                const uint4* gl = reinterpret_cast<const uint4*>(A.flo + (long long)blk * (Sh::LO_BYTES / 2));
+                uint4* sm = reinterpret_cast<uint4*>(smem);
+                uint4 v[2 * NL / kFThreads];
+#pragma unroll
+                for (int q = 0; q < 2 * NL / kFThreads; ++q) {
+                    const int f = q * kFThreads + threadIdx.x;
+                    v[q] = f < NL ? gm2[f] : gl[f - NL];
+                }
+#pragma unroll
+                for (int q = 0; q < 2 * NL / kFThreads; ++q) sm[NH + q * kFThreads + threadIdx.x] = v[q];
+            }
+            __syncthreads();
+            if (tmask != 0u) {
+                // the expanded form's terms are too large for its FP32
+                // accumulation and the weights can be sizeable: this seed's
+                // distances to the block are recomputed exactly
+                const bool exact_seed = live && (Rin + dist) * (Rin + dist) > kExpandedMax &&
+                                        dist * (1.0f - 1e-5f) - Rin < kFarLower;
+                // the compensated E's bound for the outliers (R their radius)
+                const float eps3 = 1.2e-6f * R * dist + 1e-6f * (R + dist) * (R + dist);
+                float wb = 0.0f;   // this lane's weight sum over the block
+                unsigned long long nlive = 0;
+#pragma unroll 1
+                for (int tt = 0; tt < kFBlk / 32; ++tt) {
+                    if (!((tmask >> tt) & 1u)) continue;
+                    // the hi products again (the same values as the screen's)
+                    f32x16 E;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) E[v] = -ns;
+#pragma unroll
+                    for (int kb = 0; kb < KBH; ++kb) {
+                        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(shi + (tt * KBH + kb) * 512 + hf * 256 + col * 8);
+                        E = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[kb], E, 0, 0, 0);
+                    }
                     nlive += (unsigned long long)__popcll(lmask) * 16;
                     // 3. the compensated products, in an accumulator of their
                     //    own (their sizes are u and u^2 of the hi products)
