@@ -310,15 +310,17 @@ def config_c4(api, torch, workloads):
     e["algorithmic_hbm_frac"] = e["algorithmic_bytes"] / t_it / 1e9 / HBM_PEAK_GBS
     out["roofline"] = e
 
-    def fit_all():
+    def fit_all(precision="fp32"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        per, lab, k_off, rounds = api.fit_batched(Xa, xo, 1.0)
+        per, lab, k_off, rounds = api.fit_batched(Xa, xo, 1.0, precision=precision)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, k_off, rounds
 
     fit_all()
     t_fb, k_off, rounds = min((fit_all() for _ in range(3)), key=lambda r: r[0])
+    fit_all("bf16")
+    t_fb16, k_off16, rounds16 = min((fit_all("bf16") for _ in range(3)), key=lambda r: r[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for c, x in enumerate(Xc):
@@ -326,7 +328,11 @@ def config_c4(api, torch, workloads):
     torch.cuda.synchronize()
     t_pf = time.perf_counter() - t0
     out["fit_batched"] = {"ms_per_call": t_fb * 1e3, "rounds": rounds, "modes_total": int(k_off[-1]),
-                          "per_cloud_fit_calls_ms": t_pf * 1e3, "speedup_vs_per_cloud_fits": t_pf / t_fb}
+                          "per_cloud_fit_calls_ms": t_pf * 1e3, "speedup_vs_per_cloud_fits": t_pf / t_fb,
+                          "bf16": {"ms_per_call": t_fb16 * 1e3, "rounds": rounds16,
+                                   "modes_total": int(k_off16[-1]),
+                                   "clouds_with_fp32_mode_count": int((np.diff(k_off16) == np.diff(k_off)).sum()),
+                                   "speedup_vs_fp32": t_fb / t_fb16}}
     return out
 
 
@@ -547,13 +553,14 @@ def main():
                     help="skip the secondary shapes (flat window, cosine metric, images, frames, small clouds)")
     ap.add_argument("--kernel-iters", type=int, default=20)
     ap.add_argument("--phase", default="all",
-                    choices=["all", "kernel", "fit", "c3", "c3flat", "c3kernel", "batched", "c4kernel", "c5"],
+                    choices=["all", "kernel", "fit", "c3", "c3flat", "c3kernel", "batched", "batched_bf16", "c4kernel",
+                             "c5"],
                     help="kernel: the 200K mixture's largest launch (both precisions) and a 256 MiB copy "
                          "that calibrates the traffic counters; fit: --steps fits per precision of the 200K "
                          "mixture; c3: --steps fits per precision of the 32-D embeddings; c3flat: the same "
                          "with the flat window (every window a singleton); c3kernel: their "
                          "largest launch (8,192 seeds) and the copy; batched: --steps whole-method calls on "
-                         "the 512 uneven clouds; c4kernel: one batched-step call of --kernel-iters iterations "
+                         "the 512 uneven clouds (FP32; batched_bf16: the BF16 form); c4kernel: one batched-step call of --kernel-iters iterations "
                          "per precision on those clouds (every seed active) and the copy; c5: --steps steps of "
                          "the differentiable form; all: the benchmark")
     args = ap.parse_args()
@@ -578,19 +585,21 @@ def main():
         torch.cuda.synchronize()
         out["copy_bytes_each_way"] = src.numel() * 4
 
-    if args.phase == "batched":
+    if args.phase in ("batched", "batched_bf16"):
+        prec = "bf16" if args.phase == "batched_bf16" else "fp32"
         clouds = workloads.clouds16(seed=0)
         xo = np.concatenate([[0], np.cumsum([len(c[0]) for c in clouds])]).astype(np.int64)
         Xa = torch.from_numpy(np.concatenate([c[0] for c in clouds])).cuda()
         log(f"workload clouds16: {len(clouds)} clouds, {int(xo[-1])} points, D=16")
         for _ in range(args.warmup):
-            api.fit_batched(Xa, xo, 1.0)
+            api.fit_batched(Xa, xo, 1.0, precision=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, _, k_off, rounds = api.fit_batched(Xa, xo, 1.0)
+            _, _, k_off, rounds = api.fit_batched(Xa, xo, 1.0, precision=prec)
         torch.cuda.synchronize()
-        print(json.dumps({"phase": "batched", "ms_per_call": (time.perf_counter() - t0) / args.steps * 1e3,
+        print(json.dumps({"phase": "batched", "precision": prec,
+                          "ms_per_call": (time.perf_counter() - t0) / args.steps * 1e3,
                           "rounds": rounds, "modes_total": int(k_off[-1])}), flush=True)
         return
     if args.phase == "c4kernel":

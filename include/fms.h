@@ -335,9 +335,13 @@ int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
  * converged seeds into its own modes, coverage and compaction act on its own
  * pool, and its seed-count rule is its own.  Labels are the nearest mode
  * within the point's cloud.
- *   p          as ms_fit; p->precision must be MS_PREC_FP32, metric
- *              Euclidean and gamma 1 (every round runs until each seed
- *              converged, failed or made max_iter updates).
+ *   p          as ms_fit; metric Euclidean and gamma 1 (every round runs
+ *              until each seed converged, failed or made max_iter
+ *              updates).  p->precision MS_PREC_FP32, or MS_PREC_BF16_REFINE
+ *              for the Gaussian kernel at 5 <= d <= 32 (else MS_E_INVALID):
+ *              the iterations take ms_step_batched's BF16 form, the clouds'
+ *              points sorted and their block features built once per call;
+ *              merges, coverage and labels stay FP32.
  *   X          device, n x d row-major float32, the clouds' points
  *              concatenated; cloud c is rows x_off[c] .. x_off[c+1].
  *   x_off      host, ncl + 1 nondecreasing offsets, x_off[0] = 0, at
@@ -353,8 +357,10 @@ int ms_seed_draw(uint64_t *state, const int32_t *pool, int32_t len,
  *   rounds     host, may be NULL: rounds run (the most any cloud ran).
  * Errors: MS_E_INVALID (arguments), MS_E_CAPACITY (more modes than
  * max_modes), MS_E_NO_MODES (a cloud with points has no converged seed),
- * MS_E_NOMEM, MS_E_HIP.  Host-synchronous (the host merges between rounds).
- * Allocates device workspace on `stream`.
+ * MS_E_NOMEM, MS_E_HIP.  Host-synchronous: the host draws the seeds and
+ * applies the seed-count rule between rounds, and reads back whether a
+ * round's seeds and its merge passes are done; the merges run on the
+ * device.  Allocates device workspace on `stream`.
  */
 int ms_fit_batched(const ms_params *p, const float *X, const int64_t *x_off, int32_t ncl, int32_t d,
                    float *modes, int64_t max_modes, int64_t *k_off, int32_t *labels, int32_t *rounds,

@@ -339,11 +339,12 @@ def step_batched(X, x_off, seeds, s_off, h, kernel="gaussian", tol=1e-3, n_iter=
 
 def fit_batched(X, x_off, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_radius=1.0,
                 cover_radius=1.0, n_initial=128, L=8, all_points=False, rng_seed=0, max_modes=None,
-                labels=True):
+                labels=True, precision="fp32"):
     """ms_fit_batched: the whole method on every cloud of a CSR batch (cloud c
     owns X[x_off[c]:x_off[c+1]] and draws with SplitMix64 state rng_seed + c).
-    Returns (modes list of per-cloud tensors, labels tensor or None, k_off
-    numpy array, rounds)."""
+    precision "bf16" runs the iterations in the batched BF16 form (Gaussian,
+    5 <= d <= 32).  Returns (modes list of per-cloud tensors, labels tensor
+    or None, k_off numpy array, rounds)."""
     import numpy as np
     torch = _torch()
     Xp = _dev(X, torch.float32, 2, "X")
@@ -353,7 +354,7 @@ def fit_batched(X, x_off, h, kernel="gaussian", tol=1e-3, max_iter=100, merge_ra
         raise ValueError("x_off must have ncl + 1 entries")
     ncl = len(xo) - 1
     max_modes = int(max_modes or n)
-    p = make_params(h, kernel, "fp32", tol, max_iter, merge_radius, cover_radius, 1.0, n_initial, L,
+    p = make_params(h, kernel, precision, tol, max_iter, merge_radius, cover_radius, 1.0, n_initial, L,
                     all_points=all_points, rng_seed=rng_seed)
     modes = torch.empty((max_modes, d), dtype=torch.float32, device=X.device)
     lab = torch.empty((n,), dtype=torch.int32, device=X.device) if labels else None

@@ -1197,17 +1197,21 @@ TuneKey tune_key(int d, long long n, long long M, int ncl, int precision) {
 // Points of a batch already packed (DP columns, packed units of the call's
 // parameters) with the point and seed offsets on the device: a caller that
 // runs several step calls over the same clouds packs them once.
+struct BatchedBf16;
 struct BatchedPrepared {
     const float* Xp;
     int DP;
     const long long* xo_dev;
     const int32_t* so_dev;
-    DevCache* cache;   // the calling fit's cache for the step's buffers (kept across calls), or NULL
+    DevCache* cache;          // the calling fit's cache for the step's buffers (kept across calls), or NULL
+    const BatchedBf16* bb;    // the BF16 form: the points' order and features (prepared once), else NULL
 };
 
 // The BF16 form over many clouds (Gaussian, padded D in {8, 16, 32}): each
 // cloud's points in the spatial order of the one-cloud form (its own pivots),
-// their block features, and the per-cloud offsets the kernels use.
+// their block features, and the per-cloud offsets the kernels use.  The
+// point part depends on the clouds only; the seed part (stpre, soff,
+// stiles) on each call's seed offsets.
 struct BatchedBf16 {
     float* Xs = nullptr;
     void* feat = nullptr;
@@ -1226,27 +1230,21 @@ bool batched_bf16_ok(const ms_params* p, int d) {
 }
 
 // Sorts the packed points Xp of the clouds and builds their features (the
-// workspace comes from ws); the offsets are xo / so (host) and xo_dev.
-int prepare_batched_bf16(Workspace& ws, const float* Xp, int n, int D, const std::vector<long long>& xo,
-                         const std::vector<int32_t>& so, const long long* xo_dev, int ncl, int M, BatchedBf16& bb,
-                         hipStream_t s) {
-    std::vector<int32_t> poff(ncl + 1, 0), boff(ncl + 1, 0), stpre(ncl + 1, 0);
-    std::vector<long long> soff(ncl + 1, 0);
+// workspace comes from ws); the offsets are xo (host) and xo_dev.  count
+// sizes the sort workspace: at least the points and every later call's seeds.
+int prepare_batched_bf16_points(Workspace& ws, const float* Xp, int n, int D, const std::vector<long long>& xo,
+                                const long long* xo_dev, int ncl, int count, BatchedBf16& bb, hipStream_t s) {
+    std::vector<int32_t> poff(ncl + 1, 0), boff(ncl + 1, 0);
     for (int c = 0; c < ncl; ++c) {
         const long long nc = xo[c + 1] - xo[c];
         poff[c + 1] = poff[c] + batched_pivot_count(nc);
         boff[c + 1] = boff[c] + (int)((nc + 255) / 256);
-        stpre[c + 1] = stpre[c] + (so[c + 1] - so[c] + 255) / 256;
-        soff[c + 1] = so[c + 1];
     }
     bb.ptot = poff[ncl];
     bb.nblk = boff[ncl];
-    bb.stiles = stpre[ncl];
-    bb.count = std::max(std::max(n, M), 1);
+    bb.count = std::max(std::max(n, count), 1);
     FMS_CHECK(ws.alloc(&bb.poff, (size_t)ncl + 1));
     FMS_CHECK(ws.alloc(&bb.boff, (size_t)ncl + 1));
-    FMS_CHECK(ws.alloc(&bb.stpre, (size_t)ncl + 1));
-    FMS_CHECK(ws.alloc(&bb.soff, (size_t)ncl + 1));
     FMS_CHECK(ws.alloc(&bb.zero, (size_t)D));
     FMS_CHECK(ws.alloc(&bb.Xs, (size_t)std::max(n, 1) * D));
     char* feat;
@@ -1258,13 +1256,30 @@ int prepare_batched_bf16(Workspace& ws, const float* Xp, int n, int D, const std
     const size_t ob = (size_t)(ncl + 1) * sizeof(int32_t);
     FMS_HIP(hipMemcpyAsync(bb.poff, poff.data(), ob, hipMemcpyHostToDevice, s));
     FMS_HIP(hipMemcpyAsync(bb.boff, boff.data(), ob, hipMemcpyHostToDevice, s));
-    FMS_HIP(hipMemcpyAsync(bb.stpre, stpre.data(), ob, hipMemcpyHostToDevice, s));
-    FMS_HIP(hipMemcpyAsync(bb.soff, soff.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
     FMS_HIP(hipMemsetAsync(bb.zero, 0, (size_t)D * 4, s));
     FMS_HIP(hipStreamSynchronize(s));   // the host copies go out of scope
     const CloudRows pts{ncl, xo_dev, bb.boff, bb.nblk};
     FMS_HIP(launch_batched_sort(Xp, n, D, pts, bb.poff, bb.ptot, bb.Xs, bb.sws, bb.count, s));
     FMS_HIP(launch_bf16f_features_batched(bb.Xs, D, xo_dev, bb.boff, ncl, bb.nblk, bb.feat, s));
+    return MS_OK;
+}
+
+// The seed part of bb for the seed offsets so (host), from ws.
+int prepare_batched_bf16_seeds(Workspace& ws, const std::vector<int32_t>& so, int ncl, BatchedBf16& bb,
+                               hipStream_t s) {
+    std::vector<int32_t> stpre(ncl + 1, 0);
+    std::vector<long long> soff(ncl + 1, 0);
+    for (int c = 0; c < ncl; ++c) {
+        stpre[c + 1] = stpre[c] + (so[c + 1] - so[c] + 255) / 256;
+        soff[c + 1] = so[c + 1];
+    }
+    if (so[ncl] > bb.count) return fail(MS_E_HIP, "more seeds than the prepared sort workspace holds");
+    bb.stiles = stpre[ncl];
+    FMS_CHECK(ws.alloc(&bb.stpre, (size_t)ncl + 1));
+    FMS_CHECK(ws.alloc(&bb.soff, (size_t)ncl + 1));
+    FMS_HIP(hipMemcpyAsync(bb.stpre, stpre.data(), (size_t)(ncl + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    FMS_HIP(hipMemcpyAsync(bb.soff, soff.data(), (size_t)(ncl + 1) * sizeof(long long), hipMemcpyHostToDevice, s));
+    FMS_HIP(hipStreamSynchronize(s));   // the host copies go out of scope
     return MS_OK;
 }
 
@@ -1278,7 +1293,7 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
     const bool bf = p->precision == MS_PREC_BF16_REFINE;
     if (bf && !batched_bf16_ok(p, d))
         return fail(MS_E_INVALID, "the batched BF16 form is built for the Gaussian kernel at 5 <= d <= 32");
-    if (bf && pre) return fail(MS_E_INVALID, "the batched BF16 form takes unprepared points");
+    if (bf && pre && !pre->bb) return fail(MS_E_HIP, "the batched BF16 form needs its prepared points");
     StepShape sh = step_shape_for(d, std::max(1, M / ncl));
     // default: at most two seeds per lane up to D = 8 and one above (timed on
     // 512 uneven clouds: more seeds per lane cost occupancy here, and the
@@ -1346,7 +1361,11 @@ int step_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, 
         so_dev = sod;
     }
     BatchedBf16 bb;
-    if (bf) FMS_CHECK(prepare_batched_bf16(ws, Xp, n, sh.D, xo, so, xo_dev, ncl, M, bb, s));
+    if (bf) {
+        if (pre) bb = *pre->bb;
+        else FMS_CHECK(prepare_batched_bf16_points(ws, Xp, n, sh.D, xo, xo_dev, ncl, M, bb, s));
+        FMS_CHECK(prepare_batched_bf16_seeds(ws, so, ncl, bb, s));
+    }
     Batch b;
     fill_batch(b, n, d, M, sh, p, scale, Xp, nullptr);
     b.grid = (int)std::min<long long>(INT_MAX, std::max(1LL, max_items));   // capped by the launcher
@@ -1545,7 +1564,12 @@ int fit_batched_impl(const ms_params* p, const float* X, const int64_t* x_off, i
     FMS_CHECK(cache_get(C, budget, SL_XP, (size_t)n * DP, &Xp));
     FMS_CHECK(ws.alloc(&so32_dev, (size_t)ncl + 1));
     FMS_HIP(launch_pack_points(X, (int)n, d, DP, packed_scale(&q), Xp, s));
-    const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev, &C};
+    // the BF16 form: the clouds' spatial order and block features, once per
+    // call (a round's seeds are never more than the points)
+    BatchedBf16 bb;
+    const bool bf = p->precision == MS_PREC_BF16_REFINE;
+    if (bf) FMS_CHECK(prepare_batched_bf16_points(ws, Xp, (int)n, step_shape(d).D, xo, xo_dev, ncl, (int)n, bb, s));
+    const BatchedPrepared pre{Xp, DP, xo_dev, so32_dev, &C, bf ? &bb : nullptr};
     FMS_HIP(launch_bf_iota(xo_dev, ncl, pool[0], n, s));
     FMS_HIP(launch_bf_fill_i32(kcnt_dev, ncl, 0, s));
     FMS_HIP(launch_fill_u8(removed, (int)n, 0, s));
@@ -1863,7 +1887,6 @@ int ms_fit_batched(const ms_params* p, const float* X, const int64_t* x_off, int
     FMS_CHECK(check_params(p, true));
     FMS_CHECK(check_batched_args(p, X, x_off, x_off, ncl, d));
     if (p->gamma != 1.0f) return fail(MS_E_INVALID, "ms_fit_batched runs every round to convergence: gamma must be 1");
-    if (p->precision != MS_PREC_FP32) return fail(MS_E_INVALID, "ms_fit_batched computes the FP32 form only");
     if (!k_off) return fail(MS_E_INVALID, "k_off is NULL");
     if (!modes) return fail(MS_E_INVALID, "modes is NULL");
     if (max_modes < 1) return fail(MS_E_INVALID, "max_modes must be >= 1");

@@ -147,8 +147,11 @@ def test_null_pointers_and_reserved(api):
     assert L.ms_tune_batched(ctypes.byref(p), FAKE, xo, FAKE, so, 2, 2, 4, ctypes.byref(best), None,
                              None, None, None) == -1
     assert "Gaussian kernel at 5 <= d <= 32" in api.last_error()
-    assert L.ms_fit_batched(ctypes.byref(p), FAKE, xo, 2, 16, FAKE, 10, kf, None, None, None) == -1
-    assert "FP32 form only" in api.last_error()
+    assert L.ms_fit_batched(ctypes.byref(p), FAKE, xo, 2, 4, FAKE, 10, kf, None, None, None) == -1
+    assert "Gaussian kernel at 5 <= d <= 32" in api.last_error()
+    pf = api.make_params(1.0, kernel="flat", precision="bf16")
+    assert L.ms_fit_batched(ctypes.byref(pf), FAKE, xo, 2, 16, FAKE, 10, kf, None, None, None) == -1
+    assert "Gaussian kernel at 5 <= d <= 32" in api.last_error()
 
 
 def test_error_message_is_thread_local_and_cleared(api):

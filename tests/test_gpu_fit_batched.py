@@ -153,3 +153,44 @@ def test_fit_batched_merge_chains(orc, all_points):
         assert np.abs(g - ref.modes[:ref.k]).max() <= MODE_TOL, c
         diff = np.nonzero(lab[xo[c]:xo[c + 1]] != ref.labels)[0]
         assert (ref.margin[diff] < MARGIN_TOL).all(), (c, len(diff))
+
+
+@pytest.mark.parametrize("d", [5, 8, 16, 32])
+def test_fit_batched_bf16_matches_oracle_per_cloud(orc, d):
+    """The BF16 form of the batched step inside the whole method: each cloud's
+    fit against the oracle's fit of that cloud alone (the modes within
+    1e-4 h, the same K and order, labels except at near-ties)."""
+    sizes = [300, 0, 2500, 1, 4100, 64, 1800, 257]
+    Xs, xo = _clouds(40 + d, sizes, d)
+    say("fit_batched bf16", d, sizes)
+    per, lab, k_off, rounds = api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0,
+                                              rng_seed=11, precision="bf16")
+    torch.cuda.synchronize()
+    say("K per cloud", np.diff(k_off).tolist(), "rounds", rounds)
+    _compare(orc, Xs, xo, 1.0, "gaussian", False, 11, per, lab, k_off)
+
+
+def test_fit_batched_bf16_all_points_and_repeat(orc):
+    """Every point a seed (one round of the batched BF16 step over all of a
+    cloud's points) against the oracle; a second call gives the same bits."""
+    Xs, xo = _clouds(8, [700, 5, 1500, 300], 16)
+    X = torch.from_numpy(np.concatenate(Xs)).to(DEV)
+    first = api.fit_batched(X, xo, 1.0, all_points=True, precision="bf16")
+    torch.cuda.synchronize()
+    assert first[3] == 1
+    _compare(orc, Xs, xo, 1.0, "gaussian", True, 0, first[0], first[1], first[2])
+    again = api.fit_batched(X, xo, 1.0, all_points=True, precision="bf16")
+    torch.cuda.synchronize()
+    assert np.array_equal(first[2], again[2])
+    for a, b in zip(first[0], again[0]):
+        assert torch.equal(a, b)
+    assert torch.equal(first[1], again[1])
+
+
+def test_fit_batched_bf16_rejects_what_is_not_built():
+    Xs, xo = _clouds(3, [300, 500], 3)
+    with pytest.raises(api.MeanShiftError, match="Gaussian kernel at 5 <= d <= 32"):
+        api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0, precision="bf16")
+    Xs, xo = _clouds(3, [300, 500], 16)
+    with pytest.raises(api.MeanShiftError, match="Gaussian kernel at 5 <= d <= 32"):
+        api.fit_batched(torch.from_numpy(np.concatenate(Xs)).to(DEV), xo, 1.0, kernel="flat", precision="bf16")

@@ -11,9 +11,9 @@
 * The largest step launch of that fit: 8,192 seeds over all 262,144 points
   (radix seed order, many seed tiles), a 256-seed sample against the
   oracle's trajectories.
-* The whole method on the 512 uneven clouds in one ms_fit_batched call: the
-  smallest, the largest and six random clouds against the oracle's fit of
-  each cloud alone.
+* The whole method on the 512 uneven clouds in one ms_fit_batched call, FP32
+  and BF16: the smallest, the largest and six random clouds against the
+  oracle's fit of each cloud alone.
 """
 import os
 import sys
@@ -121,12 +121,13 @@ def test_step_embed32_8192_seeds(orc, embed, kernel, precision):
     say(rep, "converged", int((conv == 1).sum()), "of 8192")
 
 
-def test_fit_batched_512_clouds_sampled(orc):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fit_batched_512_clouds_sampled(orc, precision):
     clouds = workloads.clouds16(seed=0)
     Xs = [c[0] for c in clouds]
     xo = np.concatenate([[0], np.cumsum([len(x) for x in Xs])]).astype(np.int64)
-    say("fit_batched 512 clouds", int(xo[-1]), "points")
-    per, lab, k_off, rounds = api.fit_batched(_gpu(np.concatenate(Xs)), xo, 1.0)
+    say("fit_batched 512 clouds", int(xo[-1]), "points", precision)
+    per, lab, k_off, rounds = api.fit_batched(_gpu(np.concatenate(Xs)), xo, 1.0, precision=precision)
     torch.cuda.synchronize()
     lab = lab.cpu().numpy()
     sizes = np.array([len(x) for x in Xs])
