@@ -729,7 +729,9 @@ def main():
     step_name = "step_bf16_kernel<3, 1, 1>" if args.precision == "bf16" else "step_cull_kernel<3, 1, 1>"
     roof = roofline_entry(pairs, d, t_it, m, n, args.precision, f"{m} seeds x {n} points",
                           f"one fused-step iteration: {step_name} + finalize_fused_kernel<3, 4, 1> "
-                          "(chunk reduction and finalize in one launch)",
+                          "(chunk reduction and finalize in one launch)"
+                          + (" + ordered_compact_kernel<3> (the active list in list order)"
+                             if args.precision == "bf16" else ""),
                           counter_figures("c2", args.precision))
     log(f"kernel: {t_it * 1e3:.1f} us/iteration at {m}x{n}: {pairs / (t_it * 1e-3):.3e} pairs/s, "
         f"{roof['achieved']:.2f} TFLOP/s")

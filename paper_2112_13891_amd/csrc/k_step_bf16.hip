@@ -268,18 +268,19 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             const float rr = gm[4] + sqrtf(ns);
             const float eps = A.kappa * rr * rr;
             {
-                // every live seed of the wave has the whole block within the
-                // refine radius, by a bound: (|s~| + R)^2 <= -e_thr, so
-                // E + eps >= -|x - s|^2 >= e_thr for every pair and the bf16
-                // path below would recompute every pair exactly too.  The wave
-                // then computes its half block exactly in FP32 (points from
-                // LDS) with no products; the arithmetic and its order are
-                // those of the recompute below, so a seed's result is the
-                // same either way and never depends on its wave mates (whose
-                // grouping follows the order of the active list)
-                const float ub = (sqrtf(ns) + gm[4]) * (1.0f + 1e-5f);
-                const bool inside = ub * ub <= -A.e_thr;
-                if (!__ballot(live[0] && !inside)) {
+                // some seed of the wave may have a pair of this block within
+                // the refine radius (its bound admits E + eps >= e_thr): the
+                // wave computes its half block exactly in FP32 (points from
+                // LDS), every pair of every seed, with no products -- the live
+                // blocks near the seeds mostly lie within the radius anyway.
+                // Otherwise no pair of the block can need the recompute and
+                // the products below serve.  A seed's result thus depends on
+                // its wave mates; the finalize of this form compacts the
+                // active list in list order (StepArgs::ordered), so the
+                // grouping, and the result, are the same on every run
+                const float lbk = sqrtf(ns) - gm[4];
+                const bool may = live[0] && !(lbk > 0.0f && lbk * lbk > -A.e_thr + 2.0f * eps);
+                if (__ballot(may)) {
                     const long long pb = (long long)blk * kBlk + half * kPtsPerWave;
                     unsigned long long nex = 0;
 #pragma unroll 1
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(kB16Threads) void step_bf16_kernel(Bf16Args A, int 
             for (int k = 0; k <= D; ++k) v[k] = red[2 * g][k][c] + red[2 * g + 1][k][c];
         }
         __syncthreads();
-        if (chunks == 1) {
+        if (chunks == 1 && !a.ordered) {
             float* sums = &red[0][0][0];   // (D + 1) x 64 floats: sums[k * TS + pos]
             if (pos < TS) {
 #pragma unroll
@@ -497,6 +498,7 @@ hipError_t launch_bf16_t(Batch& b, int t, hipStream_t s) {
     a.inv_scale = b.inv_scale;
     a.thr2 = b.thr2;
     a.metric = b.metric;
+    a.ordered = 1;
     A.Xs = b.Xs;
     A.geom = b.geom;
     A.pf = (const __bf16*)b.pf;

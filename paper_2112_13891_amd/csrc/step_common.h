@@ -54,6 +54,12 @@ struct StepArgs {
     Ctl* ctl;
     float h2, scale, inv_scale, thr2;
     int metric = MS_METRIC_EUCLIDEAN;   // cosine: the updated seed is renormalized
+    // 1: the finalize compacts in list order (each 64-slot run's kept ids and
+    // count go to the run's own rows of `red`, and ordered_compact_kernel
+    // places the runs one after the other), so the grouping of seeds into
+    // waves is the same on every run; 0: one atomic per wave (run order is
+    // the order of the atomics)
+    int ordered = 0;
 };
 
 // Done once per iteration by thread 0 of workgroup 0 of the step kernel:
@@ -313,18 +319,131 @@ constexpr int kFinWaves = kFinThreads / 64;
 constexpr int kDirectChunks = 16;   // one round of loads per seed in the finalize
 constexpr int kRedThreads = 1024;
 
+// Rows of `red` that hold the kept ids (64) and their count (at 64) of the
+// 64-slot run starting at slot `base` in the ordered compaction: the run's
+// own 64 x (D+1) floats, which the finalize has read before it writes them.
+template <int D>
+__device__ __forceinline__ int32_t* run_rows(const StepArgs& a, int base) {
+    static_assert(64 * (D + 1) >= 65, "a run's rows hold its ids and count");
+    return reinterpret_cast<int32_t*>(a.red + (long long)base * (D + 1));
+}
+
 template <int D, int DP>
 __device__ __forceinline__ void compact_wave(const StepArgs& a, int t, int slot, int res) {
     const int lane = threadIdx.x & 63;
     const unsigned long long keep = __ballot(res == 1);
     const unsigned long long done = __ballot(res == 2);
+    const int rank = __popcll(keep & ((1ull << lane) - 1ull));
+    if (a.ordered) {
+        int32_t* rows = run_rows<D>(a, slot - lane);
+        if (res == 1) rows[rank] = a.act_in[slot];
+        if (lane == 0) {
+            rows[64] = __popcll(keep);
+            if (done) add_converged(a.ctl, t, __popcll(done));
+        }
+        return;
+    }
     int off = 0;
     if (lane == 0) {
         if (keep) off = atomicAdd(&a.ctl->count[(t + 1) % 3], __popcll(keep));
         if (done) add_converged(a.ctl, t, __popcll(done));
     }
     off = __shfl(off, 0);
-    if (res == 1) a.act_out[off + __popcll(keep & ((1ull << lane) - 1ull))] = a.act_in[slot];
+    if (res == 1) a.act_out[off + rank] = a.act_in[slot];
+}
+
+// The ordered compaction's second half, by one workgroup of kFinThreads
+// after the finalize has written every run's rows: the kept ids of the runs,
+// run after run, into act_out, and the next iteration's active count.
+// Up to 64 runs (4,096 active slots), wave w takes runs w, w + 16, w + 32,
+// w + 48, whose rows it loads together with the active count (`cap_runs`,
+// the runs the rows of `red` hold, bounds those loads; rows past the count
+// are loaded but not used).  More runs: their counts are scanned
+// kFinThreads at a time, and wave w copies runs w, w + 16, ... of each batch.
+// A last-workgroup placement inside the finalize (device-scope fences
+// around a count of finished workgroups) measured slower on the 512 x 200K
+// iteration than this launch of its own.
+constexpr int kRunsPerWave = 4;
+
+template <int D>
+__device__ void ordered_place_many(const StepArgs& a, int t, int nruns) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ int pre[kFinThreads], cnt[kFinThreads], wtot[kFinWaves];
+    int total = 0;
+    for (int r0 = 0; r0 < nruns; r0 += kFinThreads) {
+        const int r = r0 + threadIdx.x;
+        const int c = r < nruns ? run_rows<D>(a, r * 64)[64] : 0;
+        int x = c;   // inclusive scan within the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        __syncthreads();
+        int wbase = 0, btot = 0;
+        for (int w = 0; w < kFinWaves; ++w) {
+            wbase += w < wave ? wtot[w] : 0;
+            btot += wtot[w];
+        }
+        pre[threadIdx.x] = total + wbase + x - c;
+        cnt[threadIdx.x] = c;
+        __syncthreads();
+        const int nr = nruns - r0 < kFinThreads ? nruns - r0 : kFinThreads;
+        for (int q = wave; q < nr; q += kFinWaves) {
+            if (lane < cnt[q]) a.act_out[pre[q] + lane] = run_rows<D>(a, (r0 + q) * 64)[lane];
+        }
+        total += btot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.ctl->count[(t + 1) % 3] = total;
+}
+
+template <int D>
+__global__ __launch_bounds__(kFinThreads) void ordered_compact_kernel(StepArgs a, int t, int cap_runs) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c[kRunsPerWave], id[kRunsPerWave];
+#pragma unroll
+    for (int u = 0; u < kRunsPerWave; ++u) {
+        const int r = wave + kFinWaves * u;
+        c[u] = 0;
+        id[u] = 0;
+        if (r < cap_runs) {
+            const int32_t* rows = run_rows<D>(a, r * 64);
+            c[u] = rows[64];
+            id[u] = rows[lane];
+        }
+    }
+    const int m = active_count(a.ctl, t);
+    if (m == 0) return;
+    const int nruns = (m + 63) / 64;
+    if (nruns > kFinWaves * kRunsPerWave) {
+        ordered_place_many<D>(a, t, nruns);
+        return;
+    }
+    __shared__ int wc[kFinWaves * kRunsPerWave];
+    if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < kRunsPerWave; ++u) {
+            const int r = wave + kFinWaves * u;
+            wc[r] = r < nruns ? c[u] : 0;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRunsPerWave; ++u) {
+        const int r = wave + kFinWaves * u;
+        if (r < nruns) {
+            int off = 0;   // kept ids of the runs before r
+            for (int q = 0; q < r; ++q) off += wc[q];
+            if (lane < c[u]) a.act_out[off + lane] = id[u];
+        }
+    }
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int q = 0; q < nruns; ++q) total += wc[q];
+        a.ctl->count[(t + 1) % 3] = total;
+    }
 }
 
 template <int D, int R>
@@ -388,7 +507,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(StepArgs a, int t
     const int m = active_count(a.ctl, t);
     if (m == 0) return;
     const int chunks = chunks_for(m, TS, a.n, grid, a.min_chunk);
-    if (chunks == 1) return;   // finalized inside the step kernel
+    if (chunks == 1 && !a.ordered) return;   // finalized inside the step kernel
     const bool pre = chunks > kDirectChunks;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -457,7 +576,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_fused_kernel(StepArgs a,
     const int m = active_count(a.ctl, t);
     if (m == 0) return;
     const int chunks = chunks_for(m, TS, a.n, grid, a.min_chunk);
-    if (chunks == 1) return;   // finalized inside the step kernel
+    if (chunks == 1 && !a.ordered) return;   // finalized inside the step kernel
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ float wsum[kFinWaves - 1][D + 1][64];
@@ -522,6 +641,10 @@ inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hip
             if (fblocks < 1) fblocks = 1;
             hipLaunchKernelGGL((finalize_fused_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a,
                                t, grid);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess || !a.ordered) return e;
+            hipLaunchKernelGGL((ordered_compact_kernel<D>), dim3(1), dim3(kFinThreads), 0, s, a, t,
+                               (B + 63) / 64);
             return hipGetLastError();
         }
     }
@@ -536,6 +659,9 @@ inline hipError_t launch_finalize(const StepArgs& a, int t, int grid, int B, hip
     if (fblocks < 1) fblocks = 1;
     hipLaunchKernelGGL((finalize_kernel<D, DP, R>), dim3(fblocks), dim3(kFinThreads), 0, s, a, t,
                        grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.ordered) return e;
+    hipLaunchKernelGGL((ordered_compact_kernel<D>), dim3(1), dim3(kFinThreads), 0, s, a, t, (B + 63) / 64);
     return hipGetLastError();
 }
 

@@ -352,6 +352,40 @@ def test_bf16_fit_flat_small(orc):
         say(fit_parity(g, ref, X, 2.5, orc=orc, kernel="flat"))
 
 
+def _mixture2d(seed, n):
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0, 100, (8, 2))
+    y = rng.integers(0, 8, n)
+    return (C[y] + 2.0 * rng.standard_normal((n, 2))).astype(np.float32)
+
+
+def test_bf16_step_many_seeds_repeatable(orc):
+    """More than 4,096 active seeds (the ordered compaction places more than
+    64 runs): every point of a 12,000-point 2-D mixture as a seed, 1 and 3
+    iterations against the oracle, and a second call gives the same bits."""
+    X = _mixture2d(21, 12000)
+    h = 4.0
+    for n_iter in (1, 3):
+        say("bf16 step, 12000 seeds, n_iter", n_iter)
+        S, conv, it, sh = api.step(_gpu(X), _gpu(X), h, precision="bf16", n_iter=n_iter)
+        torch.cuda.synchronize()
+        ref, ost, oit, osh = orc.step(X, X.astype(np.float64), h, "gaussian", tol=1e-3, n_iter=n_iter)
+        ragged_check(orc, X, X, h, "gaussian", n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                     conv.cpu().numpy(), ref, oit, ost)
+    again = api.step(_gpu(X), _gpu(X), h, precision="bf16", n_iter=3)
+    torch.cuda.synchronize()
+    for a, b in zip((S, conv, it, sh), again):
+        torch.testing.assert_close(b.cpu(), a.cpu(), rtol=0, atol=0, equal_nan=True)
+
+
+def test_bf16_fit_all_points_many_seeds(orc):
+    """Algorithm 1 with 12,000 seeds in the BF16 form against the oracle."""
+    X = _mixture2d(22, 12000)
+    g = api.fit(_gpu(X), 4.0, precision="bf16", all_points=True, trace=True)
+    ref = orc.fit(X, 4.0, all_points=True)
+    say("bf16 fit, all 12000 points as seeds", fit_parity(g, ref, X, 4.0, orc=orc))
+
+
 def test_bf16_deterministic(aniso):
     X = _gpu(aniso.X)
     a = api.fit(X, aniso.h, precision="bf16", trace=True)
