@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
                                                                float* info, const long long* __restrict__ x_off,
                                                                const int32_t* __restrict__ boff, int ncl) {
     using Sh = FShape<D>;
-    __shared__ __attribute__((aligned(16))) float vals[kFBlk];
+    constexpr int kW = kFBlk / 64;
+    __shared__ float srt[kW][64];   // each wave's values of one coordinate, ascending
     __shared__ float ctr[D];
     __shared__ float rmax[3][kFBlk / 64];
     __shared__ float omin[kFBlk / 64][D], omax[kFBlk / 64][D], oc[D];
@@ -140,24 +141,43 @@ __global__ __launch_bounds__(kFBlk) void bf16f_features_kernel(const float* __re
 #pragma unroll
     for (int k = 0; k < D; ++k) x[k] = live ? Xs[row * D + k] : 0.0f;
     if (tid < D) ctr[tid] = Xs[row0 * D + tid];   // stands in if ranks tie oddly (NaN)
+    // per coordinate, the value of rank mid among the live points (padding
+    // lanes hold +inf and sort last): each wave sorts its 64 values by a
+    // bitonic network over lane shuffles, and the value at position p of
+    // wave w has rank p + (values of the earlier waves <= it) + (values of
+    // the later waves < it) -- a permutation of 0..255, so exactly one lane
+    // holds rank mid, and its value is the coordinate's median
+    const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll 1
     for (int k = 0; k < D; ++k) {
-        const float xv = x[k];
-        vals[tid] = live ? xv : __builtin_inff();
-        __syncthreads();
-        int rank = 0;
-        const float4* v4 = reinterpret_cast<const float4*>(vals);
-#pragma unroll 4
-        for (int j4 = 0; j4 < kFBlk / 4; ++j4) {
-            const float4 u = v4[j4];
-            const int j = 4 * j4;
-            rank += (u.x < xv) || (u.x == xv && j < tid);
-            rank += (u.y < xv) || (u.y == xv && j + 1 < tid);
-            rank += (u.z < xv) || (u.z == xv && j + 2 < tid);
-            rank += (u.w < xv) || (u.w == xv && j + 3 < tid);
+        float v = live ? x[k] : __builtin_inff();
+#pragma unroll
+        for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const float y = __shfl_xor(v, j);
+                const bool keep_min = ((lane & kk) == 0) == ((lane & j) == 0);
+                v = keep_min ? fminf(v, y) : fmaxf(v, y);
+            }
         }
-        if (live && rank == mid) ctr[k] = xv;
-        __syncthreads();   // vals is rewritten for the next coordinate
+        srt[wv][lane] = v;
+        __syncthreads();
+        int rank = lane;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) {
+            if (w == wv) continue;
+            // values of wave w below v (w > wv) or not above v (w < wv)
+            int lo = 0, hi = 64;
+            while (lo < hi) {
+                const int md = (lo + hi) >> 1;
+                const float u = srt[w][md];
+                if (w < wv ? (u <= v) : (u < v)) lo = md + 1;
+                else hi = md;
+            }
+            rank += lo;
+        }
+        if (rank == mid) ctr[k] = v;
+        __syncthreads();   // srt is rewritten for the next coordinate
     }
     float xt[D];
     float nx = 0.0f;
