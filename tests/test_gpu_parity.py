@@ -378,6 +378,33 @@ def test_bf16_step_many_seeds_repeatable(orc):
         torch.testing.assert_close(b.cpu(), a.cpu(), rtol=0, atol=0, equal_nan=True)
 
 
+@pytest.mark.parametrize("n,d", [(300_000, 3), (230_000, 4)])
+def test_bf16_step_reduced_partials_ordered(orc, n, d):
+    """Enough points that a tile's chunk partials exceed the one-launch
+    reduce-and-finalize (more than 2,048 floats per slot): the reduction,
+    the finalize and the ordered placement of the active list run as three
+    launches, the finalize reading the reduced sums from the rows it then
+    fills with each run's kept seeds.  256 seeds, 1 and 3 iterations
+    against the oracle; a second call gives the same bits."""
+    rng = np.random.default_rng(n + d)
+    C = rng.uniform(0, 400, (30, d))
+    y = rng.integers(0, 30, n)
+    X = (C[y] + 6.0 * rng.standard_normal((n, d))).astype(np.float32)
+    S0 = X[rng.choice(n, 256, replace=False)]
+    h = 10.0
+    for n_iter in (1, 3):
+        say("bf16 step, reduced partials", n, d, "n_iter", n_iter)
+        S, conv, it, sh = api.step(_gpu(X), _gpu(S0), h, precision="bf16", n_iter=n_iter)
+        torch.cuda.synchronize()
+        ref, ost, oit, osh = orc.step(X, S0.astype(np.float64), h, "gaussian", tol=1e-3, n_iter=n_iter)
+        ragged_check(orc, X, S0, h, "gaussian", n_iter, S.cpu().numpy(), it.cpu().numpy(),
+                     conv.cpu().numpy(), ref, oit, ost)
+    again = api.step(_gpu(X), _gpu(S0), h, precision="bf16", n_iter=3)
+    torch.cuda.synchronize()
+    for a, b in zip((S, conv, it, sh), again):
+        torch.testing.assert_close(b.cpu(), a.cpu(), rtol=0, atol=0, equal_nan=True)
+
+
 def test_bf16_fit_all_points_many_seeds(orc):
     """Algorithm 1 with 12,000 seeds in the BF16 form against the oracle."""
     X = _mixture2d(22, 12000)
