@@ -33,6 +33,7 @@ import os
 import statistics
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -247,7 +248,7 @@ def config_c3(api, torch, workloads, gpu_fits, iters):
     return out
 
 
-def config_c4(api, torch, workloads):
+def config_c4(api, torch, workloads, gpu_fits):
     import numpy as np
     clouds = workloads.clouds16(seed=0)
     Xs = [c[0] for c in clouds]
@@ -315,6 +316,7 @@ def config_c4(api, torch, workloads):
         t0 = time.perf_counter()
         per, lab, k_off, rounds = api.fit_batched(Xa, xo, 1.0, precision=precision)
         torch.cuda.synchronize()
+        gpu_fits[("c4", precision)] = (per, lab, k_off, xo, Xs)
         return time.perf_counter() - t0, k_off, rounds
 
     fit_all()
@@ -533,10 +535,33 @@ def cpu_baseline(workloads, gpu_fits):
             if g is not None:
                 errors.setdefault("c3", {})[prec] = fit_error(g, z["modes"], z["labels"].astype(np.int64), margin,
                                                               int(z["k"]), w3.h)
+    # the 512 clouds' whole-method call: the smallest, the largest and two
+    # other clouds against the oracle's fit of each cloud alone (cloud c
+    # draws with state c), every sampled cloud's figures combined
+    for prec in ("fp32", "bf16"):
+        fb = gpu_fits.get(("c4", prec))
+        if fb is None:
+            continue
+        per, lab, k_off, xo, Xs = fb
+        sizes = np.diff(xo)
+        pick = sorted({int(sizes.argmin()), int(sizes.argmax()), 100, 400})
+        agg = {"clouds_checked": pick, "K_equal": True, "max_mode_err_over_h": 0.0, "labels_differ": 0,
+               "labels_differ_away_from_ties": 0}
+        for c in pick:
+            ref = oracle.fit(Xs[c], 1.0, rng_seed=c, nthreads=nt)
+            g = types.SimpleNamespace(modes=per[c], k=int(k_off[c + 1] - k_off[c]),
+                                      labels=lab[int(xo[c]):int(xo[c + 1])])
+            e = fit_error(g, ref.modes, ref.labels, ref.margin, ref.k, 1.0)
+            agg["K_equal"] = agg["K_equal"] and e["K_equal"]
+            agg["max_mode_err_over_h"] = max(agg["max_mode_err_over_h"], e.get("max_mode_err_over_h", float("inf")))
+            agg["labels_differ"] += e.get("labels_differ", 0)
+            agg["labels_differ_away_from_ties"] += e.get("labels_differ_away_from_ties", 0)
+        errors.setdefault("c4", {})[prec] = agg
     value = res["c2_pair_evals_per_s_all"]
     return {"value": value, "unit": "pair evals/s", "cores": nt, "kind": "oracle",
             "sample": "the FP64 oracle's whole fit of the 200K mixture (median of 3 on all host threads); "
-                      "also one thread, the 2-D blobs and a 64-seed sample of the 32-D embeddings",
+                      "also one thread, the 2-D blobs and a 64-seed sample of the 32-D embeddings; "
+                      "four of the 512 clouds fitted once each for their errors",
             "time_to_cluster_ms": res["c2_fit_s_all_threads"] * 1e3, "detail": res,
             "error_vs_fp64": errors}
 
@@ -795,7 +820,7 @@ def main():
         c2[p_].update(fit_summary(dt_ / args.steps, r_))
     out["configs"] = {"C1": config_c1(api, torch, workloads, gpu_fits), "C2": c2,
                       "C3": config_c3(api, torch, workloads, gpu_fits, max(3, args.kernel_iters // 4)),
-                      "C4": config_c4(api, torch, workloads), "C5": config_c5(api, torch, workloads)}
+                      "C4": config_c4(api, torch, workloads, gpu_fits), "C5": config_c5(api, torch, workloads)}
     if not args.no_other_configs:
         out["other_configs"] = other_configs(api, torch, workloads)
     if not args.no_cpu_baseline:
