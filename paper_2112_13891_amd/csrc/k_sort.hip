@@ -322,26 +322,30 @@ __global__ void shift_kernel(const float* __restrict__ bnd, int D, float* shift)
 
 // Nearest pivot of each row r of `rows` (stride DPr, times `scale`), pivots
 // being the points Xp[j * n / P], j < P, in two launches: pivot_near_kernel
-// takes a tile of rows against a chunk of kPivChunk pivots (so that few rows
-// still fill the machine) and folds its result into best[r] = (squared
-// distance bits << 32 | pivot index) with a 64-bit atomic minimum (the
-// nearest pivot, ties to the lowest index, whatever the order of the
-// chunks); pivot_key_kernel turns it into the sort key.
+// takes a tile of rows against a chunk of PC pivots and folds its result into
+// best[r] = (squared distance bits << 32 | pivot index) with a 64-bit atomic
+// minimum (the nearest pivot, ties to the lowest index, whatever the order of
+// the chunks); pivot_key_kernel turns it into the sort key.  Chunks of
+// kPivChunk pivots for the seeds (few rows still fill the machine), of
+// kPivChunkPoints for the points (each row is loaded, and its minimum folded,
+// once per chunk: at 262,144 x 32 with 1,024 pivots, 16 chunks re-read the
+// rows 16 times).
 constexpr int kPivChunk = 64;
+constexpr int kPivChunkPoints = 256;
 
 // Many clouds (rc.roff set): blockIdx.x is a 256-row tile of one cloud's
 // rows, whose pivots are the cloud's own (points Xp[xoff[c] ..], poff).
-template <int D>
+template <int D, int PC = kPivChunk>
 __global__ __launch_bounds__(256) void pivot_near_kernel(const float* __restrict__ rows, long long m, int DPr,
                                                          float scale, const float* __restrict__ Xp, int n,
                                                          int DP, int P, unsigned long long* best,
                                                          CloudRows rc, const long long* __restrict__ xoff,
                                                          const int32_t* __restrict__ poff) {
-    static_assert(D % 4 == 0 && (kPivChunk * D) % 256 == 0, "pivot chunk layout");
-    constexpr int kPer = kPivChunk * D / 256;   // pivot coordinates each thread stages
-    __shared__ __attribute__((aligned(16))) float piv[kPivChunk][D];
+    static_assert(D % 4 == 0 && (PC * D) % 256 == 0, "pivot chunk layout");
+    constexpr int kPer = PC * D / 256;   // pivot coordinates each thread stages
+    __shared__ __attribute__((aligned(16))) float piv[PC][D];
     long long r = (long long)blockIdx.x * 256 + threadIdx.x;
-    const int j0 = blockIdx.y * kPivChunk;
+    const int j0 = blockIdx.y * PC;
     if (rc.roff) {
         const int c = upper_cloud(rc.tpre, rc.ncl, blockIdx.x);
         r = rc.roff[c] + (long long)(blockIdx.x - rc.tpre[c]) * 256 + threadIdx.x;
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(256) void pivot_near_kernel(const float* __restrict
         Xp += x0 * DP;
         if (j0 >= P) return;   // the whole workgroup
     }
-    const int cnt = min(kPivChunk, P - j0);
+    const int cnt = min(PC, P - j0);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int e = u * 256 + threadIdx.x;
@@ -829,10 +833,10 @@ hipError_t launch_spatial_sort(const float* Xp, int n, int DP, int D, float* Xs,
         FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(1), dim3(1024), 0, s, Xp, n, DP,
                                                 P, knn, prank, nullptr, nullptr));
         hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, ~0ull);
-        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>),
-                                                dim3((n + 255) / 256, (P + kPivChunk - 1) / kPivChunk), dim3(256), 0,
-                                                s, Xp, (long long)n, DP, 1.0f, Xp, n, DP, P, w.best, CloudRows{},
-                                                nullptr, nullptr));
+        FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD, kPivChunkPoints>),
+                                                dim3((n + 255) / 256, (P + kPivChunkPoints - 1) / kPivChunkPoints),
+                                                dim3(256), 0, s, Xp, (long long)n, DP, 1.0f, Xp, n, DP, P, w.best,
+                                                CloudRows{}, nullptr, nullptr));
         hipLaunchKernelGGL(pivot_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, nullptr, prank,
                            w.k0, w.v0);
     }
@@ -901,9 +905,9 @@ hipError_t launch_batched_sort(const float* Xp, int n, int D, const CloudRows& p
     FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_chain_kernel<DD>), dim3(ncl), dim3(1024), 0, s, Xp, 0, D, 0,
                                             knn, prank, pts.roff, poff));
     hipLaunchKernelGGL(fill_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, n, ~0ull);
-    const dim3 ngrid(pts.tiles, (kBatchedPivotMax + kPivChunk - 1) / kPivChunk);
-    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD>), ngrid, dim3(256), 0, s, Xp, (long long)n, D,
-                                            1.0f, Xp, 0, D, 0, w.best, pts, pts.roff, poff));
+    const dim3 ngrid(pts.tiles, (kBatchedPivotMax + kPivChunkPoints - 1) / kPivChunkPoints);
+    FMS_PIVOT_DSWITCH(D, hipLaunchKernelGGL((pivot_near_kernel<DD, kPivChunkPoints>), ngrid, dim3(256), 0, s, Xp,
+                                            (long long)n, D, 1.0f, Xp, 0, D, 0, w.best, pts, pts.roff, poff));
     hipLaunchKernelGGL(bpivot_key_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w.best, (long long)n, nullptr,
                        pts.roff, ncl, poff, prank, w.k0, w.v0);
     const int* sorted = radix_sort_pairs(w, n, s, 4);
